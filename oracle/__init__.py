@@ -1,0 +1,193 @@
+"""FP64 CPU oracle for the 3D scattering solve -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may import
+this package.  The product path (the HIP library and its Python binding) never imports, calls or
+links anything here, and nothing here imports the product path.
+
+The arithmetic lives in ``oracle.c`` (plain C, FP64, built with gcc); this module only builds and
+loads it and marshals numpy arrays.  ``dense_os_solution`` adds the plain definition of the converged
+result for tiny grids: the linear system (I - Lambda diag(1-eps)) J = Lambda (eps B) + J_bc.
+
+Pins (closed forms, invariants, brute force) live in ``tests/test_oracle_*.py``.  Parity unpinned:
+the *number* of outer iterations to convergence (it depends on the readings of the Jacobi depth and
+the initial guess, which the paper does not state).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP over directions)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-Wall", _SRC, "-o", _LIB + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
+        i, d = C.c_int, C.c_double
+        L.orc_gauss_legendre.argtypes = [i, _dp, _dp]
+        L.orc_quadrature.argtypes = [i, i, _dp, _dp, _dp, _dp]
+        L.orc_trace_layer.argtypes = [i, i, i, i, i, i, i, i, i, _ip, _dp, i]
+        L.orc_formal_solution.argtypes = [i, i, i, i, i, _dp, _dp, d, C.c_void_p, _dp, C.c_void_p,
+                                          C.c_void_p, i]
+        L.orc_lstar.argtypes = [i, i, i, i, i, _dp, _dp, i]
+        L.orc_lambda_bruteforce.argtypes = [i, i, i, i, i, _dp, _dp, i]
+        L.orc_os_step.argtypes = [i, i, i, i, i, _dp, _dp, _dp, d, i, _dp, _dp, i,
+                                  C.POINTER(C.c_double), C.c_void_p, i]
+        L.orc_solve.argtypes = [i, i, i, i, i, _dp, _dp, _dp, d, i, C.c_void_p, _dp, d, i, i,
+                                C.POINTER(C.c_int), C.POINTER(C.c_double), i]
+        L.orc_pp1d.argtypes = [i, i, _dp, _dp, d, d, _dp]
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+    return rc
+
+
+def gauss_legendre(n: int):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    _check(lib().orc_gauss_legendre(n, x, w), "gauss_legendre")
+    return x, w
+
+
+def quadrature(n_theta: int, n_phi: int):
+    """Returns (mu, ox, oy, W) over directions d = a * n_phi + b."""
+    nd = n_theta * n_phi
+    mu, ox, oy, wt = (np.zeros(nd) for _ in range(4))
+    _check(lib().orc_quadrature(n_theta, n_phi, mu, ox, oy, wt), "quadrature")
+    return mu, ox, oy, wt
+
+
+def trace_layer(nx, ny, nz, n_theta, n_phi, d, i, j, k, max_seg=64):
+    """Segments (voxel index, length) of line (i,j), direction d, inside layer k, in travel order."""
+    v = np.zeros(max_seg, dtype=np.int32)
+    ln = np.zeros(max_seg)
+    n = _check(lib().orc_trace_layer(nx, ny, nz, n_theta, n_phi, d, i, j, k, v, ln, max_seg),
+               "trace_layer")
+    return v[:n].copy(), ln[:n].copy()
+
+
+def formal_solution(chi, S, n_theta, n_phi, I_top=0.0, I_bot=None, want_emergent=False,
+                    want_ibar=False, n_threads=0):
+    """J = FS(S).  chi, S: (nz, ny, nx).  I_bot: (ny, nx) or None (zero).
+
+    Returns J (and the top-plane emergent intensities [n_up, ny, nx] and the per-direction voxel
+    intensities [n_dir, nz, ny, nx] when asked for)."""
+    chi = _f64(chi)
+    S = _f64(S)
+    nz, ny, nx = chi.shape
+    J = np.zeros_like(chi)
+    nd = n_theta * n_phi
+    Iem = np.zeros((nd // 2, ny, nx)) if want_emergent else None
+    Ibar = np.zeros((nd,) + chi.shape) if want_ibar else None
+    ib = None if I_bot is None else _f64(np.broadcast_to(I_bot, (ny, nx)))
+    _check(lib().orc_formal_solution(nx, ny, nz, n_theta, n_phi, chi, S, float(I_top), _ptr(ib), J,
+                                     _ptr(Iem), _ptr(Ibar), n_threads), "formal_solution")
+    out = [J]
+    if want_emergent:
+        out.append(Iem)
+    if want_ibar:
+        out.append(Ibar)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def lstar(chi, n_theta, n_phi, n_threads=0):
+    """Lambda* as [27, nz, ny, nx], neighbour index o = 9(dk+1) + 3(dj+1) + (di+1)."""
+    chi = _f64(chi)
+    nz, ny, nx = chi.shape
+    L = np.zeros((27,) + chi.shape)
+    _check(lib().orc_lstar(nx, ny, nz, n_theta, n_phi, chi, L, n_threads), "lstar")
+    return L
+
+
+def lambda_bruteforce(chi, n_theta, n_phi, n_threads=0):
+    """Dense Lambda [V, V] from unit-source formal solutions (tiny grids only)."""
+    chi = _f64(chi)
+    nz, ny, nx = chi.shape
+    V = chi.size
+    Lam = np.zeros((V, V))
+    _check(lib().orc_lambda_bruteforce(nx, ny, nz, n_theta, n_phi, chi, Lam, n_threads), "bruteforce")
+    return Lam
+
+
+def os_step(chi, eps, B, Lstar, J, n_theta, n_phi, M, I_top=0.0, bottom_from_B=True, n_threads=0,
+            want_jfs=False):
+    """One operator-splitting step.  Returns (J_new, c) (and J_fs when asked for)."""
+    chi, eps, B, Lstar = _f64(chi), _f64(eps), _f64(B), _f64(Lstar)
+    nz, ny, nx = chi.shape
+    Jn = _f64(J).copy()
+    c = C.c_double(0.0)
+    Jfs = np.zeros_like(chi) if want_jfs else None
+    _check(lib().orc_os_step(nx, ny, nz, n_theta, n_phi, chi, eps, B, float(I_top), int(bottom_from_B),
+                             Lstar, Jn, int(M), C.byref(c), _ptr(Jfs), n_threads), "os_step")
+    return (Jn, c.value, Jfs) if want_jfs else (Jn, c.value)
+
+
+def solve(chi, eps, B, n_theta, n_phi, tol, max_iter, M, J0=None, Lstar=None, I_top=0.0,
+          bottom_from_B=True, n_threads=0):
+    """Outer OS iteration from J0 (default B) until c < tol.  Returns (J, iters, c, converged)."""
+    chi, eps, B = _f64(chi), _f64(eps), _f64(B)
+    nz, ny, nx = chi.shape
+    J = (B if J0 is None else _f64(J0)).copy()
+    Ls = None if Lstar is None else _f64(Lstar)
+    it = C.c_int(0)
+    c = C.c_double(0.0)
+    rc = _check(lib().orc_solve(nx, ny, nz, n_theta, n_phi, chi, eps, B, float(I_top),
+                                int(bottom_from_B), _ptr(Ls), J, float(tol), int(max_iter), int(M),
+                                C.byref(it), C.byref(c), n_threads), "solve")
+    return J, it.value, c.value, rc == 0
+
+
+def pp1d(dtau, S, n_theta, I_top=0.0, I_bot=0.0):
+    """Plane-parallel J_k for layer thicknesses dtau[k] (k = 0 bottom) and sources S[k]."""
+    dtau, S = _f64(dtau), _f64(S)
+    J = np.zeros_like(dtau)
+    _check(lib().orc_pp1d(dtau.size, n_theta, dtau, S, float(I_top), float(I_bot), J), "pp1d")
+    return J
+
+
+def dense_os_solution(chi, eps, B, n_theta, n_phi, I_top=0.0, bottom_from_B=True, n_threads=0):
+    """Converged J by its plain definition (tiny grids): solve (I - Lambda diag(1-eps)) J = rhs,
+    rhs = Lambda (eps B) + J_bc, where J_bc is the mean intensity of the boundary light alone."""
+    chi, eps, B = _f64(chi), _f64(eps), _f64(B)
+    Lam = lambda_bruteforce(chi, n_theta, n_phi, n_threads)
+    V = chi.size
+    J_bc = formal_solution(chi, np.zeros_like(chi), n_theta, n_phi, I_top=I_top,
+                           I_bot=(B[0] if bottom_from_B else None), n_threads=n_threads).ravel()
+    A = np.eye(V) - Lam * (1.0 - eps.ravel())[None, :]
+    rhs = Lam @ (eps * B).ravel() + J_bc
+    return np.linalg.solve(A, rhs).reshape(chi.shape)

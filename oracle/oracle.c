@@ -1,0 +1,577 @@
+/*
+ * oracle.c -- plain, slow, FP64 CPU oracle for the 3D radiative-transfer scattering solve of
+ * Hauschildt & Baron, "A 3D radiative transfer framework XIII: OpenCL implementation".
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load this library.  It shares no code, header, table or helper with the HIP library.
+ *
+ * What is computed (section "Method" and its two implementation subsections):
+ *   - the formal solution (FS) along characteristics through a Cartesian voxel grid that is
+ *     periodic in x and y, for every solid angle ("Implementation of the formal solution");
+ *   - the mean intensity J and the nearest-neighbour (3x3x3) Lambda* operator;
+ *   - the operator-splitting (OS) step that solves (1 - Lambda* (1-eps)) dJ = J_fs - J_old by
+ *     Jacobi ("Jordan") iterations ("Implementation of the operator splitting step"),
+ *     with S = eps B + (1-eps) J for coherent isotropic scattering ("Test case setup").
+ *
+ * The paper defers the discretisation to the earlier papers of its series.  The readings used here:
+ *   grid      unit voxels (i,j,k), k = 0 at the bottom (inner boundary), k = nz-1 at the top;
+ *   angles    Gauss-Legendre in mu (n_theta even) x uniform phi_b = 2 pi (b + 1/2) / n_phi,
+ *             weight W = w_a / (2 n_phi), so that the weights sum to one;
+ *   lines     for every direction one straight line per column (i,j), through (i+1/2, j+1/2, nz);
+ *             the same lines serve Omega and -Omega; downward lines start at the top with I_top,
+ *             upward lines start at z = 0 with I_bot of the bottom voxel they enter;
+ *   medium    chi and S constant inside a voxel, so each piece of line inside one voxel
+ *             ("segment") is integrated exactly;
+ *   voxel I   Ibar_v(Omega) is the path-length-weighted average of I over all segments of the
+ *             direction's lines inside v; every voxel holds exactly 1/|mu| of path per direction;
+ *   Lambda*   the 27-point band of the exact Lambda operator (S -> J with zero boundary light);
+ *   OS        dJ^0 = 0, a fixed number M of Jacobi sweeps, J <- J + dJ^M,
+ *             convergence measure c = max_v |dJ_v| / |J_v^new|, initial guess J^0 = B.
+ *
+ * Layout: every per-voxel field is [k][j][i] with i fastest; Lambda* is [27][V] with neighbour
+ * offset index o = 9 (dk+1) + 3 (dj+1) + (di+1), u = v + (di, dj, dk), periodic in i and j.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EARG -1
+#define ORC_ENOMEM -2
+
+/* ------------------------------------------------------------------------------------------------
+ * Angular quadrature.
+ * --------------------------------------------------------------------------------------------- */
+
+/* Gauss-Legendre nodes x[0..n-1] (ascending) and weights on [-1,1]: Newton iteration on P_n,
+ * evaluated with the three-term recurrence (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1}. */
+int orc_gauss_legendre(int n, double *x, double *w)
+{
+    if (n < 2 || !x || !w) return ORC_EARG;
+    for (int r = 0; r < n; ++r) {
+        /* r-th root counted from +1 downwards; Chebyshev-like starting guess */
+        double z = cos(M_PI * (r + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 1; k < n; ++k) {
+                double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            /* derivative: (1 - z^2) P_n' = n (P_{n-1} - z P_n) */
+            dp = n * (p0 - z * p1) / (1.0 - z * z);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        /* recompute P_n' at the converged root for the weight */
+        {
+            double p0 = 1.0, p1 = z;
+            for (int k = 1; k < n; ++k) {
+                double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (p0 - z * p1) / (1.0 - z * z);
+        }
+        x[n - 1 - r] = z;
+        w[n - 1 - r] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+    return ORC_OK;
+}
+
+/* Direction set: d = a * n_phi + b, a over the Gauss-Legendre mu nodes (ascending), b over phi.
+ * Omega_d = (sqrt(1-mu^2) cos phi_b, sqrt(1-mu^2) sin phi_b, mu_a), W_d = w_a / (2 n_phi). */
+int orc_quadrature(int n_theta, int n_phi, double *mu, double *ox, double *oy, double *wt)
+{
+    if (n_theta < 2 || (n_theta & 1) || n_phi < 4 || (n_phi % 4) != 0) return ORC_EARG;
+    double *xg = (double *)malloc(sizeof(double) * n_theta);
+    double *wg = (double *)malloc(sizeof(double) * n_theta);
+    if (!xg || !wg) { free(xg); free(wg); return ORC_ENOMEM; }
+    orc_gauss_legendre(n_theta, xg, wg);
+    for (int a = 0; a < n_theta; ++a) {
+        double st = sqrt(1.0 - xg[a] * xg[a]);
+        for (int b = 0; b < n_phi; ++b) {
+            int d = a * n_phi + b;
+            double phi = 2.0 * M_PI * (b + 0.5) / n_phi;
+            mu[d] = xg[a];
+            ox[d] = st * cos(phi);
+            oy[d] = st * sin(phi);
+            wt[d] = wg[a] / (2.0 * n_phi);
+        }
+    }
+    free(xg);
+    free(wg);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------------------------------
+ * Geometry: one line through one layer.
+ * --------------------------------------------------------------------------------------------- */
+
+typedef struct {
+    int nx, ny, nz, n_theta, n_phi, n_dir;
+    double *mu, *ox, *oy, *wt;
+} Geom;
+
+static int geom_init(Geom *g, int nx, int ny, int nz, int n_theta, int n_phi)
+{
+    if (nx < 3 || ny < 3 || nz < 1) return ORC_EARG;
+    g->nx = nx; g->ny = ny; g->nz = nz; g->n_theta = n_theta; g->n_phi = n_phi;
+    g->n_dir = n_theta * n_phi;
+    g->mu = (double *)malloc(sizeof(double) * 4 * g->n_dir);
+    if (!g->mu) return ORC_ENOMEM;
+    g->ox = g->mu + g->n_dir;
+    g->oy = g->ox + g->n_dir;
+    g->wt = g->oy + g->n_dir;
+    int rc = orc_quadrature(n_theta, n_phi, g->mu, g->ox, g->oy, g->wt);
+    if (rc) { free(g->mu); g->mu = NULL; }
+    return rc;
+}
+
+static void geom_free(Geom *g) { free(g->mu); g->mu = NULL; }
+
+static int imod(long a, int n) { long r = a % n; return (int)(r < 0 ? r + n : r); }
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Upper bound on the number of segments of one line inside one layer. */
+static int max_segments(const Geom *g, int d)
+{
+    double tx = fabs(g->ox[d] / g->mu[d]), ty = fabs(g->oy[d] / g->mu[d]);
+    return (int)ceil(tx) + (int)ceil(ty) + 3;
+}
+
+/* Segments of line (i,j) of direction d inside layer k, in the order the photon travels.
+ * The line is x(z) = i + 1/2 + (z - nz) Omega_x / mu, y(z) likewise.  Breakpoints are the
+ * parameters f in (0,1) along the layer path where x or y crosses an integer; each piece between
+ * breakpoints lies in the voxel that contains its midpoint and has length (f1 - f0) / |mu|.
+ * Returns the number of segments written (zero-length pieces at exact ties are dropped). */
+static int trace_layer(const Geom *g, int d, int i, int j, int k, double *fbuf,
+                       int *seg_v, double *seg_len)
+{
+    const double mu = g->mu[d];
+    const double tx = g->ox[d] / mu, ty = g->oy[d] / mu;
+    const double za = (mu < 0.0) ? (double)(k + 1) : (double)k;   /* entry height */
+    const double zb = (mu < 0.0) ? (double)k : (double)(k + 1);   /* exit height  */
+    const double xa = i + 0.5 + (za - g->nz) * tx, xb = i + 0.5 + (zb - g->nz) * tx;
+    const double ya = j + 0.5 + (za - g->nz) * ty, yb = j + 0.5 + (zb - g->nz) * ty;
+    int nf = 0;
+    fbuf[nf++] = 0.0;
+    {
+        double lo = fmin(xa, xb), hi = fmax(xa, xb);
+        for (double X = floor(lo) + 1.0; X < hi; X += 1.0) fbuf[nf++] = (X - xa) / (xb - xa);
+    }
+    {
+        double lo = fmin(ya, yb), hi = fmax(ya, yb);
+        for (double Y = floor(lo) + 1.0; Y < hi; Y += 1.0) fbuf[nf++] = (Y - ya) / (yb - ya);
+    }
+    qsort(fbuf + 1, nf - 1, sizeof(double), cmp_double);
+    fbuf[nf++] = 1.0;
+    int ns = 0;
+    const double inv_mu = 1.0 / fabs(mu);
+    for (int q = 0; q + 1 < nf; ++q) {
+        double f0 = fbuf[q], f1 = fbuf[q + 1];
+        if (!(f1 > f0)) continue;
+        double fm = 0.5 * (f0 + f1);
+        double xm = xa + fm * (xb - xa), ym = ya + fm * (yb - ya);
+        int iv = imod((long)floor(xm), g->nx), jv = imod((long)floor(ym), g->ny);
+        seg_v[ns] = (k * g->ny + jv) * g->nx + iv;
+        seg_len[ns] = (f1 - f0) * inv_mu;
+        ++ns;
+    }
+    return ns;
+}
+
+/* Exported for the geometry tests: segments of line (i,j), direction d, layer k. */
+int orc_trace_layer(int nx, int ny, int nz, int n_theta, int n_phi, int d, int i, int j, int k,
+                    int *seg_v, double *seg_len, int max_seg)
+{
+    Geom g;
+    int rc = geom_init(&g, nx, ny, nz, n_theta, n_phi);
+    if (rc) return rc;
+    if (d < 0 || d >= g.n_dir || k < 0 || k >= nz) { geom_free(&g); return ORC_EARG; }
+    int ms = max_segments(&g, d);
+    if (max_seg < ms) { geom_free(&g); return ORC_EARG; }
+    double *fbuf = (double *)malloc(sizeof(double) * (ms + 2));
+    int ns = trace_layer(&g, d, i, j, k, fbuf, seg_v, seg_len);
+    free(fbuf);
+    geom_free(&g);
+    return ns;
+}
+
+/* ------------------------------------------------------------------------------------------------
+ * Formal solution.
+ * --------------------------------------------------------------------------------------------- */
+
+/* One direction: trace every line from its boundary through all layers, integrate I exactly across
+ * each segment and accumulate D_s = chi_v * (integral of I over the segment) per voxel.
+ *   dtau = chi_v l,  em1 = expm1(-dtau) = e^{-dtau} - 1,
+ *   I_out = I_in + (I_in - S_v) em1,          (exact solution for constant chi, S)
+ *   D_s   = S_v dtau - (I_in - S_v) em1.
+ * Dsum[v] receives sum_s D_s; Iem (optional) receives I at the top plane of upward lines. */
+static void fs_direction(const Geom *g, int d, const double *chi, const double *S, double I_top,
+                         const double *I_bot, double *Dsum, double *Iem, double *fbuf,
+                         int *seg_v, double *seg_len)
+{
+    const double mu = g->mu[d];
+    for (int j = 0; j < g->ny; ++j) {
+        for (int i = 0; i < g->nx; ++i) {
+            double I = I_top;
+            for (int step = 0; step < g->nz; ++step) {
+                int k = (mu < 0.0) ? g->nz - 1 - step : step;
+                int ns = trace_layer(g, d, i, j, k, fbuf, seg_v, seg_len);
+                if (mu > 0.0 && step == 0) {
+                    /* upward line: boundary intensity of the bottom voxel it enters */
+                    /* in layer 0 the voxel index equals the column index j*nx + i */
+                    I = I_bot ? I_bot[seg_v[0]] : 0.0;
+                }
+                for (int s = 0; s < ns; ++s) {
+                    int v = seg_v[s];
+                    double dtau = chi[v] * seg_len[s];
+                    double em1 = expm1(-dtau);
+                    double D = S[v] * dtau - (I - S[v]) * em1;
+                    I = I + (I - S[v]) * em1;
+                    Dsum[v] += D;
+                }
+            }
+            if (Iem && mu > 0.0) Iem[j * g->nx + i] = I;
+        }
+    }
+}
+
+static int n_threads_of(int req)
+{
+#ifdef _OPENMP
+    if (req > 0) return req;
+    return omp_get_max_threads();
+#else
+    (void)req;
+    return 1;
+#endif
+}
+
+/* J_v = sum_d W_d Ibar_v(d),  Ibar_v(d) = |mu_d| / chi_v * sum_{s in v} D_s.
+ * I_bot: [ny][nx] intensities entering the bottom plane (NULL = zero).
+ * Iem (optional): [n_up][ny][nx], I leaving the top plane along the upward directions, in
+ * direction order.  Ibar (optional): [n_dir][V] per-direction voxel intensities.
+ * Threads split the directions; each thread sums its own directions in order, and the threads'
+ * partial sums are added in thread order. */
+int orc_formal_solution(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi,
+                        const double *S, double I_top, const double *I_bot, double *J,
+                        double *Iem, double *Ibar, int n_threads)
+{
+    Geom g;
+    int rc = geom_init(&g, nx, ny, nz, n_theta, n_phi);
+    if (rc) return rc;
+    const long V = (long)nx * ny * nz;
+    const int nt = n_threads_of(n_threads);
+    double *Jt = (double *)calloc((size_t)nt * V, sizeof(double));
+    if (!Jt) { geom_free(&g); return ORC_ENOMEM; }
+    const int n_down = g.n_dir / 2;   /* mu nodes ascending: the first half of d points down */
+    int fail = 0;
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        int ms = 0;
+        for (int d = 0; d < g.n_dir; ++d) if (max_segments(&g, d) > ms) ms = max_segments(&g, d);
+        double *fbuf = (double *)malloc(sizeof(double) * (ms + 2));
+        int *seg_v = (int *)malloc(sizeof(int) * ms);
+        double *seg_len = (double *)malloc(sizeof(double) * ms);
+        double *Dsum = (double *)malloc(sizeof(double) * V);
+        if (!fbuf || !seg_v || !seg_len || !Dsum) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+            double *Jmine = Jt + (size_t)tid * V;
+            for (int d = tid; d < g.n_dir; d += nt) {
+                memset(Dsum, 0, sizeof(double) * V);
+                double *Iem_d = (Iem && g.mu[d] > 0.0) ? Iem + (size_t)(d - n_down) * nx * ny : NULL;
+                fs_direction(&g, d, chi, S, I_top, I_bot, Dsum, Iem_d, fbuf, seg_v, seg_len);
+                const double amu = fabs(g.mu[d]);
+                for (long v = 0; v < V; ++v) {
+                    double ib = amu / chi[v] * Dsum[v];
+                    if (Ibar) Ibar[(size_t)d * V + v] = ib;
+                    Jmine[v] += g.wt[d] * ib;
+                }
+            }
+        }
+        free(fbuf); free(seg_v); free(seg_len); free(Dsum);
+    }
+    if (!fail) {
+        for (long v = 0; v < V; ++v) {
+            double s = 0.0;
+            for (int t = 0; t < nt; ++t) s += Jt[(size_t)t * V + v];
+            J[v] = s;
+        }
+    }
+    free(Jt);
+    geom_free(&g);
+    return fail ? ORC_ENOMEM : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------------------------------
+ * Lambda*: the 27-point band of Lambda, built along the lines.
+ * --------------------------------------------------------------------------------------------- */
+
+/* Neighbour offset index of u relative to v, or -1 if u is not in the 3x3x3 block around v. */
+static int nb_index(const Geom *g, int v, int u)
+{
+    int iv = v % g->nx, jv = (v / g->nx) % g->ny, kv = v / (g->nx * g->ny);
+    int iu = u % g->nx, ju = (u / g->nx) % g->ny, ku = u / (g->nx * g->ny);
+    int dk = ku - kv;
+    if (dk < -1 || dk > 1) return -1;
+    int di = imod(iu - iv, g->nx), dj = imod(ju - jv, g->ny);
+    if (di == g->nx - 1) di = -1; else if (di > 1) return -1;
+    if (dj == g->ny - 1) dj = -1; else if (dj > 1) return -1;
+    return 9 * (dk + 1) + 3 * (dj + 1) + (di + 1);
+}
+
+/* Lambda*_{vu} = sum_d W_d dIbar_v(d)/dS_u for u in the 3x3x3 block of v.
+ * For segment s in voxel v:  dD_s/dS_u = delta_uv (dtau_s + em1_s) - em1_s dI_in,s/dS_u, and
+ * dI_in,s/dS_u = sum over earlier segments s' in u of c_{s'->s} = (1 - e_{s'}) prod_{s'<s''<s} e_{s''},
+ * e = exp(-dtau).  Lines are monotone in z, so every earlier segment that can lie in the 3x3x3 block
+ * is in the current or the previous layer: a window of those segments with their running c values
+ * makes the band exact (all segments in u are included, also when a line wraps around a small grid). */
+int orc_lstar(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi, double *L,
+              int n_threads)
+{
+    Geom g;
+    int rc = geom_init(&g, nx, ny, nz, n_theta, n_phi);
+    if (rc) return rc;
+    const long V = (long)nx * ny * nz;
+    const int nt = n_threads_of(n_threads);
+    double *Lt = (double *)calloc((size_t)nt * 27 * V, sizeof(double));
+    if (!Lt) { geom_free(&g); return ORC_ENOMEM; }
+    int fail = 0;
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        int ms = 0;
+        for (int d = 0; d < g.n_dir; ++d) if (max_segments(&g, d) > ms) ms = max_segments(&g, d);
+        double *fbuf = (double *)malloc(sizeof(double) * (ms + 2));
+        int *seg_v = (int *)malloc(sizeof(int) * ms);
+        double *seg_len = (double *)malloc(sizeof(double) * ms);
+        /* window: voxel, layer and c of every segment in the current and the previous layer */
+        int *win_v = (int *)malloc(sizeof(int) * 2 * ms);
+        int *win_k = (int *)malloc(sizeof(int) * 2 * ms);
+        double *win_c = (double *)malloc(sizeof(double) * 2 * ms);
+        if (!fbuf || !seg_v || !seg_len || !win_v || !win_k || !win_c) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+            double *Lm = Lt + (size_t)tid * 27 * V;
+            for (int d = tid; d < g.n_dir; d += nt) {
+                const double mu = g.mu[d], amu = fabs(mu), W = g.wt[d];
+                for (int j = 0; j < ny; ++j) {
+                    for (int i = 0; i < nx; ++i) {
+                        int nw = 0;
+                        for (int step = 0; step < nz; ++step) {
+                            int k = (mu < 0.0) ? nz - 1 - step : step;
+                            /* drop window entries two or more layers upstream */
+                            int keep = 0;
+                            for (int q = 0; q < nw; ++q) {
+                                if (abs(win_k[q] - k) <= 1) {
+                                    win_v[keep] = win_v[q]; win_k[keep] = win_k[q];
+                                    win_c[keep] = win_c[q]; ++keep;
+                                }
+                            }
+                            nw = keep;
+                            int ns = trace_layer(&g, d, i, j, k, fbuf, seg_v, seg_len);
+                            for (int s = 0; s < ns; ++s) {
+                                int v = seg_v[s];
+                                double dtau = chi[v] * seg_len[s];
+                                double em1 = expm1(-dtau);
+                                double fac = W * amu / chi[v];
+                                Lm[13 * V + v] += fac * (dtau + em1);
+                                for (int q = 0; q < nw; ++q) {
+                                    int o = nb_index(&g, v, win_v[q]);
+                                    if (o >= 0) Lm[(size_t)o * V + v] += fac * (-em1) * win_c[q];
+                                }
+                                for (int q = 0; q < nw; ++q) win_c[q] *= (1.0 + em1);
+                                win_v[nw] = v; win_k[nw] = k; win_c[nw] = -em1; ++nw;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        free(fbuf); free(seg_v); free(seg_len); free(win_v); free(win_k); free(win_c);
+    }
+    if (!fail) {
+        for (long q = 0; q < 27 * V; ++q) {
+            double s = 0.0;
+            for (int t = 0; t < nt; ++t) s += Lt[(size_t)t * 27 * V + q];
+            L[q] = s;
+        }
+    }
+    free(Lt);
+    geom_free(&g);
+    return fail ? ORC_ENOMEM : ORC_OK;
+}
+
+/* Dense Lambda by brute force (tiny grids only): column u is the mean intensity produced by a unit
+ * source in voxel u alone, with zero boundary intensities.  Lam[v * V + u]. */
+int orc_lambda_bruteforce(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi,
+                          double *Lam, int n_threads)
+{
+    const long V = (long)nx * ny * nz;
+    double *S = (double *)calloc(V, sizeof(double));
+    double *J = (double *)malloc(sizeof(double) * V);
+    if (!S || !J) { free(S); free(J); return ORC_ENOMEM; }
+    int rc = ORC_OK;
+    for (long u = 0; u < V && rc == ORC_OK; ++u) {
+        S[u] = 1.0;
+        rc = orc_formal_solution(nx, ny, nz, n_theta, n_phi, chi, S, 0.0, NULL, J, NULL, NULL,
+                                 n_threads);
+        for (long v = 0; v < V; ++v) Lam[v * V + u] = J[v];
+        S[u] = 0.0;
+    }
+    free(S);
+    free(J);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------------------
+ * Operator splitting.
+ * --------------------------------------------------------------------------------------------- */
+
+/* One OS step ("Implementation of the operator splitting step"):
+ *   S = eps B + (1-eps) J;  J_fs = FS(S);  r = J_fs - J;
+ *   M Jacobi sweeps from dJ^0 = 0 of
+ *     dJ^{m+1}_v = (r_v + sum_{u != v} Lstar_vu (1-eps_u) dJ^m_u) / (1 - Lstar_vv (1-eps_v));
+ *   J <- J + dJ^M;  c = max_v |dJ_v| / |J_v|.
+ * Boundary light: I_top at the top; at the bottom I_bot = B of the bottom layer if bottom_from_B,
+ * else zero.  Jfs_out (optional) receives J_fs. */
+int orc_os_step(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi, const double *eps,
+                const double *B, double I_top, int bottom_from_B, const double *Lstar, double *J,
+                int M, double *c_out, double *Jfs_out, int n_threads)
+{
+    if (M < 1) return ORC_EARG;
+    const long V = (long)nx * ny * nz;
+    double *S = (double *)malloc(sizeof(double) * V);
+    double *Jfs = (double *)malloc(sizeof(double) * V);
+    double *r = (double *)malloc(sizeof(double) * V);
+    double *dJ = (double *)calloc(V, sizeof(double));
+    double *dJn = (double *)malloc(sizeof(double) * V);
+    if (!S || !Jfs || !r || !dJ || !dJn) {
+        free(S); free(Jfs); free(r); free(dJ); free(dJn);
+        return ORC_ENOMEM;
+    }
+    for (long v = 0; v < V; ++v) S[v] = eps[v] * B[v] + (1.0 - eps[v]) * J[v];
+    int rc = orc_formal_solution(nx, ny, nz, n_theta, n_phi, chi, S, I_top,
+                                 bottom_from_B ? B : NULL, Jfs, NULL, NULL, n_threads);
+    if (rc == ORC_OK) {
+        for (long v = 0; v < V; ++v) r[v] = Jfs[v] - J[v];
+        for (int m = 0; m < M; ++m) {
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        long v = ((long)k * ny + j) * nx + i;
+                        double acc = r[v];
+                        for (int dk = -1; dk <= 1; ++dk) {
+                            if (k + dk < 0 || k + dk >= nz) continue;
+                            for (int dj = -1; dj <= 1; ++dj)
+                                for (int di = -1; di <= 1; ++di) {
+                                    int o = 9 * (dk + 1) + 3 * (dj + 1) + (di + 1);
+                                    if (o == 13) continue;
+                                    long u = ((long)(k + dk) * ny + imod(j + dj, ny)) * nx
+                                             + imod(i + di, nx);
+                                    acc += Lstar[(size_t)o * V + v] * (1.0 - eps[u]) * dJ[u];
+                                }
+                        }
+                        dJn[v] = acc / (1.0 - Lstar[13 * V + v] * (1.0 - eps[v]));
+                    }
+            double *t = dJ; dJ = dJn; dJn = t;
+        }
+        double c = 0.0;
+        for (long v = 0; v < V; ++v) {
+            J[v] += dJ[v];
+            double q = fabs(dJ[v]) / fabs(J[v]);
+            if (q > c || q != q) c = q;
+        }
+        if (c_out) *c_out = c;
+        if (Jfs_out) memcpy(Jfs_out, Jfs, sizeof(double) * V);
+    }
+    free(S); free(Jfs); free(r); free(dJ); free(dJn);
+    return rc;
+}
+
+/* Outer OS iteration until c < tol (or max_iter steps).  J holds the initial guess on entry (the
+ * usual start is J = B) and the last iterate on exit.  Lstar may be NULL: it is then built here.
+ * Returns the number of steps in *iters and the last c in *c_out; the return code is 1 when
+ * max_iter was reached without c < tol. */
+int orc_solve(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi, const double *eps,
+              const double *B, double I_top, int bottom_from_B, const double *Lstar, double *J,
+              double tol, int max_iter, int M, int *iters, double *c_out, int n_threads)
+{
+    const long V = (long)nx * ny * nz;
+    double *Lown = NULL;
+    if (!Lstar) {
+        Lown = (double *)malloc(sizeof(double) * 27 * V);
+        if (!Lown) return ORC_ENOMEM;
+        int rc = orc_lstar(nx, ny, nz, n_theta, n_phi, chi, Lown, n_threads);
+        if (rc) { free(Lown); return rc; }
+        Lstar = Lown;
+    }
+    double c = INFINITY;
+    int n = 0, rc = ORC_OK;
+    while (n < max_iter) {
+        rc = orc_os_step(nx, ny, nz, n_theta, n_phi, chi, eps, B, I_top, bottom_from_B, Lstar, J, M,
+                         &c, NULL, n_threads);
+        ++n;
+        if (rc != ORC_OK || c < tol) break;
+    }
+    free(Lown);
+    if (iters) *iters = n;
+    if (c_out) *c_out = c;
+    if (rc != ORC_OK) return rc;
+    return (c < tol) ? ORC_OK : 1;
+}
+
+/* ------------------------------------------------------------------------------------------------
+ * Plane-parallel (1D) formal solution, written without any 3D geometry.
+ * --------------------------------------------------------------------------------------------- */
+
+/* Layers k = 0 (bottom) .. nz-1 (top) with vertical optical thickness dtau[k] > 0 and source S[k].
+ * For each Gauss-Legendre node mu_a the slant thickness is dtau/|mu|; the layer-averaged intensity
+ * of an exactly integrated constant-source layer is  Ibar = S - (I_in - S) em1 / (dtau/|mu|),
+ * and J_k = sum_a (w_a / 2) Ibar_k(mu_a). */
+int orc_pp1d(int nz, int n_theta, const double *dtau, const double *S, double I_top, double I_bot,
+             double *J)
+{
+    if (nz < 1 || n_theta < 2 || (n_theta & 1)) return ORC_EARG;
+    double *x = (double *)malloc(sizeof(double) * n_theta);
+    double *w = (double *)malloc(sizeof(double) * n_theta);
+    if (!x || !w) { free(x); free(w); return ORC_ENOMEM; }
+    orc_gauss_legendre(n_theta, x, w);
+    for (int k = 0; k < nz; ++k) J[k] = 0.0;
+    for (int a = 0; a < n_theta; ++a) {
+        double amu = fabs(x[a]);
+        double I = (x[a] < 0.0) ? I_top : I_bot;
+        for (int step = 0; step < nz; ++step) {
+            int k = (x[a] < 0.0) ? nz - 1 - step : step;
+            double t = dtau[k] / amu;
+            double em1 = expm1(-t);
+            J[k] += 0.5 * w[a] * (S[k] - (I - S[k]) * em1 / t);
+            I = I + (I - S[k]) * em1;
+        }
+    }
+    free(x);
+    free(w);
+    return ORC_OK;
+}

@@ -1,0 +1,136 @@
+"""Seeded synthetic media for the 3D scattering solve.
+
+This module is the only code that the HIP path's tests and the CPU oracle's tests share.  It builds
+*inputs* only -- opacity chi, thermalisation parameter epsilon and Planck function B on an
+``(nz, ny, nx)`` grid (x fastest, k = 0 is the bottom layer) -- and holds none of the arithmetic of
+the method itself (no formal solution, no Lambda operator, no operator splitting).
+
+The workloads stand in for the paper's parameterised slab test ("Test case setup": a plane-parallel
+slab with periodic x,y, a power-law continuum optical depth spanning many decades, an isothermal
+source, coherent isotropic scattering with a constant epsilon).  The paper's own atmosphere needs its
+earlier papers and physical units; here the medium is a synthetic stratified atmosphere with the same
+structure: unit voxels, chi falling exponentially with height over about seven decades, a seeded
+perturbation on chi, uniform epsilon and a given B profile.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = ["Workload", "WORKLOADS", "stratified_profile", "make_medium", "random_medium"]
+
+
+@dataclass(frozen=True)
+class Workload:
+    """One named synthetic workload: grid, angle set, medium recipe and stopping rule."""
+
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    n_theta: int
+    n_phi: int
+    tau_total: float          # vertical optical depth of the unperturbed column
+    eps: float                # uniform thermalisation parameter
+    b_profile: str            # "const" (B = b_value) or "linear_10_1" (10 at the bottom, 1 at the top)
+    noise: str                # "iid" (i.i.d. log-normal) or "grf" (Gaussian random field, periodic in x,y)
+    sigma: float              # standard deviation of log(chi) perturbation
+    seed: int
+    tol: float = 1e-8         # outer stopping threshold on max_v |dJ_v| / |J_v|
+    corr_len: float = 4.0     # correlation length in voxels ("grf" only)
+    b_value: float = 1.0
+    I_top: float = 0.0        # incoming intensity at the outer (top) boundary
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def n_dir(self):
+        return self.n_theta * self.n_phi
+
+    @property
+    def n_vox(self):
+        return self.nx * self.ny * self.nz
+
+
+# The three plain-method / precision-form workloads.  Sizes and angle counts follow the benchmark
+# configurations; the stratification scale is H = nz / (7 ln 10) so that chi spans about seven
+# decades between the bottom and the top voxel.
+WORKLOADS = {
+    "strat17": Workload("strat17", 17, 17, 17, 8, 8, tau_total=1e3, eps=1e-2, b_profile="const",
+                        noise="iid", sigma=0.05, seed=1, tol=1e-8),
+    "grf65": Workload("grf65", 65, 65, 65, 16, 16, tau_total=1e4, eps=1e-4, b_profile="linear_10_1",
+                      noise="grf", sigma=0.2, seed=2, tol=1e-8),
+    "strat129": Workload("strat129", 129, 129, 129, 16, 16, tau_total=1e3, eps=1e-6, b_profile="const",
+                         noise="iid", sigma=0.05, seed=3, tol=1e-8),
+}
+
+
+def stratified_profile(nz: int, tau_total: float, decades: float = 7.0) -> np.ndarray:
+    """chi_k = chi0 * exp(-(k + 1/2) / H) with H = nz / (decades * ln 10) and sum_k chi_k = tau_total."""
+    H = nz / (decades * math.log(10.0))
+    zc = np.arange(nz, dtype=np.float64) + 0.5
+    prof = np.exp(-zc / H)
+    return prof * (tau_total / prof.sum())
+
+
+def _grf(rng: np.random.Generator, nz: int, ny: int, nx: int, corr_len: float) -> np.ndarray:
+    """Unit-variance Gaussian random field with covariance exp(-r^2 / (2 l^2)).
+
+    Periodic in x,y (FFT on the true grid); z is generated on a box padded by 3 l on each side and
+    cropped, so the top and bottom are not correlated with each other."""
+    pad = int(math.ceil(3.0 * corr_len))
+    nzp = nz + 2 * pad
+    white = rng.standard_normal((nzp, ny, nx))
+    kz = np.fft.fftfreq(nzp) * 2.0 * math.pi
+    ky = np.fft.fftfreq(ny) * 2.0 * math.pi
+    kx = np.fft.fftfreq(nx) * 2.0 * math.pi
+    k2 = kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2
+    amp = np.exp(-0.25 * corr_len ** 2 * k2)        # square root of the Gaussian spectral density
+    field_ = np.real(np.fft.ifftn(np.fft.fftn(white) * amp))[pad:pad + nz]
+    field_ -= field_.mean()
+    return field_ / field_.std()
+
+
+def make_medium(w: Workload | str):
+    """Return dict(chi, eps, B) as C-contiguous float64 arrays of shape (nz, ny, nx)."""
+    if isinstance(w, str):
+        w = WORKLOADS[w]
+    rng = np.random.Generator(np.random.PCG64(w.seed))
+    prof = stratified_profile(w.nz, w.tau_total)
+    if w.noise == "iid":
+        g = rng.standard_normal(w.shape)
+    elif w.noise == "grf":
+        g = _grf(rng, w.nz, w.ny, w.nx, w.corr_len)
+    elif w.noise == "none":
+        g = np.zeros(w.shape)
+    else:
+        raise ValueError(f"unknown noise model {w.noise!r}")
+    chi = prof[:, None, None] * np.exp(w.sigma * g)
+    eps = np.full(w.shape, w.eps)
+    if w.b_profile == "const":
+        B = np.full(w.shape, w.b_value)
+    elif w.b_profile == "linear_10_1":
+        k = np.arange(w.nz, dtype=np.float64)
+        B = np.broadcast_to((10.0 - 9.0 * k / (w.nz - 1))[:, None, None], w.shape).copy()
+    else:
+        raise ValueError(f"unknown B profile {w.b_profile!r}")
+    return {"chi": np.ascontiguousarray(chi), "eps": np.ascontiguousarray(eps),
+            "B": np.ascontiguousarray(B)}
+
+
+def random_medium(nx: int, ny: int, nz: int, seed: int, chi_range=(1e-2, 1e2),
+                  eps_range=(1e-3, 1.0), b_range=(0.5, 2.0)):
+    """Small fully heterogeneous medium for parity tests: log-uniform chi and eps, uniform B."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = (nz, ny, nx)
+    lo, hi = np.log(chi_range[0]), np.log(chi_range[1])
+    chi = np.exp(rng.uniform(lo, hi, shape))
+    elo, ehi = np.log(eps_range[0]), np.log(eps_range[1])
+    eps = np.exp(rng.uniform(elo, ehi, shape))
+    B = rng.uniform(b_range[0], b_range[1], shape)
+    return {"chi": chi, "eps": eps, "B": B}

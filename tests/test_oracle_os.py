@@ -1,0 +1,122 @@
+"""Pins of the oracle's operator-splitting (OS) iteration.
+
+The OS iteration must reach the plain definition of the result: the solution of
+(I - Lambda diag(1-eps)) J = Lambda (eps B) + J_bc, solved densely on tiny grids.  Lambda* only
+changes the path to it (Lambda* = 0 and a diagonal Lambda* reach the same J).  With eps = 1 the
+source does not depend on J, so the first step is already exact.  For a semi-infinite medium with
+constant eps and B the source at the surface is sqrt(eps) B (the sqrt(eps) law); the discretised
+problem approaches it as the surface layers are refined.
+"""
+import numpy as np
+import pytest
+
+from paper_1107_5719_amd.inputs import random_medium, stratified_profile
+
+
+@pytest.mark.parametrize("shape,seed", [((5, 5, 5), 1), ((6, 5, 7), 2), ((7, 7, 7), 3)])
+def test_fixed_point_equals_dense_solve(orc, shape, seed):
+    nz, ny, nx = shape
+    m = random_medium(nx, ny, nz, seed=seed, chi_range=(1e-2, 1e1), eps_range=(1e-2, 1.0))
+    Jd = orc.dense_os_solution(m["chi"], m["eps"], m["B"], 8, 8, I_top=0.1)
+    J, it, c, ok = orc.solve(m["chi"], m["eps"], m["B"], 8, 8, tol=1e-14, max_iter=400, M=50,
+                             I_top=0.1)
+    assert ok
+    assert np.max(np.abs(J / Jd - 1)) < 1e-10
+
+
+def test_fixed_point_independent_of_lstar(orc):
+    nz = ny = nx = 5
+    chi = np.broadcast_to(stratified_profile(nz, 10.0)[:, None, None], (nz, ny, nx)).copy()
+    chi *= np.exp(0.1 * np.random.default_rng(4).standard_normal(chi.shape))
+    eps = np.full(chi.shape, 0.05)
+    B = np.ones(chi.shape)
+    L = orc.lstar(chi, 8, 8)
+    Ld = np.zeros_like(L)
+    Ld[13] = L[13]
+    Jf, it_f, _, ok_f = orc.solve(chi, eps, B, 8, 8, tol=1e-13, max_iter=3000, M=20, Lstar=L)
+    Jd, it_d, _, ok_d = orc.solve(chi, eps, B, 8, 8, tol=1e-13, max_iter=3000, M=20, Lstar=Ld)
+    J0, it_0, _, ok_0 = orc.solve(chi, eps, B, 8, 8, tol=1e-13, max_iter=3000, M=1,
+                                  Lstar=np.zeros_like(L))
+    assert ok_f and ok_d and ok_0
+    assert it_f <= it_d <= it_0
+    assert np.max(np.abs(Jd / Jf - 1)) < 1e-9
+    assert np.max(np.abs(J0 / Jf - 1)) < 1e-9
+
+
+def test_eps_one_is_exact_in_one_step(orc):
+    m = random_medium(5, 4, 6, seed=8)
+    eps = np.ones_like(m["chi"])
+    L = orc.lstar(m["chi"], 8, 8)
+    J1, c1 = orc.os_step(m["chi"], eps, m["B"], L, m["B"] * 0.5, 8, 8, M=7, I_top=0.0)
+    Jfs = orc.formal_solution(m["chi"], m["B"], 8, 8, I_bot=m["B"][0])
+    assert np.max(np.abs(J1 / Jfs - 1)) < 1e-14
+    J2, c2 = orc.os_step(m["chi"], eps, m["B"], L, J1, 8, 8, M=7, I_top=0.0)
+    assert c2 < 1e-14
+
+
+def test_one_sweep_step_by_hand(orc):
+    """M = 1: dJ = (J_fs - J) / (1 - Lambda*_vv (1 - eps_v)); M = 2 adds the neighbour coupling."""
+    m = random_medium(5, 5, 4, seed=9, eps_range=(0.1, 0.9))
+    chi, eps, B = m["chi"], m["eps"], m["B"]
+    L = orc.lstar(chi, 8, 8)
+    J0 = B * 0.9
+    S = eps * B + (1 - eps) * J0
+    Jfs = orc.formal_solution(chi, S, 8, 8, I_bot=B[0])
+    r = Jfs - J0
+    den = 1 - L[13] * (1 - eps)
+    J1, c1 = orc.os_step(chi, eps, B, L, J0, 8, 8, M=1)
+    assert np.max(np.abs(J1 - (J0 + r / den))) < 1e-14
+    dJ1 = r / den
+    acc = r.copy()
+    nz, ny, nx = chi.shape
+    for o in range(27):
+        if o == 13:
+            continue
+        dk, dj, di = o // 9 - 1, (o // 3) % 3 - 1, o % 3 - 1
+        sh = np.roll((1 - eps) * dJ1, (-dj, -di), (1, 2))
+        if dk == 1:
+            sh = np.concatenate([sh[1:], np.zeros_like(sh[:1])])
+        elif dk == -1:
+            sh = np.concatenate([np.zeros_like(sh[:1]), sh[:-1]])
+        acc += L[o] * sh
+    J2, c2 = orc.os_step(chi, eps, B, L, J0, 8, 8, M=2)
+    assert np.max(np.abs(J2 - (J0 + acc / den))) < 1e-13
+    assert abs(c2 - np.max(np.abs(acc / den) / np.abs(J2))) < 1e-15
+
+
+@pytest.mark.slow
+def test_sqrt_eps_law_under_refinement(orc):
+    """Horizontally homogeneous 3x3xN column, chi over 9 decades (tau_total = 1e4), B = 1,
+    eps = 1e-2: the surface source S_top = eps B + (1 - eps) J_top approaches sqrt(eps) B as the
+    layers are refined (3D OS iteration to convergence)."""
+    eps0 = 1e-2
+    errs = []
+    for nz in (65, 129, 257):
+        chi_k = stratified_profile(nz, 1e4, decades=9.0)
+        chi = np.broadcast_to(chi_k[:, None, None], (nz, 3, 3)).copy()
+        eps = np.full(chi.shape, eps0)
+        B = np.ones(chi.shape)
+        J, it, c, ok = orc.solve(chi, eps, B, 8, 8, tol=1e-12, max_iter=3000, M=30)
+        assert ok
+        S_top = eps0 + (1 - eps0) * J[-1, 0, 0]
+        errs.append(abs(S_top / np.sqrt(eps0) - 1))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[-1] < 0.02
+
+
+@pytest.mark.parametrize("eps0,bound", [(1e-2, 1e-3), (1e-4, 0.08)])
+def test_sqrt_eps_law_plane_parallel_limit(orc, eps0, bound):
+    """Same law on finer columns with the plane-parallel solver and a dense solve of
+    (I - Lambda (1 - eps)) J = Lambda eps B; the error falls more than twofold per refinement."""
+    errs = []
+    for nz in (257, 513, 1025):
+        chi = stratified_profile(nz, 1e6, decades=10.0)
+        Lam = np.zeros((nz, nz))
+        for u in range(nz):
+            e = np.zeros(nz)
+            e[u] = 1.0
+            Lam[:, u] = orc.pp1d(chi, e, 8)
+        J = np.linalg.solve(np.eye(nz) - Lam * (1 - eps0), Lam @ np.full(nz, eps0))
+        errs.append(abs((eps0 + (1 - eps0) * J[-1]) / np.sqrt(eps0) - 1))
+    assert errs[0] > 2 * errs[1] > 4 * errs[2]
+    assert errs[-1] < bound
