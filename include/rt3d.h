@@ -1,0 +1,168 @@
+/*
+ * rt3d.h -- C ABI of the MI355X (gfx950) hot path of the 3D radiative-transfer scattering solve of
+ * Hauschildt & Baron, "A 3D radiative transfer framework XIII: OpenCL implementation".
+ *
+ * The library computes, with hand-written HIP kernels:
+ *   - the formal solution (FS) along characteristics through a Cartesian voxel grid periodic in x
+ *     and y, per solid angle (section "Implementation of the formal solution and Lambda*
+ *     computation");
+ *   - the mean intensity J and the nearest-neighbour (3x3x3 = 27-point) Lambda* operator;
+ *   - the non-local operator-splitting (OS) step, solving (1 - Lambda* (1-eps)) dJ = J_fs - J_old
+ *     by Jacobi ("Jordan") iterations (section "Implementation of the operator splitting step"),
+ *     with the coherent isotropic scattering source S = eps B + (1-eps) J (section "Test case
+ *     setup").
+ * All state lives on the device; only opacities/eps/B go in and J comes out (section "Method").
+ *
+ * Discretisation (the paper defers it to earlier papers of its series; these are the readings):
+ *   voxels    unit cubes (i,j,k), i fastest; k = 0 is the bottom (inner boundary), k = nz-1 the top;
+ *   angles    n_theta-point Gauss-Legendre in mu (n_theta even) x n_phi uniform azimuths
+ *             phi_b = 2 pi (b + 1/2) / n_phi (n_phi a multiple of 4), weight w_a / (2 n_phi);
+ *             direction index d = a * n_phi + b with the mu nodes ascending (first half downward);
+ *   lines     per direction one straight line per column (i,j) through (i+1/2, j+1/2, nz); the
+ *             same lines serve Omega and -Omega; chi and S are constant per voxel and every
+ *             segment of a line inside a voxel is integrated exactly;
+ *   voxel I   the path-length-weighted average over all segments of the direction inside the voxel;
+ *   Lambda*   the exact 27-point band of Lambda (S -> J with no boundary light);
+ *   OS step   dJ^0 = 0, M Jacobi sweeps, J <- J + dJ^M, c = max_v |dJ_v| / |J_v|; J^0 = B.
+ *
+ * Layouts: per-voxel fields are float64 [nz][ny][nx] (x fastest).  Lambda* is float64 [27][nz][ny][nx]
+ * with neighbour index o = 9 (dk+1) + 3 (dj+1) + (di+1), u = v + (di,dj,dk), periodic in i and j;
+ * entries whose u would lie outside 0 <= k+dk < nz are zero.
+ *
+ * Conventions for every call:
+ *   - The return value is an rt3d_status (0 = RT3D_OK, negative = error); nothing throws across the
+ *     ABI.  On error the context keeps its previous valid state unless stated otherwise, and
+ *     rt3d_last_error() describes the failure.
+ *   - ptr_kind selects where a caller buffer lives: RT3D_HOST (0) or RT3D_DEVICE (1).  Device
+ *     buffers must be valid on the context's stream; the library does not keep any caller pointer
+ *     after the call returns.  Calls with host buffers synchronise the stream before returning.
+ *   - The caller owns every buffer it passes; the context owns everything it allocates.
+ *   - One context per thread; a context may be used from one host thread at a time.
+ */
+#ifndef RT3D_H
+#define RT3D_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RT3D_OK = 0,
+    RT3D_ERR_ARG = -1,           /* invalid argument (sizes, pointers, non-finite or out-of-range data) */
+    RT3D_ERR_OOM = -2,           /* device or host allocation failed */
+    RT3D_ERR_HIP = -3,           /* a HIP runtime call failed (message in rt3d_last_error) */
+    RT3D_ERR_NOT_CONVERGED = -4, /* max_iter reached; J and the last c are valid */
+    RT3D_ERR_NONFINITE = -5,     /* a NaN or Inf appeared in dJ or J */
+    RT3D_ERR_STATE = -6          /* call out of order (e.g. no medium set, Lambda* not built) */
+} rt3d_status;
+
+enum { RT3D_HOST = 0, RT3D_DEVICE = 1 };
+
+typedef enum {
+    RT3D_FP64 = 0,        /* every step in float64 */
+    RT3D_FP32_SWEEP = 1   /* FS sweeps in float32; J accumulation, Lambda*, OS solve and the
+                             convergence test in float64 */
+} rt3d_precision;
+
+typedef struct {
+    int nx, ny, nz;        /* voxels; nx, ny, nz >= 3 */
+    int n_theta, n_phi;    /* n_theta even >= 2; n_phi >= 4 and a multiple of 4 */
+    double I_top;          /* intensity entering through the top plane (outer boundary), >= 0 */
+    int bottom_bc;         /* 0: an upward line enters with I = B of the bottom voxel it enters;
+                              1: I = 0 at the bottom plane */
+} rt3d_grid_desc;
+
+typedef struct rt3d_ctx rt3d_ctx;
+
+/* Create a context: validates *g on the host, builds the angle set and the per-direction segment
+ * tables, and allocates all device buffers on the current HIP device.  hip_stream is a hipStream_t
+ * (NULL = the default stream); every kernel of this context is launched on it.
+ * Errors: RT3D_ERR_ARG (bad descriptor or precision, out == NULL), RT3D_ERR_OOM, RT3D_ERR_HIP. */
+int rt3d_create(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, void *hip_stream);
+
+/* Free every device buffer and the context.  NULL is ignored. */
+void rt3d_destroy(rt3d_ctx *ctx);
+
+/* Set the medium: chi (opacity per unit voxel edge, finite and > 0), eps (thermalisation
+ * parameter, 0 < eps <= 1) and B (Planck function, finite), each [nz][ny][nx].  Host data is
+ * validated on the host; device data is validated by a device check that reads back one flag.
+ * Resets J to B and invalidates Lambda*.  Errors: RT3D_ERR_ARG, RT3D_ERR_HIP. */
+int rt3d_set_medium(rt3d_ctx *ctx, const double *chi, const double *eps, const double *B,
+                    int ptr_kind);
+
+/* Set the current iterate J ([nz][ny][nx], finite): an initial guess or a resumed state.
+ * Errors: RT3D_ERR_STATE (no medium), RT3D_ERR_ARG, RT3D_ERR_HIP. */
+int rt3d_set_J(rt3d_ctx *ctx, const double *J, int ptr_kind);
+
+/* Copy the current iterate J out.  Errors: RT3D_ERR_STATE, RT3D_ERR_ARG, RT3D_ERR_HIP. */
+int rt3d_get_J(rt3d_ctx *ctx, double *J_out, int ptr_kind);
+
+/* One formal solution for all directions: J_fs = sum_d W_d Ibar(d) for the source S_or_null
+ * ([nz][ny][nx]) or, when S_or_null is NULL, for S = eps B + (1-eps) J.  Boundary light as in the
+ * descriptor.  Also records the top-plane intensities of the upward lines.
+ * Errors: RT3D_ERR_STATE, RT3D_ERR_ARG, RT3D_ERR_HIP. */
+int rt3d_formal_solution(rt3d_ctx *ctx, const double *S_or_null, double *J_fs_out, int ptr_kind);
+
+/* Build Lambda* (the 27-point band of Lambda) for the current chi; idempotent until the next
+ * rt3d_set_medium.  Errors: RT3D_ERR_STATE, RT3D_ERR_HIP. */
+int rt3d_build_lstar(rt3d_ctx *ctx);
+
+/* Copy Lambda* out as [27][nz][ny][nx].  Errors: RT3D_ERR_STATE (not built), RT3D_ERR_ARG,
+ * RT3D_ERR_HIP. */
+int rt3d_get_lstar(rt3d_ctx *ctx, double *out, int ptr_kind);
+
+/* One OS step (builds Lambda* first if needed): S from J, FS, r = J_fs - J, inner_sweeps >= 1
+ * Jacobi sweeps from dJ = 0, J <- J + dJ, *max_rel_dJ_out = max_v |dJ_v| / |J_v| (may be NULL).
+ * Errors: RT3D_ERR_STATE, RT3D_ERR_ARG, RT3D_ERR_NONFINITE (J is then not trustworthy),
+ * RT3D_ERR_HIP. */
+int rt3d_os_step(rt3d_ctx *ctx, int inner_sweeps, double *max_rel_dJ_out);
+
+/* OS steps until max_rel_dJ < tol or max_iter steps.  *iters_out and *final_rel_dJ_out (may be
+ * NULL) receive the step count and the last c.  Returns RT3D_ERR_NOT_CONVERGED when max_iter was
+ * reached (J and c remain valid), RT3D_ERR_NONFINITE, RT3D_ERR_ARG, RT3D_ERR_STATE, RT3D_ERR_HIP. */
+int rt3d_solve_to_convergence(rt3d_ctx *ctx, double tol, int max_iter, int inner_sweeps,
+                              int *iters_out, double *final_rel_dJ_out);
+
+/* Top-plane intensities of the upward lines from the last formal solution, [n_theta/2 * n_phi][ny][nx]
+ * in direction order (the upward directions are d = n_dir/2 .. n_dir-1); entry (j,i) belongs to the
+ * line through (i+1/2, j+1/2, nz).  Errors: RT3D_ERR_STATE (no FS yet), RT3D_ERR_ARG, RT3D_ERR_HIP. */
+int rt3d_get_emergent_top(rt3d_ctx *ctx, double *out, int ptr_kind);
+
+/* Enable (1) or disable (0) per-kernel timing with HIP events on the context stream.  While enabled
+ * every launch of the sweep, reduce, Lambda* and Jacobi kernels is bracketed by events and the
+ * durations are accumulated (read with rt3d_get_stats).  Errors: RT3D_ERR_ARG. */
+int rt3d_set_timing(rt3d_ctx *ctx, int enable);
+
+/* Statistics as a NUL-terminated JSON object: grid, angles, precision, outer iterations, inner
+ * sweeps, device bytes, and per-kernel {launches, total_ms} when timing is enabled.
+ * Errors: RT3D_ERR_ARG (buffer too small or NULL). */
+int rt3d_get_stats(rt3d_ctx *ctx, char *json_buf, int buflen);
+
+/* Static text for a status code. */
+const char *rt3d_status_str(int status);
+
+/* Last error message of a context ("" if none); valid until the next call on the context. */
+const char *rt3d_last_error(const rt3d_ctx *ctx);
+
+/* ---- host-only helpers (no device needed) ------------------------------------------------- */
+
+/* The angle set: mu[d], ox[d], oy[d] (direction cosines) and weights w[d] for d = a*n_phi + b,
+ * each array n_theta*n_phi long (caller-owned host memory).  Errors: RT3D_ERR_ARG. */
+int rt3d_quadrature(int n_theta, int n_phi, double *mu, double *ox, double *oy, double *w);
+
+/* Segments of the line through (i0+1/2, j0+1/2, nz) for direction d inside layer k, in travel order:
+ * voxel column offsets (di[s], dj[s]) relative to (i0, j0) -- not reduced modulo the grid -- and path
+ * lengths len[s].  Returns the number of segments (>= 1) or RT3D_ERR_ARG (also when max_seg is too
+ * small).  The table is the same for every line of the direction (translation invariance). */
+int rt3d_segment_table(const rt3d_grid_desc *g, int d, int k, int *di, int *dj, double *len,
+                       int max_seg);
+
+/* Validate a descriptor and (optionally, any may be NULL) host medium arrays exactly as
+ * rt3d_create / rt3d_set_medium do.  Returns RT3D_OK or RT3D_ERR_ARG. */
+int rt3d_validate(const rt3d_grid_desc *g, const double *chi, const double *eps, const double *B);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RT3D_H */

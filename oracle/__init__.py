@@ -52,6 +52,8 @@ def lib():
         L.orc_trace_layer.argtypes = [i, i, i, i, i, i, i, i, i, _ip, _dp, i]
         L.orc_formal_solution.argtypes = [i, i, i, i, i, _dp, _dp, d, C.c_void_p, _dp, C.c_void_p,
                                           C.c_void_p, i]
+        L.orc_formal_solution_dirs.argtypes = [i, i, i, i, i, _dp, _dp, d, C.c_void_p, _dp,
+                                               C.c_void_p, C.c_void_p, i, _ip, i]
         L.orc_lstar.argtypes = [i, i, i, i, i, _dp, _dp, i]
         L.orc_lambda_bruteforce.argtypes = [i, i, i, i, i, _dp, _dp, i]
         L.orc_os_step.argtypes = [i, i, i, i, i, _dp, _dp, _dp, d, i, _dp, _dp, i,
@@ -123,6 +125,19 @@ def formal_solution(chi, S, n_theta, n_phi, I_top=0.0, I_bot=None, want_emergent
     if want_ibar:
         out.append(Ibar)
     return out[0] if len(out) == 1 else tuple(out)
+
+
+def formal_solution_dirs(chi, S, n_theta, n_phi, dirs, I_top=0.0, I_bot=None, n_threads=0):
+    """The share of J from the listed directions only (used to time a bounded sample)."""
+    chi = _f64(chi)
+    S = _f64(S)
+    nz, ny, nx = chi.shape
+    J = np.zeros_like(chi)
+    dl = np.ascontiguousarray(dirs, dtype=np.int32)
+    ib = None if I_bot is None else _f64(np.broadcast_to(I_bot, (ny, nx)))
+    _check(lib().orc_formal_solution_dirs(nx, ny, nz, n_theta, n_phi, chi, S, float(I_top), _ptr(ib),
+                                          J, None, None, n_threads, dl, dl.size), "formal_solution_dirs")
+    return J
 
 
 def lstar(chi, n_theta, n_phi, n_threads=0):

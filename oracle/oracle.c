@@ -265,9 +265,25 @@ static int n_threads_of(int req)
  * direction order.  Ibar (optional): [n_dir][V] per-direction voxel intensities.
  * Threads split the directions; each thread sums its own directions in order, and the threads'
  * partial sums are added in thread order. */
+int orc_formal_solution_dirs(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi,
+                             const double *S, double I_top, const double *I_bot, double *J,
+                             double *Iem, double *Ibar, int n_threads, const int *dir_list,
+                             int n_list);
+
 int orc_formal_solution(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi,
                         const double *S, double I_top, const double *I_bot, double *J,
                         double *Iem, double *Ibar, int n_threads)
+{
+    return orc_formal_solution_dirs(nx, ny, nz, n_theta, n_phi, chi, S, I_top, I_bot, J, Iem, Ibar,
+                                    n_threads, NULL, 0);
+}
+
+/* As orc_formal_solution, restricted to the directions in dir_list[0..n_list-1] (all directions
+ * when dir_list is NULL): J then holds only their share of the angle sum. */
+int orc_formal_solution_dirs(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi,
+                             const double *S, double I_top, const double *I_bot, double *J,
+                             double *Iem, double *Ibar, int n_threads, const int *dir_list,
+                             int n_list)
 {
     Geom g;
     int rc = geom_init(&g, nx, ny, nz, n_theta, n_phi);
@@ -295,7 +311,10 @@ int orc_formal_solution(int nx, int ny, int nz, int n_theta, int n_phi, const do
             fail = 1;
         } else {
             double *Jmine = Jt + (size_t)tid * V;
-            for (int d = tid; d < g.n_dir; d += nt) {
+            const int n_sel = dir_list ? n_list : g.n_dir;
+            for (int q = tid; q < n_sel; q += nt) {
+                const int d = dir_list ? dir_list[q] : q;
+                if (d < 0 || d >= g.n_dir) continue;
                 memset(Dsum, 0, sizeof(double) * V);
                 double *Iem_d = (Iem && g.mu[d] > 0.0) ? Iem + (size_t)(d - n_down) * nx * ny : NULL;
                 fs_direction(&g, d, chi, S, I_top, I_bot, Dsum, Iem_d, fbuf, seg_v, seg_len);
@@ -336,6 +355,21 @@ static int nb_index(const Geom *g, int v, int u)
     if (di == g->nx - 1) di = -1; else if (di > 1) return -1;
     if (dj == g->ny - 1) dj = -1; else if (dj > 1) return -1;
     return 9 * (dk + 1) + 3 * (dj + 1) + (di + 1);
+}
+
+/* e^{-x} - 1 + x for x >= 0 (the self term of dD/dS), summed as its Taylor series
+ * x^2/2! - x^3/3! + ... below x = 1/2 so that thin segments do not lose digits to cancellation. */
+static double self_term(double x)
+{
+    if (x >= 0.5) return x + expm1(-x);
+    double fact = 1.0;                      /* 17! built up, then divided down */
+    for (int n = 2; n <= 17; ++n) fact *= n;
+    double r = 1.0 / fact;                  /* coefficient of x^15 in the bracket: 1/17! */
+    for (int n = 17; n > 2; --n) {
+        fact /= n;                          /* now (n-1)! */
+        r = 1.0 / fact - x * r;
+    }
+    return x * x * r;
 }
 
 /* Lambda*_{vu} = sum_d W_d dIbar_v(d)/dS_u for u in the 3x3x3 block of v.
@@ -397,12 +431,15 @@ int orc_lstar(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi,
                                 double dtau = chi[v] * seg_len[s];
                                 double em1 = expm1(-dtau);
                                 double fac = W * amu / chi[v];
-                                Lm[13 * V + v] += fac * (dtau + em1);
+                                Lm[13 * V + v] += fac * self_term(dtau);
                                 for (int q = 0; q < nw; ++q) {
                                     int o = nb_index(&g, v, win_v[q]);
                                     if (o >= 0) Lm[(size_t)o * V + v] += fac * (-em1) * win_c[q];
                                 }
-                                for (int q = 0; q < nw; ++q) win_c[q] *= (1.0 + em1);
+                                /* attenuation e^{-dtau} itself: 1 + em1 would lose all relative
+                                 * accuracy once dtau >> 1 */
+                                const double att = exp(-dtau);
+                                for (int q = 0; q < nw; ++q) win_c[q] *= att;
                                 win_v[nw] = v; win_k[nw] = k; win_c[nw] = -em1; ++nw;
                             }
                         }

@@ -1,0 +1,68 @@
+// Host-side geometry of the HIP library: angle set, per-direction segment tables and the work plan
+// of the line sweep.  Internal to the library (not part of the C ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace rt3d {
+
+struct AngleSet {
+    int n_theta = 0, n_phi = 0, n_dir = 0;
+    std::vector<double> mu, ox, oy, w;   // per direction d = a * n_phi + b
+};
+
+// Gauss-Legendre nodes (ascending) by Sturm-sequence bisection on the Jacobi matrix of the Legendre
+// polynomials, weights by the Christoffel sum 1 / sum_k (k + 1/2) P_k(x)^2.
+bool gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
+bool make_angle_set(int n_theta, int n_phi, AngleSet &out);
+
+// Segments of the reference line (through (1/2, 1/2, nz)) of one direction inside layer k, in travel
+// order: column offsets (di, dj) relative to the line's top column and path lengths.
+struct LayerSegments {
+    std::vector<int> di, dj;
+    std::vector<double> len;
+};
+void layer_segments(int nz, double mu, double ox, double oy, int k, LayerSegments &out);
+
+// Per-direction metadata used by the device kernels (plain old data, copied to the device).
+struct DirInfo {
+    double wmu;        // W_d * |mu_d|
+    int down;          // 1 if mu < 0 (sweep from the top layer down)
+    int band_rows;     // Bj: line rows per band (last band may be shorter)
+    int n_bands;       // nb
+    int win_rows;      // Hw = Bj + span: rows of the deposit window of one band
+    int last_rows;     // rows of the last band: ny - (nb - 1) * Bj
+    int64_t p_off;     // element offset of this direction's partial planes in P
+};
+
+// One workgroup of the sweep: direction d, band of line rows [j0, j0 + rows).
+struct WorkItem {
+    int d, band, j0, rows;
+};
+
+struct SweepPlan {
+    int nx = 0, ny = 0, nz = 0, n_dir = 0;
+    int lines_per_wg = 0;                 // threads * lines per thread
+    // segment tables, flat; index of (d, k) is d * nz + k
+    std::vector<int> seg_off, seg_n;      // per (d, k)
+    std::vector<int> seg_a;               // column offset modulo nx, in [0, nx)
+    std::vector<int> seg_bb;              // row offset minus the layer's minimum, in [0, span]
+    std::vector<int> seg_bm;              // seg_bb modulo ny
+    std::vector<int> seg_ai, seg_bi;      // unreduced column / row offsets (for Lambda*)
+    std::vector<double> seg_len;
+    std::vector<int> row_min;             // per (d, k): minimum row offset modulo ny
+    std::vector<DirInfo> dirs;
+    std::vector<WorkItem> items;          // in dispatch order (most expensive first)
+    int64_t p_elems = 0;                  // size of the partial-plane buffer P in elements
+    int max_win_rows = 0;
+    int max_seg_per_layer = 0;
+    double mean_segments = 0.0;           // per voxel and angle
+};
+
+// Build segment tables and the band plan.  threads * lines_per_thread bounds the lines of one band.
+bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int threads, int lines_per_thread,
+                      SweepPlan &plan, std::string &err);
+
+}  // namespace rt3d

@@ -1,0 +1,1100 @@
+// rt3d.hip -- HIP kernels (gfx950) and C ABI of the 3D radiative-transfer scattering hot path:
+// formal solution (FS) along characteristics on a grid periodic in x,y, mean intensity J, the
+// 27-point Lambda* operator and the operator-splitting (OS) step solved by Jacobi sweeps
+// (Hauschildt & Baron, "A 3D radiative transfer framework XIII", sections "Implementation of the
+// formal solution and Lambda* computation" and "Implementation of the operator splitting step").
+//
+// Kernels
+//   source_kernel   S = eps B + (1-eps) J packed with chi as {chi, S} per voxel (one 16-byte gather
+//                   per segment in the sweep).
+//   sweep_kernel    one workgroup per (direction, band of line rows): every thread owns a few lines
+//                   and carries their intensity down (or up) through all layers.  All lines of a
+//                   direction share one segment table, so segment s of every line in a layer lands
+//                   in a distinct voxel: the deposits D_s go into an LDS window without atomics, one
+//                   segment index at a time, and each layer's window is written once to a per-band
+//                   partial plane P.  Deterministic; no float atomics.
+//   reduce_kernel   per voxel, sums the partial planes of all directions in a fixed order:
+//                   J_fs = (1/chi) sum_d W_d |mu_d| sum_bands P, and r = J_fs - J.
+//   lstar_kernel    per voxel, the 27 derivatives dJ_v/dS_u along the lines through v (exact band).
+//   coef_kernel     A_vu = Lambda*_vu (1 - eps_u) and the Jacobi denominator 1 - Lambda*_vv (1-eps_v).
+//   jacobi_kernel   one Jacobi sweep of the OS equations (27-point stencil); the last sweep also
+//                   updates J and reduces max |dJ|/|J| (and flags NaN/Inf).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rt3d.h"
+#include "geometry.h"
+
+using rt3d::DirInfo;
+using rt3d::WorkItem;
+
+namespace {
+
+constexpr int kSweepThreads = 256;
+constexpr int kLinesPerThread = 8;
+constexpr int kPlaneThreads = 256;   // voxel-parallel kernels: one thread per voxel of a k-plane
+
+template <typename real> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+__device__ inline double dev_expm1(double x) { return expm1(x); }
+__device__ inline float dev_expm1(float x) { return expm1f(x); }
+
+// ------------------------------------------------------------------------------------------------
+// S update
+// ------------------------------------------------------------------------------------------------
+
+template <typename real>
+__global__ void source_kernel(long V, const double *__restrict__ chi, const double *__restrict__ eps,
+                              const double *__restrict__ B, const double *__restrict__ J,
+                              const double *__restrict__ S_given, typename Vec2<real>::type *cs)
+{
+    long v = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    double S = S_given ? S_given[v] : eps[v] * B[v] + (1.0 - eps[v]) * J[v];
+    typename Vec2<real>::type c;
+    c.x = real(chi[v]);
+    c.y = real(S);
+    cs[v] = c;
+}
+
+// ------------------------------------------------------------------------------------------------
+// FS sweep
+// ------------------------------------------------------------------------------------------------
+
+struct SweepArgs {
+    int nx, ny, nz, n_down;
+    const int *seg_off, *seg_n, *seg_a, *seg_bb, *seg_bm, *row_min;
+    const void *seg_len;          // real
+    const DirInfo *dirs;
+    const WorkItem *items;
+    const void *cs;               // Vec2<real>
+    const double *Ibot;           // [ny][nx] intensities at the bottom plane, or null (zero)
+    double I_top;
+    void *P;                      // real
+    double *Iem;                  // [n_up][ny][nx] or null
+};
+
+template <typename real, int LPT>
+__global__ __launch_bounds__(kSweepThreads) void sweep_kernel(SweepArgs a)
+{
+    using real2 = typename Vec2<real>::type;
+    extern __shared__ unsigned char smem_raw[];
+    real *win = reinterpret_cast<real *>(smem_raw);
+    const WorkItem it = a.items[blockIdx.x];
+    const DirInfo di = a.dirs[it.d];
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nlines = it.rows * nx;
+    const int Hw = di.win_rows;
+    const int wsize = Hw * nx;
+    const real *seg_len = static_cast<const real *>(a.seg_len);
+    const real2 *cs = static_cast<const real2 *>(a.cs);
+    real *P = static_cast<real *>(a.P) + di.p_off + long(it.band) * nz * wsize;
+
+    for (int e = threadIdx.x; e < wsize; e += blockDim.x) win[e] = real(0);
+
+    real I[LPT];
+    int li[LPT], lj[LPT];
+#pragma unroll
+    for (int t = 0; t < LPT; ++t) {
+        const int q = threadIdx.x + t * kSweepThreads;
+        const int qq = q < nlines ? q : 0;
+        lj[t] = qq / nx;
+        li[t] = q < nlines ? qq - lj[t] * nx : -1;   // -1 marks an unused slot
+        I[t] = real(a.I_top);
+    }
+    __syncthreads();
+
+    for (int step = 0; step < nz; ++step) {
+        const int k = di.down ? nz - 1 - step : step;
+        const int dk = it.d * nz + k;
+        const int off = a.seg_off[dk];
+        const int ns = a.seg_n[dk];
+        const int rmin = a.row_min[dk];
+        const real2 *csk = cs + long(k) * nx * ny;
+        int r0[LPT];
+#pragma unroll
+        for (int t = 0; t < LPT; ++t) {
+            int r = it.j0 + lj[t] + rmin;
+            r -= (r >= ny) ? ny : 0;
+            r -= (r >= ny) ? ny : 0;
+            r0[t] = r;
+        }
+        if (!di.down && step == 0) {
+            // upward lines enter through the bottom plane: boundary light of the entry voxel
+            const int sa = a.seg_a[off], sm = a.seg_bm[off];
+#pragma unroll
+            for (int t = 0; t < LPT; ++t) {
+                if (li[t] < 0) continue;
+                int col = li[t] + sa;
+                col -= (col >= nx) ? nx : 0;
+                int row = r0[t] + sm;
+                row -= (row >= ny) ? ny : 0;
+                I[t] = a.Ibot ? real(a.Ibot[row * nx + col]) : real(0);
+            }
+        }
+        for (int s = 0; s < ns; ++s) {
+            const int sa = a.seg_a[off + s];
+            const int sb = a.seg_bb[off + s];
+            const int sm = a.seg_bm[off + s];
+            const real len = seg_len[off + s];
+            real2 c[LPT];
+            int col[LPT];
+#pragma unroll
+            for (int t = 0; t < LPT; ++t) {
+                int cc = li[t] + sa;
+                cc -= (cc >= nx) ? nx : 0;
+                int row = r0[t] + sm;
+                row -= (row >= ny) ? ny : 0;
+                col[t] = cc;
+                if (li[t] >= 0) c[t] = csk[row * nx + cc];
+            }
+#pragma unroll
+            for (int t = 0; t < LPT; ++t) {
+                if (li[t] < 0) continue;
+                const real dtau = c[t].x * len;
+                const real em1 = dev_expm1(-dtau);          // e^{-dtau} - 1
+                const real dI = (I[t] - c[t].y) * em1;
+                const real D = c[t].y * dtau - dI;          // chi * integral of I over the segment
+                I[t] += dI;
+                win[(lj[t] + sb) * nx + col[t]] += D;
+            }
+            __syncthreads();
+        }
+        real *Pk = P + long(k) * wsize;
+        for (int e = threadIdx.x; e < wsize; e += blockDim.x) {
+            Pk[e] = win[e];
+            win[e] = real(0);
+        }
+        __syncthreads();
+    }
+    if (!di.down && a.Iem) {
+        double *E = a.Iem + long(it.d - a.n_down) * nx * ny;
+#pragma unroll
+        for (int t = 0; t < LPT; ++t)
+            if (li[t] >= 0) E[(it.j0 + lj[t]) * nx + li[t]] = double(I[t]);
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Angle reduction of the partial planes
+// ------------------------------------------------------------------------------------------------
+
+struct ReduceArgs {
+    int nx, ny, nz, n_dir;
+    const DirInfo *dirs;
+    const int *row_min;
+    const void *P;            // real
+    const double *chi;
+    const double *J;          // for r = J_fs - J (may be null)
+    double *Jfs;
+    double *r;                // may be null
+};
+
+template <typename real>
+__global__ __launch_bounds__(kPlaneThreads) void reduce_kernel(ReduceArgs a)
+{
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (p >= nx * ny) return;
+    const int j = p / nx, i = p - j * nx;
+    const real *P = static_cast<const real *>(a.P);
+    double acc = 0.0;
+    for (int d = 0; d < a.n_dir; ++d) {
+        const DirInfo di = a.dirs[d];
+        const int rmin = a.row_min[d * nz + k];
+        int jj = j - rmin;
+        jj += (jj < 0) ? ny : 0;
+        // band whose lines start this row's window offset
+        int b = int((float(jj) + 0.5f) / float(di.band_rows));
+        b = min(b, di.n_bands - 1);
+        if (b * di.band_rows > jj) --b;
+        while (b < di.n_bands - 1 && (b + 1) * di.band_rows <= jj) ++b;
+        int off = jj - b * di.band_rows;
+        const long plane = long(di.win_rows) * nx;
+        const real *Pd = P + di.p_off + long(k) * plane + i;
+        double sd = 0.0;
+        int bb = b;
+        while (true) {
+            sd += double(Pd[long(bb) * nz * plane + long(off) * nx]);
+            bb = (bb == 0) ? di.n_bands - 1 : bb - 1;
+            off += (bb == di.n_bands - 1) ? di.last_rows : di.band_rows;
+            if (off >= di.win_rows) break;
+        }
+        acc += di.wmu * sd;
+    }
+    const long v = long(k) * nx * ny + p;
+    const double Jfs = acc / a.chi[v];
+    a.Jfs[v] = Jfs;
+    if (a.r) a.r[v] = Jfs - a.J[v];
+}
+
+// ------------------------------------------------------------------------------------------------
+// Lambda*
+// ------------------------------------------------------------------------------------------------
+
+struct LstarArgs {
+    int nx, ny, nz, n_dir;
+    int early_exit;                 // 1: no line can wrap back onto a neighbour within two layers
+    const DirInfo *dirs;
+    const int *seg_off, *seg_n, *seg_ai, *seg_bi;
+    const double *seg_len;
+    const double *chi;
+    double *L;                      // [27][V]
+};
+
+// x + expm1(-x) = e^{-x} - 1 + x for x >= 0; below 1/2 by Horner on x^2 (1/2! - x/3! + x^2/4! - ...)
+// through x^15/17!, which avoids the cancellation of the direct form for thin segments.
+__device__ inline double self_term(double x)
+{
+    if (x >= 0.5) return x + expm1(-x);
+    constexpr double inv_fact[18] = {
+        1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720, 1.0 / 5040, 1.0 / 40320,
+        1.0 / 362880, 1.0 / 3628800, 1.0 / 39916800, 1.0 / 479001600, 1.0 / 6227020800.0,
+        1.0 / 87178291200.0, 1.0 / 1307674368000.0, 1.0 / 20922789888000.0,
+        1.0 / 355687428096000.0};
+    double r = inv_fact[17];
+#pragma unroll
+    for (int n = 16; n >= 2; --n) r = inv_fact[n] - x * r;
+    return x * x * r;
+}
+
+__device__ inline int wrap_small(int a, int n)
+{
+    // a may be any integer; returns a mod n in [0, n)
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// Lambda*_{vu} = sum_d W_d |mu_d| / chi_v * sum over the segments s of direction d inside v of
+//   delta_uv (dtau_s + em1_s) - em1_s * sum over earlier segments s' in u of c_{s'->s},
+//   c_{s'->s} = (1 - e_{s'}) prod_{s' < s'' < s} e_{s''},  e = exp(-dtau).
+// The lines through v are the reference line shifted so that its segment s lies in v; walking that
+// line backwards through the current and the previous layer reaches every earlier segment that can
+// lie in the 3x3x3 block (lines are monotone in z).
+__global__ __launch_bounds__(kPlaneThreads) void lstar_kernel(LstarArgs a)
+{
+    __shared__ double acc[27][kPlaneThreads];
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    const bool valid = p < nx * ny;
+    const int j = valid ? p / nx : 0, i = valid ? p - (p / nx) * nx : 0;
+    const long plane = long(nx) * ny;
+    const long V = plane * nz;
+    const long v = k * plane + long(j) * nx + i;
+    for (int o = 0; o < 27; ++o) acc[o][threadIdx.x] = 0.0;
+    const double chiv = a.chi[v];
+    for (int d = 0; d < a.n_dir; ++d) {
+        const DirInfo di = a.dirs[d];
+        const double fac = di.wmu / chiv;
+        const int dk = d * nz + k;
+        const int off = a.seg_off[dk], n = a.seg_n[dk];
+        const int ku = di.down ? k + 1 : k - 1;
+        const bool has_up = ku >= 0 && ku < nz;
+        const int offu = has_up ? a.seg_off[d * nz + ku] : 0;
+        const int nu = has_up ? a.seg_n[d * nz + ku] : 0;
+        for (int s = 0; s < n; ++s) {
+            const int as = a.seg_ai[off + s], bs = a.seg_bi[off + s];
+            const double dtau = chiv * a.seg_len[off + s];
+            const double em1 = expm1(-dtau);
+            acc[13][threadIdx.x] += fac * self_term(dtau);
+            const double g = -fac * em1;
+            double prod = 1.0;
+            // walk back: current layer s-1 .. 0, then the previous layer from its last segment
+            const int total = s + nu;
+            for (int w = 0; w < total; ++w) {
+                int idx, dkk;
+                if (w < s) { idx = off + s - 1 - w; dkk = 0; }
+                else { idx = offu + nu - 1 - (w - s); dkk = ku - k; }
+                const int dA = a.seg_ai[idx] - as, dB = a.seg_bi[idx] - bs;
+                if (a.early_exit && (dA > 1 || dA < -1 || dB > 1 || dB < -1)) break;
+                const int mA = wrap_small(dA, nx), mB = wrap_small(dB, ny);
+                int col = i + mA;
+                col -= (col >= nx) ? nx : 0;
+                int row = j + mB;
+                row -= (row >= ny) ? ny : 0;
+                const long u = long(k + dkk) * plane + long(row) * nx + col;
+                const double tau_u = a.chi[u] * a.seg_len[idx];
+                const double c = -expm1(-tau_u) * prod;
+                const int oi = (mA == 0) ? 1 : (mA == 1) ? 2 : (mA == nx - 1) ? 0 : -1;
+                const int oj = (mB == 0) ? 1 : (mB == 1) ? 2 : (mB == ny - 1) ? 0 : -1;
+                if (oi >= 0 && oj >= 0) acc[9 * (dkk + 1) + 3 * oj + oi][threadIdx.x] += g * c;
+                prod *= exp(-tau_u);   // not 1 + expm1: keeps relative accuracy for thick segments
+            }
+        }
+    }
+    if (valid)
+        for (int o = 0; o < 27; ++o) a.L[o * V + v] = acc[o][threadIdx.x];
+}
+
+// A_o(v) = Lambda*_o(v) (1 - eps_u) for o != 13, A_13(v) = 1 - Lambda*_13(v) (1 - eps_v).
+__global__ __launch_bounds__(kPlaneThreads) void coef_kernel(int nx, int ny, int nz,
+                                                             const double *__restrict__ L,
+                                                             const double *__restrict__ eps,
+                                                             double *__restrict__ A)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (p >= nx * ny) return;
+    const int j = p / nx, i = p - j * nx;
+    const long plane = long(nx) * ny, V = plane * nz, v = k * plane + p;
+    for (int o = 0; o < 27; ++o) {
+        const int dk = o / 9 - 1, dj = (o / 3) % 3 - 1, di = o % 3 - 1;
+        const int kk = k + dk;
+        double val = 0.0;
+        if (o == 13) {
+            val = 1.0 - L[13 * V + v] * (1.0 - eps[v]);
+        } else if (kk >= 0 && kk < nz) {
+            int jj = j + dj, ii = i + di;
+            jj += (jj < 0) ? ny : 0;
+            jj -= (jj >= ny) ? ny : 0;
+            ii += (ii < 0) ? nx : 0;
+            ii -= (ii >= nx) ? nx : 0;
+            val = L[o * V + v] * (1.0 - eps[kk * plane + long(jj) * nx + ii]);
+        }
+        A[o * V + v] = val;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Jacobi sweep of the OS equations, optionally fused with the J update and max |dJ|/|J|
+// ------------------------------------------------------------------------------------------------
+
+struct JacobiArgs {
+    int nx, ny, nz;
+    const double *r;
+    const double *A;             // [27][V]; A[13] holds the denominator
+    const double *dJ_in;         // null: dJ^0 = 0 (first sweep)
+    double *dJ_out;              // may be null when J is updated
+    double *J;                   // null: no update
+    unsigned long long *maxrel;  // bits of max |dJ|/|J| (non-negative doubles order like integers)
+    int *nonfinite;
+};
+
+__global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel(JacobiArgs a)
+{
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    const bool valid = p < nx * ny;
+    double q = 0.0;
+    bool bad = false;
+    if (valid) {
+        const int j = p / nx, i = p - j * nx;
+        const long plane = long(nx) * ny, V = plane * nz, v = k * plane + p;
+        double acc = a.r[v];
+        if (a.dJ_in) {
+            const int im = (i == 0) ? nx - 1 : i - 1, ip = (i == nx - 1) ? 0 : i + 1;
+            const int jm = (j == 0) ? ny - 1 : j - 1, jp = (j == ny - 1) ? 0 : j + 1;
+            const int cols[3] = {im, i, ip};
+            const int rows[3] = {jm, j, jp};
+#pragma unroll
+            for (int o = 0; o < 27; ++o) {
+                if (o == 13) continue;
+                const int kk = k + o / 9 - 1;
+                if (kk < 0 || kk >= nz) continue;
+                const long u = kk * plane + long(rows[(o / 3) % 3]) * nx + cols[o % 3];
+                acc += a.A[o * V + v] * a.dJ_in[u];
+            }
+        }
+        const double dJ = acc / a.A[13 * V + v];
+        if (a.dJ_out) a.dJ_out[v] = dJ;
+        if (a.J) {
+            const double Jn = a.J[v] + dJ;
+            a.J[v] = Jn;
+            q = fabs(dJ) / fabs(Jn);
+            bad = !isfinite(Jn) || !isfinite(q);
+        }
+    }
+    if (!a.J) return;
+    // block max of q; NaN/Inf raise the flag
+    if (bad) { atomicOr(a.nonfinite, 1); q = 0.0; }
+    for (int offs = 32; offs > 0; offs >>= 1) q = fmax(q, __shfl_xor(q, offs));
+    __shared__ double wmax[kPlaneThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) wmax[wid] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = wmax[0];
+        for (int w = 1; w < kPlaneThreads / 64; ++w) m = fmax(m, wmax[w]);
+        atomicMax(a.maxrel, static_cast<unsigned long long>(__double_as_longlong(m)));
+    }
+}
+
+// finiteness / range check of a device medium
+__global__ void check_medium_kernel(long V, const double *chi, const double *eps, const double *B,
+                                    int *flag)
+{
+    long v = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const double c = chi[v], e = eps[v], b = B[v];
+    const bool ok = isfinite(c) && c > 0.0 && isfinite(e) && e > 0.0 && e <= 1.0 && isfinite(b);
+    if (!ok) atomicOr(flag, 1);
+}
+
+__global__ void check_finite_kernel(long V, const double *x, int *flag)
+{
+    long v = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    if (!isfinite(x[v])) atomicOr(flag, 1);
+}
+
+}  // namespace
+
+// ================================================================================================
+// Context
+// ================================================================================================
+
+enum KernelId { K_SOURCE, K_SWEEP, K_REDUCE, K_LSTAR, K_COEF, K_JACOBI, K_COUNT };
+static const char *kKernelNames[K_COUNT] = {"source", "sweep", "reduce", "lstar", "coef", "jacobi"};
+
+struct rt3d_ctx {
+    rt3d_grid_desc g{};
+    int precision = RT3D_FP64;
+    hipStream_t stream = nullptr;
+    rt3d::AngleSet A;
+    rt3d::SweepPlan plan;
+    long V = 0;
+    size_t real_size = 8;
+    int lstar_early_exit = 0;
+    // device buffers (owned)
+    double *chi = nullptr, *eps = nullptr, *B = nullptr, *J = nullptr, *Jfs = nullptr, *r = nullptr;
+    double *dJa = nullptr, *dJb = nullptr, *L = nullptr, *Acoef = nullptr, *Iem = nullptr;
+    double *Sbuf = nullptr;
+    void *cs = nullptr, *P = nullptr, *seg_len = nullptr;
+    double *seg_len64 = nullptr;
+    int *seg_off = nullptr, *seg_n = nullptr, *seg_a = nullptr, *seg_bb = nullptr, *seg_bm = nullptr;
+    int *seg_ai = nullptr, *seg_bi = nullptr, *row_min = nullptr;
+    DirInfo *dirs = nullptr;
+    WorkItem *items = nullptr;
+    unsigned long long *d_maxrel = nullptr;
+    int *d_flag = nullptr;
+    size_t device_bytes = 0;
+    bool have_medium = false, have_lstar = false, have_fs = false;
+    long outer_iters = 0, inner_sweeps = 0;
+    // timing
+    bool timing = false;
+    struct Pending { int kid; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    double kernel_ms[K_COUNT] = {0};
+    long kernel_launches[K_COUNT] = {0};
+    std::string err;
+};
+
+namespace {
+
+int fail(rt3d_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(rt3d_ctx *c, hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (c) c->err = m;
+    return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? RT3D_ERR_OOM : RT3D_ERR_HIP;
+}
+
+#define HIP_TRY(ctx, expr, what)                     \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+template <typename T>
+int dev_alloc(rt3d_ctx *c, T **p, size_t count)
+{
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_fail(c, e, "hipMalloc");
+    }
+    c->device_bytes += bytes;
+    return RT3D_OK;
+}
+
+template <typename T>
+int upload(rt3d_ctx *c, T **p, const std::vector<T> &h)
+{
+    int rc = dev_alloc(c, p, h.size());
+    if (rc) return rc;
+    if (!h.empty()) HIP_TRY(c, hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+    return RT3D_OK;
+}
+
+hipEvent_t get_event(rt3d_ctx *c)
+{
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct TimedLaunch {
+    rt3d_ctx *c;
+    int kid;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(rt3d_ctx *ctx, int id) : c(ctx), kid(id)
+    {
+        if (c->timing) {
+            a = get_event(c);
+            b = get_event(c);
+            if (a) hipEventRecord(a, c->stream);
+        }
+    }
+    ~TimedLaunch()
+    {
+        if (c->timing && a && b) {
+            hipEventRecord(b, c->stream);
+            c->pending.push_back({kid, a, b});
+        }
+        c->kernel_launches[kid] += 1;
+    }
+};
+
+// Resolve pending timing events (call after the stream has been synchronised).
+void resolve_timing(rt3d_ctx *c)
+{
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) c->kernel_ms[p.kid] += ms;
+        c->event_pool.push_back(p.a);
+        c->event_pool.push_back(p.b);
+    }
+    c->pending.clear();
+}
+
+int sync(rt3d_ctx *c)
+{
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    resolve_timing(c);
+    return RT3D_OK;
+}
+
+int check_launch(rt3d_ctx *c, const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, what);
+    return RT3D_OK;
+}
+
+int validate_desc(const rt3d_grid_desc *g, std::string &msg)
+{
+    if (!g) { msg = "grid descriptor is NULL"; return RT3D_ERR_ARG; }
+    if (g->nx < 3 || g->ny < 3 || g->nz < 3) { msg = "nx, ny, nz must be >= 3"; return RT3D_ERR_ARG; }
+    if (long(g->nx) * g->ny * g->nz > (1L << 31) / 27) { msg = "grid too large"; return RT3D_ERR_ARG; }
+    if (g->n_theta < 2 || (g->n_theta % 2) != 0) { msg = "n_theta must be even and >= 2"; return RT3D_ERR_ARG; }
+    if (g->n_phi < 4 || (g->n_phi % 4) != 0) { msg = "n_phi must be a positive multiple of 4"; return RT3D_ERR_ARG; }
+    if (!std::isfinite(g->I_top) || g->I_top < 0.0) { msg = "I_top must be finite and >= 0"; return RT3D_ERR_ARG; }
+    if (g->bottom_bc != 0 && g->bottom_bc != 1) { msg = "bottom_bc must be 0 or 1"; return RT3D_ERR_ARG; }
+    return RT3D_OK;
+}
+
+int validate_medium_host(long V, const double *chi, const double *eps, const double *B, std::string &msg)
+{
+    for (long v = 0; chi && v < V; ++v)
+        if (!std::isfinite(chi[v]) || !(chi[v] > 0.0)) { msg = "chi must be finite and > 0"; return RT3D_ERR_ARG; }
+    for (long v = 0; eps && v < V; ++v)
+        if (!(eps[v] > 0.0) || !(eps[v] <= 1.0)) { msg = "eps must lie in (0, 1]"; return RT3D_ERR_ARG; }
+    for (long v = 0; B && v < V; ++v)
+        if (!std::isfinite(B[v])) { msg = "B must be finite"; return RT3D_ERR_ARG; }
+    return RT3D_OK;
+}
+
+hipMemcpyKind kind_in(int ptr_kind) { return ptr_kind == RT3D_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
+hipMemcpyKind kind_out(int ptr_kind) { return ptr_kind == RT3D_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
+
+dim3 plane_grid(const rt3d_ctx *c)
+{
+    return dim3((c->g.nx * c->g.ny + kPlaneThreads - 1) / kPlaneThreads, c->g.nz);
+}
+
+int launch_source(rt3d_ctx *c, const double *S_given)
+{
+    TimedLaunch t(c, K_SOURCE);
+    const int blocks = int((c->V + 255) / 256);
+    if (c->precision == RT3D_FP64)
+        hipLaunchKernelGGL(source_kernel<double>, dim3(blocks), dim3(256), 0, c->stream, c->V, c->chi,
+                           c->eps, c->B, c->J, S_given, static_cast<double2 *>(c->cs));
+    else
+        hipLaunchKernelGGL(source_kernel<float>, dim3(blocks), dim3(256), 0, c->stream, c->V, c->chi,
+                           c->eps, c->B, c->J, S_given, static_cast<float2 *>(c->cs));
+    return check_launch(c, "source_kernel");
+}
+
+int launch_sweep(rt3d_ctx *c)
+{
+    SweepArgs a;
+    a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
+    a.n_down = c->A.n_dir / 2;
+    a.seg_off = c->seg_off; a.seg_n = c->seg_n; a.seg_a = c->seg_a; a.seg_bb = c->seg_bb;
+    a.seg_bm = c->seg_bm; a.row_min = c->row_min;
+    a.seg_len = c->seg_len;
+    a.dirs = c->dirs; a.items = c->items;
+    a.cs = c->cs;
+    a.Ibot = (c->g.bottom_bc == 0) ? c->B : nullptr;
+    a.I_top = c->g.I_top;
+    a.P = c->P;
+    a.Iem = c->Iem;
+    const size_t smem = size_t(c->plan.max_win_rows) * c->g.nx * c->real_size;
+    TimedLaunch t(c, K_SWEEP);
+    if (c->precision == RT3D_FP64)
+        hipLaunchKernelGGL((sweep_kernel<double, kLinesPerThread>), dim3(c->plan.items.size()),
+                           dim3(kSweepThreads), smem, c->stream, a);
+    else
+        hipLaunchKernelGGL((sweep_kernel<float, kLinesPerThread>), dim3(c->plan.items.size()),
+                           dim3(kSweepThreads), smem, c->stream, a);
+    return check_launch(c, "sweep_kernel");
+}
+
+int launch_reduce(rt3d_ctx *c, bool with_residual)
+{
+    ReduceArgs a;
+    a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.n_dir = c->A.n_dir;
+    a.dirs = c->dirs; a.row_min = c->row_min; a.P = c->P; a.chi = c->chi;
+    a.J = c->J; a.Jfs = c->Jfs; a.r = with_residual ? c->r : nullptr;
+    TimedLaunch t(c, K_REDUCE);
+    if (c->precision == RT3D_FP64)
+        hipLaunchKernelGGL(reduce_kernel<double>, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
+    else
+        hipLaunchKernelGGL(reduce_kernel<float>, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
+    return check_launch(c, "reduce_kernel");
+}
+
+// S (given, or from J) -> J_fs (and r when with_residual)
+int run_fs(rt3d_ctx *c, const double *S_dev, bool with_residual)
+{
+    int rc = launch_source(c, S_dev);
+    if (!rc) rc = launch_sweep(c);
+    if (!rc) rc = launch_reduce(c, with_residual);
+    if (!rc) c->have_fs = true;
+    return rc;
+}
+
+int ensure_lstar(rt3d_ctx *c)
+{
+    if (c->have_lstar) return RT3D_OK;
+    LstarArgs a;
+    a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.n_dir = c->A.n_dir;
+    a.early_exit = c->lstar_early_exit;
+    a.dirs = c->dirs; a.seg_off = c->seg_off; a.seg_n = c->seg_n; a.seg_ai = c->seg_ai;
+    a.seg_bi = c->seg_bi; a.seg_len = c->seg_len64; a.chi = c->chi; a.L = c->L;
+    {
+        TimedLaunch t(c, K_LSTAR);
+        hipLaunchKernelGGL(lstar_kernel, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
+    }
+    int rc = check_launch(c, "lstar_kernel");
+    if (rc) return rc;
+    {
+        TimedLaunch t(c, K_COEF);
+        hipLaunchKernelGGL(coef_kernel, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, c->g.nx,
+                           c->g.ny, c->g.nz, c->L, c->eps, c->Acoef);
+    }
+    rc = check_launch(c, "coef_kernel");
+    if (rc) return rc;
+    c->have_lstar = true;
+    return RT3D_OK;
+}
+
+int launch_jacobi(rt3d_ctx *c, const double *dJ_in, double *dJ_out, bool update)
+{
+    JacobiArgs a;
+    a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
+    a.r = c->r; a.A = c->Acoef; a.dJ_in = dJ_in; a.dJ_out = dJ_out;
+    a.J = update ? c->J : nullptr;
+    a.maxrel = c->d_maxrel; a.nonfinite = c->d_flag;
+    TimedLaunch t(c, K_JACOBI);
+    hipLaunchKernelGGL(jacobi_kernel, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
+    return check_launch(c, "jacobi_kernel");
+}
+
+void free_all(rt3d_ctx *c)
+{
+    void *ptrs[] = {c->chi, c->eps, c->B, c->J, c->Jfs, c->r, c->dJa, c->dJb, c->L, c->Acoef, c->Iem,
+                    c->Sbuf, c->cs, c->P, c->seg_len, c->seg_len64, c->seg_off, c->seg_n, c->seg_a,
+                    c->seg_bb, c->seg_bm, c->seg_ai, c->seg_bi, c->row_min, c->dirs, c->items,
+                    c->d_maxrel, c->d_flag};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    for (auto &p : c->pending) {
+        hipEventDestroy(p.a);
+        hipEventDestroy(p.b);
+    }
+    for (auto e : c->event_pool) hipEventDestroy(e);
+}
+
+}  // namespace
+
+// ================================================================================================
+// C ABI
+// ================================================================================================
+
+extern "C" {
+
+const char *rt3d_status_str(int status)
+{
+    switch (status) {
+    case RT3D_OK: return "ok";
+    case RT3D_ERR_ARG: return "invalid argument";
+    case RT3D_ERR_OOM: return "out of memory";
+    case RT3D_ERR_HIP: return "HIP runtime error";
+    case RT3D_ERR_NOT_CONVERGED: return "not converged";
+    case RT3D_ERR_NONFINITE: return "non-finite value";
+    case RT3D_ERR_STATE: return "invalid call order";
+    default: return "unknown status";
+    }
+}
+
+const char *rt3d_last_error(const rt3d_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int rt3d_quadrature(int n_theta, int n_phi, double *mu, double *ox, double *oy, double *w)
+{
+    rt3d::AngleSet A;
+    if (!mu || !ox || !oy || !w || !rt3d::make_angle_set(n_theta, n_phi, A)) return RT3D_ERR_ARG;
+    std::memcpy(mu, A.mu.data(), sizeof(double) * A.n_dir);
+    std::memcpy(ox, A.ox.data(), sizeof(double) * A.n_dir);
+    std::memcpy(oy, A.oy.data(), sizeof(double) * A.n_dir);
+    std::memcpy(w, A.w.data(), sizeof(double) * A.n_dir);
+    return RT3D_OK;
+}
+
+int rt3d_segment_table(const rt3d_grid_desc *g, int d, int k, int *di, int *dj, double *len, int max_seg)
+{
+    std::string msg;
+    if (validate_desc(g, msg) != RT3D_OK || !di || !dj || !len) return RT3D_ERR_ARG;
+    rt3d::AngleSet A;
+    if (!rt3d::make_angle_set(g->n_theta, g->n_phi, A)) return RT3D_ERR_ARG;
+    if (d < 0 || d >= A.n_dir || k < 0 || k >= g->nz) return RT3D_ERR_ARG;
+    rt3d::LayerSegments L;
+    rt3d::layer_segments(g->nz, A.mu[d], A.ox[d], A.oy[d], k, L);
+    const int n = int(L.di.size());
+    if (n > max_seg) return RT3D_ERR_ARG;
+    for (int s = 0; s < n; ++s) {
+        di[s] = L.di[s];
+        dj[s] = L.dj[s];
+        len[s] = L.len[s];
+    }
+    return n;
+}
+
+int rt3d_validate(const rt3d_grid_desc *g, const double *chi, const double *eps, const double *B)
+{
+    std::string msg;
+    int rc = validate_desc(g, msg);
+    if (rc) return rc;
+    return validate_medium_host(long(g->nx) * g->ny * g->nz, chi, eps, B, msg);
+}
+
+int rt3d_create(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, void *hip_stream)
+{
+    if (!out) return RT3D_ERR_ARG;
+    *out = nullptr;
+    std::string msg;
+    if (validate_desc(g, msg) != RT3D_OK) return RT3D_ERR_ARG;
+    if (precision != RT3D_FP64 && precision != RT3D_FP32_SWEEP) return RT3D_ERR_ARG;
+    rt3d_ctx *c = new (std::nothrow) rt3d_ctx();
+    if (!c) return RT3D_ERR_OOM;
+    c->g = *g;
+    c->precision = precision;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->real_size = (precision == RT3D_FP64) ? sizeof(double) : sizeof(float);
+    c->V = long(g->nx) * g->ny * g->nz;
+    if (!rt3d::make_angle_set(g->n_theta, g->n_phi, c->A)) { delete c; return RT3D_ERR_ARG; }
+    if (!rt3d::build_sweep_plan(g->nx, g->ny, g->nz, c->A, kSweepThreads, kLinesPerThread, c->plan, msg)) {
+        delete c;
+        return RT3D_ERR_ARG;
+    }
+    const size_t smem = size_t(c->plan.max_win_rows) * g->nx * c->real_size;
+    if (smem > 64 * 1024) { delete c; return RT3D_ERR_ARG; }
+    // Lambda* walk may stop at the first non-neighbour only if no line wraps back within two layers
+    {
+        double tmax_x = 0.0, tmax_y = 0.0;
+        for (int d = 0; d < c->A.n_dir; ++d) {
+            tmax_x = std::max(tmax_x, std::fabs(c->A.ox[d] / c->A.mu[d]));
+            tmax_y = std::max(tmax_y, std::fabs(c->A.oy[d] / c->A.mu[d]));
+        }
+        c->lstar_early_exit = (g->nx > 2.0 * tmax_x + 4.0 && g->ny > 2.0 * tmax_y + 4.0) ? 1 : 0;
+    }
+    const long V = c->V;
+    const auto &P = c->plan;
+    int rc = RT3D_OK;
+    auto chk = [&](int r) { if (!rc) rc = r; };
+    chk(dev_alloc(c, &c->chi, V)); chk(dev_alloc(c, &c->eps, V)); chk(dev_alloc(c, &c->B, V));
+    chk(dev_alloc(c, &c->J, V)); chk(dev_alloc(c, &c->Jfs, V)); chk(dev_alloc(c, &c->r, V));
+    chk(dev_alloc(c, &c->dJa, V)); chk(dev_alloc(c, &c->dJb, V)); chk(dev_alloc(c, &c->Sbuf, V));
+    chk(dev_alloc(c, &c->L, 27 * V)); chk(dev_alloc(c, &c->Acoef, 27 * V));
+    chk(dev_alloc(c, &c->Iem, size_t(c->A.n_dir / 2) * g->nx * g->ny));
+    if (!rc) {
+        if (precision == RT3D_FP64) {
+            double2 *cs = nullptr; double *Pp = nullptr;
+            chk(dev_alloc(c, &cs, V)); chk(dev_alloc(c, &Pp, size_t(P.p_elems)));
+            c->cs = cs; c->P = Pp;
+            double *sl = nullptr;
+            chk(upload(c, &sl, P.seg_len));
+            c->seg_len = sl;
+        } else {
+            float2 *cs = nullptr; float *Pp = nullptr;
+            chk(dev_alloc(c, &cs, V)); chk(dev_alloc(c, &Pp, size_t(P.p_elems)));
+            c->cs = cs; c->P = Pp;
+            std::vector<float> lf(P.seg_len.begin(), P.seg_len.end());
+            float *sl = nullptr;
+            chk(upload(c, &sl, lf));
+            c->seg_len = sl;
+        }
+    }
+    chk(upload(c, &c->seg_len64, P.seg_len));
+    chk(upload(c, &c->seg_off, P.seg_off)); chk(upload(c, &c->seg_n, P.seg_n));
+    chk(upload(c, &c->seg_a, P.seg_a)); chk(upload(c, &c->seg_bb, P.seg_bb)); chk(upload(c, &c->seg_bm, P.seg_bm));
+    chk(upload(c, &c->seg_ai, P.seg_ai)); chk(upload(c, &c->seg_bi, P.seg_bi));
+    chk(upload(c, &c->row_min, P.row_min));
+    chk(upload(c, &c->dirs, P.dirs)); chk(upload(c, &c->items, P.items));
+    chk(dev_alloc(c, &c->d_maxrel, 1)); chk(dev_alloc(c, &c->d_flag, 1));
+    if (rc) {
+        free_all(c);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return RT3D_OK;
+}
+
+void rt3d_destroy(rt3d_ctx *ctx)
+{
+    if (!ctx) return;
+    hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    delete ctx;
+}
+
+int rt3d_set_medium(rt3d_ctx *c, const double *chi, const double *eps, const double *B, int ptr_kind)
+{
+    if (!c) return RT3D_ERR_ARG;
+    if (!chi || !eps || !B || (ptr_kind != RT3D_HOST && ptr_kind != RT3D_DEVICE))
+        return fail(c, RT3D_ERR_ARG, "null medium pointer or bad ptr_kind");
+    const long V = c->V;
+    if (ptr_kind == RT3D_HOST) {
+        std::string msg;
+        if (validate_medium_host(V, chi, eps, B, msg)) return fail(c, RT3D_ERR_ARG, msg);
+    }
+    // staged copies: the context state changes only once the new medium is known to be valid
+    HIP_TRY(c, hipMemcpyAsync(c->dJa, chi, V * 8, kind_in(ptr_kind), c->stream), "copy chi");
+    HIP_TRY(c, hipMemcpyAsync(c->dJb, eps, V * 8, kind_in(ptr_kind), c->stream), "copy eps");
+    HIP_TRY(c, hipMemcpyAsync(c->Sbuf, B, V * 8, kind_in(ptr_kind), c->stream), "copy B");
+    if (ptr_kind == RT3D_DEVICE) {
+        HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream), "memset flag");
+        hipLaunchKernelGGL(check_medium_kernel, dim3((V + 255) / 256), dim3(256), 0, c->stream, V,
+                           c->dJa, c->dJb, c->Sbuf, c->d_flag);
+        int rc = check_launch(c, "check_medium_kernel");
+        if (rc) return rc;
+        int flag = 0;
+        HIP_TRY(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream), "flag");
+        HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+        if (flag) return fail(c, RT3D_ERR_ARG, "device medium: chi must be finite > 0, eps in (0,1], B finite");
+    }
+    std::swap(c->chi, c->dJa);
+    std::swap(c->eps, c->dJb);
+    std::swap(c->B, c->Sbuf);
+    HIP_TRY(c, hipMemcpyAsync(c->J, c->B, V * 8, hipMemcpyDeviceToDevice, c->stream), "J = B");
+    c->have_medium = true;
+    c->have_lstar = false;
+    c->have_fs = false;
+    c->outer_iters = 0;
+    c->inner_sweeps = 0;
+    return sync(c);
+}
+
+int rt3d_set_J(rt3d_ctx *c, const double *J, int ptr_kind)
+{
+    if (!c) return RT3D_ERR_ARG;
+    if (!c->have_medium) return fail(c, RT3D_ERR_STATE, "set the medium first");
+    if (!J || (ptr_kind != RT3D_HOST && ptr_kind != RT3D_DEVICE)) return fail(c, RT3D_ERR_ARG, "bad J");
+    const long V = c->V;
+    if (ptr_kind == RT3D_HOST) {
+        for (long v = 0; v < V; ++v)
+            if (!std::isfinite(J[v])) return fail(c, RT3D_ERR_ARG, "J must be finite");
+        HIP_TRY(c, hipMemcpyAsync(c->J, J, V * 8, hipMemcpyHostToDevice, c->stream), "copy J");
+        return sync(c);
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->dJa, J, V * 8, hipMemcpyDeviceToDevice, c->stream), "copy J");
+    HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream), "memset flag");
+    hipLaunchKernelGGL(check_finite_kernel, dim3((V + 255) / 256), dim3(256), 0, c->stream, V, c->dJa, c->d_flag);
+    int rc = check_launch(c, "check_finite_kernel");
+    if (rc) return rc;
+    int flag = 0;
+    HIP_TRY(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream), "flag");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+    if (flag) return fail(c, RT3D_ERR_ARG, "J must be finite");
+    std::swap(c->J, c->dJa);
+    return sync(c);
+}
+
+int rt3d_get_J(rt3d_ctx *c, double *J_out, int ptr_kind)
+{
+    if (!c) return RT3D_ERR_ARG;
+    if (!c->have_medium) return fail(c, RT3D_ERR_STATE, "no medium");
+    if (!J_out || (ptr_kind != RT3D_HOST && ptr_kind != RT3D_DEVICE)) return fail(c, RT3D_ERR_ARG, "bad output");
+    HIP_TRY(c, hipMemcpyAsync(J_out, c->J, c->V * 8, kind_out(ptr_kind), c->stream), "copy J out");
+    return ptr_kind == RT3D_HOST ? sync(c) : RT3D_OK;
+}
+
+int rt3d_formal_solution(rt3d_ctx *c, const double *S_or_null, double *J_fs_out, int ptr_kind)
+{
+    if (!c) return RT3D_ERR_ARG;
+    if (!c->have_medium) return fail(c, RT3D_ERR_STATE, "set the medium first");
+    if (!J_fs_out || (ptr_kind != RT3D_HOST && ptr_kind != RT3D_DEVICE)) return fail(c, RT3D_ERR_ARG, "bad output");
+    const double *S_dev = nullptr;
+    if (S_or_null) {
+        if (ptr_kind == RT3D_HOST) {
+            for (long v = 0; v < c->V; ++v)
+                if (!std::isfinite(S_or_null[v])) return fail(c, RT3D_ERR_ARG, "S must be finite");
+        }
+        HIP_TRY(c, hipMemcpyAsync(c->Sbuf, S_or_null, c->V * 8, kind_in(ptr_kind), c->stream), "copy S");
+        S_dev = c->Sbuf;
+    }
+    int rc = run_fs(c, S_dev, false);
+    if (rc) return rc;
+    HIP_TRY(c, hipMemcpyAsync(J_fs_out, c->Jfs, c->V * 8, kind_out(ptr_kind), c->stream), "copy J_fs");
+    return sync(c);
+}
+
+int rt3d_build_lstar(rt3d_ctx *c)
+{
+    if (!c) return RT3D_ERR_ARG;
+    if (!c->have_medium) return fail(c, RT3D_ERR_STATE, "set the medium first");
+    int rc = ensure_lstar(c);
+    if (rc) return rc;
+    return sync(c);
+}
+
+int rt3d_get_lstar(rt3d_ctx *c, double *out, int ptr_kind)
+{
+    if (!c) return RT3D_ERR_ARG;
+    if (!c->have_lstar) return fail(c, RT3D_ERR_STATE, "Lambda* not built");
+    if (!out || (ptr_kind != RT3D_HOST && ptr_kind != RT3D_DEVICE)) return fail(c, RT3D_ERR_ARG, "bad output");
+    HIP_TRY(c, hipMemcpyAsync(out, c->L, 27 * c->V * 8, kind_out(ptr_kind), c->stream), "copy Lambda*");
+    return sync(c);
+}
+
+int rt3d_os_step(rt3d_ctx *c, int inner_sweeps, double *max_rel_dJ_out)
+{
+    if (!c) return RT3D_ERR_ARG;
+    if (!c->have_medium) return fail(c, RT3D_ERR_STATE, "set the medium first");
+    if (inner_sweeps < 1) return fail(c, RT3D_ERR_ARG, "inner_sweeps must be >= 1");
+    int rc = ensure_lstar(c);
+    if (!rc) rc = run_fs(c, nullptr, true);
+    if (rc) return rc;
+    HIP_TRY(c, hipMemsetAsync(c->d_maxrel, 0, sizeof(unsigned long long), c->stream), "memset");
+    HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream), "memset");
+    // sweep 1 from dJ = 0; sweeps 2..M from the previous one; the last also updates J
+    const double *in = nullptr;
+    double *bufs[2] = {c->dJa, c->dJb};
+    for (int m = 0; m < inner_sweeps; ++m) {
+        const bool last = (m == inner_sweeps - 1);
+        double *out = last ? nullptr : bufs[m & 1];
+        rc = launch_jacobi(c, in, out, last);
+        if (rc) return rc;
+        in = out;
+    }
+    unsigned long long bits = 0;
+    int flag = 0;
+    HIP_TRY(c, hipMemcpyAsync(&bits, c->d_maxrel, sizeof(bits), hipMemcpyDeviceToHost, c->stream), "maxrel");
+    HIP_TRY(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream), "flag");
+    rc = sync(c);
+    if (rc) return rc;
+    c->outer_iters += 1;
+    c->inner_sweeps += inner_sweeps;
+    double cval;
+    std::memcpy(&cval, &bits, sizeof(cval));
+    if (flag) {
+        if (max_rel_dJ_out) *max_rel_dJ_out = NAN;
+        return fail(c, RT3D_ERR_NONFINITE, "NaN or Inf in dJ or J");
+    }
+    if (max_rel_dJ_out) *max_rel_dJ_out = cval;
+    return RT3D_OK;
+}
+
+int rt3d_solve_to_convergence(rt3d_ctx *c, double tol, int max_iter, int inner_sweeps, int *iters_out,
+                              double *final_rel_dJ_out)
+{
+    if (!c) return RT3D_ERR_ARG;
+    if (!(tol > 0.0) || max_iter < 1 || inner_sweeps < 1) return fail(c, RT3D_ERR_ARG, "bad tol/max_iter/inner_sweeps");
+    double cval = INFINITY;
+    int n = 0, rc = RT3D_OK;
+    while (n < max_iter) {
+        rc = rt3d_os_step(c, inner_sweeps, &cval);
+        ++n;
+        if (rc != RT3D_OK || cval < tol) break;
+    }
+    if (iters_out) *iters_out = n;
+    if (final_rel_dJ_out) *final_rel_dJ_out = cval;
+    if (rc != RT3D_OK) return rc;
+    return cval < tol ? RT3D_OK : fail(c, RT3D_ERR_NOT_CONVERGED, "max_iter reached");
+}
+
+int rt3d_get_emergent_top(rt3d_ctx *c, double *out, int ptr_kind)
+{
+    if (!c) return RT3D_ERR_ARG;
+    if (!c->have_fs) return fail(c, RT3D_ERR_STATE, "no formal solution yet");
+    if (!out || (ptr_kind != RT3D_HOST && ptr_kind != RT3D_DEVICE)) return fail(c, RT3D_ERR_ARG, "bad output");
+    const size_t n = size_t(c->A.n_dir / 2) * c->g.nx * c->g.ny;
+    HIP_TRY(c, hipMemcpyAsync(out, c->Iem, n * 8, kind_out(ptr_kind), c->stream), "copy emergent");
+    return sync(c);
+}
+
+int rt3d_set_timing(rt3d_ctx *c, int enable)
+{
+    if (!c || (enable != 0 && enable != 1)) return RT3D_ERR_ARG;
+    int rc = sync(c);
+    if (rc) return rc;
+    c->timing = enable != 0;
+    for (int k = 0; k < K_COUNT; ++k) {
+        c->kernel_ms[k] = 0.0;
+        c->kernel_launches[k] = 0;
+    }
+    return RT3D_OK;
+}
+
+int rt3d_get_stats(rt3d_ctx *c, char *buf, int buflen)
+{
+    if (!c || !buf || buflen < 2) return RT3D_ERR_ARG;
+    int rc = sync(c);
+    if (rc) return rc;
+    std::string s = "{";
+    char tmp[512];
+    std::snprintf(tmp, sizeof tmp,
+                  "\"nx\":%d,\"ny\":%d,\"nz\":%d,\"n_dir\":%d,\"precision\":\"%s\",\"outer_iters\":%ld,"
+                  "\"inner_sweeps\":%ld,\"device_bytes\":%zu,\"partial_plane_bytes\":%lld,"
+                  "\"sweep_workgroups\":%zu,\"mean_segments\":%.6f,\"timing\":%s,\"kernels\":{",
+                  c->g.nx, c->g.ny, c->g.nz, c->A.n_dir, c->precision == RT3D_FP64 ? "fp64" : "fp32_sweep",
+                  c->outer_iters, c->inner_sweeps, c->device_bytes,
+                  (long long)(c->plan.p_elems * (long long)c->real_size), c->plan.items.size(),
+                  c->plan.mean_segments, c->timing ? "true" : "false");
+    s += tmp;
+    for (int k = 0; k < K_COUNT; ++k) {
+        std::snprintf(tmp, sizeof tmp, "%s\"%s\":{\"launches\":%ld,\"total_ms\":%.6f}", k ? "," : "",
+                      kKernelNames[k], c->kernel_launches[k], c->kernel_ms[k]);
+        s += tmp;
+    }
+    s += "}}";
+    if (int(s.size()) + 1 > buflen) return fail(c, RT3D_ERR_ARG, "stats buffer too small");
+    std::memcpy(buf, s.c_str(), s.size() + 1);
+    return RT3D_OK;
+}
+
+}  // extern "C"

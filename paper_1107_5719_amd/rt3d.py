@@ -1,0 +1,334 @@
+"""Thin Python binding of the C ABI in ``include/rt3d.h`` (librt3d.so, HIP kernels for gfx950).
+
+Argument marshalling only: every step of the hot path runs in the library's kernels.  Host arrays
+are numpy float64; device arrays are torch float64 CUDA tensors (passed by ``data_ptr()``, with
+``torch.cuda.current_stream()`` as the context stream).  Every non-zero status raises
+:class:`Rt3dError` carrying the status and the library's message.
+
+The library must have been built (``python -m paper_1107_5719_amd.build``); importing this module
+raises if ``librt3d.so`` is missing.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librt3d.so")
+
+RT3D_OK = 0
+RT3D_ERR_ARG = -1
+RT3D_ERR_OOM = -2
+RT3D_ERR_HIP = -3
+RT3D_ERR_NOT_CONVERGED = -4
+RT3D_ERR_NONFINITE = -5
+RT3D_ERR_STATE = -6
+RT3D_HOST = 0
+RT3D_DEVICE = 1
+RT3D_FP64 = 0
+RT3D_FP32_SWEEP = 1
+
+EXPORTED = [
+    "rt3d_create", "rt3d_destroy", "rt3d_set_medium", "rt3d_set_J", "rt3d_get_J",
+    "rt3d_formal_solution", "rt3d_build_lstar", "rt3d_get_lstar", "rt3d_os_step",
+    "rt3d_solve_to_convergence", "rt3d_get_emergent_top", "rt3d_set_timing", "rt3d_get_stats",
+    "rt3d_status_str", "rt3d_last_error", "rt3d_quadrature", "rt3d_segment_table", "rt3d_validate",
+]
+
+
+class Rt3dError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"rt3d status {status}: {message}")
+        self.status = status
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("n_theta", C.c_int),
+                ("n_phi", C.c_int), ("I_top", C.c_double), ("bottom_bc", C.c_int)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1107_5719_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+_vp, _i, _d = C.c_void_p, C.c_int, C.c_double
+_sig = {
+    "rt3d_create": (_i, [C.POINTER(_vp), C.POINTER(GridDesc), _i, _vp]),
+    "rt3d_destroy": (None, [_vp]),
+    "rt3d_set_medium": (_i, [_vp, _vp, _vp, _vp, _i]),
+    "rt3d_set_J": (_i, [_vp, _vp, _i]),
+    "rt3d_get_J": (_i, [_vp, _vp, _i]),
+    "rt3d_formal_solution": (_i, [_vp, _vp, _vp, _i]),
+    "rt3d_build_lstar": (_i, [_vp]),
+    "rt3d_get_lstar": (_i, [_vp, _vp, _i]),
+    "rt3d_os_step": (_i, [_vp, _i, C.POINTER(_d)]),
+    "rt3d_solve_to_convergence": (_i, [_vp, _d, _i, _i, C.POINTER(_i), C.POINTER(_d)]),
+    "rt3d_get_emergent_top": (_i, [_vp, _vp, _i]),
+    "rt3d_set_timing": (_i, [_vp, _i]),
+    "rt3d_get_stats": (_i, [_vp, C.c_char_p, _i]),
+    "rt3d_status_str": (C.c_char_p, [_i]),
+    "rt3d_last_error": (C.c_char_p, [_vp]),
+    "rt3d_quadrature": (_i, [_i, _i, _vp, _vp, _vp, _vp]),
+    "rt3d_segment_table": (_i, [C.POINTER(GridDesc), _i, _i, _vp, _vp, _vp, _i]),
+    "rt3d_validate": (_i, [C.POINTER(GridDesc), _vp, _vp, _vp]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def library():
+    """The loaded ctypes library (for tests that check the exported symbols)."""
+    return _lib
+
+
+def _raise(ctx, status: int, what: str):
+    if status == RT3D_OK:
+        return status
+    msg = ""
+    if ctx:
+        m = _lib.rt3d_last_error(ctx)
+        msg = m.decode() if m else ""
+    if not msg:
+        msg = _lib.rt3d_status_str(status).decode()
+    raise Rt3dError(status, f"{what}: {msg}")
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _arg(x, n=None, writable=False):
+    """Return (pointer, ptr_kind, keepalive) for a numpy array or a torch CUDA tensor."""
+    if x is None:
+        return None, RT3D_HOST, None
+    if _is_torch(x):
+        import torch
+
+        if not x.is_cuda or x.dtype != torch.float64 or not x.is_contiguous():
+            raise ValueError("device arrays must be contiguous float64 CUDA tensors")
+        if n is not None and x.numel() != n:
+            raise ValueError(f"expected {n} elements, got {x.numel()}")
+        return C.c_void_p(x.data_ptr()), RT3D_DEVICE, x
+    if writable:
+        if not (isinstance(x, np.ndarray) and x.dtype == np.float64 and x.flags.c_contiguous):
+            raise ValueError("host outputs must be C-contiguous float64 numpy arrays")
+        a = x
+    else:
+        a = np.ascontiguousarray(x, dtype=np.float64)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} elements, got {a.size}")
+    return a.ctypes.data_as(C.c_void_p), RT3D_HOST, a
+
+
+def _desc(nx, ny, nz, n_theta, n_phi, I_top=0.0, bottom_bc=0):
+    return GridDesc(int(nx), int(ny), int(nz), int(n_theta), int(n_phi), float(I_top), int(bottom_bc))
+
+
+# ---- functions with the C names -------------------------------------------------------------------
+
+def rt3d_create(desc: GridDesc, precision: int = RT3D_FP64, stream=None):
+    """Returns an opaque context handle (c_void_p).  stream: a hipStream_t as int, or None for the
+    current torch stream when torch is initialised on a GPU, else the default stream."""
+    if stream is None:
+        stream = 0
+        try:
+            import torch
+
+            if torch.cuda.is_available():
+                stream = torch.cuda.current_stream().cuda_stream
+        except ImportError:
+            pass
+    ctx = C.c_void_p()
+    st = _lib.rt3d_create(C.byref(ctx), C.byref(desc), int(precision), C.c_void_p(stream))
+    _raise(None, st, "rt3d_create")
+    return ctx
+
+
+def rt3d_destroy(ctx):
+    _lib.rt3d_destroy(ctx)
+
+
+def rt3d_set_medium(ctx, chi, eps, B):
+    kinds = []
+    ptrs = []
+    keep = []
+    for a in (chi, eps, B):
+        p, k, h = _arg(a)
+        ptrs.append(p)
+        kinds.append(k)
+        keep.append(h)
+    if len(set(kinds)) != 1:
+        raise ValueError("chi, eps and B must all be host arrays or all device tensors")
+    return _raise(ctx, _lib.rt3d_set_medium(ctx, *ptrs, kinds[0]), "rt3d_set_medium")
+
+
+def rt3d_set_J(ctx, J):
+    p, k, h = _arg(J)
+    return _raise(ctx, _lib.rt3d_set_J(ctx, p, k), "rt3d_set_J")
+
+
+def rt3d_get_J(ctx, out):
+    p, k, h = _arg(out, writable=True)
+    return _raise(ctx, _lib.rt3d_get_J(ctx, p, k), "rt3d_get_J")
+
+
+def rt3d_formal_solution(ctx, S, out):
+    """S: None (S from the current J) or an array of the same kind as out."""
+    po, ko, ho = _arg(out, writable=True)
+    ps, ks, hs = _arg(S)
+    if S is not None and ks != ko:
+        raise ValueError("S and out must live in the same memory")
+    return _raise(ctx, _lib.rt3d_formal_solution(ctx, ps, po, ko), "rt3d_formal_solution")
+
+
+def rt3d_build_lstar(ctx):
+    return _raise(ctx, _lib.rt3d_build_lstar(ctx), "rt3d_build_lstar")
+
+
+def rt3d_get_lstar(ctx, out):
+    p, k, h = _arg(out, writable=True)
+    return _raise(ctx, _lib.rt3d_get_lstar(ctx, p, k), "rt3d_get_lstar")
+
+
+def rt3d_os_step(ctx, inner_sweeps: int):
+    """Returns max |dJ|/|J| of the step."""
+    c = C.c_double(0.0)
+    _raise(ctx, _lib.rt3d_os_step(ctx, int(inner_sweeps), C.byref(c)), "rt3d_os_step")
+    return c.value
+
+
+def rt3d_solve_to_convergence(ctx, tol: float, max_iter: int, inner_sweeps: int, check=True):
+    """Returns (status, iterations, last max |dJ|/|J|); raises on any error except
+    RT3D_ERR_NOT_CONVERGED unless check is False."""
+    it = C.c_int(0)
+    c = C.c_double(0.0)
+    st = _lib.rt3d_solve_to_convergence(ctx, float(tol), int(max_iter), int(inner_sweeps),
+                                        C.byref(it), C.byref(c))
+    if check and st not in (RT3D_OK, RT3D_ERR_NOT_CONVERGED):
+        _raise(ctx, st, "rt3d_solve_to_convergence")
+    return st, it.value, c.value
+
+
+def rt3d_get_emergent_top(ctx, out):
+    p, k, h = _arg(out, writable=True)
+    return _raise(ctx, _lib.rt3d_get_emergent_top(ctx, p, k), "rt3d_get_emergent_top")
+
+
+def rt3d_set_timing(ctx, enable: bool):
+    return _raise(ctx, _lib.rt3d_set_timing(ctx, 1 if enable else 0), "rt3d_set_timing")
+
+
+def rt3d_get_stats(ctx) -> dict:
+    buf = C.create_string_buffer(8192)
+    _raise(ctx, _lib.rt3d_get_stats(ctx, buf, len(buf)), "rt3d_get_stats")
+    return json.loads(buf.value.decode())
+
+
+def rt3d_status_str(status: int) -> str:
+    return _lib.rt3d_status_str(int(status)).decode()
+
+
+def rt3d_last_error(ctx) -> str:
+    m = _lib.rt3d_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def rt3d_quadrature(n_theta: int, n_phi: int):
+    nd = n_theta * n_phi
+    mu, ox, oy, w = (np.zeros(nd) for _ in range(4))
+    st = _lib.rt3d_quadrature(int(n_theta), int(n_phi), *(a.ctypes.data_as(_vp) for a in (mu, ox, oy, w)))
+    _raise(None, st, "rt3d_quadrature")
+    return mu, ox, oy, w
+
+
+def rt3d_segment_table(desc: GridDesc, d: int, k: int, max_seg: int = 128):
+    di = np.zeros(max_seg, dtype=np.int32)
+    dj = np.zeros(max_seg, dtype=np.int32)
+    ln = np.zeros(max_seg)
+    n = _lib.rt3d_segment_table(C.byref(desc), int(d), int(k), di.ctypes.data_as(_vp),
+                                dj.ctypes.data_as(_vp), ln.ctypes.data_as(_vp), int(max_seg))
+    if n < 0:
+        _raise(None, n, "rt3d_segment_table")
+    return di[:n].copy(), dj[:n].copy(), ln[:n].copy()
+
+
+def rt3d_validate(desc: GridDesc, chi=None, eps=None, B=None) -> int:
+    args = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (chi, eps, B)]
+    ptrs = [None if a is None else a.ctypes.data_as(_vp) for a in args]
+    return _lib.rt3d_validate(C.byref(desc), *ptrs)
+
+
+# ---- convenience wrapper ----------------------------------------------------------------------------
+
+class Solver:
+    """Owns one context; methods map one-to-one onto the C calls."""
+
+    def __init__(self, nx, ny, nz, n_theta, n_phi, I_top=0.0, bottom_bc=0, precision=RT3D_FP64,
+                 stream=None):
+        self.desc = _desc(nx, ny, nz, n_theta, n_phi, I_top, bottom_bc)
+        self.shape = (nz, ny, nx)
+        self.n_dir = n_theta * n_phi
+        self.ctx = rt3d_create(self.desc, precision, stream)
+
+    def close(self):
+        if self.ctx:
+            rt3d_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_medium(self, chi, eps, B):
+        rt3d_set_medium(self.ctx, chi, eps, B)
+
+    def set_J(self, J):
+        rt3d_set_J(self.ctx, J)
+
+    def get_J(self, out=None):
+        out = np.zeros(self.shape) if out is None else out
+        rt3d_get_J(self.ctx, out)
+        return out
+
+    def formal_solution(self, S=None, out=None):
+        out = np.zeros(self.shape) if out is None else out
+        rt3d_formal_solution(self.ctx, S, out)
+        return out
+
+    def build_lstar(self):
+        rt3d_build_lstar(self.ctx)
+
+    def get_lstar(self, out=None):
+        out = np.zeros((27,) + self.shape) if out is None else out
+        rt3d_get_lstar(self.ctx, out)
+        return out
+
+    def os_step(self, inner_sweeps):
+        return rt3d_os_step(self.ctx, inner_sweeps)
+
+    def solve(self, tol, max_iter, inner_sweeps):
+        return rt3d_solve_to_convergence(self.ctx, tol, max_iter, inner_sweeps)
+
+    def emergent_top(self, out=None):
+        out = np.zeros((self.n_dir // 2, self.shape[1], self.shape[2])) if out is None else out
+        rt3d_get_emergent_top(self.ctx, out)
+        return out
+
+    def set_timing(self, enable=True):
+        rt3d_set_timing(self.ctx, enable)
+
+    def stats(self):
+        return rt3d_get_stats(self.ctx)

@@ -1,0 +1,266 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle, element by element.
+
+Bar (FP64 path): |x_gpu - x_oracle| <= 1e-10 |x_oracle| (+ a tiny absolute floor for entries that
+are exactly zero), on J_fs, the top-plane intensities, Lambda*, every OS iterate, and the converged
+J.  The oracle never sees anything the GPU produced: both sides get the same seeded media.
+"""
+import numpy as np
+import pytest
+
+from paper_1107_5719_amd.inputs import WORKLOADS, make_medium, random_medium
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def R():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.zeros(1, device="cuda")
+    from paper_1107_5719_amd import rt3d
+
+    return rt3d
+
+
+def _close(a, b, rtol=RTOL, floor=1e-300):
+    err = np.abs(a - b)
+    lim = rtol * np.abs(b) + floor
+    bad = err > lim
+    assert not bad.any(), f"{bad.sum()} of {bad.size} off; worst rel {np.max(err / (np.abs(b) + floor)):.3e}"
+
+
+def _close_rows(L, L_ref, rtol=RTOL):
+    """Lambda* parity scaled per voxel row: |dL[o, v]| <= rtol * max_o' |L_ref[o', v]|.  Entries that
+    are exponentially small next to their row (thick voxels) carry the ~1e-14 rounding of the two
+    sides' independent segment lengths times chi, which is ~1e-10 of a 1e-70 entry; the row scale is
+    what enters the operator-splitting sum."""
+    scale = np.max(np.abs(L_ref), axis=0, keepdims=True)
+    err = np.abs(L - L_ref)
+    bad = err > rtol * scale + 1e-300
+    assert not bad.any(), f"{bad.sum()} of {bad.size} off; worst {np.max(err / (scale + 1e-300)):.3e}"
+
+
+def _medium_case(name):
+    if name in WORKLOADS:
+        w = WORKLOADS[name]
+        m = make_medium(w)
+        return m, w.n_theta, w.n_phi, w.I_top
+    raise KeyError(name)
+
+
+FS_CASES = [
+    # (shape (nz, ny, nx), n_theta, n_phi, seed, I_top, bottom_bc)
+    ((5, 5, 5), 8, 8, 1, 0.3, 0),
+    ((11, 7, 9), 16, 16, 2, 0.0, 0),     # non-cubic, odd sizes
+    ((3, 3, 3), 16, 16, 3, 0.7, 0),      # minimum grid: shallow lines wrap many times per layer
+    ((7, 5, 6), 8, 8, 4, 0.0, 1),        # zero light at the bottom
+    ((4, 40, 33), 16, 16, 5, 0.1, 0),    # several bands per direction and a ragged last band
+    ((6, 9, 131), 8, 8, 6, 0.0, 0),      # rows longer than two wavefronts
+]
+
+
+@pytest.mark.parametrize("case", FS_CASES, ids=[f"{c[0]}-{c[1]}x{c[2]}" for c in FS_CASES])
+def test_formal_solution_parity(R, orc, case):
+    shape, nt, nph, seed, I_top, bbc = case
+    nz, ny, nx = shape
+    m = random_medium(nx, ny, nz, seed=seed, chi_range=(1e-4, 1e2))
+    S = np.random.default_rng(seed).uniform(0.1, 3.0, shape)
+    J_orc, Iem_orc = orc.formal_solution(m["chi"], S, nt, nph, I_top=I_top,
+                                         I_bot=(m["B"][0] if bbc == 0 else None), want_emergent=True)
+    with R.Solver(nx, ny, nz, nt, nph, I_top=I_top, bottom_bc=bbc) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        J = s.formal_solution(S)
+        Iem = s.emergent_top()
+    _close(J, J_orc)
+    _close(Iem, Iem_orc)
+
+
+def test_formal_solution_source_from_J_and_device_pointers(R, orc):
+    import torch
+
+    nz, ny, nx = 6, 7, 8
+    m = random_medium(nx, ny, nz, seed=7)
+    J0 = np.random.default_rng(7).uniform(0.5, 2.0, (nz, ny, nx))
+    S = m["eps"] * m["B"] + (1 - m["eps"]) * J0
+    J_orc = orc.formal_solution(m["chi"], S, 8, 8, I_bot=m["B"][0])
+    dev = {k: torch.from_numpy(v).cuda() for k, v in m.items()}
+    with R.Solver(nx, ny, nz, 8, 8) as s:
+        s.set_medium(dev["chi"], dev["eps"], dev["B"])
+        s.set_J(torch.from_numpy(J0).cuda())
+        out = torch.zeros((nz, ny, nx), dtype=torch.float64, device="cuda")
+        s.formal_solution(None, out)
+        torch.cuda.synchronize()
+        _close(out.cpu().numpy(), J_orc)
+        _close(s.get_J(), J0, rtol=0.0, floor=0.0)
+
+
+LSTAR_CASES = [((5, 5, 5), 8, 8, 1), ((7, 5, 6), 16, 16, 2), ((3, 4, 3), 16, 16, 3), ((9, 12, 11), 8, 8, 4)]
+
+
+@pytest.mark.parametrize("case", LSTAR_CASES, ids=[str(c[0]) + f"-{c[1]}" for c in LSTAR_CASES])
+def test_lstar_parity(R, orc, case):
+    shape, nt, nph, seed = case
+    nz, ny, nx = shape
+    m = random_medium(nx, ny, nz, seed=seed, chi_range=(1e-3, 1e2))
+    L_orc = orc.lstar(m["chi"], nt, nph)
+    with R.Solver(nx, ny, nz, nt, nph) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        s.build_lstar()
+        L = s.get_lstar()
+    _close_rows(L, L_orc)
+
+
+def test_lstar_and_fs_parity_strat17(R, orc):
+    m, nt, nph, I_top = _medium_case("strat17")
+    nz, ny, nx = m["chi"].shape
+    L_orc = orc.lstar(m["chi"], nt, nph)
+    S = m["eps"] * m["B"] + (1 - m["eps"]) * m["B"]
+    J_orc = orc.formal_solution(m["chi"], S, nt, nph, I_top=I_top, I_bot=m["B"][0])
+    with R.Solver(nx, ny, nz, nt, nph, I_top=I_top) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        J = s.formal_solution(None)
+        s.build_lstar()
+        L = s.get_lstar()
+    _close(J, J_orc)
+    _close_rows(L, L_orc)
+
+
+@pytest.mark.parametrize("M", [1, 2, 7])
+def test_os_iterates_parity(R, orc, M):
+    """The same outer iteration on both sides: every iterate and every convergence measure."""
+    nz, ny, nx = 6, 5, 7
+    m = random_medium(nx, ny, nz, seed=11, chi_range=(1e-2, 1e2), eps_range=(1e-3, 1.0))
+    L = orc.lstar(m["chi"], 8, 8)
+    J_orc = m["B"].copy()
+    with R.Solver(nx, ny, nz, 8, 8, I_top=0.2) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        for it in range(6):
+            c = s.os_step(M)
+            J_orc, c_orc = orc.os_step(m["chi"], m["eps"], m["B"], L, J_orc, 8, 8, M=M, I_top=0.2)
+            _close(s.get_J(), J_orc)
+            assert abs(c - c_orc) <= 1e-6 * c_orc + 1e-14, (it, c, c_orc)
+
+
+def test_converged_equals_dense_solution(R, orc):
+    nz, ny, nx = 5, 5, 5
+    m = random_medium(nx, ny, nz, seed=12, chi_range=(1e-2, 1e1), eps_range=(1e-2, 1.0))
+    Jd = orc.dense_os_solution(m["chi"], m["eps"], m["B"], 8, 8, I_top=0.1)
+    with R.Solver(nx, ny, nz, 8, 8, I_top=0.1) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        st, it, c = s.solve(1e-14, 500, 50)
+        assert st == R.RT3D_OK
+        _close(s.get_J(), Jd)
+
+
+def test_solve_parity_strat17(R, orc):
+    """17^3 x 64 angles, eps = 1e-2, stop at max rel dJ < 1e-8: same iteration count and J."""
+    w = WORKLOADS["strat17"]
+    m = make_medium(w)
+    M = 20
+    J_orc, it_orc, c_orc, ok = orc.solve(m["chi"], m["eps"], m["B"], w.n_theta, w.n_phi, tol=w.tol,
+                                         max_iter=500, M=M, I_top=w.I_top)
+    assert ok
+    with R.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi, I_top=w.I_top) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        st, it, c = s.solve(w.tol, 500, M)
+        assert st == R.RT3D_OK
+        assert it == it_orc
+        _close(s.get_J(), J_orc)
+
+
+def test_fs_and_os_step_parity_grf65(R, orc):
+    """65^3 x 256 angles: J_fs, Lambda* and one OS step against the oracle."""
+    w = WORKLOADS["grf65"]
+    m = make_medium(w)
+    M = 4
+    S = m["eps"] * m["B"] + (1 - m["eps"]) * m["B"]
+    J_fs_orc = orc.formal_solution(m["chi"], S, w.n_theta, w.n_phi, I_top=w.I_top, I_bot=m["B"][0])
+    L_orc = orc.lstar(m["chi"], w.n_theta, w.n_phi)
+    J1_orc, c_orc = orc.os_step(m["chi"], m["eps"], m["B"], L_orc, m["B"], w.n_theta, w.n_phi, M=M,
+                                I_top=w.I_top)
+    with R.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi, I_top=w.I_top) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        _close(s.formal_solution(None), J_fs_orc)
+        s.build_lstar()
+        _close_rows(s.get_lstar(), L_orc)
+        c = s.os_step(M)
+        _close(s.get_J(), J1_orc)
+        assert abs(c - c_orc) <= 1e-8 * c_orc
+
+
+def test_fs_parity_strat129(R, orc):
+    """129^3 x 256 angles (the benchmark workload, launched exactly as the benchmark launches it):
+    every voxel of J_fs against the oracle."""
+    w = WORKLOADS["strat129"]
+    m = make_medium(w)
+    S = m["eps"] * m["B"] + (1 - m["eps"]) * m["B"]
+    J_orc = orc.formal_solution(m["chi"], S, w.n_theta, w.n_phi, I_top=w.I_top, I_bot=m["B"][0])
+    with R.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi, I_top=w.I_top) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        J = s.formal_solution(None)
+    _close(J, J_orc)
+
+
+def test_error_paths(R):
+    import torch
+
+    nz, ny, nx = 4, 4, 4
+    m = random_medium(nx, ny, nz, seed=13)
+    with R.Solver(nx, ny, nz, 8, 8) as s:
+        with pytest.raises(R.Rt3dError) as e:
+            s.formal_solution(None)
+        assert e.value.status == R.RT3D_ERR_STATE
+        with pytest.raises(R.Rt3dError) as e:
+            s.get_lstar()
+        assert e.value.status == R.RT3D_ERR_STATE
+        bad = m["chi"].copy()
+        bad[1, 2, 3] = np.nan
+        with pytest.raises(R.Rt3dError) as e:
+            s.set_medium(bad, m["eps"], m["B"])
+        assert e.value.status == R.RT3D_ERR_ARG
+        dev = {k: torch.from_numpy(v).cuda() for k, v in m.items()}
+        dev_bad_eps = dev["eps"].clone()
+        dev_bad_eps[0, 0, 0] = 0.0
+        with pytest.raises(R.Rt3dError) as e:
+            s.set_medium(dev["chi"], dev_bad_eps, dev["B"])
+        assert e.value.status == R.RT3D_ERR_ARG
+        s.set_medium(dev["chi"], dev["eps"], dev["B"])
+        with pytest.raises(R.Rt3dError) as e:
+            s.os_step(0)
+        assert e.value.status == R.RT3D_ERR_ARG
+        st, it, c = s.solve(1e-30, 2, 3)
+        assert st == R.RT3D_ERR_NOT_CONVERGED and it == 2 and np.isfinite(c)
+        Jbad = np.ones((nz, ny, nx))
+        Jbad[0, 1, 1] = np.inf
+        with pytest.raises(R.Rt3dError) as e:
+            s.set_J(Jbad)
+        assert e.value.status == R.RT3D_ERR_ARG
+
+
+def test_determinism_and_resume(R):
+    """Two runs are bitwise identical, and 3 + 3 steps through get_J / set_J in a fresh context equal
+    6 straight steps bitwise (the kernels use no atomics in any floating-point sum)."""
+    w = WORKLOADS["strat17"]
+    m = make_medium(w)
+    runs = []
+    for _ in range(2):
+        with R.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi) as s:
+            s.set_medium(m["chi"], m["eps"], m["B"])
+            for _ in range(6):
+                s.os_step(5)
+            runs.append(s.get_J())
+    assert np.array_equal(runs[0], runs[1])
+    with R.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        for _ in range(3):
+            s.os_step(5)
+        J3 = s.get_J()
+    with R.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        s.set_J(J3)
+        for _ in range(3):
+            s.os_step(5)
+        assert np.array_equal(s.get_J(), runs[0])
