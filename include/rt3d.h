@@ -123,6 +123,17 @@ int rt3d_os_step(rt3d_ctx *ctx, int inner_sweeps, double *max_rel_dJ_out);
 int rt3d_solve_to_convergence(rt3d_ctx *ctx, double tol, int max_iter, int inner_sweeps,
                               int *iters_out, double *final_rel_dJ_out);
 
+/* Ng acceleration of rt3d_solve_to_convergence (the paper names Ng acceleration among the host-side
+ * parts of the method, section "Method"): after every OS step the iterate joins a history that
+ * restarts at each extrapolation; once it holds ng_every steps, the newest ng_order + 2 iterates
+ * x_n, x_{n-1}, ... are replaced by (1 - sum a_i) x_n + sum_i a_i x_{n-i}, where a minimises
+ * sum_v (delta_0 - sum_i a_i (delta_0 - delta_i))_v^2 / x_n,v^2 with delta_i = x_{n-i} - x_{n-i-1}.
+ * ng_order 0 switches it off (the default); 1 <= ng_order <= 3 needs ng_every >= ng_order + 1.
+ * Dot products are reduced in a fixed order, so runs stay bitwise reproducible.  Allocates
+ * (ng_order + 2) history vectors of V float64 on the device.
+ * Errors: RT3D_ERR_ARG, RT3D_ERR_OOM, RT3D_ERR_HIP. */
+int rt3d_set_acceleration(rt3d_ctx *ctx, int ng_order, int ng_every);
+
 /* Top-plane intensities of the upward lines from the last formal solution, [n_theta/2 * n_phi][ny][nx]
  * in direction order (the upward directions are d = n_dir/2 .. n_dir-1); entry (j,i) belongs to the
  * line through (i+1/2, j+1/2, nz).  Errors: RT3D_ERR_STATE (no FS yet), RT3D_ERR_ARG, RT3D_ERR_HIP. */

@@ -60,6 +60,9 @@ def lib():
                                   C.POINTER(C.c_double), C.c_void_p, i]
         L.orc_solve.argtypes = [i, i, i, i, i, _dp, _dp, _dp, d, i, C.c_void_p, _dp, d, i, i,
                                 C.POINTER(C.c_int), C.POINTER(C.c_double), i]
+        L.orc_solve_ng.argtypes = [i, i, i, i, i, _dp, _dp, _dp, d, i, C.c_void_p, _dp, d, i, i, i, i,
+                                   C.POINTER(C.c_int), C.POINTER(C.c_double), i]
+        L.orc_ng_extrapolate.argtypes = [C.c_long, i, _dp, i, _dp]
         L.orc_pp1d.argtypes = [i, i, _dp, _dp, d, d, _dp]
         _lib = L
     return _lib
@@ -185,6 +188,31 @@ def solve(chi, eps, B, n_theta, n_phi, tol, max_iter, M, J0=None, Lstar=None, I_
                                 int(bottom_from_B), _ptr(Ls), J, float(tol), int(max_iter), int(M),
                                 C.byref(it), C.byref(c), n_threads), "solve")
     return J, it.value, c.value, rc == 0
+
+
+def solve_ng(chi, eps, B, n_theta, n_phi, tol, max_iter, M, ng_order, ng_every, J0=None, Lstar=None,
+             I_top=0.0, bottom_from_B=True, n_threads=0):
+    """Outer OS iteration with Ng acceleration (order 1..3 every ng_every steps; 0 = plain).
+    Returns (J, iters, c, converged)."""
+    chi, eps, B = _f64(chi), _f64(eps), _f64(B)
+    nz, ny, nx = chi.shape
+    J = (B if J0 is None else _f64(J0)).copy()
+    Ls = None if Lstar is None else _f64(Lstar)
+    it = C.c_int(0)
+    c = C.c_double(0.0)
+    rc = _check(lib().orc_solve_ng(nx, ny, nz, n_theta, n_phi, chi, eps, B, float(I_top),
+                                   int(bottom_from_B), _ptr(Ls), J, float(tol), int(max_iter), int(M),
+                                   int(ng_order), int(ng_every), C.byref(it), C.byref(c), n_threads),
+                "solve_ng")
+    return J, it.value, c.value, rc == 0
+
+
+def ng_extrapolate(hist, order):
+    """Ng extrapolation of the iterates hist[0..m] (oldest first).  Returns (x, ok)."""
+    h = _f64(np.stack([np.ravel(x) for x in hist]))
+    out = np.zeros(h.shape[1])
+    rc = _check(lib().orc_ng_extrapolate(h.shape[1], int(order), h, h.shape[0] - 1, out), "ng")
+    return out.reshape(np.shape(hist[0])), rc == 0
 
 
 def pp1d(dtau, S, n_theta, I_top=0.0, I_bot=0.0):

@@ -548,6 +548,125 @@ int orc_os_step(int nx, int ny, int nz, int n_theta, int n_phi, const double *ch
     return rc;
 }
 
+/* Ng acceleration of the outer iteration (named among the host-side parts of the method in the
+ * "Method" section; the paper does not spell it out -- this is Ng's least-squares extrapolation).
+ * hist[0..m] are the m+1 newest iterates, hist[m] the newest.  With delta_i = x_{n-i} - x_{n-i-1}
+ * and Q_i = delta_0 - delta_i (i = 1..order), the coefficients a minimise
+ * sum_v w_v (delta_0 - sum_i a_i Q_i)_v^2 with w = 1 / x_n^2, and the new iterate is
+ * (1 - sum a_i) x_n + sum_i a_i x_{n-i}.  Returns 0 on success, 1 if the normal equations are
+ * singular (the caller then keeps x_n). */
+static int ng_extrapolate(long V, int order, double *const *hist, int m, double *out)
+{
+    double A[3][3] = {{0}}, b[3] = {0}, a[3] = {0};
+    const double *x0 = hist[m];
+    for (long v = 0; v < V; ++v) {
+        double w = 1.0 / (x0[v] * x0[v]);
+        double d0 = hist[m][v] - hist[m - 1][v];
+        double Q[3];
+        for (int i = 1; i <= order; ++i) Q[i - 1] = d0 - (hist[m - i][v] - hist[m - i - 1][v]);
+        for (int i = 0; i < order; ++i) {
+            b[i] += w * d0 * Q[i];
+            for (int j = 0; j < order; ++j) A[i][j] += w * Q[i] * Q[j];
+        }
+    }
+    /* Gaussian elimination with partial pivoting on the order x order system */
+    int n = order;
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r) if (fabs(A[r][c]) > fabs(A[p][c])) p = r;
+        if (!(fabs(A[p][c]) > 0.0)) return 1;
+        if (p != c) {
+            for (int q = 0; q < n; ++q) { double t = A[c][q]; A[c][q] = A[p][q]; A[p][q] = t; }
+            double t = b[c]; b[c] = b[p]; b[p] = t;
+        }
+        for (int r = c + 1; r < n; ++r) {
+            double f = A[r][c] / A[c][c];
+            for (int q = c; q < n; ++q) A[r][q] -= f * A[c][q];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int c = n - 1; c >= 0; --c) {
+        double t = b[c];
+        for (int q = c + 1; q < n; ++q) t -= A[c][q] * a[q];
+        a[c] = t / A[c][c];
+    }
+    double sa = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (!isfinite(a[i])) return 1;
+        sa += a[i];
+    }
+    for (long v = 0; v < V; ++v) {
+        double x = (1.0 - sa) * x0[v];
+        for (int i = 1; i <= n; ++i) x += a[i - 1] * hist[m - i][v];
+        out[v] = x;
+    }
+    return 0;
+}
+
+/* Exported for the Ng pins: hist is [m+1][V] (oldest first); writes the extrapolated iterate. */
+int orc_ng_extrapolate(long V, int order, const double *hist_flat, int m, double *out)
+{
+    if (order < 1 || order > 3 || m < order + 1) return ORC_EARG;
+    double *ptrs[8];
+    if (m >= 8) return ORC_EARG;
+    for (int q = 0; q <= m; ++q) ptrs[q] = (double *)(hist_flat + (size_t)q * V);
+    return ng_extrapolate(V, order, ptrs, m, out);
+}
+
+/* Outer OS iteration with optional Ng acceleration: after every OS step the iterate joins a history
+ * that restarts at each extrapolation; once it holds ng_every >= ng_order + 1 steps the newest
+ * iterates are extrapolated (ng_order 1..3; 0 = plain iteration).  The convergence test uses c of
+ * the OS step that was just taken. */
+int orc_solve_ng(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi,
+                 const double *eps, const double *B, double I_top, int bottom_from_B,
+                 const double *Lstar, double *J, double tol, int max_iter, int M, int ng_order,
+                 int ng_every, int *iters, double *c_out, int n_threads)
+{
+    if (ng_order < 0 || ng_order > 3 || (ng_order > 0 && ng_every < ng_order + 1)) return ORC_EARG;
+    const long V = (long)nx * ny * nz;
+    double *Lown = NULL;
+    if (!Lstar) {
+        Lown = (double *)malloc(sizeof(double) * 27 * V);
+        if (!Lown) return ORC_ENOMEM;
+        int rc = orc_lstar(nx, ny, nz, n_theta, n_phi, chi, Lown, n_threads);
+        if (rc) { free(Lown); return rc; }
+        Lstar = Lown;
+    }
+    const int cap = ng_order > 0 ? ng_every + 1 : 0;
+    double **hist = NULL;
+    if (cap) {
+        hist = (double **)calloc(cap, sizeof(double *));
+        for (int q = 0; hist && q < cap; ++q) hist[q] = (double *)malloc(sizeof(double) * V);
+        if (!hist || !hist[cap - 1]) { free(Lown); return ORC_ENOMEM; }
+        memcpy(hist[0], J, sizeof(double) * V);
+    }
+    int nh = 1;
+    double c = INFINITY;
+    int n = 0, rc = ORC_OK;
+    while (n < max_iter) {
+        rc = orc_os_step(nx, ny, nz, n_theta, n_phi, chi, eps, B, I_top, bottom_from_B, Lstar, J, M,
+                         &c, NULL, n_threads);
+        ++n;
+        if (rc != ORC_OK || c < tol) break;
+        if (cap) {
+            memcpy(hist[nh], J, sizeof(double) * V);
+            ++nh;
+            if (nh - 1 >= ng_every) {
+                if (ng_extrapolate(V, ng_order, hist, nh - 1, J) == 0) { /* J extrapolated */ }
+                memcpy(hist[0], J, sizeof(double) * V);
+                nh = 1;
+            }
+        }
+    }
+    for (int q = 0; q < cap; ++q) free(hist[q]);
+    free(hist);
+    free(Lown);
+    if (iters) *iters = n;
+    if (c_out) *c_out = c;
+    if (rc != ORC_OK) return rc;
+    return (c < tol) ? ORC_OK : 1;
+}
+
 /* Outer OS iteration until c < tol (or max_iter steps).  J holds the initial guess on entry (the
  * usual start is J = B) and the last iterate on exit.  Lstar may be NULL: it is then built here.
  * Returns the number of steps in *iters and the last c in *c_out; the return code is 1 when

@@ -430,6 +430,89 @@ __global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel(JacobiArgs a)
     }
 }
 
+// ------------------------------------------------------------------------------------------------
+// Ng acceleration: weighted dot products (fixed-order two-level reduction) and the combination
+// ------------------------------------------------------------------------------------------------
+
+constexpr int kNgSums = 9;          // A00 A01 A02 A11 A12 A22 b0 b1 b2
+constexpr int kNgBlocks = 1024;
+constexpr int kNgThreads = 256;
+
+struct NgArgs {
+    long V;
+    int order;
+    const double *x[5];             // x[0] newest iterate, x[i] the i-th older one
+    double *partial;                // [kNgBlocks][kNgSums]
+};
+
+__global__ __launch_bounds__(kNgThreads) void ng_dots_kernel(NgArgs a)
+{
+    double acc[kNgSums];
+#pragma unroll
+    for (int q = 0; q < kNgSums; ++q) acc[q] = 0.0;
+    for (long v = long(blockIdx.x) * kNgThreads + threadIdx.x; v < a.V; v += long(kNgBlocks) * kNgThreads) {
+        const double x0 = a.x[0][v];
+        const double w = 1.0 / (x0 * x0);
+        const double d0 = x0 - a.x[1][v];
+        double Q[3] = {0.0, 0.0, 0.0};
+        for (int i = 1; i <= a.order; ++i) Q[i - 1] = d0 - (a.x[i][v] - a.x[i + 1][v]);
+        acc[0] += w * Q[0] * Q[0];
+        acc[1] += w * Q[0] * Q[1];
+        acc[2] += w * Q[0] * Q[2];
+        acc[3] += w * Q[1] * Q[1];
+        acc[4] += w * Q[1] * Q[2];
+        acc[5] += w * Q[2] * Q[2];
+        acc[6] += w * d0 * Q[0];
+        acc[7] += w * d0 * Q[1];
+        acc[8] += w * d0 * Q[2];
+    }
+    __shared__ double red[kNgSums][kNgThreads];
+#pragma unroll
+    for (int q = 0; q < kNgSums; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int h = kNgThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            for (int q = 0; q < kNgSums; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < kNgSums) a.partial[blockIdx.x * kNgSums + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// one block: sums the per-block partials in a fixed order
+__global__ __launch_bounds__(kNgThreads) void ng_sum_kernel(const double *partial, double *out)
+{
+    __shared__ double red[kNgSums][kNgThreads];
+    for (int q = 0; q < kNgSums; ++q) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < kNgBlocks; b += kNgThreads) s += partial[b * kNgSums + q];
+        red[q][threadIdx.x] = s;
+    }
+    __syncthreads();
+    for (int h = kNgThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            for (int q = 0; q < kNgSums; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < kNgSums) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+struct NgCombineArgs {
+    long V;
+    int order;
+    double c0, c[3];                // x_new = c0 x[0] + sum_i c[i-1] x[i]
+    const double *x[4];
+    double *out;
+};
+
+__global__ void ng_combine_kernel(NgCombineArgs a)
+{
+    long v = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= a.V) return;
+    double r = a.c0 * a.x[0][v];
+    for (int i = 1; i <= a.order; ++i) r += a.c[i - 1] * a.x[i][v];
+    a.out[v] = r;
+}
+
 // finiteness / range check of a device medium
 __global__ void check_medium_kernel(long V, const double *chi, const double *eps, const double *B,
                                     int *flag)
@@ -478,6 +561,10 @@ struct rt3d_ctx {
     WorkItem *items = nullptr;
     unsigned long long *d_maxrel = nullptr;
     int *d_flag = nullptr;
+    // Ng acceleration
+    int ng_order = 0, ng_every = 0;
+    double *ng_hist = nullptr;          // [ng_order + 2][V] ring of iterates
+    double *ng_partial = nullptr;       // [kNgBlocks * kNgSums + kNgSums]
     size_t device_bytes = 0;
     bool have_medium = false, have_lstar = false, have_fs = false;
     long outer_iters = 0, inner_sweeps = 0;
@@ -724,12 +811,75 @@ int launch_jacobi(rt3d_ctx *c, const double *dJ_in, double *dJ_out, bool update)
     return check_launch(c, "jacobi_kernel");
 }
 
+// Solve the order x order normal equations of Ng's method (Gaussian elimination, partial
+// pivoting).  Returns false when the system is singular or the result is not finite.
+bool ng_solve_small(int n, double A[3][3], double b[3], double a[3])
+{
+    for (int col = 0; col < n; ++col) {
+        int p = col;
+        for (int r = col + 1; r < n; ++r) if (std::fabs(A[r][col]) > std::fabs(A[p][col])) p = r;
+        if (!(std::fabs(A[p][col]) > 0.0)) return false;
+        if (p != col) {
+            for (int q = 0; q < n; ++q) std::swap(A[col][q], A[p][q]);
+            std::swap(b[col], b[p]);
+        }
+        for (int r = col + 1; r < n; ++r) {
+            const double f = A[r][col] / A[col][col];
+            for (int q = col; q < n; ++q) A[r][q] -= f * A[col][q];
+            b[r] -= f * b[col];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double t = b[r];
+        for (int q = r + 1; q < n; ++q) t -= A[r][q] * a[q];
+        a[r] = t / A[r][r];
+        if (!std::isfinite(a[r])) return false;
+    }
+    return true;
+}
+
+// Extrapolate J from the ring entries newest = index m (ring of ng_order + 2 vectors).
+int ng_step(rt3d_ctx *c, int m)
+{
+    const int R = c->ng_order + 2;
+    const long V = c->V;
+    NgArgs a;
+    a.V = V;
+    a.order = c->ng_order;
+    for (int i = 0; i < 5; ++i) a.x[i] = c->ng_hist + long((m - std::min(i, c->ng_order + 1) + 4 * R) % R) * V;
+    a.partial = c->ng_partial;
+    hipLaunchKernelGGL(ng_dots_kernel, dim3(kNgBlocks), dim3(kNgThreads), 0, c->stream, a);
+    int rc = check_launch(c, "ng_dots_kernel");
+    if (rc) return rc;
+    double *sums_dev = c->ng_partial + kNgBlocks * kNgSums;
+    hipLaunchKernelGGL(ng_sum_kernel, dim3(1), dim3(kNgThreads), 0, c->stream, c->ng_partial, sums_dev);
+    rc = check_launch(c, "ng_sum_kernel");
+    if (rc) return rc;
+    double sums[kNgSums];
+    HIP_TRY(c, hipMemcpyAsync(sums, sums_dev, sizeof(sums), hipMemcpyDeviceToHost, c->stream), "ng sums");
+    rc = sync(c);
+    if (rc) return rc;
+    double A[3][3] = {{sums[0], sums[1], sums[2]}, {sums[1], sums[3], sums[4]}, {sums[2], sums[4], sums[5]}};
+    double b[3] = {sums[6], sums[7], sums[8]}, coef[3] = {0, 0, 0};
+    if (!ng_solve_small(c->ng_order, A, b, coef)) return RT3D_OK;   // keep the plain iterate
+    NgCombineArgs k;
+    k.V = V;
+    k.order = c->ng_order;
+    double sa = 0.0;
+    for (int i = 0; i < c->ng_order; ++i) { k.c[i] = coef[i]; sa += coef[i]; }
+    k.c0 = 1.0 - sa;
+    for (int i = 0; i < 4; ++i) k.x[i] = c->ng_hist + long((m - std::min(i, c->ng_order) + 4 * R) % R) * V;
+    k.out = c->J;
+    hipLaunchKernelGGL(ng_combine_kernel, dim3((V + 255) / 256), dim3(256), 0, c->stream, k);
+    return check_launch(c, "ng_combine_kernel");
+}
+
 void free_all(rt3d_ctx *c)
 {
     void *ptrs[] = {c->chi, c->eps, c->B, c->J, c->Jfs, c->r, c->dJa, c->dJb, c->L, c->Acoef, c->Iem,
                     c->Sbuf, c->cs, c->P, c->seg_len, c->seg_len64, c->seg_off, c->seg_n, c->seg_a,
                     c->seg_bb, c->seg_bm, c->seg_ai, c->seg_bi, c->row_min, c->dirs, c->items,
-                    c->d_maxrel, c->d_flag};
+                    c->d_maxrel, c->d_flag, c->ng_hist, c->ng_partial};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (auto &p : c->pending) {
@@ -1036,15 +1186,54 @@ int rt3d_solve_to_convergence(rt3d_ctx *c, double tol, int max_iter, int inner_s
     if (!(tol > 0.0) || max_iter < 1 || inner_sweeps < 1) return fail(c, RT3D_ERR_ARG, "bad tol/max_iter/inner_sweeps");
     double cval = INFINITY;
     int n = 0, rc = RT3D_OK;
+    const int R = c->ng_order + 2;
+    const size_t vbytes = size_t(c->V) * sizeof(double);
+    int nh = 0;   // iterates in the Ng history since the last extrapolation (the start included)
+    if (c->ng_order > 0) {
+        HIP_TRY(c, hipMemcpyAsync(c->ng_hist, c->J, vbytes, hipMemcpyDeviceToDevice, c->stream), "ng hist");
+        nh = 1;
+    }
     while (n < max_iter) {
         rc = rt3d_os_step(c, inner_sweeps, &cval);
         ++n;
         if (rc != RT3D_OK || cval < tol) break;
+        if (c->ng_order > 0) {
+            HIP_TRY(c, hipMemcpyAsync(c->ng_hist + long(nh % R) * c->V, c->J, vbytes,
+                                      hipMemcpyDeviceToDevice, c->stream), "ng hist");
+            ++nh;
+            if (nh - 1 >= c->ng_every) {
+                rc = ng_step(c, (nh - 1) % R);
+                if (rc) break;
+                HIP_TRY(c, hipMemcpyAsync(c->ng_hist, c->J, vbytes, hipMemcpyDeviceToDevice, c->stream),
+                        "ng hist");
+                nh = 1;
+            }
+        }
     }
     if (iters_out) *iters_out = n;
     if (final_rel_dJ_out) *final_rel_dJ_out = cval;
     if (rc != RT3D_OK) return rc;
     return cval < tol ? RT3D_OK : fail(c, RT3D_ERR_NOT_CONVERGED, "max_iter reached");
+}
+
+int rt3d_set_acceleration(rt3d_ctx *c, int ng_order, int ng_every)
+{
+    if (!c) return RT3D_ERR_ARG;
+    if (ng_order < 0 || ng_order > 3 || (ng_order > 0 && ng_every < ng_order + 1))
+        return fail(c, RT3D_ERR_ARG, "ng_order must be 0..3 and ng_every >= ng_order + 1");
+    int rc = sync(c);
+    if (rc) return rc;
+    if (c->ng_hist) { hipFree(c->ng_hist); c->ng_hist = nullptr; }
+    if (c->ng_partial) { hipFree(c->ng_partial); c->ng_partial = nullptr; }
+    c->ng_order = 0;
+    c->ng_every = 0;
+    if (ng_order == 0) return RT3D_OK;
+    rc = dev_alloc(c, &c->ng_hist, size_t(ng_order + 2) * c->V);
+    if (!rc) rc = dev_alloc(c, &c->ng_partial, size_t(kNgBlocks) * kNgSums + kNgSums);
+    if (rc) return rc;
+    c->ng_order = ng_order;
+    c->ng_every = ng_every;
+    return RT3D_OK;
 }
 
 int rt3d_get_emergent_top(rt3d_ctx *c, double *out, int ptr_kind)

@@ -34,7 +34,7 @@ RT3D_FP32_SWEEP = 1
 EXPORTED = [
     "rt3d_create", "rt3d_destroy", "rt3d_set_medium", "rt3d_set_J", "rt3d_get_J",
     "rt3d_formal_solution", "rt3d_build_lstar", "rt3d_get_lstar", "rt3d_os_step",
-    "rt3d_solve_to_convergence", "rt3d_get_emergent_top", "rt3d_set_timing", "rt3d_get_stats",
+    "rt3d_solve_to_convergence", "rt3d_set_acceleration", "rt3d_get_emergent_top", "rt3d_set_timing", "rt3d_get_stats",
     "rt3d_status_str", "rt3d_last_error", "rt3d_quadrature", "rt3d_segment_table", "rt3d_validate",
 ]
 
@@ -66,6 +66,7 @@ _sig = {
     "rt3d_get_lstar": (_i, [_vp, _vp, _i]),
     "rt3d_os_step": (_i, [_vp, _i, C.POINTER(_d)]),
     "rt3d_solve_to_convergence": (_i, [_vp, _d, _i, _i, C.POINTER(_i), C.POINTER(_d)]),
+    "rt3d_set_acceleration": (_i, [_vp, _i, _i]),
     "rt3d_get_emergent_top": (_i, [_vp, _vp, _i]),
     "rt3d_set_timing": (_i, [_vp, _i]),
     "rt3d_get_stats": (_i, [_vp, C.c_char_p, _i]),
@@ -214,6 +215,11 @@ def rt3d_solve_to_convergence(ctx, tol: float, max_iter: int, inner_sweeps: int,
     return st, it.value, c.value
 
 
+def rt3d_set_acceleration(ctx, ng_order: int, ng_every: int):
+    return _raise(ctx, _lib.rt3d_set_acceleration(ctx, int(ng_order), int(ng_every)),
+                  "rt3d_set_acceleration")
+
+
 def rt3d_get_emergent_top(ctx, out):
     p, k, h = _arg(out, writable=True)
     return _raise(ctx, _lib.rt3d_get_emergent_top(ctx, p, k), "rt3d_get_emergent_top")
@@ -321,6 +327,9 @@ class Solver:
 
     def solve(self, tol, max_iter, inner_sweeps):
         return rt3d_solve_to_convergence(self.ctx, tol, max_iter, inner_sweeps)
+
+    def set_acceleration(self, ng_order, ng_every):
+        rt3d_set_acceleration(self.ctx, ng_order, ng_every)
 
     def emergent_top(self, out=None):
         out = np.zeros((self.n_dir // 2, self.shape[1], self.shape[2])) if out is None else out

@@ -1,0 +1,123 @@
+"""GPU checks of Ng acceleration and of the FP32-sweep form.
+
+Ng: the GPU's accelerated solve must follow the oracle's accelerated solve (independent code) step
+for step: same number of outer iterations and the same J to 1e-10.
+
+FP32 sweeps (chi, S, line intensities and per-direction deposits in float32; the angle sum, J,
+Lambda*, the OS solve and the convergence test in float64): J_fs and the top-plane intensities must
+match the FP64 oracle to 1e-5 relative, the bound stated for the reduced-precision form.  (Per
+segment the float32 arithmetic rounds at ~6e-8; attenuation damps what a line carries, so the error
+of a voxel average stays within a few hundred roundings even on 129-layer columns.)
+"""
+import numpy as np
+import pytest
+
+from paper_1107_5719_amd.inputs import WORKLOADS, make_medium, random_medium, stratified_profile
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.zeros(1, device="cuda")
+    from paper_1107_5719_amd import rt3d
+
+    return rt3d
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+@pytest.mark.parametrize("order,every", [(1, 3), (2, 5), (3, 6)])
+def test_ng_solve_parity(R, orc, order, every):
+    nz, ny, nx = 33, 5, 6
+    chi = np.broadcast_to(stratified_profile(nz, 300.0)[:, None, None], (nz, ny, nx)).copy()
+    chi *= np.exp(0.1 * np.random.default_rng(17).standard_normal(chi.shape))
+    eps = np.full(chi.shape, 1e-3)
+    B = np.ones(chi.shape)
+    M = 10
+    J_o, it_o, c_o, ok = orc.solve_ng(chi, eps, B, 8, 8, 1e-10, 2000, M, order, every)
+    assert ok
+    J_p, it_p, _, _ = orc.solve_ng(chi, eps, B, 8, 8, 1e-10, 2000, M, 0, 0)
+    assert it_o < it_p
+    with R.Solver(nx, ny, nz, 8, 8) as s:
+        s.set_medium(chi, eps, B)
+        s.set_acceleration(order, every)
+        st, it, c = s.solve(1e-10, 2000, M)
+        assert st == R.RT3D_OK
+        assert it == it_o
+        J = s.get_J()
+    assert _rel(J, J_o) < 1e-10
+
+
+def test_ng_argument_checks(R):
+    with R.Solver(4, 4, 4, 2, 4) as s:
+        for bad in ((4, 6), (2, 2), (-1, 3)):
+            with pytest.raises(R.Rt3dError) as e:
+                s.set_acceleration(*bad)
+            assert e.value.status == R.RT3D_ERR_ARG
+        s.set_acceleration(2, 3)
+        s.set_acceleration(0, 0)
+
+
+FP32_CASES = [((5, 5, 5), 8, 8, 1), ((11, 7, 9), 16, 16, 2), ((4, 40, 33), 16, 16, 5)]
+
+
+@pytest.mark.parametrize("case", FP32_CASES, ids=[str(c[0]) for c in FP32_CASES])
+def test_fp32_sweep_formal_solution(R, orc, case):
+    shape, nt, nph, seed = case
+    nz, ny, nx = shape
+    m = random_medium(nx, ny, nz, seed=seed, chi_range=(1e-4, 1e2))
+    S = np.random.default_rng(seed).uniform(0.1, 3.0, shape)
+    J_o, Iem_o = orc.formal_solution(m["chi"], S, nt, nph, I_top=0.2, I_bot=m["B"][0], want_emergent=True)
+    with R.Solver(nx, ny, nz, nt, nph, I_top=0.2, precision=R.RT3D_FP32_SWEEP) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        J = s.formal_solution(S)
+        Iem = s.emergent_top()
+    assert _rel(J, J_o) < 1e-5
+    assert _rel(Iem, Iem_o) < 1e-5
+
+
+@pytest.mark.parametrize("name", ["strat17", "grf65", "strat129"])
+def test_fp32_sweep_formal_solution_workloads(R, orc, name):
+    w = WORKLOADS[name]
+    m = make_medium(w)
+    S = m["eps"] * m["B"] + (1 - m["eps"]) * m["B"]
+    J_o = orc.formal_solution(m["chi"], S, w.n_theta, w.n_phi, I_top=w.I_top, I_bot=m["B"][0])
+    with R.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi, I_top=w.I_top, precision=R.RT3D_FP32_SWEEP) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        J = s.formal_solution(None)
+    err = _rel(J, J_o)
+    print(f"{name}: FP32-sweep J_fs max rel error vs FP64 oracle = {err:.3e}")
+    assert err < 1e-5
+
+
+def test_fp32_sweep_lstar_is_fp64(R, orc):
+    """Lambda* is built in float64 in both forms."""
+    m = random_medium(6, 5, 7, seed=3)
+    with R.Solver(6, 5, 7, 8, 8, precision=R.RT3D_FP32_SWEEP) as s32, R.Solver(6, 5, 7, 8, 8) as s64:
+        for s in (s32, s64):
+            s.set_medium(m["chi"], m["eps"], m["B"])
+            s.build_lstar()
+        assert np.array_equal(s32.get_lstar(), s64.get_lstar())
+
+
+def test_fp32_sweep_converged_error_strat17(R, orc):
+    """Converged J of the FP32-sweep form against the tightly converged FP64 oracle (eps = 1e-2):
+    the error stays at the float32 level."""
+    w = WORKLOADS["strat17"]
+    m = make_medium(w)
+    J_o, _, _, ok = orc.solve_ng(m["chi"], m["eps"], m["B"], w.n_theta, w.n_phi, 1e-13, 2000, 20, 2, 5)
+    assert ok
+    with R.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi, precision=R.RT3D_FP32_SWEEP) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        s.set_acceleration(2, 5)
+        st, it, c = s.solve(1e-6, 500, 20)
+        J = s.get_J()
+    err = _rel(J, J_o)
+    print(f"strat17 FP32-sweep converged J: {it} iterations, max rel error {err:.3e}")
+    assert err < 1e-5

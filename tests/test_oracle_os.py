@@ -120,3 +120,40 @@ def test_sqrt_eps_law_plane_parallel_limit(orc, eps0, bound):
         errs.append(abs((eps0 + (1 - eps0) * J[-1]) / np.sqrt(eps0) - 1))
     assert errs[0] > 2 * errs[1] > 4 * errs[2]
     assert errs[-1] < bound
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_ng_extrapolation_is_exact_for_geometric_modes(orc, order):
+    """Iterates whose error lies in at most `order` geometric modes, x_k = x* + sum_i c_i l_i^k v_i,
+    are extrapolated to x* exactly (the minimal-polynomial property behind Ng's method)."""
+    rng = np.random.default_rng(order)
+    V = 50
+    xs = rng.uniform(1.0, 2.0, V)
+    lam = [0.9, -0.5, 0.3][:order]
+    vecs = [rng.standard_normal(V) * 0.1 for _ in range(order)]
+    hist = [xs + sum(l ** k * v for l, v in zip(lam, vecs)) for k in range(order + 2)]
+    x, ok = orc.ng_extrapolate(hist, order)
+    assert ok
+    assert np.max(np.abs(x - xs)) < 1e-12
+    # one mode fewer than the order is also exact; more modes than the order is not
+    if order > 1:
+        hist2 = [xs + sum(l ** k * v for l, v in zip(lam, vecs)) + 0.7 ** k * (0.05 * vecs[0][::-1])
+                 for k in range(order + 2)]
+        x2, _ = orc.ng_extrapolate(hist2, order - 1)
+        assert np.max(np.abs(x2 - xs)) > 1e-6
+
+
+def test_ng_reaches_the_same_fixed_point_faster(orc):
+    nz = ny = nx = 5
+    chi = np.broadcast_to(stratified_profile(nz, 30.0)[:, None, None], (nz, ny, nx)).copy()
+    chi *= np.exp(0.1 * np.random.default_rng(6).standard_normal(chi.shape))
+    eps = np.full(chi.shape, 1e-3)
+    B = np.ones(chi.shape)
+    Jd = orc.dense_os_solution(chi, eps, B, 8, 8)
+    J0, it0, _, ok0 = orc.solve_ng(chi, eps, B, 8, 8, 1e-13, 5000, 10, 0, 0)
+    J2, it2, _, ok2 = orc.solve_ng(chi, eps, B, 8, 8, 1e-13, 5000, 10, 2, 5)
+    J3, it3, _, ok3 = orc.solve_ng(chi, eps, B, 8, 8, 1e-13, 5000, 10, 3, 6)
+    assert ok0 and ok2 and ok3
+    assert it2 < it0 and it3 < it0
+    for J in (J0, J2, J3):
+        assert np.max(np.abs(J / Jd - 1)) < 1e-9
