@@ -70,6 +70,11 @@ bool gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
     return true;
 }
 
+int mirror_x(int b, int n_phi)
+{
+    return (b < n_phi / 2) ? n_phi / 2 - 1 - b : 3 * n_phi / 2 - 1 - b;
+}
+
 bool make_angle_set(int n_theta, int n_phi, AngleSet &out)
 {
     if (n_theta < 2 || (n_theta % 2) != 0 || n_phi < 4 || (n_phi % 4) != 0) return false;
@@ -92,6 +97,15 @@ bool make_angle_set(int n_theta, int n_phi, AngleSet &out)
             out.ox[d] = sin_t * std::cos(phi);
             out.oy[d] = sin_t * std::sin(phi);
             out.w[d] = w[a] / (2.0 * n_phi);
+        }
+        // exact mirror symmetry x -> -x (phi -> pi - phi): the mirror of b is
+        // n_phi/2 - 1 - b for b < n_phi/2 and 3 n_phi/2 - 1 - b otherwise
+        for (int b = 0; b < n_phi; ++b) {
+            const int bm = mirror_x(b, n_phi);
+            if (bm > b) {
+                out.ox[a * n_phi + bm] = -out.ox[a * n_phi + b];
+                out.oy[a * n_phi + bm] = out.oy[a * n_phi + b];
+            }
         }
     }
     return true;
@@ -160,16 +174,16 @@ static int pos_mod(int a, int n)
     return r < 0 ? r + n : r;
 }
 
-bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int threads, int lines_per_thread,
-                      SweepPlan &P, std::string &err)
+bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int lines_per_wg, int target_seg_per_wg,
+                      size_t window_bytes_max, int elem_bytes, SweepPlan &P, std::string &err)
 {
     P = SweepPlan();
     P.nx = nx;
     P.ny = ny;
     P.nz = nz;
     P.n_dir = A.n_dir;
-    P.lines_per_wg = threads * lines_per_thread;
-    const int max_rows = P.lines_per_wg / nx;
+    P.lines_per_wg = lines_per_wg;
+    const int max_rows = lines_per_wg / nx;
     if (max_rows < 1) {
         err = "nx exceeds the lines one sweep workgroup can hold";
         return false;
@@ -178,18 +192,18 @@ bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int threads, in
     P.seg_n.assign(size_t(A.n_dir) * nz, 0);
     P.row_min.assign(size_t(A.n_dir) * nz, 0);
     P.dirs.resize(A.n_dir);
-    std::vector<double> dir_cost(A.n_dir, 0.0);
+    std::vector<int> span(A.n_dir, 0);
+    std::vector<double> seg_per_layer(A.n_dir, 0.0);
     LayerSegments L;
     long total_segments = 0;
     for (int d = 0; d < A.n_dir; ++d) {
-        int span_max = 0;
         long nseg = 0;
         for (int k = 0; k < nz; ++k) {
             layer_segments(nz, A.mu[d], A.ox[d], A.oy[d], k, L);
             const int n = int(L.di.size());
             const int bmin = *std::min_element(L.dj.begin(), L.dj.end());
             const int bmax = *std::max_element(L.dj.begin(), L.dj.end());
-            span_max = std::max(span_max, bmax - bmin);
+            span[d] = std::max(span[d], bmax - bmin);
             const size_t dk = size_t(d) * nz + k;
             P.seg_off[dk] = int(P.seg_a.size());
             P.seg_n[dk] = n;
@@ -206,45 +220,80 @@ bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int threads, in
             nseg += n;
         }
         total_segments += nseg;
-        const double seg_per_layer = double(nseg) / nz;
-        dir_cost[d] = seg_per_layer;
-        // Band height: aim at about 8 line-segments per thread and layer, never thinner than the
-        // window halo (span) so that at most a few bands overlap in a voxel row.
-        const double target = 8.0 * threads;
-        int rows = int(std::lround(target / (nx * seg_per_layer)));
-        rows = std::max(rows, std::max(1, span_max));
-        rows = std::min(rows, max_rows);
-        rows = std::min(rows, ny);
-        DirInfo &di = P.dirs[d];
-        di.wmu = A.w[d] * std::fabs(A.mu[d]);
-        di.down = A.mu[d] < 0.0 ? 1 : 0;
-        di.band_rows = rows;
-        di.n_bands = (ny + rows - 1) / rows;
-        di.win_rows = rows + span_max;
-        di.last_rows = ny - (di.n_bands - 1) * rows;
-        P.max_win_rows = std::max(P.max_win_rows, di.win_rows);
+        seg_per_layer[d] = double(nseg) / nz;
+        P.dirs[d].wmu = A.w[d] * std::fabs(A.mu[d]);
+        P.dirs[d].down = A.mu[d] < 0.0 ? 1 : 0;
+        P.dirs[d].pad = 0;
     }
     P.mean_segments = double(total_segments) / (double(A.n_dir) * nz);
-    // partial-plane offsets and work items
+    // pairs mirrored in x: the partner's tables must equal the owner's up to negated columns
+    for (int a = 0; a < A.n_theta; ++a) {
+        for (int b = 0; b < A.n_phi; ++b) {
+            const int bm = mirror_x(b, A.n_phi);
+            if (bm < b) continue;
+            const int dA = a * A.n_phi + b, dB = a * A.n_phi + bm;
+            for (int k = 0; k < nz; ++k) {
+                const size_t ka = size_t(dA) * nz + k, kb = size_t(dB) * nz + k;
+                if (P.seg_n[ka] != P.seg_n[kb] || P.row_min[ka] != P.row_min[kb]) {
+                    err = "mirrored directions do not share their segment structure";
+                    return false;
+                }
+                for (int s = 0; s < P.seg_n[ka]; ++s) {
+                    const int ia = P.seg_off[ka] + s, ib = P.seg_off[kb] + s;
+                    if (P.seg_ai[ia] != -P.seg_ai[ib] || P.seg_bi[ia] != P.seg_bi[ib] ||
+                        P.seg_len[ia] != P.seg_len[ib]) {
+                        err = "mirrored directions do not share their segment structure";
+                        return false;
+                    }
+                }
+            }
+            PairInfo pi{};
+            pi.wmu = P.dirs[dA].wmu;
+            pi.dA = dA;
+            pi.dB = dB;
+            pi.down = P.dirs[dA].down;
+            // Band height: about target_seg_per_wg line-segments per layer for the two directions,
+            // never thinner than the window's halo, within the line and LDS budgets.
+            int rows = int(std::lround(target_seg_per_wg / (2.0 * nx * seg_per_layer[dA])));
+            rows = std::max(rows, std::max(1, span[dA]));
+            rows = std::min(rows, max_rows);
+            while (rows > 1 && size_t(2) * (rows + span[dA]) * nx * elem_bytes > window_bytes_max) --rows;
+            rows = std::min(rows, ny);
+            if (size_t(2) * (rows + span[dA]) * nx * elem_bytes > window_bytes_max) {
+                err = "the deposit windows of one band exceed the LDS budget";
+                return false;
+            }
+            pi.band_rows = rows;
+            pi.n_bands = (ny + rows - 1) / rows;
+            pi.win_rows = rows + span[dA];
+            pi.last_rows = ny - (pi.n_bands - 1) * rows;
+            P.max_win_rows = std::max(P.max_win_rows, pi.win_rows);
+            P.pairs.push_back(pi);
+        }
+    }
+    P.n_pair = int(P.pairs.size());
     int64_t off = 0;
-    for (int d = 0; d < A.n_dir; ++d) {
-        DirInfo &di = P.dirs[d];
-        di.p_off = off;
-        off += int64_t(di.n_bands) * nz * di.win_rows * nx;
-        for (int b = 0; b < di.n_bands; ++b) {
+    std::vector<std::pair<double, WorkItem>> work;
+    for (int p = 0; p < P.n_pair; ++p) {
+        PairInfo &pi = P.pairs[p];
+        pi.p_off = off;
+        off += int64_t(pi.n_bands) * nz * pi.win_rows * nx;
+        for (int b = 0; b < pi.n_bands; ++b) {
             WorkItem it;
-            it.d = d;
+            it.pair = p;
             it.band = b;
-            it.j0 = b * di.band_rows;
-            it.rows = std::min(di.band_rows, ny - it.j0);
-            P.items.push_back(it);
+            it.j0 = b * pi.band_rows;
+            it.rows = std::min(pi.band_rows, ny - it.j0);
+            work.push_back({it.rows * seg_per_layer[pi.dA], it});
         }
     }
     P.p_elems = off;
     // dispatch the most expensive bands first
-    std::stable_sort(P.items.begin(), P.items.end(), [&](const WorkItem &a, const WorkItem &b) {
-        return a.rows * dir_cost[a.d] > b.rows * dir_cost[b.d];
-    });
+    std::stable_sort(work.begin(), work.end(),
+                     [](const std::pair<double, WorkItem> &x, const std::pair<double, WorkItem> &y) {
+                         return x.first > y.first;
+                     });
+    for (auto &w : work) P.items.push_back(w.second);
     return true;
 }
 

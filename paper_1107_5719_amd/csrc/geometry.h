@@ -26,25 +26,40 @@ struct LayerSegments {
 };
 void layer_segments(int nz, double mu, double ox, double oy, int k, LayerSegments &out);
 
-// Per-direction metadata used by the device kernels (plain old data, copied to the device).
+// Index of the azimuth mirrored in x (phi -> pi - phi).
+int mirror_x(int b, int n_phi);
+
+// Per-direction metadata (plain old data, copied to the device).
 struct DirInfo {
     double wmu;        // W_d * |mu_d|
     int down;          // 1 if mu < 0 (sweep from the top layer down)
+    int pad;
+};
+
+// A pair of directions mirrored in x, (mu, phi) and (mu, pi - phi).  Their lines cross the same
+// faces at the same heights: the segment lengths and row offsets are identical and the column
+// offsets are negated, so one workgroup sweeps both through the same band and one partial plane
+// holds both.  W |mu| is the same for both.
+struct PairInfo {
+    double wmu;        // W |mu| of either direction
+    int dA, dB;        // the two directions; dA owns the shared tables
+    int down;          // 1 if mu < 0
     int band_rows;     // Bj: line rows per band (last band may be shorter)
     int n_bands;       // nb
     int win_rows;      // Hw = Bj + span: rows of the deposit window of one band
     int last_rows;     // rows of the last band: ny - (nb - 1) * Bj
-    int64_t p_off;     // element offset of this direction's partial planes in P
+    int pad;
+    int64_t p_off;     // element offset of this pair's partial planes in P
 };
 
-// One workgroup of the sweep: direction d, band of line rows [j0, j0 + rows).
+// One workgroup of the sweep: direction pair p, band of line rows [j0, j0 + rows).
 struct WorkItem {
-    int d, band, j0, rows;
+    int pair, band, j0, rows;
 };
 
 struct SweepPlan {
-    int nx = 0, ny = 0, nz = 0, n_dir = 0;
-    int lines_per_wg = 0;                 // threads * lines per thread
+    int nx = 0, ny = 0, nz = 0, n_dir = 0, n_pair = 0;
+    int lines_per_wg = 0;                 // lines of one direction in one workgroup
     // segment tables, flat; index of (d, k) is d * nz + k
     std::vector<int> seg_off, seg_n;      // per (d, k)
     std::vector<int> seg_a;               // column offset modulo nx, in [0, nx)
@@ -54,6 +69,7 @@ struct SweepPlan {
     std::vector<double> seg_len;
     std::vector<int> row_min;             // per (d, k): minimum row offset modulo ny
     std::vector<DirInfo> dirs;
+    std::vector<PairInfo> pairs;
     std::vector<WorkItem> items;          // in dispatch order (most expensive first)
     int64_t p_elems = 0;                  // size of the partial-plane buffer P in elements
     int max_win_rows = 0;
@@ -61,8 +77,9 @@ struct SweepPlan {
     double mean_segments = 0.0;           // per voxel and angle
 };
 
-// Build segment tables and the band plan.  threads * lines_per_thread bounds the lines of one band.
-bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int threads, int lines_per_thread,
-                      SweepPlan &plan, std::string &err);
+// Build segment tables and the band plan.  lines_per_wg bounds the lines of one direction in one
+// band; window_bytes_max bounds the two LDS deposit windows of a band (element size elem_bytes).
+bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int lines_per_wg, int target_seg_per_wg,
+                      size_t window_bytes_max, int elem_bytes, SweepPlan &plan, std::string &err);
 
 }  // namespace rt3d

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -36,16 +37,60 @@ using rt3d::WorkItem;
 
 namespace {
 
-constexpr int kSweepThreads = 256;
-constexpr int kLinesPerThread = 8;
+// Sweep workgroup shapes (threads, lines per thread and direction); the context picks one.
+constexpr int kSweepThreadsA = 256, kLinesPerThreadA = 8;
+constexpr int kSweepThreadsB = 512, kLinesPerThreadB = 4;
+constexpr size_t kWindowBytes = 48 * 1024;   // LDS for the two deposit windows of a band
 constexpr int kPlaneThreads = 256;   // voxel-parallel kernels: one thread per voxel of a k-plane
 
 template <typename real> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
 
-__device__ inline double dev_expm1(double x) { return expm1(x); }
-__device__ inline float dev_expm1(float x) { return expm1f(x); }
+// e^x - 1 for x <= 0 (the argument is always -dtau).  Write x = k ln2 + r with |r| <= ln2/2; then
+// e^x - 1 = 2^k (e^r - 1) + (2^k - 1), and e^r - 1 is its Taylor series (through r^13 in float64,
+// truncation below 2e-17 relative; through r^8 in float32, below 1e-9).  ln2 is split into a high part
+// whose product with k is exact and a low part.  No range branches: x is clamped where e^x vanishes.
+__device__ inline double expm1_nonpos(double x)
+{
+    x = fmax(x, -708.0);
+    const double kf = rint(x * 1.4426950408889634);
+    double r = fma(-kf, 6.93147180369123816490e-01, x);
+    r = fma(-kf, 1.90821492927058770002e-10, r);
+    double p = 1.0 / 6227020800.0;
+    p = fma(p, r, 1.0 / 479001600.0);
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    const double two_k = ldexp(1.0, int(kf));
+    return fma(two_k, p * r, two_k - 1.0);
+}
+
+__device__ inline float expm1_nonpos(float x)
+{
+    x = fmaxf(x, -87.0f);
+    const float kf = rintf(x * 1.44269504089f);
+    float r = fmaf(-kf, 0.693145751953125f, x);
+    r = fmaf(-kf, 1.42860682e-06f, r);
+    float p = 1.0f / 40320.0f;
+    p = fmaf(p, r, 1.0f / 5040.0f);
+    p = fmaf(p, r, 1.0f / 720.0f);
+    p = fmaf(p, r, 1.0f / 120.0f);
+    p = fmaf(p, r, 1.0f / 24.0f);
+    p = fmaf(p, r, 1.0f / 6.0f);
+    p = fmaf(p, r, 0.5f);
+    p = fmaf(p, r, 1.0f);
+    const float two_k = ldexpf(1.0f, int(kf));
+    return fmaf(two_k, p * r, two_k - 1.0f);
+}
 
 // ------------------------------------------------------------------------------------------------
 // S update
@@ -73,7 +118,7 @@ struct SweepArgs {
     int nx, ny, nz, n_down;
     const int *seg_off, *seg_n, *seg_a, *seg_bb, *seg_bm, *row_min;
     const void *seg_len;          // real
-    const DirInfo *dirs;
+    const rt3d::PairInfo *pairs;
     const WorkItem *items;
     const void *cs;               // Vec2<real>
     const double *Ibot;           // [ny][nx] intensities at the bottom plane, or null (zero)
@@ -82,42 +127,47 @@ struct SweepArgs {
     double *Iem;                  // [n_up][ny][nx] or null
 };
 
-template <typename real, int LPT>
-__global__ __launch_bounds__(kSweepThreads) void sweep_kernel(SweepArgs a)
+// One workgroup sweeps the lines of one band for both directions of an x-mirrored pair.  Thread t
+// owns lines q = t + i*NT (i < LPT) of the band, for both directions.  Per layer and segment index s
+// the lines of one direction deposit into pairwise distinct cells of that direction's LDS window, so
+// each window is updated with a plain read-add-write and a barrier separates segment indices.
+template <typename real, int NT, int LPT>
+__global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs a)
 {
     using real2 = typename Vec2<real>::type;
     extern __shared__ unsigned char smem_raw[];
-    real *win = reinterpret_cast<real *>(smem_raw);
     const WorkItem it = a.items[blockIdx.x];
-    const DirInfo di = a.dirs[it.d];
+    const rt3d::PairInfo pi = a.pairs[it.pair];
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int nlines = it.rows * nx;
-    const int Hw = di.win_rows;
-    const int wsize = Hw * nx;
+    const int wsize = pi.win_rows * nx;
+    real *winA = reinterpret_cast<real *>(smem_raw);
+    real *winB = winA + wsize;
     const real *seg_len = static_cast<const real *>(a.seg_len);
     const real2 *cs = static_cast<const real2 *>(a.cs);
-    real *P = static_cast<real *>(a.P) + di.p_off + long(it.band) * nz * wsize;
+    real *P = static_cast<real *>(a.P) + pi.p_off + long(it.band) * nz * wsize;
 
-    for (int e = threadIdx.x; e < wsize; e += blockDim.x) win[e] = real(0);
+    for (int e = threadIdx.x; e < 2 * wsize; e += NT) winA[e] = real(0);
 
-    real I[LPT];
+    real IA[LPT], IB[LPT];
     int li[LPT], lj[LPT];
 #pragma unroll
     for (int t = 0; t < LPT; ++t) {
-        const int q = threadIdx.x + t * kSweepThreads;
+        const int q = threadIdx.x + t * NT;
         const int qq = q < nlines ? q : 0;
         lj[t] = qq / nx;
         li[t] = q < nlines ? qq - lj[t] * nx : -1;   // -1 marks an unused slot
-        I[t] = real(a.I_top);
+        IA[t] = real(a.I_top);
+        IB[t] = real(a.I_top);
     }
     __syncthreads();
 
     for (int step = 0; step < nz; ++step) {
-        const int k = di.down ? nz - 1 - step : step;
-        const int dk = it.d * nz + k;
-        const int off = a.seg_off[dk];
-        const int ns = a.seg_n[dk];
-        const int rmin = a.row_min[dk];
+        const int k = pi.down ? nz - 1 - step : step;
+        const int offA = a.seg_off[pi.dA * nz + k];
+        const int offB = a.seg_off[pi.dB * nz + k];
+        const int ns = a.seg_n[pi.dA * nz + k];
+        const int rmin = a.row_min[pi.dA * nz + k];
         const real2 *csk = cs + long(k) * nx * ny;
         int r0[LPT];
 #pragma unroll
@@ -127,59 +177,82 @@ __global__ __launch_bounds__(kSweepThreads) void sweep_kernel(SweepArgs a)
             r -= (r >= ny) ? ny : 0;
             r0[t] = r;
         }
-        if (!di.down && step == 0) {
+        if (!pi.down && step == 0) {
             // upward lines enter through the bottom plane: boundary light of the entry voxel
-            const int sa = a.seg_a[off], sm = a.seg_bm[off];
+            const int saA = a.seg_a[offA], saB = a.seg_a[offB], sm = a.seg_bm[offA];
 #pragma unroll
             for (int t = 0; t < LPT; ++t) {
                 if (li[t] < 0) continue;
-                int col = li[t] + sa;
-                col -= (col >= nx) ? nx : 0;
                 int row = r0[t] + sm;
                 row -= (row >= ny) ? ny : 0;
-                I[t] = a.Ibot ? real(a.Ibot[row * nx + col]) : real(0);
+                int cA = li[t] + saA, cB = li[t] + saB;
+                cA -= (cA >= nx) ? nx : 0;
+                cB -= (cB >= nx) ? nx : 0;
+                IA[t] = a.Ibot ? real(a.Ibot[row * nx + cA]) : real(0);
+                IB[t] = a.Ibot ? real(a.Ibot[row * nx + cB]) : real(0);
             }
         }
         for (int s = 0; s < ns; ++s) {
-            const int sa = a.seg_a[off + s];
-            const int sb = a.seg_bb[off + s];
-            const int sm = a.seg_bm[off + s];
-            const real len = seg_len[off + s];
-            real2 c[LPT];
-            int col[LPT];
+            const int saA = a.seg_a[offA + s];
+            const int saB = a.seg_a[offB + s];
+            const int sb = a.seg_bb[offA + s];
+            const int sm = a.seg_bm[offA + s];
+            const real len = seg_len[offA + s];
+            real2 cA[LPT], cB[LPT];
+            int colA[LPT], colB[LPT], grow[LPT];
 #pragma unroll
             for (int t = 0; t < LPT; ++t) {
-                int cc = li[t] + sa;
-                cc -= (cc >= nx) ? nx : 0;
                 int row = r0[t] + sm;
                 row -= (row >= ny) ? ny : 0;
-                col[t] = cc;
-                if (li[t] >= 0) c[t] = csk[row * nx + cc];
+                int ca = li[t] + saA, cb = li[t] + saB;
+                ca -= (ca >= nx) ? nx : 0;
+                cb -= (cb >= nx) ? nx : 0;
+                colA[t] = ca;
+                colB[t] = cb;
+                grow[t] = row * nx;
+                if (li[t] >= 0) {
+                    cA[t] = csk[grow[t] + ca];
+                    cB[t] = csk[grow[t] + cb];
+                }
             }
 #pragma unroll
             for (int t = 0; t < LPT; ++t) {
                 if (li[t] < 0) continue;
-                const real dtau = c[t].x * len;
-                const real em1 = dev_expm1(-dtau);          // e^{-dtau} - 1
-                const real dI = (I[t] - c[t].y) * em1;
-                const real D = c[t].y * dtau - dI;          // chi * integral of I over the segment
-                I[t] += dI;
-                win[(lj[t] + sb) * nx + col[t]] += D;
+                const int wrow = (lj[t] + sb) * nx;
+                {
+                    const real dtau = cA[t].x * len;
+                    const real em1 = expm1_nonpos(-dtau);          // e^{-dtau} - 1
+                    const real dI = (IA[t] - cA[t].y) * em1;
+                    IA[t] += dI;
+                    winA[wrow + colA[t]] += cA[t].y * dtau - dI;   // chi * integral of I
+                }
+                {
+                    const real dtau = cB[t].x * len;
+                    const real em1 = expm1_nonpos(-dtau);
+                    const real dI = (IB[t] - cB[t].y) * em1;
+                    IB[t] += dI;
+                    winB[wrow + colB[t]] += cB[t].y * dtau - dI;
+                }
             }
             __syncthreads();
         }
         real *Pk = P + long(k) * wsize;
-        for (int e = threadIdx.x; e < wsize; e += blockDim.x) {
-            Pk[e] = win[e];
-            win[e] = real(0);
+        for (int e = threadIdx.x; e < wsize; e += NT) {
+            Pk[e] = winA[e] + winB[e];
+            winA[e] = real(0);
+            winB[e] = real(0);
         }
         __syncthreads();
     }
-    if (!di.down && a.Iem) {
-        double *E = a.Iem + long(it.d - a.n_down) * nx * ny;
+    if (!pi.down && a.Iem) {
+        double *EA = a.Iem + long(pi.dA - a.n_down) * nx * ny;
+        double *EB = a.Iem + long(pi.dB - a.n_down) * nx * ny;
 #pragma unroll
-        for (int t = 0; t < LPT; ++t)
-            if (li[t] >= 0) E[(it.j0 + lj[t]) * nx + li[t]] = double(I[t]);
+        for (int t = 0; t < LPT; ++t) {
+            if (li[t] < 0) continue;
+            EA[(it.j0 + lj[t]) * nx + li[t]] = double(IA[t]);
+            EB[(it.j0 + lj[t]) * nx + li[t]] = double(IB[t]);
+        }
     }
 }
 
@@ -188,8 +261,8 @@ __global__ __launch_bounds__(kSweepThreads) void sweep_kernel(SweepArgs a)
 // ------------------------------------------------------------------------------------------------
 
 struct ReduceArgs {
-    int nx, ny, nz, n_dir;
-    const DirInfo *dirs;
+    int nx, ny, nz, n_pair;
+    const rt3d::PairInfo *pairs;
     const int *row_min;
     const void *P;            // real
     const double *chi;
@@ -198,6 +271,9 @@ struct ReduceArgs {
     double *r;                // may be null
 };
 
+// J_fs(v) = (1/chi_v) sum_pairs W|mu| sum over the bands whose deposit windows cover v.  The band of
+// voxel row j at layer k is found from the row's offset to the layer's window origin; the previous
+// bands (cyclically) still cover the row while the offset stays inside their windows.
 template <typename real>
 __global__ __launch_bounds__(kPlaneThreads) void reduce_kernel(ReduceArgs a)
 {
@@ -208,28 +284,27 @@ __global__ __launch_bounds__(kPlaneThreads) void reduce_kernel(ReduceArgs a)
     const int j = p / nx, i = p - j * nx;
     const real *P = static_cast<const real *>(a.P);
     double acc = 0.0;
-    for (int d = 0; d < a.n_dir; ++d) {
-        const DirInfo di = a.dirs[d];
-        const int rmin = a.row_min[d * nz + k];
+    for (int q = 0; q < a.n_pair; ++q) {
+        const rt3d::PairInfo pi = a.pairs[q];
+        const int rmin = a.row_min[pi.dA * nz + k];
         int jj = j - rmin;
         jj += (jj < 0) ? ny : 0;
-        // band whose lines start this row's window offset
-        int b = int((float(jj) + 0.5f) / float(di.band_rows));
-        b = min(b, di.n_bands - 1);
-        if (b * di.band_rows > jj) --b;
-        while (b < di.n_bands - 1 && (b + 1) * di.band_rows <= jj) ++b;
-        int off = jj - b * di.band_rows;
-        const long plane = long(di.win_rows) * nx;
-        const real *Pd = P + di.p_off + long(k) * plane + i;
+        int b = int((float(jj) + 0.5f) / float(pi.band_rows));
+        b = min(b, pi.n_bands - 1);
+        if (b * pi.band_rows > jj) --b;
+        while (b < pi.n_bands - 1 && (b + 1) * pi.band_rows <= jj) ++b;
+        int off = jj - b * pi.band_rows;
+        const long plane = long(pi.win_rows) * nx;
+        const real *Pq = P + pi.p_off + long(k) * plane + i;
         double sd = 0.0;
         int bb = b;
         while (true) {
-            sd += double(Pd[long(bb) * nz * plane + long(off) * nx]);
-            bb = (bb == 0) ? di.n_bands - 1 : bb - 1;
-            off += (bb == di.n_bands - 1) ? di.last_rows : di.band_rows;
-            if (off >= di.win_rows) break;
+            sd += double(Pq[long(bb) * nz * plane + long(off) * nx]);
+            bb = (bb == 0) ? pi.n_bands - 1 : bb - 1;
+            off += (bb == pi.n_bands - 1) ? pi.last_rows : pi.band_rows;
+            if (off >= pi.win_rows) break;
         }
-        acc += di.wmu * sd;
+        acc += pi.wmu * sd;
     }
     const long v = long(k) * nx * ny + p;
     const double Jfs = acc / a.chi[v];
@@ -549,6 +624,7 @@ struct rt3d_ctx {
     long V = 0;
     size_t real_size = 8;
     int lstar_early_exit = 0;
+    int sweep_nt = kSweepThreadsB;
     // device buffers (owned)
     double *chi = nullptr, *eps = nullptr, *B = nullptr, *J = nullptr, *Jfs = nullptr, *r = nullptr;
     double *dJa = nullptr, *dJb = nullptr, *L = nullptr, *Acoef = nullptr, *Iem = nullptr;
@@ -558,6 +634,7 @@ struct rt3d_ctx {
     int *seg_off = nullptr, *seg_n = nullptr, *seg_a = nullptr, *seg_bb = nullptr, *seg_bm = nullptr;
     int *seg_ai = nullptr, *seg_bi = nullptr, *row_min = nullptr;
     DirInfo *dirs = nullptr;
+    rt3d::PairInfo *pairs = nullptr;
     WorkItem *items = nullptr;
     unsigned long long *d_maxrel = nullptr;
     int *d_flag = nullptr;
@@ -733,28 +810,38 @@ int launch_sweep(rt3d_ctx *c)
     a.seg_off = c->seg_off; a.seg_n = c->seg_n; a.seg_a = c->seg_a; a.seg_bb = c->seg_bb;
     a.seg_bm = c->seg_bm; a.row_min = c->row_min;
     a.seg_len = c->seg_len;
-    a.dirs = c->dirs; a.items = c->items;
+    a.pairs = c->pairs; a.items = c->items;
     a.cs = c->cs;
     a.Ibot = (c->g.bottom_bc == 0) ? c->B : nullptr;
     a.I_top = c->g.I_top;
     a.P = c->P;
     a.Iem = c->Iem;
-    const size_t smem = size_t(c->plan.max_win_rows) * c->g.nx * c->real_size;
+    const size_t smem = 2 * size_t(c->plan.max_win_rows) * c->g.nx * c->real_size;
+    const dim3 grid(c->plan.items.size());
     TimedLaunch t(c, K_SWEEP);
-    if (c->precision == RT3D_FP64)
-        hipLaunchKernelGGL((sweep_kernel<double, kLinesPerThread>), dim3(c->plan.items.size()),
-                           dim3(kSweepThreads), smem, c->stream, a);
-    else
-        hipLaunchKernelGGL((sweep_kernel<float, kLinesPerThread>), dim3(c->plan.items.size()),
-                           dim3(kSweepThreads), smem, c->stream, a);
+    if (c->sweep_nt == kSweepThreadsA) {
+        if (c->precision == RT3D_FP64)
+            hipLaunchKernelGGL((sweep_kernel<double, kSweepThreadsA, kLinesPerThreadA>), grid,
+                               dim3(kSweepThreadsA), smem, c->stream, a);
+        else
+            hipLaunchKernelGGL((sweep_kernel<float, kSweepThreadsA, kLinesPerThreadA>), grid,
+                               dim3(kSweepThreadsA), smem, c->stream, a);
+    } else {
+        if (c->precision == RT3D_FP64)
+            hipLaunchKernelGGL((sweep_kernel<double, kSweepThreadsB, kLinesPerThreadB>), grid,
+                               dim3(kSweepThreadsB), smem, c->stream, a);
+        else
+            hipLaunchKernelGGL((sweep_kernel<float, kSweepThreadsB, kLinesPerThreadB>), grid,
+                               dim3(kSweepThreadsB), smem, c->stream, a);
+    }
     return check_launch(c, "sweep_kernel");
 }
 
 int launch_reduce(rt3d_ctx *c, bool with_residual)
 {
     ReduceArgs a;
-    a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.n_dir = c->A.n_dir;
-    a.dirs = c->dirs; a.row_min = c->row_min; a.P = c->P; a.chi = c->chi;
+    a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.n_pair = c->plan.n_pair;
+    a.pairs = c->pairs; a.row_min = c->row_min; a.P = c->P; a.chi = c->chi;
     a.J = c->J; a.Jfs = c->Jfs; a.r = with_residual ? c->r : nullptr;
     TimedLaunch t(c, K_REDUCE);
     if (c->precision == RT3D_FP64)
@@ -878,7 +965,7 @@ void free_all(rt3d_ctx *c)
 {
     void *ptrs[] = {c->chi, c->eps, c->B, c->J, c->Jfs, c->r, c->dJa, c->dJb, c->L, c->Acoef, c->Iem,
                     c->Sbuf, c->cs, c->P, c->seg_len, c->seg_len64, c->seg_off, c->seg_n, c->seg_a,
-                    c->seg_bb, c->seg_bm, c->seg_ai, c->seg_bi, c->row_min, c->dirs, c->items,
+                    c->seg_bb, c->seg_bm, c->seg_ai, c->seg_bi, c->row_min, c->dirs, c->items, c->pairs,
                     c->d_maxrel, c->d_flag, c->ng_hist, c->ng_partial};
     for (void *p : ptrs)
         if (p) hipFree(p);
@@ -966,12 +1053,17 @@ int rt3d_create(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, void *hi
     c->real_size = (precision == RT3D_FP64) ? sizeof(double) : sizeof(float);
     c->V = long(g->nx) * g->ny * g->nz;
     if (!rt3d::make_angle_set(g->n_theta, g->n_phi, c->A)) { delete c; return RT3D_ERR_ARG; }
-    if (!rt3d::build_sweep_plan(g->nx, g->ny, g->nz, c->A, kSweepThreads, kLinesPerThread, c->plan, msg)) {
+    // workgroup shape of the sweep (512 x 4 lines by default; RT3D_SWEEP_THREADS=256 for 256 x 8)
+    if (const char *e = std::getenv("RT3D_SWEEP_THREADS")) {
+        if (std::atoi(e) == kSweepThreadsA) c->sweep_nt = kSweepThreadsA;
+    }
+    const int lines = (c->sweep_nt == kSweepThreadsA) ? kSweepThreadsA * kLinesPerThreadA
+                                                      : kSweepThreadsB * kLinesPerThreadB;
+    if (!rt3d::build_sweep_plan(g->nx, g->ny, g->nz, c->A, lines, 16 * c->sweep_nt, kWindowBytes,
+                                int(c->real_size), c->plan, msg)) {
         delete c;
         return RT3D_ERR_ARG;
     }
-    const size_t smem = size_t(c->plan.max_win_rows) * g->nx * c->real_size;
-    if (smem > 64 * 1024) { delete c; return RT3D_ERR_ARG; }
     // Lambda* walk may stop at the first non-neighbour only if no line wraps back within two layers
     {
         double tmax_x = 0.0, tmax_y = 0.0;
@@ -1013,7 +1105,7 @@ int rt3d_create(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, void *hi
     chk(upload(c, &c->seg_a, P.seg_a)); chk(upload(c, &c->seg_bb, P.seg_bb)); chk(upload(c, &c->seg_bm, P.seg_bm));
     chk(upload(c, &c->seg_ai, P.seg_ai)); chk(upload(c, &c->seg_bi, P.seg_bi));
     chk(upload(c, &c->row_min, P.row_min));
-    chk(upload(c, &c->dirs, P.dirs)); chk(upload(c, &c->items, P.items));
+    chk(upload(c, &c->dirs, P.dirs)); chk(upload(c, &c->items, P.items)); chk(upload(c, &c->pairs, P.pairs));
     chk(dev_alloc(c, &c->d_maxrel, 1)); chk(dev_alloc(c, &c->d_flag, 1));
     if (rc) {
         free_all(c);
@@ -1269,11 +1361,11 @@ int rt3d_get_stats(rt3d_ctx *c, char *buf, int buflen)
     std::snprintf(tmp, sizeof tmp,
                   "\"nx\":%d,\"ny\":%d,\"nz\":%d,\"n_dir\":%d,\"precision\":\"%s\",\"outer_iters\":%ld,"
                   "\"inner_sweeps\":%ld,\"device_bytes\":%zu,\"partial_plane_bytes\":%lld,"
-                  "\"sweep_workgroups\":%zu,\"mean_segments\":%.6f,\"timing\":%s,\"kernels\":{",
+                  "\"sweep_workgroups\":%zu,\"sweep_threads\":%d,\"mean_segments\":%.6f,\"timing\":%s,\"kernels\":{",
                   c->g.nx, c->g.ny, c->g.nz, c->A.n_dir, c->precision == RT3D_FP64 ? "fp64" : "fp32_sweep",
                   c->outer_iters, c->inner_sweeps, c->device_bytes,
                   (long long)(c->plan.p_elems * (long long)c->real_size), c->plan.items.size(),
-                  c->plan.mean_segments, c->timing ? "true" : "false");
+                  c->sweep_nt, c->plan.mean_segments, c->timing ? "true" : "false");
     s += tmp;
     for (int k = 0; k < K_COUNT; ++k) {
         std::snprintf(tmp, sizeof tmp, "%s\"%s\":{\"launches\":%ld,\"total_ms\":%.6f}", k ? "," : "",
