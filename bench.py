@@ -33,16 +33,64 @@ def sweep_bytes_per_update(precision: str) -> int:
     return 2 * s_r + s_r
 
 
+def _timed_steps(rt3d, torch, w, d_med, prec, stream, steps, warmup, M):
+    """K timed OS steps after W warm-up steps; per-kernel HIP-event times from the library."""
+    s = rt3d.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi, I_top=w.I_top, precision=prec, stream=stream)
+    s.set_medium(d_med["chi"], d_med["eps"], d_med["B"])
+    t0 = time.perf_counter()
+    s.build_lstar()
+    lstar_s = time.perf_counter() - t0
+    for _ in range(warmup):
+        s.os_step(M)
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.os_step(M)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = s.stats()
+    s.close()
+    per_launch = {k: (v["total_ms"] / v["launches"] if v["launches"] else None)
+                  for k, v in st["kernels"].items()}
+    return elapsed, per_launch, lstar_s, st
+
+
+def _converge(rt3d, torch, w, d_med, prec, stream, M, ng_order, ng_every, tol, max_iter):
+    """Time from resident inputs (Lambda* build included) to max rel dJ < tol."""
+    s = rt3d.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi, I_top=w.I_top, precision=prec, stream=stream)
+    s.set_medium(d_med["chi"], d_med["eps"], d_med["B"])
+    if ng_order:
+        s.set_acceleration(ng_order, ng_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, iters, c = s.solve(tol, max_iter, M)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    st = s.stats()
+    J = torch.zeros((w.nz, w.ny, w.nx), dtype=torch.float64, device="cuda")
+    s.get_J(J)
+    s.close()
+    return J, {"seconds": round(secs, 4), "outer_iterations": iters, "final_max_rel_dJ": c,
+               "converged": status == rt3d.RT3D_OK, "fp64_sweeps": st["fp64_sweeps"],
+               "fp32_sweeps": st["fp32_sweeps"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="strat129")
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--inner-sweeps", type=int, default=20, help="Jacobi sweeps per OS step (M)")
-    ap.add_argument("--converge-max-iter", type=int, default=400,
-                    help="outer-iteration cap of the time-to-converged-J run (0 skips it)")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="form whose step rate is the headline value")
+    ap.add_argument("--inner-sweeps", type=int, default=30, help="Jacobi sweeps per OS step (M)")
+    ap.add_argument("--ng-order", type=int, default=3)
+    ap.add_argument("--ng-every", type=int, default=6)
+    ap.add_argument("--converge-max-iter", type=int, default=600,
+                    help="outer-iteration cap of the time-to-converged-J runs (0 skips them)")
+    ap.add_argument("--reference-tol", type=float, default=1e-12,
+                    help="tolerance of the float64 reference solve the converged forms are measured against")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-every", type=int, default=8,
                     help="the CPU oracle times every n-th direction of the full grid")
@@ -57,7 +105,6 @@ def main() -> int:
         print("bench.py: launched with WORLD_SIZE > 1; one GPU only", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     if not torch.cuda.is_available():
@@ -75,56 +122,44 @@ def main() -> int:
     torch.cuda.synchronize()
     V = w.n_vox
     n_dir = w.n_dir
-    prec = rt3d.RT3D_FP64 if args.precision == "fp64" else rt3d.RT3D_FP32_SWEEP
     stream = torch.cuda.current_stream().cuda_stream
+    forms = {"fp64": rt3d.RT3D_FP64, "fp32": rt3d.RT3D_FP32_SWEEP}
+    M = args.inner_sweeps
 
-    # ---- timed steps -------------------------------------------------------------------------
-    s = rt3d.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi, I_top=w.I_top, precision=prec, stream=stream)
-    s.set_medium(d_med["chi"], d_med["eps"], d_med["B"])
-    t0 = time.perf_counter()
-    s.build_lstar()
-    lstar_s = time.perf_counter() - t0
-    for _ in range(args.warmup):
-        s.os_step(args.inner_sweeps)
-    s.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    last_c = None
-    for _ in range(args.steps):
-        last_c = s.os_step(args.inner_sweeps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    st = s.stats()
-    s.set_timing(False)
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = V * n_dir * args.steps / elapsed
-    kern = st["kernels"]
-    per_launch = {k: (v["total_ms"] / v["launches"] if v["launches"] else None) for k, v in kern.items()}
-    sweep_ms = per_launch["sweep"]
-    fs_ms = sum(per_launch[k] for k in ("source", "sweep", "reduce"))
-    b_unit = sweep_bytes_per_update(args.precision)
+    # ---- timed steps, both forms ----------------------------------------------------------------
+    step = {}
+    for name, prec in forms.items():
+        elapsed, per_launch, lstar_s, st = _timed_steps(rt3d, torch, w, d_med, prec, stream, args.steps,
+                                                        args.warmup, M)
+        fs_ms = sum(per_launch[k] for k in ("source", "sweep", "reduce"))
+        step[name] = {"ms_per_step": 1e3 * elapsed / args.steps,
+                      "value": V * n_dir * args.steps / elapsed,
+                      "fs_updates_per_s_fs_kernels_only": V * n_dir / (fs_ms * 1e-3),
+                      "kernel_ms_per_launch": {k: (round(v, 4) if v is not None else None)
+                                               for k, v in per_launch.items()},
+                      "lstar_build_s": round(lstar_s, 4),
+                      "sweeps": {"fp64": st["fp64_sweeps"], "fp32": st["fp32_sweeps"]}}
+    main_form = args.precision
+    sweep_ms = step[main_form]["kernel_ms_per_launch"]["sweep"]
+    b_unit = sweep_bytes_per_update(main_form)
     achieved = b_unit * V * n_dir / (sweep_ms * 1e-3) / 1e9
     roofline = {"kernel": "sweep_kernel", "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_update": b_unit,
-                "sweep_ms_per_launch": round(sweep_ms, 4)}
-    s.close()
+                "traffic": None, "bytes_per_update": b_unit, "sweep_ms_per_launch": sweep_ms}
 
-    # ---- time to converged J (Lambda* build included) -----------------------------------------
+    # ---- time to converged J, both forms, against a tight float64 reference -------------------------
     conv = None
     if args.converge_max_iter > 0:
-        s2 = rt3d.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi, I_top=w.I_top, precision=prec,
-                         stream=stream)
-        s2.set_medium(d_med["chi"], d_med["eps"], d_med["B"])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        status, iters, c = s2.solve(w.tol, args.converge_max_iter, args.inner_sweeps)
-        torch.cuda.synchronize()
-        tconv = time.perf_counter() - t0
-        conv = {"seconds": round(tconv, 4), "outer_iterations": iters,
-                "inner_sweeps_per_step": args.inner_sweeps, "final_max_rel_dJ": c,
-                "tol": w.tol, "converged": status == rt3d.RT3D_OK}
-        s2.close()
+        conv = {"tol": w.tol, "inner_sweeps": M, "ng_order": args.ng_order, "ng_every": args.ng_every}
+        J_ref, ref = _converge(rt3d, torch, w, d_med, rt3d.RT3D_FP64, stream, M, args.ng_order,
+                               args.ng_every, args.reference_tol, 20 * args.converge_max_iter)
+        conv["reference"] = {"tol": args.reference_tol, **ref}
+        for name, prec in forms.items():
+            J, res = _converge(rt3d, torch, w, d_med, prec, stream, M, args.ng_order, args.ng_every, w.tol,
+                               args.converge_max_iter)
+            res["max_rel_err_vs_reference"] = float(torch.max(torch.abs(J / J_ref - 1)).item())
+            conv[name] = res
+        conv["fp32_form_speedup"] = round(conv["fp64"]["seconds"] / conv["fp32"]["seconds"], 3)
 
     # ---- CPU oracle on a bounded sample of the same workload -------------------------------------
     cpu = None
@@ -138,36 +173,33 @@ def main() -> int:
         oracle.formal_solution_dirs(med["chi"], S, w.n_theta, w.n_phi, dirs, I_top=w.I_top,
                                     I_bot=med["B"][0], n_threads=threads)
         tcpu = time.perf_counter() - t0
-        cpu = {"value": V * len(dirs) / tcpu, "unit": "voxel-angle FS updates/s", "cores": min(threads, len(dirs)),
-               "kind": "oracle",
+        cpu = {"value": V * len(dirs) / tcpu, "unit": "voxel-angle FS updates/s",
+               "cores": min(threads, len(dirs)), "kind": "oracle",
                "sample": f"FP64 oracle formal solution of {len(dirs)} of the {n_dir} directions "
                          f"(every {args.cpu_sample_every}th) on the full {w.nx}x{w.ny}x{w.nz} grid, "
                          f"{tcpu:.2f} s wall"}
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": step[main_form]["value"],
         "unit": "voxel-angle FS updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": step[main_form]["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "dtype": "f64" if main_form == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} voxels x {n_dir} angles "
                                f"({w.n_theta} mu x {w.n_phi} phi), eps={w.eps:g}, tau_total={w.tau_total:g}, "
                                f"chi log-normal sigma={w.sigma}, seed {w.seed}",
-                   "precision": "fp64" if args.precision == "fp64" else "fp32 sweeps, fp64 J/OS/convergence",
-                   "inner_sweeps": args.inner_sweeps,
+                   "precision": "fp64" if main_form == "fp64" else "fp32 sweeps, fp64 J/OS/convergence",
+                   "inner_sweeps": M,
                    "step": "one OS iteration: S update, FS over all angles, J reduction + residual, "
                            "M Jacobi sweeps, J update + max rel dJ"},
-        "fs_updates_per_s_fs_kernels_only": V * n_dir / (fs_ms * 1e-3),
-        "kernel_ms_per_launch": {k: (round(v, 4) if v is not None else None) for k, v in per_launch.items()},
-        "lstar_build_s": round(lstar_s, 4),
-        "last_step_max_rel_dJ": last_c,
+        "forms": step,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_converged": conv,

@@ -61,7 +61,7 @@ enum { RT3D_HOST = 0, RT3D_DEVICE = 1 };
 typedef enum {
     RT3D_FP64 = 0,        /* every step in float64 */
     RT3D_FP32_SWEEP = 1   /* FS sweeps in float32; J accumulation, Lambda*, OS solve and the
-                             convergence test in float64 */
+                             convergence test in float64 (see rt3d_os_step) */
 } rt3d_precision;
 
 typedef struct {
@@ -113,12 +113,20 @@ int rt3d_get_lstar(rt3d_ctx *ctx, double *out, int ptr_kind);
 
 /* One OS step (builds Lambda* first if needed): S from J, FS, r = J_fs - J, inner_sweeps >= 1
  * Jacobi sweeps from dJ = 0, J <- J + dJ, *max_rel_dJ_out = max_v |dJ_v| / |J_v| (may be NULL).
+ * In the RT3D_FP32_SWEEP form the context keeps an anchor iterate Ja with its float64 formal
+ * solution F_a; a step sweeps the source change (1-eps)(J - Ja) in float32 with no boundary light and
+ * uses J_fs = F_a + that sweep, summed in float64, so the float32 error scales with |J - Ja| rather
+ * than with J.  A float64 sweep re-anchors at the current J on the first step, after rt3d_set_J or
+ * rt3d_set_medium, and whenever the last step's c fell below 1e-3 of max_v |J_v - Ja_v| / |J_v|.  The
+ * Jacobi coefficients are stored in float32 in this form (they only precondition; the fixed point is
+ * set by the residual); the Jacobi arithmetic is float64.
  * Errors: RT3D_ERR_STATE, RT3D_ERR_ARG, RT3D_ERR_NONFINITE (J is then not trustworthy),
  * RT3D_ERR_HIP. */
 int rt3d_os_step(rt3d_ctx *ctx, int inner_sweeps, double *max_rel_dJ_out);
 
 /* OS steps until max_rel_dJ < tol or max_iter steps.  *iters_out and *final_rel_dJ_out (may be
- * NULL) receive the step count and the last c.  Returns RT3D_ERR_NOT_CONVERGED when max_iter was
+ * NULL) receive the step count and the last c.  The RT3D_FP32_SWEEP form accepts c < tol only from a
+ * step whose formal solution was float64 (a re-anchoring step); a float32 step below tol triggers one.  Returns RT3D_ERR_NOT_CONVERGED when max_iter was
  * reached (J and c remain valid), RT3D_ERR_NONFINITE, RT3D_ERR_ARG, RT3D_ERR_STATE, RT3D_ERR_HIP. */
 int rt3d_solve_to_convergence(rt3d_ctx *ctx, double tol, int max_iter, int inner_sweeps,
                               int *iters_out, double *final_rel_dJ_out);

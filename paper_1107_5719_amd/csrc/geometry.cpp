@@ -267,6 +267,7 @@ bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int lines_per_w
             pi.n_bands = (ny + rows - 1) / rows;
             pi.win_rows = rows + span[dA];
             pi.last_rows = ny - (pi.n_bands - 1) * rows;
+            pi.inv_rows = 1.0f / float(rows);
             P.max_win_rows = std::max(P.max_win_rows, pi.win_rows);
             P.pairs.push_back(pi);
         }

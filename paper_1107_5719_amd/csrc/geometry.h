@@ -48,7 +48,7 @@ struct PairInfo {
     int n_bands;       // nb
     int win_rows;      // Hw = Bj + span: rows of the deposit window of one band
     int last_rows;     // rows of the last band: ny - (nb - 1) * Bj
-    int pad;
+    float inv_rows;    // 1 / Bj (band lookup; corrected exactly in the kernel)
     int64_t p_off;     // element offset of this pair's partial planes in P
 };
 

@@ -41,6 +41,7 @@ namespace {
 constexpr int kSweepThreadsA = 256, kLinesPerThreadA = 8;
 constexpr int kSweepThreadsB = 512, kLinesPerThreadB = 4;
 constexpr size_t kWindowBytes = 48 * 1024;   // LDS for the two deposit windows of a band
+constexpr double kAnchorRatio = 1e-3;        // FP32 form: re-anchor when c < ratio * max|J - Ja|/|J|
 constexpr int kPlaneThreads = 256;   // voxel-parallel kernels: one thread per voxel of a k-plane
 
 template <typename real> struct Vec2;
@@ -96,14 +97,20 @@ __device__ inline float expm1_nonpos(float x)
 // S update
 // ------------------------------------------------------------------------------------------------
 
+// S_given: the source itself.  Ja (difference mode of the FP32 form): the source change since the
+// anchor iterate, (1 - eps)(J - Ja), whose formal solution is added to the anchor's.
 template <typename real>
 __global__ void source_kernel(long V, const double *__restrict__ chi, const double *__restrict__ eps,
                               const double *__restrict__ B, const double *__restrict__ J,
-                              const double *__restrict__ S_given, typename Vec2<real>::type *cs)
+                              const double *__restrict__ S_given, const double *__restrict__ Ja,
+                              typename Vec2<real>::type *cs)
 {
     long v = long(blockIdx.x) * blockDim.x + threadIdx.x;
     if (v >= V) return;
-    double S = S_given ? S_given[v] : eps[v] * B[v] + (1.0 - eps[v]) * J[v];
+    double S;
+    if (S_given) S = S_given[v];
+    else if (Ja) S = (1.0 - eps[v]) * (J[v] - Ja[v]);
+    else S = eps[v] * B[v] + (1.0 - eps[v]) * J[v];
     typename Vec2<real>::type c;
     c.x = real(chi[v]);
     c.y = real(S);
@@ -125,6 +132,7 @@ struct SweepArgs {
     double I_top;
     void *P;                      // real
     double *Iem;                  // [n_up][ny][nx] or null
+    const double *Iem_base;       // added to Iem in difference mode (or null)
 };
 
 // One workgroup sweeps the lines of one band for both directions of an x-mirrored pair.  Thread t
@@ -250,8 +258,12 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs a)
 #pragma unroll
         for (int t = 0; t < LPT; ++t) {
             if (li[t] < 0) continue;
-            EA[(it.j0 + lj[t]) * nx + li[t]] = double(IA[t]);
-            EB[(it.j0 + lj[t]) * nx + li[t]] = double(IB[t]);
+            const long ea = (EA - a.Iem) + (it.j0 + lj[t]) * nx + li[t];
+            const long eb = (EB - a.Iem) + (it.j0 + lj[t]) * nx + li[t];
+            const double baseA = a.Iem_base ? a.Iem_base[ea] : 0.0;
+            const double baseB = a.Iem_base ? a.Iem_base[eb] : 0.0;
+            a.Iem[ea] = baseA + double(IA[t]);
+            a.Iem[eb] = baseB + double(IB[t]);
         }
     }
 }
@@ -267,6 +279,7 @@ struct ReduceArgs {
     const void *P;            // real
     const double *chi;
     const double *J;          // for r = J_fs - J (may be null)
+    const double *base;       // difference mode: J_fs of the anchor, added (may be null)
     double *Jfs;
     double *r;                // may be null
 };
@@ -284,30 +297,40 @@ __global__ __launch_bounds__(kPlaneThreads) void reduce_kernel(ReduceArgs a)
     const int j = p / nx, i = p - j * nx;
     const real *P = static_cast<const real *>(a.P);
     double acc = 0.0;
+#pragma unroll 4
     for (int q = 0; q < a.n_pair; ++q) {
         const rt3d::PairInfo pi = a.pairs[q];
+        const int rows = pi.band_rows, nb = pi.n_bands, Hw = pi.win_rows;
         const int rmin = a.row_min[pi.dA * nz + k];
         int jj = j - rmin;
         jj += (jj < 0) ? ny : 0;
-        int b = int((float(jj) + 0.5f) / float(pi.band_rows));
-        b = min(b, pi.n_bands - 1);
-        if (b * pi.band_rows > jj) --b;
-        while (b < pi.n_bands - 1 && (b + 1) * pi.band_rows <= jj) ++b;
-        int off = jj - b * pi.band_rows;
-        const long plane = long(pi.win_rows) * nx;
+        int b = min(int((float(jj) + 0.5f) * pi.inv_rows), nb - 1);
+        b -= (b * rows > jj) ? 1 : 0;
+        b += (b < nb - 1 && (b + 1) * rows <= jj) ? 1 : 0;
+        const int off0 = jj - b * rows;
+        const long plane = long(Hw) * nx;
+        const long band_stride = long(nz) * plane;
         const real *Pq = P + pi.p_off + long(k) * plane + i;
-        double sd = 0.0;
-        int bb = b;
-        while (true) {
-            sd += double(Pq[long(bb) * nz * plane + long(off) * nx]);
-            bb = (bb == 0) ? pi.n_bands - 1 : bb - 1;
-            off += (bb == pi.n_bands - 1) ? pi.last_rows : pi.band_rows;
-            if (off >= pi.win_rows) break;
+        // the band that starts the row's window offset, and the band before it (cyclically)
+        const int b1 = (b == 0) ? nb - 1 : b - 1;
+        const int off1 = off0 + ((b1 == nb - 1) ? pi.last_rows : rows);
+        const double v0 = double(Pq[long(b) * band_stride + long(off0) * nx]);
+        const double v1 = (off1 < Hw) ? double(Pq[long(b1) * band_stride + long(off1) * nx]) : 0.0;
+        double sd = v0 + v1;
+        if (off1 < Hw) {
+            // bands thinner than the window halo: still earlier bands may cover the row
+            int bb = b1, off = off1;
+            while (true) {
+                bb = (bb == 0) ? nb - 1 : bb - 1;
+                off += (bb == nb - 1) ? pi.last_rows : rows;
+                if (off >= Hw) break;
+                sd += double(Pq[long(bb) * band_stride + long(off) * nx]);
+            }
         }
         acc += pi.wmu * sd;
     }
     const long v = long(k) * nx * ny + p;
-    const double Jfs = acc / a.chi[v];
+    const double Jfs = a.base ? a.base[v] + acc / a.chi[v] : acc / a.chi[v];
     a.Jfs[v] = Jfs;
     if (a.r) a.r[v] = Jfs - a.J[v];
 }
@@ -415,7 +438,7 @@ __global__ __launch_bounds__(kPlaneThreads) void lstar_kernel(LstarArgs a)
 __global__ __launch_bounds__(kPlaneThreads) void coef_kernel(int nx, int ny, int nz,
                                                              const double *__restrict__ L,
                                                              const double *__restrict__ eps,
-                                                             double *__restrict__ A)
+                                                             double *__restrict__ A, float *__restrict__ A32)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y;
@@ -437,6 +460,7 @@ __global__ __launch_bounds__(kPlaneThreads) void coef_kernel(int nx, int ny, int
             val = L[o * V + v] * (1.0 - eps[kk * plane + long(jj) * nx + ii]);
         }
         A[o * V + v] = val;
+        if (A32) A32[o * V + v] = float(val);
     }
 }
 
@@ -447,16 +471,23 @@ __global__ __launch_bounds__(kPlaneThreads) void coef_kernel(int nx, int ny, int
 struct JacobiArgs {
     int nx, ny, nz;
     const double *r;
-    const double *A;             // [27][V]; A[13] holds the denominator
+    const void *A;               // [27][V] coefficients (double, or float in the FP32 form);
+                                 // A[13] holds the denominator
     const double *dJ_in;         // null: dJ^0 = 0 (first sweep)
     double *dJ_out;              // may be null when J is updated
     double *J;                   // null: no update
     unsigned long long *maxrel;  // bits of max |dJ|/|J| (non-negative doubles order like integers)
+    const double *Ja;            // anchor iterate of the FP32 form (may be null)
+    unsigned long long *maxdist; // bits of max |J - Ja|/|J| when Ja is given
     int *nonfinite;
 };
 
+// Arithmetic is float64 for either coefficient type.
+template <typename coef>
 __global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel(JacobiArgs a)
 {
+    const coef *Ac = static_cast<const coef *>(a.A);
+    double dist = 0.0;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y;
@@ -478,30 +509,35 @@ __global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel(JacobiArgs a)
                 const int kk = k + o / 9 - 1;
                 if (kk < 0 || kk >= nz) continue;
                 const long u = kk * plane + long(rows[(o / 3) % 3]) * nx + cols[o % 3];
-                acc += a.A[o * V + v] * a.dJ_in[u];
+                acc += double(Ac[o * V + v]) * a.dJ_in[u];
             }
         }
-        const double dJ = acc / a.A[13 * V + v];
+        const double dJ = acc / double(Ac[13 * V + v]);
         if (a.dJ_out) a.dJ_out[v] = dJ;
         if (a.J) {
             const double Jn = a.J[v] + dJ;
             a.J[v] = Jn;
             q = fabs(dJ) / fabs(Jn);
+            if (a.Ja) dist = fabs(Jn - a.Ja[v]) / fabs(Jn);
             bad = !isfinite(Jn) || !isfinite(q);
         }
     }
     if (!a.J) return;
-    // block max of q; NaN/Inf raise the flag
-    if (bad) { atomicOr(a.nonfinite, 1); q = 0.0; }
-    for (int offs = 32; offs > 0; offs >>= 1) q = fmax(q, __shfl_xor(q, offs));
-    __shared__ double wmax[kPlaneThreads / 64];
+    // block max of q (and of the anchor distance); NaN/Inf raise the flag
+    if (bad) { atomicOr(a.nonfinite, 1); q = 0.0; dist = 0.0; }
+    for (int offs = 32; offs > 0; offs >>= 1) {
+        q = fmax(q, __shfl_xor(q, offs));
+        dist = fmax(dist, __shfl_xor(dist, offs));
+    }
+    __shared__ double wmax[2][kPlaneThreads / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) wmax[wid] = q;
+    if (lane == 0) { wmax[0][wid] = q; wmax[1][wid] = dist; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double m = wmax[0];
-        for (int w = 1; w < kPlaneThreads / 64; ++w) m = fmax(m, wmax[w]);
+        double m = wmax[0][0], md = wmax[1][0];
+        for (int w = 1; w < kPlaneThreads / 64; ++w) { m = fmax(m, wmax[0][w]); md = fmax(md, wmax[1][w]); }
         atomicMax(a.maxrel, static_cast<unsigned long long>(__double_as_longlong(m)));
+        if (a.Ja) atomicMax(a.maxdist, static_cast<unsigned long long>(__double_as_longlong(md)));
     }
 }
 
@@ -629,8 +665,16 @@ struct rt3d_ctx {
     double *chi = nullptr, *eps = nullptr, *B = nullptr, *J = nullptr, *Jfs = nullptr, *r = nullptr;
     double *dJa = nullptr, *dJb = nullptr, *L = nullptr, *Acoef = nullptr, *Iem = nullptr;
     double *Sbuf = nullptr;
-    void *cs = nullptr, *P = nullptr, *seg_len = nullptr;
+    void *cs = nullptr, *P = nullptr;       // sized for float64; float sweeps use the first half
     double *seg_len64 = nullptr;
+    float *seg_len32 = nullptr;
+    // FP32 form: anchor iterate, its float64 formal solution and top-plane light, float coefficients
+    double *Ja = nullptr, *Fa = nullptr, *Iem_a = nullptr;
+    float *A32 = nullptr;
+    unsigned long long *d_maxdist = nullptr;
+    bool anchor_valid = false, force_refresh = false, last_step_anchored = false;
+    double c_last = INFINITY, da_last = 0.0;
+    long fp64_sweeps = 0, fp32_sweeps = 0;
     int *seg_off = nullptr, *seg_n = nullptr, *seg_a = nullptr, *seg_bb = nullptr, *seg_bm = nullptr;
     int *seg_ai = nullptr, *seg_bi = nullptr, *row_min = nullptr;
     DirInfo *dirs = nullptr;
@@ -789,45 +833,49 @@ dim3 plane_grid(const rt3d_ctx *c)
     return dim3((c->g.nx * c->g.ny + kPlaneThreads - 1) / kPlaneThreads, c->g.nz);
 }
 
-int launch_source(rt3d_ctx *c, const double *S_given)
+int launch_source(rt3d_ctx *c, const double *S_given, const double *Ja, bool fp32)
 {
     TimedLaunch t(c, K_SOURCE);
     const int blocks = int((c->V + 255) / 256);
-    if (c->precision == RT3D_FP64)
+    if (!fp32)
         hipLaunchKernelGGL(source_kernel<double>, dim3(blocks), dim3(256), 0, c->stream, c->V, c->chi,
-                           c->eps, c->B, c->J, S_given, static_cast<double2 *>(c->cs));
+                           c->eps, c->B, c->J, S_given, Ja, static_cast<double2 *>(c->cs));
     else
         hipLaunchKernelGGL(source_kernel<float>, dim3(blocks), dim3(256), 0, c->stream, c->V, c->chi,
-                           c->eps, c->B, c->J, S_given, static_cast<float2 *>(c->cs));
+                           c->eps, c->B, c->J, S_given, Ja, static_cast<float2 *>(c->cs));
     return check_launch(c, "source_kernel");
 }
 
-int launch_sweep(rt3d_ctx *c)
+// diff: formal solution of a source difference (no boundary light; top-plane light added to the
+// anchor's)
+int launch_sweep(rt3d_ctx *c, bool fp32, bool diff)
 {
     SweepArgs a;
     a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
     a.n_down = c->A.n_dir / 2;
     a.seg_off = c->seg_off; a.seg_n = c->seg_n; a.seg_a = c->seg_a; a.seg_bb = c->seg_bb;
     a.seg_bm = c->seg_bm; a.row_min = c->row_min;
-    a.seg_len = c->seg_len;
+    a.seg_len = fp32 ? static_cast<const void *>(c->seg_len32) : static_cast<const void *>(c->seg_len64);
     a.pairs = c->pairs; a.items = c->items;
     a.cs = c->cs;
-    a.Ibot = (c->g.bottom_bc == 0) ? c->B : nullptr;
-    a.I_top = c->g.I_top;
+    a.Ibot = (c->g.bottom_bc == 0 && !diff) ? c->B : nullptr;
+    a.I_top = diff ? 0.0 : c->g.I_top;
     a.P = c->P;
     a.Iem = c->Iem;
-    const size_t smem = 2 * size_t(c->plan.max_win_rows) * c->g.nx * c->real_size;
+    a.Iem_base = diff ? c->Iem_a : nullptr;
+    const size_t smem = 2 * size_t(c->plan.max_win_rows) * c->g.nx * (fp32 ? sizeof(float) : sizeof(double));
     const dim3 grid(c->plan.items.size());
     TimedLaunch t(c, K_SWEEP);
+    if (fp32) c->fp32_sweeps += 1; else c->fp64_sweeps += 1;
     if (c->sweep_nt == kSweepThreadsA) {
-        if (c->precision == RT3D_FP64)
+        if (!fp32)
             hipLaunchKernelGGL((sweep_kernel<double, kSweepThreadsA, kLinesPerThreadA>), grid,
                                dim3(kSweepThreadsA), smem, c->stream, a);
         else
             hipLaunchKernelGGL((sweep_kernel<float, kSweepThreadsA, kLinesPerThreadA>), grid,
                                dim3(kSweepThreadsA), smem, c->stream, a);
     } else {
-        if (c->precision == RT3D_FP64)
+        if (!fp32)
             hipLaunchKernelGGL((sweep_kernel<double, kSweepThreadsB, kLinesPerThreadB>), grid,
                                dim3(kSweepThreadsB), smem, c->stream, a);
         else
@@ -837,28 +885,53 @@ int launch_sweep(rt3d_ctx *c)
     return check_launch(c, "sweep_kernel");
 }
 
-int launch_reduce(rt3d_ctx *c, bool with_residual)
+int launch_reduce(rt3d_ctx *c, bool with_residual, bool fp32, const double *base)
 {
     ReduceArgs a;
     a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.n_pair = c->plan.n_pair;
     a.pairs = c->pairs; a.row_min = c->row_min; a.P = c->P; a.chi = c->chi;
-    a.J = c->J; a.Jfs = c->Jfs; a.r = with_residual ? c->r : nullptr;
+    a.J = c->J; a.base = base; a.Jfs = c->Jfs; a.r = with_residual ? c->r : nullptr;
     TimedLaunch t(c, K_REDUCE);
-    if (c->precision == RT3D_FP64)
+    if (!fp32)
         hipLaunchKernelGGL(reduce_kernel<double>, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
     else
         hipLaunchKernelGGL(reduce_kernel<float>, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
     return check_launch(c, "reduce_kernel");
 }
 
-// S (given, or from J) -> J_fs (and r when with_residual)
-int run_fs(rt3d_ctx *c, const double *S_dev, bool with_residual)
+// S (given, or from J) -> J_fs (and r when with_residual), sweeps in float32 when fp32
+int run_fs(rt3d_ctx *c, const double *S_dev, bool with_residual, bool fp32)
 {
-    int rc = launch_source(c, S_dev);
-    if (!rc) rc = launch_sweep(c);
-    if (!rc) rc = launch_reduce(c, with_residual);
+    int rc = launch_source(c, S_dev, nullptr, fp32);
+    if (!rc) rc = launch_sweep(c, fp32, false);
+    if (!rc) rc = launch_reduce(c, with_residual, fp32, nullptr);
     if (!rc) c->have_fs = true;
     return rc;
+}
+
+// FP32 form, difference step: J_fs = F_a + FS32((1 - eps)(J - Ja)) with no boundary light
+int run_fs_difference(rt3d_ctx *c)
+{
+    int rc = launch_source(c, nullptr, c->Ja, true);
+    if (!rc) rc = launch_sweep(c, true, true);
+    if (!rc) rc = launch_reduce(c, true, true, c->Fa);
+    if (!rc) c->have_fs = true;
+    return rc;
+}
+
+// FP32 form, anchor refresh: a float64 formal solution at the current J becomes the new anchor
+int refresh_anchor(rt3d_ctx *c)
+{
+    int rc = run_fs(c, nullptr, true, false);
+    if (rc) return rc;
+    const size_t vb = size_t(c->V) * sizeof(double);
+    HIP_TRY(c, hipMemcpyAsync(c->Ja, c->J, vb, hipMemcpyDeviceToDevice, c->stream), "anchor J");
+    HIP_TRY(c, hipMemcpyAsync(c->Fa, c->Jfs, vb, hipMemcpyDeviceToDevice, c->stream), "anchor J_fs");
+    HIP_TRY(c, hipMemcpyAsync(c->Iem_a, c->Iem, size_t(c->A.n_dir / 2) * c->g.nx * c->g.ny * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream), "anchor top light");
+    c->anchor_valid = true;
+    c->force_refresh = false;
+    return RT3D_OK;
 }
 
 int ensure_lstar(rt3d_ctx *c)
@@ -878,7 +951,7 @@ int ensure_lstar(rt3d_ctx *c)
     {
         TimedLaunch t(c, K_COEF);
         hipLaunchKernelGGL(coef_kernel, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, c->g.nx,
-                           c->g.ny, c->g.nz, c->L, c->eps, c->Acoef);
+                           c->g.ny, c->g.nz, c->L, c->eps, c->Acoef, c->A32);
     }
     rc = check_launch(c, "coef_kernel");
     if (rc) return rc;
@@ -889,12 +962,19 @@ int ensure_lstar(rt3d_ctx *c)
 int launch_jacobi(rt3d_ctx *c, const double *dJ_in, double *dJ_out, bool update)
 {
     JacobiArgs a;
+    const bool f32 = c->precision == RT3D_FP32_SWEEP;
     a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
-    a.r = c->r; a.A = c->Acoef; a.dJ_in = dJ_in; a.dJ_out = dJ_out;
+    a.r = c->r; a.dJ_in = dJ_in; a.dJ_out = dJ_out;
+    a.A = f32 ? static_cast<const void *>(c->A32) : static_cast<const void *>(c->Acoef);
     a.J = update ? c->J : nullptr;
     a.maxrel = c->d_maxrel; a.nonfinite = c->d_flag;
+    a.Ja = (f32 && update) ? c->Ja : nullptr;
+    a.maxdist = c->d_maxdist;
     TimedLaunch t(c, K_JACOBI);
-    hipLaunchKernelGGL(jacobi_kernel, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
+    if (f32)
+        hipLaunchKernelGGL(jacobi_kernel<float>, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
+    else
+        hipLaunchKernelGGL(jacobi_kernel<double>, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
     return check_launch(c, "jacobi_kernel");
 }
 
@@ -964,7 +1044,8 @@ int ng_step(rt3d_ctx *c, int m)
 void free_all(rt3d_ctx *c)
 {
     void *ptrs[] = {c->chi, c->eps, c->B, c->J, c->Jfs, c->r, c->dJa, c->dJb, c->L, c->Acoef, c->Iem,
-                    c->Sbuf, c->cs, c->P, c->seg_len, c->seg_len64, c->seg_off, c->seg_n, c->seg_a,
+                    c->Sbuf, c->cs, c->P, c->seg_len32, c->seg_len64, c->Ja, c->Fa, c->Iem_a, c->A32,
+                    c->d_maxdist, c->seg_off, c->seg_n, c->seg_a,
                     c->seg_bb, c->seg_bm, c->seg_ai, c->seg_bi, c->row_min, c->dirs, c->items, c->pairs,
                     c->d_maxrel, c->d_flag, c->ng_hist, c->ng_partial};
     for (void *p : ptrs)
@@ -1059,8 +1140,9 @@ int rt3d_create(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, void *hi
     }
     const int lines = (c->sweep_nt == kSweepThreadsA) ? kSweepThreadsA * kLinesPerThreadA
                                                       : kSweepThreadsB * kLinesPerThreadB;
+    // one plan for both precisions: the LDS windows are budgeted for float64
     if (!rt3d::build_sweep_plan(g->nx, g->ny, g->nz, c->A, lines, 16 * c->sweep_nt, kWindowBytes,
-                                int(c->real_size), c->plan, msg)) {
+                                int(sizeof(double)), c->plan, msg)) {
         delete c;
         return RT3D_ERR_ARG;
     }
@@ -1082,25 +1164,19 @@ int rt3d_create(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, void *hi
     chk(dev_alloc(c, &c->dJa, V)); chk(dev_alloc(c, &c->dJb, V)); chk(dev_alloc(c, &c->Sbuf, V));
     chk(dev_alloc(c, &c->L, 27 * V)); chk(dev_alloc(c, &c->Acoef, 27 * V));
     chk(dev_alloc(c, &c->Iem, size_t(c->A.n_dir / 2) * g->nx * g->ny));
-    if (!rc) {
-        if (precision == RT3D_FP64) {
-            double2 *cs = nullptr; double *Pp = nullptr;
-            chk(dev_alloc(c, &cs, V)); chk(dev_alloc(c, &Pp, size_t(P.p_elems)));
-            c->cs = cs; c->P = Pp;
-            double *sl = nullptr;
-            chk(upload(c, &sl, P.seg_len));
-            c->seg_len = sl;
-        } else {
-            float2 *cs = nullptr; float *Pp = nullptr;
-            chk(dev_alloc(c, &cs, V)); chk(dev_alloc(c, &Pp, size_t(P.p_elems)));
-            c->cs = cs; c->P = Pp;
-            std::vector<float> lf(P.seg_len.begin(), P.seg_len.end());
-            float *sl = nullptr;
-            chk(upload(c, &sl, lf));
-            c->seg_len = sl;
-        }
+    {
+        double2 *cs = nullptr; double *Pp = nullptr;
+        chk(dev_alloc(c, &cs, V)); chk(dev_alloc(c, &Pp, size_t(P.p_elems)));
+        c->cs = cs; c->P = Pp;
     }
     chk(upload(c, &c->seg_len64, P.seg_len));
+    chk(upload(c, &c->seg_len32, std::vector<float>(P.seg_len.begin(), P.seg_len.end())));
+    if (precision == RT3D_FP32_SWEEP) {
+        chk(dev_alloc(c, &c->Ja, V)); chk(dev_alloc(c, &c->Fa, V));
+        chk(dev_alloc(c, &c->Iem_a, size_t(c->A.n_dir / 2) * g->nx * g->ny));
+        chk(dev_alloc(c, &c->A32, 27 * V));
+    }
+    chk(dev_alloc(c, &c->d_maxdist, 1));
     chk(upload(c, &c->seg_off, P.seg_off)); chk(upload(c, &c->seg_n, P.seg_n));
     chk(upload(c, &c->seg_a, P.seg_a)); chk(upload(c, &c->seg_bb, P.seg_bb)); chk(upload(c, &c->seg_bm, P.seg_bm));
     chk(upload(c, &c->seg_ai, P.seg_ai)); chk(upload(c, &c->seg_bi, P.seg_bi));
@@ -1156,6 +1232,8 @@ int rt3d_set_medium(rt3d_ctx *c, const double *chi, const double *eps, const dou
     c->have_medium = true;
     c->have_lstar = false;
     c->have_fs = false;
+    c->anchor_valid = false;
+    c->c_last = INFINITY;
     c->outer_iters = 0;
     c->inner_sweeps = 0;
     return sync(c);
@@ -1171,6 +1249,8 @@ int rt3d_set_J(rt3d_ctx *c, const double *J, int ptr_kind)
         for (long v = 0; v < V; ++v)
             if (!std::isfinite(J[v])) return fail(c, RT3D_ERR_ARG, "J must be finite");
         HIP_TRY(c, hipMemcpyAsync(c->J, J, V * 8, hipMemcpyHostToDevice, c->stream), "copy J");
+        c->anchor_valid = false;
+        c->c_last = INFINITY;
         return sync(c);
     }
     HIP_TRY(c, hipMemcpyAsync(c->dJa, J, V * 8, hipMemcpyDeviceToDevice, c->stream), "copy J");
@@ -1183,6 +1263,8 @@ int rt3d_set_J(rt3d_ctx *c, const double *J, int ptr_kind)
     HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
     if (flag) return fail(c, RT3D_ERR_ARG, "J must be finite");
     std::swap(c->J, c->dJa);
+    c->anchor_valid = false;
+    c->c_last = INFINITY;
     return sync(c);
 }
 
@@ -1209,7 +1291,7 @@ int rt3d_formal_solution(rt3d_ctx *c, const double *S_or_null, double *J_fs_out,
         HIP_TRY(c, hipMemcpyAsync(c->Sbuf, S_or_null, c->V * 8, kind_in(ptr_kind), c->stream), "copy S");
         S_dev = c->Sbuf;
     }
-    int rc = run_fs(c, S_dev, false);
+    int rc = run_fs(c, S_dev, false, c->precision == RT3D_FP32_SWEEP);
     if (rc) return rc;
     HIP_TRY(c, hipMemcpyAsync(J_fs_out, c->Jfs, c->V * 8, kind_out(ptr_kind), c->stream), "copy J_fs");
     return sync(c);
@@ -1239,8 +1321,20 @@ int rt3d_os_step(rt3d_ctx *c, int inner_sweeps, double *max_rel_dJ_out)
     if (!c->have_medium) return fail(c, RT3D_ERR_STATE, "set the medium first");
     if (inner_sweeps < 1) return fail(c, RT3D_ERR_ARG, "inner_sweeps must be >= 1");
     int rc = ensure_lstar(c);
-    if (!rc) rc = run_fs(c, nullptr, true);
     if (rc) return rc;
+    bool anchored = true;
+    if (c->precision == RT3D_FP32_SWEEP) {
+        // float32 sweeps of the source change since the anchor; a float64 sweep re-anchors when the
+        // step has become small next to the distance travelled since the anchor (the float32 error
+        // of a difference step scales with that distance), or when asked to
+        const bool refresh = !c->anchor_valid || c->force_refresh || c->c_last < kAnchorRatio * c->da_last;
+        rc = refresh ? refresh_anchor(c) : run_fs_difference(c);
+        anchored = refresh;
+    } else {
+        rc = run_fs(c, nullptr, true, false);
+    }
+    if (rc) return rc;
+    HIP_TRY(c, hipMemsetAsync(c->d_maxdist, 0, sizeof(unsigned long long), c->stream), "memset");
     HIP_TRY(c, hipMemsetAsync(c->d_maxrel, 0, sizeof(unsigned long long), c->stream), "memset");
     HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream), "memset");
     // sweep 1 from dJ = 0; sweeps 2..M from the previous one; the last also updates J
@@ -1253,16 +1347,21 @@ int rt3d_os_step(rt3d_ctx *c, int inner_sweeps, double *max_rel_dJ_out)
         if (rc) return rc;
         in = out;
     }
-    unsigned long long bits = 0;
+    unsigned long long bits = 0, dbits = 0;
     int flag = 0;
     HIP_TRY(c, hipMemcpyAsync(&bits, c->d_maxrel, sizeof(bits), hipMemcpyDeviceToHost, c->stream), "maxrel");
+    HIP_TRY(c, hipMemcpyAsync(&dbits, c->d_maxdist, sizeof(dbits), hipMemcpyDeviceToHost, c->stream), "maxdist");
     HIP_TRY(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream), "flag");
     rc = sync(c);
     if (rc) return rc;
     c->outer_iters += 1;
     c->inner_sweeps += inner_sweeps;
-    double cval;
+    double cval, dval;
     std::memcpy(&cval, &bits, sizeof(cval));
+    std::memcpy(&dval, &dbits, sizeof(dval));
+    c->c_last = cval;
+    c->da_last = dval;
+    c->last_step_anchored = anchored;
     if (flag) {
         if (max_rel_dJ_out) *max_rel_dJ_out = NAN;
         return fail(c, RT3D_ERR_NONFINITE, "NaN or Inf in dJ or J");
@@ -1288,7 +1387,13 @@ int rt3d_solve_to_convergence(rt3d_ctx *c, double tol, int max_iter, int inner_s
     while (n < max_iter) {
         rc = rt3d_os_step(c, inner_sweeps, &cval);
         ++n;
-        if (rc != RT3D_OK || cval < tol) break;
+        if (rc != RT3D_OK) break;
+        if (cval < tol) {
+            // the FP32 form accepts convergence only from a step whose residual is float64
+            if (c->precision != RT3D_FP32_SWEEP || c->last_step_anchored) break;
+            c->force_refresh = true;
+            continue;
+        }
         if (c->ng_order > 0) {
             HIP_TRY(c, hipMemcpyAsync(c->ng_hist + long(nh % R) * c->V, c->J, vbytes,
                                       hipMemcpyDeviceToDevice, c->stream), "ng hist");
@@ -1305,7 +1410,8 @@ int rt3d_solve_to_convergence(rt3d_ctx *c, double tol, int max_iter, int inner_s
     if (iters_out) *iters_out = n;
     if (final_rel_dJ_out) *final_rel_dJ_out = cval;
     if (rc != RT3D_OK) return rc;
-    return cval < tol ? RT3D_OK : fail(c, RT3D_ERR_NOT_CONVERGED, "max_iter reached");
+    const bool accepted = cval < tol && (c->precision != RT3D_FP32_SWEEP || c->last_step_anchored);
+    return accepted ? RT3D_OK : fail(c, RT3D_ERR_NOT_CONVERGED, "max_iter reached");
 }
 
 int rt3d_set_acceleration(rt3d_ctx *c, int ng_order, int ng_every)
@@ -1360,11 +1466,11 @@ int rt3d_get_stats(rt3d_ctx *c, char *buf, int buflen)
     char tmp[512];
     std::snprintf(tmp, sizeof tmp,
                   "\"nx\":%d,\"ny\":%d,\"nz\":%d,\"n_dir\":%d,\"precision\":\"%s\",\"outer_iters\":%ld,"
-                  "\"inner_sweeps\":%ld,\"device_bytes\":%zu,\"partial_plane_bytes\":%lld,"
+                  "\"inner_sweeps\":%ld,\"fp64_sweeps\":%ld,\"fp32_sweeps\":%ld,\"device_bytes\":%zu,\"partial_plane_bytes\":%lld,"
                   "\"sweep_workgroups\":%zu,\"sweep_threads\":%d,\"mean_segments\":%.6f,\"timing\":%s,\"kernels\":{",
                   c->g.nx, c->g.ny, c->g.nz, c->A.n_dir, c->precision == RT3D_FP64 ? "fp64" : "fp32_sweep",
-                  c->outer_iters, c->inner_sweeps, c->device_bytes,
-                  (long long)(c->plan.p_elems * (long long)c->real_size), c->plan.items.size(),
+                  c->outer_iters, c->inner_sweeps, c->fp64_sweeps, c->fp32_sweeps, c->device_bytes,
+                  (long long)(c->plan.p_elems * (long long)sizeof(double)), c->plan.items.size(),
                   c->sweep_nt, c->plan.mean_segments, c->timing ? "true" : "false");
     s += tmp;
     for (int k = 0; k < K_COUNT; ++k) {

@@ -121,3 +121,35 @@ def test_fp32_sweep_converged_error_strat17(R, orc):
     err = _rel(J, J_o)
     print(f"strat17 FP32-sweep converged J: {it} iterations, max rel error {err:.3e}")
     assert err < 1e-5
+
+
+def _strat_column(nx, ny, nz, tau, eps0, seed):
+    chi = np.broadcast_to(stratified_profile(nz, tau)[:, None, None], (nz, ny, nx)).copy()
+    chi *= np.exp(0.05 * np.random.default_rng(seed).standard_normal(chi.shape))
+    return chi, np.full(chi.shape, eps0), np.ones(chi.shape)
+
+
+@pytest.mark.parametrize("eps0", [1e-2, 1e-6])
+def test_fp32_form_reaches_fp64_accuracy(R, orc, eps0):
+    """The FP32-sweep form (float32 sweeps of the source change since a float64 anchor) converges to
+    the float64 fixed point: at the same stopping threshold its error against a tightly converged
+    FP64 oracle is within a small factor of the FP64 form's, far below the float32 level."""
+    nx, ny, nz = 7, 6, 33
+    chi, eps, B = _strat_column(nx, ny, nz, 1e3, eps0, 9)
+    J_ref, _, _, ok = orc.solve_ng(chi, eps, B, 8, 8, 1e-13, 3000, 30, 3, 6)
+    assert ok
+    errs = {}
+    for prec in (R.RT3D_FP64, R.RT3D_FP32_SWEEP):
+        with R.Solver(nx, ny, nz, 8, 8, precision=prec) as s:
+            s.set_medium(chi, eps, B)
+            s.set_acceleration(3, 6)
+            st, it, c = s.solve(1e-11, 5000, 30)
+            assert st == R.RT3D_OK
+            errs[prec] = (_rel(s.get_J(), J_ref), it, s.stats())
+    e64, e32 = errs[R.RT3D_FP64][0], errs[R.RT3D_FP32_SWEEP][0]
+    st32 = errs[R.RT3D_FP32_SWEEP][2]
+    print(f"eps={eps0}: fp64 err {e64:.2e} ({errs[R.RT3D_FP64][1]} it), fp32 form err {e32:.2e} "
+          f"({errs[R.RT3D_FP32_SWEEP][1]} it, {st32['fp64_sweeps']} fp64 + {st32['fp32_sweeps']} fp32 sweeps)")
+    assert e32 < 1e-8
+    assert e32 < 20 * e64 + 1e-10
+    assert st32["fp32_sweeps"] > st32["fp64_sweeps"]
