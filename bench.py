@@ -94,7 +94,21 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-every", type=int, default=8,
                     help="the CPU oracle times every n-th direction of the full grid")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain elementwise copy of this many MiB (3 times) and exit: the "
+                         "reference for scaling HBM byte counters")
     args = ap.parse_args()
+    if args.calibrate_copy_mib > 0:
+        import torch
+
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}), flush=True)
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the path "

@@ -270,6 +270,22 @@ bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int lines_per_w
             pi.inv_rows = 1.0f / float(rows);
             P.max_win_rows = std::max(P.max_win_rows, pi.win_rows);
             P.pairs.push_back(pi);
+            for (int k = 0; k < nz; ++k) {
+                const size_t ka = size_t(dA) * nz + k, kb = size_t(dB) * nz + k;
+                PairLayer pl{int(P.pseg.size()), P.seg_n[ka], P.row_min[ka], 0};
+                P.player.push_back(pl);
+                for (int s = 0; s < P.seg_n[ka]; ++s) {
+                    const int ia = P.seg_off[ka] + s, ib = P.seg_off[kb] + s;
+                    PairSeg ps{};
+                    ps.saA = P.seg_a[ia];
+                    ps.saB = P.seg_a[ib];
+                    ps.smnx = P.seg_bm[ia] * nx;
+                    ps.sbnx = P.seg_bb[ia] * nx;
+                    ps.len = P.seg_len[ia];
+                    ps.len32 = float(P.seg_len[ia]);
+                    P.pseg.push_back(ps);
+                }
+            }
         }
     }
     P.n_pair = int(P.pairs.size());

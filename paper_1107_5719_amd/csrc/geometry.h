@@ -52,6 +52,21 @@ struct PairInfo {
     int64_t p_off;     // element offset of this pair's partial planes in P
 };
 
+// Segment s of a pair in one layer, packed for one scalar load: column offsets of both directions
+// (modulo nx), the row offset modulo ny times nx (global row step), the row offset within the band
+// window times nx (LDS row step), and the length in both precisions.
+struct PairSeg {
+    int saA, saB, smnx, sbnx;
+    double len;
+    float len32;
+    int pad;
+};
+
+// Per (pair, layer): first entry in the packed segment list, segment count, window origin row.
+struct PairLayer {
+    int off, ns, rmin, pad;
+};
+
 // One workgroup of the sweep: direction pair p, band of line rows [j0, j0 + rows).
 struct WorkItem {
     int pair, band, j0, rows;
@@ -70,6 +85,8 @@ struct SweepPlan {
     std::vector<int> row_min;             // per (d, k): minimum row offset modulo ny
     std::vector<DirInfo> dirs;
     std::vector<PairInfo> pairs;
+    std::vector<PairSeg> pseg;            // packed per-pair segments
+    std::vector<PairLayer> player;        // per (pair, layer): index pair * nz + k
     std::vector<WorkItem> items;          // in dispatch order (most expensive first)
     int64_t p_elems = 0;                  // size of the partial-plane buffer P in elements
     int max_win_rows = 0;

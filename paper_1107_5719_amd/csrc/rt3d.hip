@@ -38,8 +38,10 @@ using rt3d::WorkItem;
 namespace {
 
 // Sweep workgroup shapes (threads, lines per thread and direction); the context picks one.
-constexpr int kSweepThreadsA = 256, kLinesPerThreadA = 8;
-constexpr int kSweepThreadsB = 512, kLinesPerThreadB = 4;
+struct SweepShape { int threads, lines; };
+// Measured on MI355X at 129^3 x 256: 512 x 2 is fastest (56 VGPRs, 8 waves/SIMD; the sweep is
+// latency-bound, so occupancy beats lines per thread and prefetching).
+constexpr SweepShape kSweepShapes[] = {{512, 2}, {512, 4}, {256, 8}, {1024, 2}, {256, 4}, {256, 2}};
 constexpr size_t kWindowBytes = 48 * 1024;   // LDS for the two deposit windows of a band
 constexpr double kAnchorRatio = 1e-3;        // FP32 form: re-anchor when c < ratio * max|J - Ja|/|J|
 constexpr int kPlaneThreads = 256;   // voxel-parallel kernels: one thread per voxel of a k-plane
@@ -123,8 +125,8 @@ __global__ void source_kernel(long V, const double *__restrict__ chi, const doub
 
 struct SweepArgs {
     int nx, ny, nz, n_down;
-    const int *seg_off, *seg_n, *seg_a, *seg_bb, *seg_bm, *row_min;
-    const void *seg_len;          // real
+    const rt3d::PairSeg *pseg;
+    const rt3d::PairLayer *player;
     const rt3d::PairInfo *pairs;
     const WorkItem *items;
     const void *cs;               // Vec2<real>
@@ -139,7 +141,14 @@ struct SweepArgs {
 // owns lines q = t + i*NT (i < LPT) of the band, for both directions.  Per layer and segment index s
 // the lines of one direction deposit into pairwise distinct cells of that direction's LDS window, so
 // each window is updated with a plain read-add-write and a barrier separates segment indices.
-template <typename real, int NT, int LPT>
+template <typename real> __device__ inline real seg_length(const rt3d::PairSeg &g);
+template <> __device__ inline double seg_length<double>(const rt3d::PairSeg &g) { return g.len; }
+template <> __device__ inline float seg_length<float>(const rt3d::PairSeg &g) { return g.len32; }
+
+// x mod n for 0 <= x < 2n, as min(x, x - n) on unsigned integers (x - n wraps when x < n)
+__device__ inline unsigned wrap_once(unsigned x, unsigned n) { return min(x, x - n); }
+
+template <typename real, int NT, int LPT, bool PF>
 __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs a)
 {
     using real2 = typename Vec2<real>::type;
@@ -147,11 +156,11 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs a)
     const WorkItem it = a.items[blockIdx.x];
     const rt3d::PairInfo pi = a.pairs[it.pair];
     const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const unsigned plane = unsigned(nx) * unsigned(ny);
     const int nlines = it.rows * nx;
     const int wsize = pi.win_rows * nx;
     real *winA = reinterpret_cast<real *>(smem_raw);
     real *winB = winA + wsize;
-    const real *seg_len = static_cast<const real *>(a.seg_len);
     const real2 *cs = static_cast<const real2 *>(a.cs);
     real *P = static_cast<real *>(a.P) + pi.p_off + long(it.band) * nz * wsize;
 
@@ -159,12 +168,14 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs a)
 
     real IA[LPT], IB[LPT];
     int li[LPT], lj[LPT];
+    unsigned lbase[LPT];
 #pragma unroll
     for (int t = 0; t < LPT; ++t) {
         const int q = threadIdx.x + t * NT;
         const int qq = q < nlines ? q : 0;
         lj[t] = qq / nx;
         li[t] = q < nlines ? qq - lj[t] * nx : -1;   // -1 marks an unused slot
+        lbase[t] = unsigned(lj[t] * nx);
         IA[t] = real(a.I_top);
         IB[t] = real(a.I_top);
     }
@@ -172,61 +183,62 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs a)
 
     for (int step = 0; step < nz; ++step) {
         const int k = pi.down ? nz - 1 - step : step;
-        const int offA = a.seg_off[pi.dA * nz + k];
-        const int offB = a.seg_off[pi.dB * nz + k];
-        const int ns = a.seg_n[pi.dA * nz + k];
-        const int rmin = a.row_min[pi.dA * nz + k];
-        const real2 *csk = cs + long(k) * nx * ny;
-        int r0[LPT];
+        const rt3d::PairLayer L = a.player[it.pair * nz + k];
+        const real2 *csk = cs + long(k) * plane;
+        unsigned grow0[LPT];
 #pragma unroll
         for (int t = 0; t < LPT; ++t) {
-            int r = it.j0 + lj[t] + rmin;
-            r -= (r >= ny) ? ny : 0;
-            r -= (r >= ny) ? ny : 0;
-            r0[t] = r;
+            unsigned r = unsigned(it.j0 + lj[t] + L.rmin);
+            r = wrap_once(wrap_once(r, ny), ny);
+            grow0[t] = r * unsigned(nx);
         }
         if (!pi.down && step == 0) {
             // upward lines enter through the bottom plane: boundary light of the entry voxel
-            const int saA = a.seg_a[offA], saB = a.seg_a[offB], sm = a.seg_bm[offA];
+            const rt3d::PairSeg g = a.pseg[L.off];
 #pragma unroll
             for (int t = 0; t < LPT; ++t) {
                 if (li[t] < 0) continue;
-                int row = r0[t] + sm;
-                row -= (row >= ny) ? ny : 0;
-                int cA = li[t] + saA, cB = li[t] + saB;
-                cA -= (cA >= nx) ? nx : 0;
-                cB -= (cB >= nx) ? nx : 0;
-                IA[t] = a.Ibot ? real(a.Ibot[row * nx + cA]) : real(0);
-                IB[t] = a.Ibot ? real(a.Ibot[row * nx + cB]) : real(0);
+                const unsigned row = wrap_once(grow0[t] + unsigned(g.smnx), plane);
+                const unsigned cA = wrap_once(unsigned(li[t] + g.saA), nx);
+                const unsigned cB = wrap_once(unsigned(li[t] + g.saB), nx);
+                IA[t] = a.Ibot ? real(a.Ibot[row + cA]) : real(0);
+                IB[t] = a.Ibot ? real(a.Ibot[row + cB]) : real(0);
             }
         }
-        for (int s = 0; s < ns; ++s) {
-            const int saA = a.seg_a[offA + s];
-            const int saB = a.seg_a[offB + s];
-            const int sb = a.seg_bb[offA + s];
-            const int sm = a.seg_bm[offA + s];
-            const real len = seg_len[offA + s];
-            real2 cA[LPT], cB[LPT];
-            int colA[LPT], colB[LPT], grow[LPT];
+        // gathers of segment s (prefetch variant: segment s+1's are issued before s is computed)
+        real2 nA[LPT], nB[LPT];
+        unsigned ncA[LPT], ncB[LPT];
+        auto gather = [&](const rt3d::PairSeg &g, real2 *dA, real2 *dB, unsigned *cA_, unsigned *cB_) {
 #pragma unroll
             for (int t = 0; t < LPT; ++t) {
-                int row = r0[t] + sm;
-                row -= (row >= ny) ? ny : 0;
-                int ca = li[t] + saA, cb = li[t] + saB;
-                ca -= (ca >= nx) ? nx : 0;
-                cb -= (cb >= nx) ? nx : 0;
-                colA[t] = ca;
-                colB[t] = cb;
-                grow[t] = row * nx;
+                const unsigned grow = wrap_once(grow0[t] + unsigned(g.smnx), plane);
+                cA_[t] = wrap_once(unsigned(li[t] + g.saA), nx);
+                cB_[t] = wrap_once(unsigned(li[t] + g.saB), nx);
                 if (li[t] >= 0) {
-                    cA[t] = csk[grow[t] + ca];
-                    cB[t] = csk[grow[t] + cb];
+                    dA[t] = csk[grow + cA_[t]];
+                    dB[t] = csk[grow + cB_[t]];
                 }
+            }
+        };
+        if (PF && L.ns > 0) gather(a.pseg[L.off], nA, nB, ncA, ncB);
+        for (int s = 0; s < L.ns; ++s) {
+            const rt3d::PairSeg g = a.pseg[L.off + s];
+            const real len = seg_length<real>(g);
+            real2 cA[LPT], cB[LPT];
+            unsigned colA[LPT], colB[LPT];
+            if (PF) {
+#pragma unroll
+                for (int t = 0; t < LPT; ++t) {
+                    cA[t] = nA[t]; cB[t] = nB[t]; colA[t] = ncA[t]; colB[t] = ncB[t];
+                }
+                if (s + 1 < L.ns) gather(a.pseg[L.off + s + 1], nA, nB, ncA, ncB);
+            } else {
+                gather(g, cA, cB, colA, colB);
             }
 #pragma unroll
             for (int t = 0; t < LPT; ++t) {
                 if (li[t] < 0) continue;
-                const int wrow = (lj[t] + sb) * nx;
+                const unsigned wrow = lbase[t] + unsigned(g.sbnx);
                 {
                     const real dtau = cA[t].x * len;
                     const real em1 = expm1_nonpos(-dtau);          // e^{-dtau} - 1
@@ -253,13 +265,12 @@ __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs a)
         __syncthreads();
     }
     if (!pi.down && a.Iem) {
-        double *EA = a.Iem + long(pi.dA - a.n_down) * nx * ny;
-        double *EB = a.Iem + long(pi.dB - a.n_down) * nx * ny;
+        const long ea0 = long(pi.dA - a.n_down) * plane, eb0 = long(pi.dB - a.n_down) * plane;
 #pragma unroll
         for (int t = 0; t < LPT; ++t) {
             if (li[t] < 0) continue;
-            const long ea = (EA - a.Iem) + (it.j0 + lj[t]) * nx + li[t];
-            const long eb = (EB - a.Iem) + (it.j0 + lj[t]) * nx + li[t];
+            const long ea = ea0 + (it.j0 + lj[t]) * nx + li[t];
+            const long eb = eb0 + (it.j0 + lj[t]) * nx + li[t];
             const double baseA = a.Iem_base ? a.Iem_base[ea] : 0.0;
             const double baseB = a.Iem_base ? a.Iem_base[eb] : 0.0;
             a.Iem[ea] = baseA + double(IA[t]);
@@ -660,7 +671,8 @@ struct rt3d_ctx {
     long V = 0;
     size_t real_size = 8;
     int lstar_early_exit = 0;
-    int sweep_nt = kSweepThreadsB;
+    int sweep_shape = 0;       // index into kSweepShapes
+    int sweep_prefetch = 0;
     // device buffers (owned)
     double *chi = nullptr, *eps = nullptr, *B = nullptr, *J = nullptr, *Jfs = nullptr, *r = nullptr;
     double *dJa = nullptr, *dJb = nullptr, *L = nullptr, *Acoef = nullptr, *Iem = nullptr;
@@ -679,6 +691,8 @@ struct rt3d_ctx {
     int *seg_ai = nullptr, *seg_bi = nullptr, *row_min = nullptr;
     DirInfo *dirs = nullptr;
     rt3d::PairInfo *pairs = nullptr;
+    rt3d::PairSeg *pseg = nullptr;
+    rt3d::PairLayer *player = nullptr;
     WorkItem *items = nullptr;
     unsigned long long *d_maxrel = nullptr;
     int *d_flag = nullptr;
@@ -853,9 +867,7 @@ int launch_sweep(rt3d_ctx *c, bool fp32, bool diff)
     SweepArgs a;
     a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
     a.n_down = c->A.n_dir / 2;
-    a.seg_off = c->seg_off; a.seg_n = c->seg_n; a.seg_a = c->seg_a; a.seg_bb = c->seg_bb;
-    a.seg_bm = c->seg_bm; a.row_min = c->row_min;
-    a.seg_len = fp32 ? static_cast<const void *>(c->seg_len32) : static_cast<const void *>(c->seg_len64);
+    a.pseg = c->pseg; a.player = c->player;
     a.pairs = c->pairs; a.items = c->items;
     a.cs = c->cs;
     a.Ibot = (c->g.bottom_bc == 0 && !diff) ? c->B : nullptr;
@@ -867,21 +879,28 @@ int launch_sweep(rt3d_ctx *c, bool fp32, bool diff)
     const dim3 grid(c->plan.items.size());
     TimedLaunch t(c, K_SWEEP);
     if (fp32) c->fp32_sweeps += 1; else c->fp64_sweeps += 1;
-    if (c->sweep_nt == kSweepThreadsA) {
-        if (!fp32)
-            hipLaunchKernelGGL((sweep_kernel<double, kSweepThreadsA, kLinesPerThreadA>), grid,
-                               dim3(kSweepThreadsA), smem, c->stream, a);
-        else
-            hipLaunchKernelGGL((sweep_kernel<float, kSweepThreadsA, kLinesPerThreadA>), grid,
-                               dim3(kSweepThreadsA), smem, c->stream, a);
-    } else {
-        if (!fp32)
-            hipLaunchKernelGGL((sweep_kernel<double, kSweepThreadsB, kLinesPerThreadB>), grid,
-                               dim3(kSweepThreadsB), smem, c->stream, a);
-        else
-            hipLaunchKernelGGL((sweep_kernel<float, kSweepThreadsB, kLinesPerThreadB>), grid,
-                               dim3(kSweepThreadsB), smem, c->stream, a);
+#define RT3D_LAUNCH_SWEEP(NT_, LPT_, PF_)                                                      \
+    do {                                                                                          \
+        if (!fp32)                                                                                \
+            hipLaunchKernelGGL((sweep_kernel<double, NT_, LPT_, PF_>), grid, dim3(NT_), smem,     \
+                               c->stream, a);                                                     \
+        else                                                                                      \
+            hipLaunchKernelGGL((sweep_kernel<float, NT_, LPT_, PF_>), grid, dim3(NT_), smem,      \
+                               c->stream, a);                                                     \
+    } while (0)
+    switch (c->sweep_shape) {
+    case 1:
+        if (c->sweep_prefetch) RT3D_LAUNCH_SWEEP(512, 4, true); else RT3D_LAUNCH_SWEEP(512, 4, false);
+        break;
+    case 2:
+        if (c->sweep_prefetch) RT3D_LAUNCH_SWEEP(256, 8, true); else RT3D_LAUNCH_SWEEP(256, 8, false);
+        break;
+    case 3: RT3D_LAUNCH_SWEEP(1024, 2, false); break;
+    case 4: RT3D_LAUNCH_SWEEP(256, 4, false); break;
+    case 5: RT3D_LAUNCH_SWEEP(256, 2, false); break;
+    default: RT3D_LAUNCH_SWEEP(512, 2, false); break;
     }
+#undef RT3D_LAUNCH_SWEEP
     return check_launch(c, "sweep_kernel");
 }
 
@@ -1046,7 +1065,7 @@ void free_all(rt3d_ctx *c)
     void *ptrs[] = {c->chi, c->eps, c->B, c->J, c->Jfs, c->r, c->dJa, c->dJb, c->L, c->Acoef, c->Iem,
                     c->Sbuf, c->cs, c->P, c->seg_len32, c->seg_len64, c->Ja, c->Fa, c->Iem_a, c->A32,
                     c->d_maxdist, c->seg_off, c->seg_n, c->seg_a,
-                    c->seg_bb, c->seg_bm, c->seg_ai, c->seg_bi, c->row_min, c->dirs, c->items, c->pairs,
+                    c->seg_bb, c->seg_bm, c->seg_ai, c->seg_bi, c->row_min, c->dirs, c->items, c->pairs, c->pseg, c->player,
                     c->d_maxrel, c->d_flag, c->ng_hist, c->ng_partial};
     for (void *p : ptrs)
         if (p) hipFree(p);
@@ -1134,14 +1153,18 @@ int rt3d_create(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, void *hi
     c->real_size = (precision == RT3D_FP64) ? sizeof(double) : sizeof(float);
     c->V = long(g->nx) * g->ny * g->nz;
     if (!rt3d::make_angle_set(g->n_theta, g->n_phi, c->A)) { delete c; return RT3D_ERR_ARG; }
-    // workgroup shape of the sweep (512 x 4 lines by default; RT3D_SWEEP_THREADS=256 for 256 x 8)
-    if (const char *e = std::getenv("RT3D_SWEEP_THREADS")) {
-        if (std::atoi(e) == kSweepThreadsA) c->sweep_nt = kSweepThreadsA;
+    // workgroup shape of the sweep: RT3D_SWEEP_SHAPE indexes kSweepShapes (default 512 threads x 2 lines)
+    if (const char *e = std::getenv("RT3D_SWEEP_SHAPE")) {
+        const int v = std::atoi(e);
+        if (v >= 0 && v < int(sizeof(kSweepShapes) / sizeof(kSweepShapes[0]))) c->sweep_shape = v;
     }
-    const int lines = (c->sweep_nt == kSweepThreadsA) ? kSweepThreadsA * kLinesPerThreadA
-                                                      : kSweepThreadsB * kLinesPerThreadB;
+    // gathers of the next segment issued before the current one is computed (RT3D_SWEEP_PREFETCH=1;
+    // shapes 1 and 2 only; slower on MI355X because it costs occupancy)
+    if (const char *e = std::getenv("RT3D_SWEEP_PREFETCH")) c->sweep_prefetch = std::atoi(e) != 0;
+    const SweepShape shape = kSweepShapes[c->sweep_shape];
+    const int lines = shape.threads * shape.lines;
     // one plan for both precisions: the LDS windows are budgeted for float64
-    if (!rt3d::build_sweep_plan(g->nx, g->ny, g->nz, c->A, lines, 16 * c->sweep_nt, kWindowBytes,
+    if (!rt3d::build_sweep_plan(g->nx, g->ny, g->nz, c->A, lines, 16 * shape.threads, kWindowBytes,
                                 int(sizeof(double)), c->plan, msg)) {
         delete c;
         return RT3D_ERR_ARG;
@@ -1182,6 +1205,7 @@ int rt3d_create(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, void *hi
     chk(upload(c, &c->seg_ai, P.seg_ai)); chk(upload(c, &c->seg_bi, P.seg_bi));
     chk(upload(c, &c->row_min, P.row_min));
     chk(upload(c, &c->dirs, P.dirs)); chk(upload(c, &c->items, P.items)); chk(upload(c, &c->pairs, P.pairs));
+    chk(upload(c, &c->pseg, P.pseg)); chk(upload(c, &c->player, P.player));
     chk(dev_alloc(c, &c->d_maxrel, 1)); chk(dev_alloc(c, &c->d_flag, 1));
     if (rc) {
         free_all(c);
@@ -1471,7 +1495,7 @@ int rt3d_get_stats(rt3d_ctx *c, char *buf, int buflen)
                   c->g.nx, c->g.ny, c->g.nz, c->A.n_dir, c->precision == RT3D_FP64 ? "fp64" : "fp32_sweep",
                   c->outer_iters, c->inner_sweeps, c->fp64_sweeps, c->fp32_sweeps, c->device_bytes,
                   (long long)(c->plan.p_elems * (long long)sizeof(double)), c->plan.items.size(),
-                  c->sweep_nt, c->plan.mean_segments, c->timing ? "true" : "false");
+                  kSweepShapes[c->sweep_shape].threads, c->plan.mean_segments, c->timing ? "true" : "false");
     s += tmp;
     for (int k = 0; k < K_COUNT; ++k) {
         std::snprintf(tmp, sizeof tmp, "%s\"%s\":{\"launches\":%ld,\"total_ms\":%.6f}", k ? "," : "",
