@@ -16,7 +16,8 @@
 //   reduce_kernel   per voxel, sums the partial planes of all directions in a fixed order:
 //                   J_fs = (1/chi) sum_d W_d |mu_d| sum_bands P, and r = J_fs - J.
 //   lstar_kernel    per voxel, the 27 derivatives dJ_v/dS_u along the lines through v (exact band).
-//   coef_kernel     A_vu = Lambda*_vu (1 - eps_u) and the Jacobi denominator 1 - Lambda*_vv (1-eps_v).
+//   coef_kernel     the Jacobi coefficients: chi_v Lambda*_vu for the 13 upper neighbours (the
+//                   lower ones follow by reciprocity) and the per-voxel scalings.
 //   jacobi_kernel   one Jacobi sweep of the OS equations (27-point stencil); the last sweep also
 //                   updates J and reduces max |dJ|/|J| (and flags NaN/Inf).
 #include <hip/hip_runtime.h>
@@ -445,48 +446,47 @@ __global__ __launch_bounds__(kPlaneThreads) void lstar_kernel(LstarArgs a)
         for (int o = 0; o < 27; ++o) a.L[o * V + v] = acc[o][threadIdx.x];
 }
 
-// A_o(v) = Lambda*_o(v) (1 - eps_u) for o != 13, A_13(v) = 1 - Lambda*_13(v) (1 - eps_v).
+// Jacobi coefficients.  K_vu = chi_v Lambda*_vu is symmetric (reciprocity: lines for Omega and -Omega
+// coincide and the weights are symmetric), so only the 13 upper neighbours o = 14..26 are stored:
+// Kc[o - 14][v] = chi_v Lambda*_o(v).  The entry for a lower neighbour u = v + d(o), o < 13, is
+// Kc[12 - o][u] (u's upper neighbour 26 - o is v).  Per voxel: invD = 1 / (chi_v (1 - Lambda*_vv (1-eps_v)))
+// and E = (1 - eps_v) invD.
+template <typename coef>
 __global__ __launch_bounds__(kPlaneThreads) void coef_kernel(int nx, int ny, int nz,
                                                              const double *__restrict__ L,
+                                                             const double *__restrict__ chi,
                                                              const double *__restrict__ eps,
-                                                             double *__restrict__ A, float *__restrict__ A32)
+                                                             coef *__restrict__ Kc, double *__restrict__ invD,
+                                                             double *__restrict__ E)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y;
     if (p >= nx * ny) return;
-    const int j = p / nx, i = p - j * nx;
     const long plane = long(nx) * ny, V = plane * nz, v = k * plane + p;
-    for (int o = 0; o < 27; ++o) {
-        const int dk = o / 9 - 1, dj = (o / 3) % 3 - 1, di = o % 3 - 1;
-        const int kk = k + dk;
-        double val = 0.0;
-        if (o == 13) {
-            val = 1.0 - L[13 * V + v] * (1.0 - eps[v]);
-        } else if (kk >= 0 && kk < nz) {
-            int jj = j + dj, ii = i + di;
-            jj += (jj < 0) ? ny : 0;
-            jj -= (jj >= ny) ? ny : 0;
-            ii += (ii < 0) ? nx : 0;
-            ii -= (ii >= nx) ? nx : 0;
-            val = L[o * V + v] * (1.0 - eps[kk * plane + long(jj) * nx + ii]);
-        }
-        A[o * V + v] = val;
-        if (A32) A32[o * V + v] = float(val);
+    const double c = chi[v];
+    for (int o = 14; o < 27; ++o) {
+        const int kk = k + o / 9 - 1;
+        Kc[(o - 14) * V + v] = coef((kk < nz) ? c * L[o * V + v] : 0.0);
     }
+    const double inv = 1.0 / (c * (1.0 - L[13 * V + v] * (1.0 - eps[v])));
+    invD[v] = inv;
+    E[v] = (1.0 - eps[v]) * inv;
 }
 
 // ------------------------------------------------------------------------------------------------
 // Jacobi sweep of the OS equations, optionally fused with the J update and max |dJ|/|J|
 // ------------------------------------------------------------------------------------------------
 
+// The sweep dJ_v <- (r_v + sum_{u != v} Lambda*_vu (1-eps_u) dJ_u) / (1 - Lambda*_vv (1-eps_v)) is
+// evaluated as (chi_v r_v + sum_u K_vu w_u) invD_v with w = (1 - eps) dJ carried between sweeps.
 struct JacobiArgs {
     int nx, ny, nz;
-    const double *r;
-    const void *A;               // [27][V] coefficients (double, or float in the FP32 form);
-                                 // A[13] holds the denominator
-    const double *dJ_in;         // null: dJ^0 = 0 (first sweep)
-    double *dJ_out;              // may be null when J is updated
-    double *J;                   // null: no update
+    const double *r, *chi;
+    const void *Kc;              // [13][V] upper coefficients (double, or float in the FP32 form)
+    const double *invD, *E;
+    const double *w_in;          // (1 - eps) dJ of the previous sweep; null: dJ^0 = 0 (first sweep)
+    double *w_out;               // (1 - eps) dJ of this sweep (intermediate sweeps)
+    double *J;                   // last sweep: J += dJ (null otherwise)
     unsigned long long *maxrel;  // bits of max |dJ|/|J| (non-negative doubles order like integers)
     const double *Ja;            // anchor iterate of the FP32 form (may be null)
     unsigned long long *maxdist; // bits of max |J - Ja|/|J| when Ja is given
@@ -497,7 +497,7 @@ struct JacobiArgs {
 template <typename coef>
 __global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel(JacobiArgs a)
 {
-    const coef *Ac = static_cast<const coef *>(a.A);
+    const coef *Kc = static_cast<const coef *>(a.Kc);
     double dist = 0.0;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -508,8 +508,8 @@ __global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel(JacobiArgs a)
     if (valid) {
         const int j = p / nx, i = p - j * nx;
         const long plane = long(nx) * ny, V = plane * nz, v = k * plane + p;
-        double acc = a.r[v];
-        if (a.dJ_in) {
+        double acc = a.chi[v] * a.r[v];
+        if (a.w_in) {
             const int im = (i == 0) ? nx - 1 : i - 1, ip = (i == nx - 1) ? 0 : i + 1;
             const int jm = (j == 0) ? ny - 1 : j - 1, jp = (j == ny - 1) ? 0 : j + 1;
             const int cols[3] = {im, i, ip};
@@ -520,12 +520,13 @@ __global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel(JacobiArgs a)
                 const int kk = k + o / 9 - 1;
                 if (kk < 0 || kk >= nz) continue;
                 const long u = kk * plane + long(rows[(o / 3) % 3]) * nx + cols[o % 3];
-                acc += double(Ac[o * V + v]) * a.dJ_in[u];
+                const double K = (o > 13) ? double(Kc[(o - 14) * V + v]) : double(Kc[(12 - o) * V + u]);
+                acc += K * a.w_in[u];
             }
         }
-        const double dJ = acc / double(Ac[13 * V + v]);
-        if (a.dJ_out) a.dJ_out[v] = dJ;
+        if (a.w_out) a.w_out[v] = acc * a.E[v];
         if (a.J) {
+            const double dJ = acc * a.invD[v];
             const double Jn = a.J[v] + dJ;
             a.J[v] = Jn;
             q = fabs(dJ) / fabs(Jn);
@@ -675,14 +676,15 @@ struct rt3d_ctx {
     int sweep_prefetch = 0;
     // device buffers (owned)
     double *chi = nullptr, *eps = nullptr, *B = nullptr, *J = nullptr, *Jfs = nullptr, *r = nullptr;
-    double *dJa = nullptr, *dJb = nullptr, *L = nullptr, *Acoef = nullptr, *Iem = nullptr;
+    double *dJa = nullptr, *dJb = nullptr, *L = nullptr, *Iem = nullptr;
+    double *Kc = nullptr, *invD = nullptr, *Ecoef = nullptr;   // Jacobi coefficients (float64 form)
     double *Sbuf = nullptr;
     void *cs = nullptr, *P = nullptr;       // sized for float64; float sweeps use the first half
     double *seg_len64 = nullptr;
     float *seg_len32 = nullptr;
     // FP32 form: anchor iterate, its float64 formal solution and top-plane light, float coefficients
     double *Ja = nullptr, *Fa = nullptr, *Iem_a = nullptr;
-    float *A32 = nullptr;
+    float *Kc32 = nullptr;                                     // Jacobi coefficients (FP32 form)
     unsigned long long *d_maxdist = nullptr;
     bool anchor_valid = false, force_refresh = false, last_step_anchored = false;
     double c_last = INFINITY, da_last = 0.0;
@@ -969,8 +971,12 @@ int ensure_lstar(rt3d_ctx *c)
     if (rc) return rc;
     {
         TimedLaunch t(c, K_COEF);
-        hipLaunchKernelGGL(coef_kernel, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, c->g.nx,
-                           c->g.ny, c->g.nz, c->L, c->eps, c->Acoef, c->A32);
+        if (c->precision == RT3D_FP32_SWEEP)
+            hipLaunchKernelGGL(coef_kernel<float>, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, c->g.nx,
+                               c->g.ny, c->g.nz, c->L, c->chi, c->eps, c->Kc32, c->invD, c->Ecoef);
+        else
+            hipLaunchKernelGGL(coef_kernel<double>, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, c->g.nx,
+                               c->g.ny, c->g.nz, c->L, c->chi, c->eps, c->Kc, c->invD, c->Ecoef);
     }
     rc = check_launch(c, "coef_kernel");
     if (rc) return rc;
@@ -978,13 +984,14 @@ int ensure_lstar(rt3d_ctx *c)
     return RT3D_OK;
 }
 
-int launch_jacobi(rt3d_ctx *c, const double *dJ_in, double *dJ_out, bool update)
+int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update)
 {
     JacobiArgs a;
     const bool f32 = c->precision == RT3D_FP32_SWEEP;
     a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
-    a.r = c->r; a.dJ_in = dJ_in; a.dJ_out = dJ_out;
-    a.A = f32 ? static_cast<const void *>(c->A32) : static_cast<const void *>(c->Acoef);
+    a.r = c->r; a.chi = c->chi; a.w_in = w_in; a.w_out = w_out;
+    a.Kc = f32 ? static_cast<const void *>(c->Kc32) : static_cast<const void *>(c->Kc);
+    a.invD = c->invD; a.E = c->Ecoef;
     a.J = update ? c->J : nullptr;
     a.maxrel = c->d_maxrel; a.nonfinite = c->d_flag;
     a.Ja = (f32 && update) ? c->Ja : nullptr;
@@ -1062,8 +1069,8 @@ int ng_step(rt3d_ctx *c, int m)
 
 void free_all(rt3d_ctx *c)
 {
-    void *ptrs[] = {c->chi, c->eps, c->B, c->J, c->Jfs, c->r, c->dJa, c->dJb, c->L, c->Acoef, c->Iem,
-                    c->Sbuf, c->cs, c->P, c->seg_len32, c->seg_len64, c->Ja, c->Fa, c->Iem_a, c->A32,
+    void *ptrs[] = {c->chi, c->eps, c->B, c->J, c->Jfs, c->r, c->dJa, c->dJb, c->L, c->Kc, c->invD, c->Ecoef, c->Iem,
+                    c->Sbuf, c->cs, c->P, c->seg_len32, c->seg_len64, c->Ja, c->Fa, c->Iem_a, c->Kc32,
                     c->d_maxdist, c->seg_off, c->seg_n, c->seg_a,
                     c->seg_bb, c->seg_bm, c->seg_ai, c->seg_bi, c->row_min, c->dirs, c->items, c->pairs, c->pseg, c->player,
                     c->d_maxrel, c->d_flag, c->ng_hist, c->ng_partial};
@@ -1185,7 +1192,9 @@ int rt3d_create(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, void *hi
     chk(dev_alloc(c, &c->chi, V)); chk(dev_alloc(c, &c->eps, V)); chk(dev_alloc(c, &c->B, V));
     chk(dev_alloc(c, &c->J, V)); chk(dev_alloc(c, &c->Jfs, V)); chk(dev_alloc(c, &c->r, V));
     chk(dev_alloc(c, &c->dJa, V)); chk(dev_alloc(c, &c->dJb, V)); chk(dev_alloc(c, &c->Sbuf, V));
-    chk(dev_alloc(c, &c->L, 27 * V)); chk(dev_alloc(c, &c->Acoef, 27 * V));
+    chk(dev_alloc(c, &c->L, 27 * V));
+    chk(dev_alloc(c, &c->invD, V)); chk(dev_alloc(c, &c->Ecoef, V));
+    if (precision == RT3D_FP64) chk(dev_alloc(c, &c->Kc, 13 * V));
     chk(dev_alloc(c, &c->Iem, size_t(c->A.n_dir / 2) * g->nx * g->ny));
     {
         double2 *cs = nullptr; double *Pp = nullptr;
@@ -1197,7 +1206,7 @@ int rt3d_create(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, void *hi
     if (precision == RT3D_FP32_SWEEP) {
         chk(dev_alloc(c, &c->Ja, V)); chk(dev_alloc(c, &c->Fa, V));
         chk(dev_alloc(c, &c->Iem_a, size_t(c->A.n_dir / 2) * g->nx * g->ny));
-        chk(dev_alloc(c, &c->A32, 27 * V));
+        chk(dev_alloc(c, &c->Kc32, 13 * V));
     }
     chk(dev_alloc(c, &c->d_maxdist, 1));
     chk(upload(c, &c->seg_off, P.seg_off)); chk(upload(c, &c->seg_n, P.seg_n));
@@ -1361,7 +1370,8 @@ int rt3d_os_step(rt3d_ctx *c, int inner_sweeps, double *max_rel_dJ_out)
     HIP_TRY(c, hipMemsetAsync(c->d_maxdist, 0, sizeof(unsigned long long), c->stream), "memset");
     HIP_TRY(c, hipMemsetAsync(c->d_maxrel, 0, sizeof(unsigned long long), c->stream), "memset");
     HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream), "memset");
-    // sweep 1 from dJ = 0; sweeps 2..M from the previous one; the last also updates J
+    // sweep 1 from dJ = 0; sweeps 2..M from the previous one (carried as (1 - eps) dJ); the last
+    // also updates J
     const double *in = nullptr;
     double *bufs[2] = {c->dJa, c->dJb};
     for (int m = 0; m < inner_sweeps; ++m) {
