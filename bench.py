@@ -24,13 +24,45 @@ sys.path.insert(0, ROOT)
 
 METRIC = "voxel·angle FS updates/s + time-to-converged J, 129³×256 angles, FP32 vs FP64"
 HBM_PEAK_GBS = 8000.0
+# MI355X vector peaks: 256 CUs x 2.4 GHz; FP64 78.6 TFLOP/s, FP32 157.3 TFLOP/s (FMA = 2 flops)
+ALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+# Arithmetic per voxel-angle update of the sweep: about 4 segments x (one exponential + ~10 multiply-
+# adds) ~ 140 FP64 or ~80 FP32 vector operations, each priced as an FMA (2 flops).
+SWEEP_OPS_PER_UPDATE = {"fp64": 140, "fp32": 80}
+SWEEP_KERNEL = {"fp64": "sweep_kernel<double,512,2>", "fp32": "sweep_kernel<float,512,2>"}
+JACOBI_KERNEL = {"fp64": "jacobi_kernel<double>", "fp32": "jacobi_kernel<float>"}
 
 
 def sweep_bytes_per_update(precision: str) -> int:
     """Algorithmic HBM bytes of the sweep kernel per voxel-angle update: chi and S of the voxel read
-    once per direction, and one partial-plane value written once per direction."""
+    once per direction, and one partial-plane value per direction pair (x-mirrored directions share
+    it), i.e. half a value per direction."""
     s_r = 8 if precision == "fp64" else 4
-    return 2 * s_r + s_r
+    return 2 * s_r + s_r // 2
+
+
+def jacobi_bytes_per_voxel(precision: str) -> int:
+    """Algorithmic HBM bytes of one Jacobi sweep per voxel: 13 stored coefficients (the other 13 are
+    their mirrors), chi, r, 1/D, E, the previous (1-eps) dJ and the new one."""
+    return 13 * (8 if precision == "fp64" else 4) + 6 * 8
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per dispatch (FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration) from the
+    committed rocprofv3 summary, or None if the kernel source changed since it was measured."""
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_1107_5719_amd", "csrc", "rt3d.hip")
+    prof = os.path.join(ROOT, "profiles", "strat129_hbm_bytes.txt")
+    if not os.path.exists(prof):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(prof):
+        if line.startswith("TRAFFIC "):
+            f = dict(kv.split("=", 1) for kv in line.split()[1:])
+            if f["kernel"] == kernel and f["source_sha"] == sha:
+                return int(f["fetch_bytes"]) + int(f["write_bytes"])
+    return None
 
 
 def _timed_steps(rt3d, torch, w, d_med, prec, stream, steps, warmup, M):
@@ -155,11 +187,23 @@ def main() -> int:
                       "sweeps": {"fp64": st["fp64_sweeps"], "fp32": st["fp32_sweeps"]}}
     main_form = args.precision
     sweep_ms = step[main_form]["kernel_ms_per_launch"]["sweep"]
+    upd_per_s = V * n_dir / (sweep_ms * 1e-3)
+    tflops = 2 * SWEEP_OPS_PER_UPDATE[main_form] * upd_per_s / 1e12
     b_unit = sweep_bytes_per_update(main_form)
-    achieved = b_unit * V * n_dir / (sweep_ms * 1e-3) / 1e9
-    roofline = {"kernel": "sweep_kernel", "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_update": b_unit, "sweep_ms_per_launch": sweep_ms}
+    hbm_gbs = b_unit * upd_per_s / 1e9
+    roofline = {"kernel": SWEEP_KERNEL[main_form], "bound": "alu", "achieved": round(tflops, 2),
+                "peak": ALU_PEAK_TFLOPS[main_form], "unit": "TFLOP/s",
+                "frac": round(tflops / ALU_PEAK_TFLOPS[main_form], 4),
+                "traffic": measured_traffic(SWEEP_KERNEL[main_form]),
+                "ops_per_update": 2 * SWEEP_OPS_PER_UPDATE[main_form], "ms_per_launch": sweep_ms,
+                "hbm_view": {"achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "bytes_per_update": b_unit}}
+    jac_ms = step[main_form]["kernel_ms_per_launch"]["jacobi"]
+    jac_gbs = jacobi_bytes_per_voxel(main_form) * V / (jac_ms * 1e-3) / 1e9
+    roofline_jacobi = {"kernel": JACOBI_KERNEL[main_form], "bound": "hbm", "achieved": round(jac_gbs, 1),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(jac_gbs / HBM_PEAK_GBS, 4),
+                       "traffic": measured_traffic(JACOBI_KERNEL[main_form]),
+                       "bytes_per_voxel": jacobi_bytes_per_voxel(main_form), "ms_per_launch": jac_ms}
 
     # ---- time to converged J, both forms, against a tight float64 reference -------------------------
     conv = None
@@ -215,6 +259,7 @@ def main() -> int:
                            "M Jacobi sweeps, J update + max rel dJ"},
         "forms": step,
         "roofline": roofline,
+        "roofline_jacobi": roofline_jacobi,
         "cpu_baseline": cpu,
         "time_to_converged": conv,
     }

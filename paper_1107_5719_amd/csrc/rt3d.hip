@@ -674,6 +674,7 @@ struct rt3d_ctx {
     int lstar_early_exit = 0;
     int sweep_shape = 0;       // index into kSweepShapes
     int sweep_prefetch = 0;
+    int jacobi_xcd = 1;        // XCD-aware Jacobi grid (RT3D_JACOBI_XCD=0 disables)
     // device buffers (owned)
     double *chi = nullptr, *eps = nullptr, *B = nullptr, *J = nullptr, *Jfs = nullptr, *r = nullptr;
     double *dJa = nullptr, *dJb = nullptr, *L = nullptr, *Iem = nullptr;
@@ -849,6 +850,15 @@ dim3 plane_grid(const rt3d_ctx *c)
     return dim3((c->g.nx * c->g.ny + kPlaneThreads - 1) / kPlaneThreads, c->g.nz);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2) in linear order.
+// Padding the chunks of a plane to a multiple of 8 sends a chunk's blocks of every plane to the same
+// XCD, so the plane-below data a Jacobi sweep re-reads is in that XCD's L2.  Padding blocks exit.
+dim3 plane_grid_xcd(const rt3d_ctx *c)
+{
+    const unsigned chunks = (c->g.nx * c->g.ny + kPlaneThreads - 1) / kPlaneThreads;
+    return dim3((chunks + 7) / 8 * 8, c->g.nz);
+}
+
 int launch_source(rt3d_ctx *c, const double *S_given, const double *Ja, bool fp32)
 {
     TimedLaunch t(c, K_SOURCE);
@@ -997,10 +1007,11 @@ int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update)
     a.Ja = (f32 && update) ? c->Ja : nullptr;
     a.maxdist = c->d_maxdist;
     TimedLaunch t(c, K_JACOBI);
+    const dim3 grid = c->jacobi_xcd ? plane_grid_xcd(c) : plane_grid(c);
     if (f32)
-        hipLaunchKernelGGL(jacobi_kernel<float>, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(jacobi_kernel<float>, grid, dim3(kPlaneThreads), 0, c->stream, a);
     else
-        hipLaunchKernelGGL(jacobi_kernel<double>, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(jacobi_kernel<double>, grid, dim3(kPlaneThreads), 0, c->stream, a);
     return check_launch(c, "jacobi_kernel");
 }
 
@@ -1168,6 +1179,7 @@ int rt3d_create(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, void *hi
     // gathers of the next segment issued before the current one is computed (RT3D_SWEEP_PREFETCH=1;
     // shapes 1 and 2 only; slower on MI355X because it costs occupancy)
     if (const char *e = std::getenv("RT3D_SWEEP_PREFETCH")) c->sweep_prefetch = std::atoi(e) != 0;
+    if (const char *e = std::getenv("RT3D_JACOBI_XCD")) c->jacobi_xcd = std::atoi(e) != 0;
     const SweepShape shape = kSweepShapes[c->sweep_shape];
     const int lines = shape.threads * shape.lines;
     // one plan for both precisions: the LDS windows are budgeted for float64
