@@ -1,0 +1,81 @@
+// context.h -- the context of one problem (grid, angle set, plan, device buffers) and the host
+// helpers shared by the single-problem ABI (rt3d.hip) and the batched ABI (batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/rt3d.h"
+#include "geometry.h"
+
+
+enum KernelId { K_SOURCE, K_SWEEP, K_REDUCE, K_LSTAR, K_COEF, K_JACOBI, K_COUNT };
+static const char *kKernelNames[K_COUNT] = {"source", "sweep", "reduce", "lstar", "coef", "jacobi"};
+
+struct rt3d_ctx {
+    rt3d_grid_desc g{};
+    int precision = RT3D_FP64;
+    hipStream_t stream = nullptr;
+    rt3d::AngleSet A;
+    rt3d::SweepPlan plan;
+    long V = 0;
+    size_t real_size = 8;
+    int lstar_early_exit = 0;
+    int sweep_shape = 0;       // index into kSweepShapes
+    int sweep_prefetch = 0;
+    int jacobi_xcd = 1;        // XCD-aware Jacobi grid (RT3D_JACOBI_XCD=0 disables)
+    // device buffers (owned)
+    double *chi = nullptr, *eps = nullptr, *B = nullptr, *J = nullptr, *Jfs = nullptr, *r = nullptr;
+    double *dJa = nullptr, *dJb = nullptr, *L = nullptr, *Iem = nullptr;
+    double *Kc = nullptr, *invD = nullptr, *Ecoef = nullptr;   // Jacobi coefficients (float64 form)
+    double *Sbuf = nullptr;
+    void *cs = nullptr, *P = nullptr;       // sized for float64; float sweeps use the first half
+    double *seg_len64 = nullptr;
+    float *seg_len32 = nullptr;
+    // FP32 form: anchor iterate, its float64 formal solution and top-plane light, float coefficients
+    double *Ja = nullptr, *Fa = nullptr, *Iem_a = nullptr;
+    float *Kc32 = nullptr;                                     // Jacobi coefficients (FP32 form)
+    unsigned long long *d_maxdist = nullptr;
+    bool anchor_valid = false, force_refresh = false, last_step_anchored = false;
+    double c_last = INFINITY, da_last = 0.0;
+    long fp64_sweeps = 0, fp32_sweeps = 0;
+    int *seg_off = nullptr, *seg_n = nullptr, *seg_a = nullptr, *seg_bb = nullptr, *seg_bm = nullptr;
+    int *seg_ai = nullptr, *seg_bi = nullptr, *row_min = nullptr;
+    rt3d::DirInfo *dirs = nullptr;
+    rt3d::PairInfo *pairs = nullptr;
+    rt3d::PairSeg *pseg = nullptr;
+    rt3d::PairLayer *player = nullptr;
+    rt3d::WorkItem *items = nullptr;
+    unsigned long long *d_maxrel = nullptr;
+    int *d_flag = nullptr;
+    // Ng acceleration
+    int ng_order = 0, ng_every = 0;
+    double *ng_hist = nullptr;          // [ng_order + 2][V] ring of iterates
+    double *ng_partial = nullptr;       // [kNgBlocks * kNgSums + kNgSums]
+    size_t device_bytes = 0;
+    bool have_medium = false, have_lstar = false, have_fs = false;
+    long outer_iters = 0, inner_sweeps = 0;
+    // timing
+    bool timing = false;
+    struct Pending { int kid; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    double kernel_ms[K_COUNT] = {0};
+    long kernel_launches[K_COUNT] = {0};
+    std::string err;
+};
+
+
+namespace rt3d_host {
+
+int fail(rt3d_ctx *c, int code, const std::string &msg);
+int hip_fail(rt3d_ctx *c, hipError_t e, const char *what);
+int sync(rt3d_ctx *c);
+int check_launch(rt3d_ctx *c, const char *what);
+int ensure_lstar(rt3d_ctx *c);
+int validate_desc(const rt3d_grid_desc *g, std::string &msg);
+
+}  // namespace rt3d_host

@@ -1,0 +1,725 @@
+// kernels.h -- HIP device code of the 3D radiative-transfer hot path (gfx950).  Included by the
+// single-problem ABI (rt3d.hip) and the batched ABI (batch.hip); every kernel body is a device
+// function with a single-problem wrapper and, where batching applies, a batched wrapper.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "geometry.h"
+
+using rt3d::DirInfo;
+using rt3d::WorkItem;
+
+namespace {
+
+// Sweep workgroup shapes (threads, lines per thread and direction); the context picks one.
+struct SweepShape { int threads, lines; };
+// Measured on MI355X at 129^3 x 256: 512 x 2 is fastest (56 VGPRs, 8 waves/SIMD; the sweep is
+// latency-bound, so occupancy beats lines per thread and prefetching).
+constexpr SweepShape kSweepShapes[] = {{512, 2}, {512, 4}, {256, 8}, {1024, 2}, {256, 4}, {256, 2}};
+constexpr size_t kWindowBytes = 48 * 1024;   // LDS for the two deposit windows of a band
+constexpr double kAnchorRatio = 1e-3;        // FP32 form: re-anchor when c < ratio * max|J - Ja|/|J|
+constexpr int kPlaneThreads = 256;   // voxel-parallel kernels: one thread per voxel of a k-plane
+
+template <typename real> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+// e^x - 1 for x <= 0 (the argument is always -dtau).  Write x = k ln2 + r with |r| <= ln2/2; then
+// e^x - 1 = 2^k (e^r - 1) + (2^k - 1), and e^r - 1 is its Taylor series (through r^13 in float64,
+// truncation below 2e-17 relative; through r^8 in float32, below 1e-9).  ln2 is split into a high part
+// whose product with k is exact and a low part.  No range branches: x is clamped where e^x vanishes.
+__device__ inline double expm1_nonpos(double x)
+{
+    x = fmax(x, -708.0);
+    const double kf = rint(x * 1.4426950408889634);
+    double r = fma(-kf, 6.93147180369123816490e-01, x);
+    r = fma(-kf, 1.90821492927058770002e-10, r);
+    double p = 1.0 / 6227020800.0;
+    p = fma(p, r, 1.0 / 479001600.0);
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    const double two_k = ldexp(1.0, int(kf));
+    return fma(two_k, p * r, two_k - 1.0);
+}
+
+__device__ inline float expm1_nonpos(float x)
+{
+    x = fmaxf(x, -87.0f);
+    const float kf = rintf(x * 1.44269504089f);
+    float r = fmaf(-kf, 0.693145751953125f, x);
+    r = fmaf(-kf, 1.42860682e-06f, r);
+    float p = 1.0f / 40320.0f;
+    p = fmaf(p, r, 1.0f / 5040.0f);
+    p = fmaf(p, r, 1.0f / 720.0f);
+    p = fmaf(p, r, 1.0f / 120.0f);
+    p = fmaf(p, r, 1.0f / 24.0f);
+    p = fmaf(p, r, 1.0f / 6.0f);
+    p = fmaf(p, r, 0.5f);
+    p = fmaf(p, r, 1.0f);
+    const float two_k = ldexpf(1.0f, int(kf));
+    return fmaf(two_k, p * r, two_k - 1.0f);
+}
+
+// ------------------------------------------------------------------------------------------------
+// S update
+// ------------------------------------------------------------------------------------------------
+
+// S_given: the source itself.  Ja (difference mode of the FP32 form): the source change since the
+// anchor iterate, (1 - eps)(J - Ja), whose formal solution is added to the anchor's.
+struct SourceArgs {
+    int nx, ny, nz;
+    const double *chi, *eps, *B, *J, *S_given, *Ja;
+    void *cs;                     // Vec2<real>
+};
+
+template <typename real>
+__device__ inline void source_body(const SourceArgs &a, int p, int k)
+{
+    if (p >= a.nx * a.ny) return;
+    const long v = long(k) * a.nx * a.ny + p;
+    double S;
+    if (a.S_given) S = a.S_given[v];
+    else if (a.Ja) S = (1.0 - a.eps[v]) * (a.J[v] - a.Ja[v]);
+    else S = a.eps[v] * a.B[v] + (1.0 - a.eps[v]) * a.J[v];
+    typename Vec2<real>::type c;
+    c.x = real(a.chi[v]);
+    c.y = real(S);
+    static_cast<typename Vec2<real>::type *>(a.cs)[v] = c;
+}
+
+template <typename real>
+__global__ __launch_bounds__(kPlaneThreads) void source_kernel(SourceArgs a)
+{
+    source_body<real>(a, blockIdx.x * kPlaneThreads + threadIdx.x, blockIdx.y);
+}
+
+// ------------------------------------------------------------------------------------------------
+// FS sweep
+// ------------------------------------------------------------------------------------------------
+
+struct SweepArgs {
+    int nx, ny, nz, n_down;
+    const rt3d::PairSeg *pseg;
+    const rt3d::PairLayer *player;
+    const rt3d::PairInfo *pairs;
+    const WorkItem *items;
+    const void *cs;               // Vec2<real>
+    const double *Ibot;           // [ny][nx] intensities at the bottom plane, or null (zero)
+    double I_top;
+    void *P;                      // real
+    double *Iem;                  // [n_up][ny][nx] or null
+    const double *Iem_base;       // added to Iem in difference mode (or null)
+};
+
+// One workgroup sweeps the lines of one band for both directions of an x-mirrored pair.  Thread t
+// owns lines q = t + i*NT (i < LPT) of the band, for both directions.  Per layer and segment index s
+// the lines of one direction deposit into pairwise distinct cells of that direction's LDS window, so
+// each window is updated with a plain read-add-write and a barrier separates segment indices.
+template <typename real> __device__ inline real seg_length(const rt3d::PairSeg &g);
+template <> __device__ inline double seg_length<double>(const rt3d::PairSeg &g) { return g.len; }
+template <> __device__ inline float seg_length<float>(const rt3d::PairSeg &g) { return g.len32; }
+
+// x mod n for 0 <= x < 2n, as min(x, x - n) on unsigned integers (x - n wraps when x < n)
+__device__ inline unsigned wrap_once(unsigned x, unsigned n) { return min(x, x - n); }
+
+template <typename real, int NT, int LPT, bool PF>
+__device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &it, unsigned char *smem_raw)
+{
+    using real2 = typename Vec2<real>::type;
+    const rt3d::PairInfo pi = a.pairs[it.pair];
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const unsigned plane = unsigned(nx) * unsigned(ny);
+    const int nlines = it.rows * nx;
+    const int wsize = pi.win_rows * nx;
+    real *winA = reinterpret_cast<real *>(smem_raw);
+    real *winB = winA + wsize;
+    const real2 *cs = static_cast<const real2 *>(a.cs);
+    real *P = static_cast<real *>(a.P) + pi.p_off + long(it.band) * nz * wsize;
+
+    for (int e = threadIdx.x; e < 2 * wsize; e += NT) winA[e] = real(0);
+
+    real IA[LPT], IB[LPT];
+    int li[LPT], lj[LPT];
+    unsigned lbase[LPT];
+#pragma unroll
+    for (int t = 0; t < LPT; ++t) {
+        const int q = threadIdx.x + t * NT;
+        const int qq = q < nlines ? q : 0;
+        lj[t] = qq / nx;
+        li[t] = q < nlines ? qq - lj[t] * nx : -1;   // -1 marks an unused slot
+        lbase[t] = unsigned(lj[t] * nx);
+        IA[t] = real(a.I_top);
+        IB[t] = real(a.I_top);
+    }
+    __syncthreads();
+
+    for (int step = 0; step < nz; ++step) {
+        const int k = pi.down ? nz - 1 - step : step;
+        const rt3d::PairLayer L = a.player[it.pair * nz + k];
+        const real2 *csk = cs + long(k) * plane;
+        unsigned grow0[LPT];
+#pragma unroll
+        for (int t = 0; t < LPT; ++t) {
+            unsigned r = unsigned(it.j0 + lj[t] + L.rmin);
+            r = wrap_once(wrap_once(r, ny), ny);
+            grow0[t] = r * unsigned(nx);
+        }
+        if (!pi.down && step == 0) {
+            // upward lines enter through the bottom plane: boundary light of the entry voxel
+            const rt3d::PairSeg g = a.pseg[L.off];
+#pragma unroll
+            for (int t = 0; t < LPT; ++t) {
+                if (li[t] < 0) continue;
+                const unsigned row = wrap_once(grow0[t] + unsigned(g.smnx), plane);
+                const unsigned cA = wrap_once(unsigned(li[t] + g.saA), nx);
+                const unsigned cB = wrap_once(unsigned(li[t] + g.saB), nx);
+                IA[t] = a.Ibot ? real(a.Ibot[row + cA]) : real(0);
+                IB[t] = a.Ibot ? real(a.Ibot[row + cB]) : real(0);
+            }
+        }
+        // gathers of segment s (prefetch variant: segment s+1's are issued before s is computed)
+        real2 nA[LPT], nB[LPT];
+        unsigned ncA[LPT], ncB[LPT];
+        auto gather = [&](const rt3d::PairSeg &g, real2 *dA, real2 *dB, unsigned *cA_, unsigned *cB_) {
+#pragma unroll
+            for (int t = 0; t < LPT; ++t) {
+                const unsigned grow = wrap_once(grow0[t] + unsigned(g.smnx), plane);
+                cA_[t] = wrap_once(unsigned(li[t] + g.saA), nx);
+                cB_[t] = wrap_once(unsigned(li[t] + g.saB), nx);
+                if (li[t] >= 0) {
+                    dA[t] = csk[grow + cA_[t]];
+                    dB[t] = csk[grow + cB_[t]];
+                }
+            }
+        };
+        if (PF && L.ns > 0) gather(a.pseg[L.off], nA, nB, ncA, ncB);
+        for (int s = 0; s < L.ns; ++s) {
+            const rt3d::PairSeg g = a.pseg[L.off + s];
+            const real len = seg_length<real>(g);
+            real2 cA[LPT], cB[LPT];
+            unsigned colA[LPT], colB[LPT];
+            if (PF) {
+#pragma unroll
+                for (int t = 0; t < LPT; ++t) {
+                    cA[t] = nA[t]; cB[t] = nB[t]; colA[t] = ncA[t]; colB[t] = ncB[t];
+                }
+                if (s + 1 < L.ns) gather(a.pseg[L.off + s + 1], nA, nB, ncA, ncB);
+            } else {
+                gather(g, cA, cB, colA, colB);
+            }
+#pragma unroll
+            for (int t = 0; t < LPT; ++t) {
+                if (li[t] < 0) continue;
+                const unsigned wrow = lbase[t] + unsigned(g.sbnx);
+                {
+                    const real dtau = cA[t].x * len;
+                    const real em1 = expm1_nonpos(-dtau);          // e^{-dtau} - 1
+                    const real dI = (IA[t] - cA[t].y) * em1;
+                    IA[t] += dI;
+                    winA[wrow + colA[t]] += cA[t].y * dtau - dI;   // chi * integral of I
+                }
+                {
+                    const real dtau = cB[t].x * len;
+                    const real em1 = expm1_nonpos(-dtau);
+                    const real dI = (IB[t] - cB[t].y) * em1;
+                    IB[t] += dI;
+                    winB[wrow + colB[t]] += cB[t].y * dtau - dI;
+                }
+            }
+            __syncthreads();
+        }
+        real *Pk = P + long(k) * wsize;
+        for (int e = threadIdx.x; e < wsize; e += NT) {
+            Pk[e] = winA[e] + winB[e];
+            winA[e] = real(0);
+            winB[e] = real(0);
+        }
+        __syncthreads();
+    }
+    if (!pi.down && a.Iem) {
+        const long ea0 = long(pi.dA - a.n_down) * plane, eb0 = long(pi.dB - a.n_down) * plane;
+#pragma unroll
+        for (int t = 0; t < LPT; ++t) {
+            if (li[t] < 0) continue;
+            const long ea = ea0 + (it.j0 + lj[t]) * nx + li[t];
+            const long eb = eb0 + (it.j0 + lj[t]) * nx + li[t];
+            const double baseA = a.Iem_base ? a.Iem_base[ea] : 0.0;
+            const double baseB = a.Iem_base ? a.Iem_base[eb] : 0.0;
+            a.Iem[ea] = baseA + double(IA[t]);
+            a.Iem[eb] = baseB + double(IB[t]);
+        }
+    }
+}
+
+template <typename real, int NT, int LPT, bool PF>
+__global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    sweep_body<real, NT, LPT, PF>(a, a.items[blockIdx.x], smem_raw);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Angle reduction of the partial planes
+// ------------------------------------------------------------------------------------------------
+
+struct ReduceArgs {
+    int nx, ny, nz, n_pair;
+    const rt3d::PairInfo *pairs;
+    const int *row_min;
+    const void *P;            // real
+    const double *chi;
+    const double *J;          // for r = J_fs - J (may be null)
+    const double *base;       // difference mode: J_fs of the anchor, added (may be null)
+    double *Jfs;
+    double *r;                // may be null
+};
+
+// J_fs(v) = (1/chi_v) sum_pairs W|mu| sum over the bands whose deposit windows cover v.  The band of
+// voxel row j at layer k is found from the row's offset to the layer's window origin; the previous
+// bands (cyclically) still cover the row while the offset stays inside their windows.
+template <typename real>
+__device__ inline void reduce_body(const ReduceArgs &a, int p, int k)
+{
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    if (p >= nx * ny) return;
+    const int j = p / nx, i = p - j * nx;
+    const real *P = static_cast<const real *>(a.P);
+    double acc = 0.0;
+#pragma unroll 4
+    for (int q = 0; q < a.n_pair; ++q) {
+        const rt3d::PairInfo pi = a.pairs[q];
+        const int rows = pi.band_rows, nb = pi.n_bands, Hw = pi.win_rows;
+        const int rmin = a.row_min[pi.dA * nz + k];
+        int jj = j - rmin;
+        jj += (jj < 0) ? ny : 0;
+        int b = min(int((float(jj) + 0.5f) * pi.inv_rows), nb - 1);
+        b -= (b * rows > jj) ? 1 : 0;
+        b += (b < nb - 1 && (b + 1) * rows <= jj) ? 1 : 0;
+        const int off0 = jj - b * rows;
+        const long plane = long(Hw) * nx;
+        const long band_stride = long(nz) * plane;
+        const real *Pq = P + pi.p_off + long(k) * plane + i;
+        // the band that starts the row's window offset, and the band before it (cyclically)
+        const int b1 = (b == 0) ? nb - 1 : b - 1;
+        const int off1 = off0 + ((b1 == nb - 1) ? pi.last_rows : rows);
+        const double v0 = double(Pq[long(b) * band_stride + long(off0) * nx]);
+        const double v1 = (off1 < Hw) ? double(Pq[long(b1) * band_stride + long(off1) * nx]) : 0.0;
+        double sd = v0 + v1;
+        if (off1 < Hw) {
+            // bands thinner than the window halo: still earlier bands may cover the row
+            int bb = b1, off = off1;
+            while (true) {
+                bb = (bb == 0) ? nb - 1 : bb - 1;
+                off += (bb == nb - 1) ? pi.last_rows : rows;
+                if (off >= Hw) break;
+                sd += double(Pq[long(bb) * band_stride + long(off) * nx]);
+            }
+        }
+        acc += pi.wmu * sd;
+    }
+    const long v = long(k) * nx * ny + p;
+    const double Jfs = a.base ? a.base[v] + acc / a.chi[v] : acc / a.chi[v];
+    a.Jfs[v] = Jfs;
+    if (a.r) a.r[v] = Jfs - a.J[v];
+}
+
+template <typename real>
+__global__ __launch_bounds__(kPlaneThreads) void reduce_kernel(ReduceArgs a)
+{
+    reduce_body<real>(a, blockIdx.x * kPlaneThreads + threadIdx.x, blockIdx.y);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Lambda*
+// ------------------------------------------------------------------------------------------------
+
+struct LstarArgs {
+    int nx, ny, nz, n_dir;
+    int early_exit;                 // 1: no line can wrap back onto a neighbour within two layers
+    const DirInfo *dirs;
+    const int *seg_off, *seg_n, *seg_ai, *seg_bi;
+    const double *seg_len;
+    const double *chi;
+    double *L;                      // [27][V]
+};
+
+// x + expm1(-x) = e^{-x} - 1 + x for x >= 0; below 1/2 by Horner on x^2 (1/2! - x/3! + x^2/4! - ...)
+// through x^15/17!, which avoids the cancellation of the direct form for thin segments.
+__device__ inline double self_term(double x)
+{
+    if (x >= 0.5) return x + expm1(-x);
+    constexpr double inv_fact[18] = {
+        1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720, 1.0 / 5040, 1.0 / 40320,
+        1.0 / 362880, 1.0 / 3628800, 1.0 / 39916800, 1.0 / 479001600, 1.0 / 6227020800.0,
+        1.0 / 87178291200.0, 1.0 / 1307674368000.0, 1.0 / 20922789888000.0,
+        1.0 / 355687428096000.0};
+    double r = inv_fact[17];
+#pragma unroll
+    for (int n = 16; n >= 2; --n) r = inv_fact[n] - x * r;
+    return x * x * r;
+}
+
+__device__ inline int wrap_small(int a, int n)
+{
+    // a may be any integer; returns a mod n in [0, n)
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// Lambda*_{vu} = sum_d W_d |mu_d| / chi_v * sum over the segments s of direction d inside v of
+//   delta_uv (dtau_s + em1_s) - em1_s * sum over earlier segments s' in u of c_{s'->s},
+//   c_{s'->s} = (1 - e_{s'}) prod_{s' < s'' < s} e_{s''},  e = exp(-dtau).
+// The lines through v are the reference line shifted so that its segment s lies in v; walking that
+// line backwards through the current and the previous layer reaches every earlier segment that can
+// lie in the 3x3x3 block (lines are monotone in z).
+__global__ __launch_bounds__(kPlaneThreads) void lstar_kernel(LstarArgs a)
+{
+    __shared__ double acc[27][kPlaneThreads];
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    const bool valid = p < nx * ny;
+    const int j = valid ? p / nx : 0, i = valid ? p - (p / nx) * nx : 0;
+    const long plane = long(nx) * ny;
+    const long V = plane * nz;
+    const long v = k * plane + long(j) * nx + i;
+    for (int o = 0; o < 27; ++o) acc[o][threadIdx.x] = 0.0;
+    const double chiv = a.chi[v];
+    for (int d = 0; d < a.n_dir; ++d) {
+        const DirInfo di = a.dirs[d];
+        const double fac = di.wmu / chiv;
+        const int dk = d * nz + k;
+        const int off = a.seg_off[dk], n = a.seg_n[dk];
+        const int ku = di.down ? k + 1 : k - 1;
+        const bool has_up = ku >= 0 && ku < nz;
+        const int offu = has_up ? a.seg_off[d * nz + ku] : 0;
+        const int nu = has_up ? a.seg_n[d * nz + ku] : 0;
+        for (int s = 0; s < n; ++s) {
+            const int as = a.seg_ai[off + s], bs = a.seg_bi[off + s];
+            const double dtau = chiv * a.seg_len[off + s];
+            const double em1 = expm1(-dtau);
+            acc[13][threadIdx.x] += fac * self_term(dtau);
+            const double g = -fac * em1;
+            double prod = 1.0;
+            // walk back: current layer s-1 .. 0, then the previous layer from its last segment
+            const int total = s + nu;
+            for (int w = 0; w < total; ++w) {
+                int idx, dkk;
+                if (w < s) { idx = off + s - 1 - w; dkk = 0; }
+                else { idx = offu + nu - 1 - (w - s); dkk = ku - k; }
+                const int dA = a.seg_ai[idx] - as, dB = a.seg_bi[idx] - bs;
+                if (a.early_exit && (dA > 1 || dA < -1 || dB > 1 || dB < -1)) break;
+                const int mA = wrap_small(dA, nx), mB = wrap_small(dB, ny);
+                int col = i + mA;
+                col -= (col >= nx) ? nx : 0;
+                int row = j + mB;
+                row -= (row >= ny) ? ny : 0;
+                const long u = long(k + dkk) * plane + long(row) * nx + col;
+                const double tau_u = a.chi[u] * a.seg_len[idx];
+                const double c = -expm1(-tau_u) * prod;
+                const int oi = (mA == 0) ? 1 : (mA == 1) ? 2 : (mA == nx - 1) ? 0 : -1;
+                const int oj = (mB == 0) ? 1 : (mB == 1) ? 2 : (mB == ny - 1) ? 0 : -1;
+                if (oi >= 0 && oj >= 0) acc[9 * (dkk + 1) + 3 * oj + oi][threadIdx.x] += g * c;
+                prod *= exp(-tau_u);   // not 1 + expm1: keeps relative accuracy for thick segments
+            }
+        }
+    }
+    if (valid)
+        for (int o = 0; o < 27; ++o) a.L[o * V + v] = acc[o][threadIdx.x];
+}
+
+// Jacobi coefficients.  K_vu = chi_v Lambda*_vu is symmetric (reciprocity: lines for Omega and -Omega
+// coincide and the weights are symmetric), so only the 13 upper neighbours o = 14..26 are stored:
+// Kc[o - 14][v] = chi_v Lambda*_o(v).  The entry for a lower neighbour u = v + d(o), o < 13, is
+// Kc[12 - o][u] (u's upper neighbour 26 - o is v).  Per voxel: invD = 1 / (chi_v (1 - Lambda*_vv (1-eps_v)))
+// and E = (1 - eps_v) invD.
+template <typename coef>
+__global__ __launch_bounds__(kPlaneThreads) void coef_kernel(int nx, int ny, int nz,
+                                                             const double *__restrict__ L,
+                                                             const double *__restrict__ chi,
+                                                             const double *__restrict__ eps,
+                                                             coef *__restrict__ Kc, double *__restrict__ invD,
+                                                             double *__restrict__ E)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (p >= nx * ny) return;
+    const long plane = long(nx) * ny, V = plane * nz, v = k * plane + p;
+    const double c = chi[v];
+    for (int o = 14; o < 27; ++o) {
+        const int kk = k + o / 9 - 1;
+        Kc[(o - 14) * V + v] = coef((kk < nz) ? c * L[o * V + v] : 0.0);
+    }
+    const double inv = 1.0 / (c * (1.0 - L[13 * V + v] * (1.0 - eps[v])));
+    invD[v] = inv;
+    E[v] = (1.0 - eps[v]) * inv;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Jacobi sweep of the OS equations, optionally fused with the J update and max |dJ|/|J|
+// ------------------------------------------------------------------------------------------------
+
+// The sweep dJ_v <- (r_v + sum_{u != v} Lambda*_vu (1-eps_u) dJ_u) / (1 - Lambda*_vv (1-eps_v)) is
+// evaluated as (chi_v r_v + sum_u K_vu w_u) invD_v with w = (1 - eps) dJ carried between sweeps.
+struct JacobiArgs {
+    int nx, ny, nz;
+    const double *r, *chi;
+    const void *Kc;              // [13][V] upper coefficients (double, or float in the FP32 form)
+    const double *invD, *E;
+    const double *w_in;          // (1 - eps) dJ of the previous sweep; null: dJ^0 = 0 (first sweep)
+    double *w_out;               // (1 - eps) dJ of this sweep (intermediate sweeps)
+    double *J;                   // last sweep: J += dJ (null otherwise)
+    unsigned long long *maxrel;  // bits of max |dJ|/|J| (non-negative doubles order like integers)
+    const double *Ja;            // anchor iterate of the FP32 form (may be null)
+    unsigned long long *maxdist; // bits of max |J - Ja|/|J| when Ja is given
+    int *nonfinite;
+};
+
+// Arithmetic is float64 for either coefficient type.
+// The whole block must call this (it ends with a block reduction when J is updated).
+template <typename coef>
+__device__ inline void jacobi_body(const JacobiArgs &a, int p, int k)
+{
+    const coef *Kc = static_cast<const coef *>(a.Kc);
+    double dist = 0.0;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const bool valid = p < nx * ny;
+    double q = 0.0;
+    bool bad = false;
+    if (valid) {
+        const int j = p / nx, i = p - j * nx;
+        const long plane = long(nx) * ny, V = plane * nz, v = k * plane + p;
+        double acc = a.chi[v] * a.r[v];
+        if (a.w_in) {
+            const int im = (i == 0) ? nx - 1 : i - 1, ip = (i == nx - 1) ? 0 : i + 1;
+            const int jm = (j == 0) ? ny - 1 : j - 1, jp = (j == ny - 1) ? 0 : j + 1;
+            const int cols[3] = {im, i, ip};
+            const int rows[3] = {jm, j, jp};
+#pragma unroll
+            for (int o = 0; o < 27; ++o) {
+                if (o == 13) continue;
+                const int kk = k + o / 9 - 1;
+                if (kk < 0 || kk >= nz) continue;
+                const long u = kk * plane + long(rows[(o / 3) % 3]) * nx + cols[o % 3];
+                const double K = (o > 13) ? double(Kc[(o - 14) * V + v]) : double(Kc[(12 - o) * V + u]);
+                acc += K * a.w_in[u];
+            }
+        }
+        if (a.w_out) a.w_out[v] = acc * a.E[v];
+        if (a.J) {
+            const double dJ = acc * a.invD[v];
+            const double Jn = a.J[v] + dJ;
+            a.J[v] = Jn;
+            q = fabs(dJ) / fabs(Jn);
+            if (a.Ja) dist = fabs(Jn - a.Ja[v]) / fabs(Jn);
+            bad = !isfinite(Jn) || !isfinite(q);
+        }
+    }
+    if (!a.J) return;
+    // block max of q (and of the anchor distance); NaN/Inf raise the flag
+    if (bad) { atomicOr(a.nonfinite, 1); q = 0.0; dist = 0.0; }
+    for (int offs = 32; offs > 0; offs >>= 1) {
+        q = fmax(q, __shfl_xor(q, offs));
+        dist = fmax(dist, __shfl_xor(dist, offs));
+    }
+    __shared__ double wmax[2][kPlaneThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { wmax[0][wid] = q; wmax[1][wid] = dist; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = wmax[0][0], md = wmax[1][0];
+        for (int w = 1; w < kPlaneThreads / 64; ++w) { m = fmax(m, wmax[0][w]); md = fmax(md, wmax[1][w]); }
+        atomicMax(a.maxrel, static_cast<unsigned long long>(__double_as_longlong(m)));
+        if (a.Ja) atomicMax(a.maxdist, static_cast<unsigned long long>(__double_as_longlong(md)));
+    }
+}
+
+template <typename coef>
+__global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel(JacobiArgs a)
+{
+    jacobi_body<coef>(a, blockIdx.x * kPlaneThreads + threadIdx.x, blockIdx.y);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Ng acceleration: weighted dot products (fixed-order two-level reduction) and the combination
+// ------------------------------------------------------------------------------------------------
+
+constexpr int kNgSums = 9;          // A00 A01 A02 A11 A12 A22 b0 b1 b2
+constexpr int kNgBlocks = 1024;
+constexpr int kNgThreads = 256;
+
+struct NgArgs {
+    long V;
+    int order;
+    const double *x[5];             // x[0] newest iterate, x[i] the i-th older one
+    double *partial;                // [kNgBlocks][kNgSums]
+};
+
+__global__ __launch_bounds__(kNgThreads) void ng_dots_kernel(NgArgs a)
+{
+    double acc[kNgSums];
+#pragma unroll
+    for (int q = 0; q < kNgSums; ++q) acc[q] = 0.0;
+    for (long v = long(blockIdx.x) * kNgThreads + threadIdx.x; v < a.V; v += long(kNgBlocks) * kNgThreads) {
+        const double x0 = a.x[0][v];
+        const double w = 1.0 / (x0 * x0);
+        const double d0 = x0 - a.x[1][v];
+        double Q[3] = {0.0, 0.0, 0.0};
+        for (int i = 1; i <= a.order; ++i) Q[i - 1] = d0 - (a.x[i][v] - a.x[i + 1][v]);
+        acc[0] += w * Q[0] * Q[0];
+        acc[1] += w * Q[0] * Q[1];
+        acc[2] += w * Q[0] * Q[2];
+        acc[3] += w * Q[1] * Q[1];
+        acc[4] += w * Q[1] * Q[2];
+        acc[5] += w * Q[2] * Q[2];
+        acc[6] += w * d0 * Q[0];
+        acc[7] += w * d0 * Q[1];
+        acc[8] += w * d0 * Q[2];
+    }
+    __shared__ double red[kNgSums][kNgThreads];
+#pragma unroll
+    for (int q = 0; q < kNgSums; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int h = kNgThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            for (int q = 0; q < kNgSums; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < kNgSums) a.partial[blockIdx.x * kNgSums + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// one block: sums the per-block partials in a fixed order
+__global__ __launch_bounds__(kNgThreads) void ng_sum_kernel(const double *partial, double *out)
+{
+    __shared__ double red[kNgSums][kNgThreads];
+    for (int q = 0; q < kNgSums; ++q) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < kNgBlocks; b += kNgThreads) s += partial[b * kNgSums + q];
+        red[q][threadIdx.x] = s;
+    }
+    __syncthreads();
+    for (int h = kNgThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            for (int q = 0; q < kNgSums; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < kNgSums) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+struct NgCombineArgs {
+    long V;
+    int order;
+    double c0, c[3];                // x_new = c0 x[0] + sum_i c[i-1] x[i]
+    const double *x[4];
+    double *out;
+};
+
+__global__ void ng_combine_kernel(NgCombineArgs a)
+{
+    long v = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= a.V) return;
+    double r = a.c0 * a.x[0][v];
+    for (int i = 1; i <= a.order; ++i) r += a.c[i - 1] * a.x[i][v];
+    a.out[v] = r;
+}
+
+// finiteness / range check of a device medium
+__global__ void check_medium_kernel(long V, const double *chi, const double *eps, const double *B,
+                                    int *flag)
+{
+    long v = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const double c = chi[v], e = eps[v], b = B[v];
+    const bool ok = isfinite(c) && c > 0.0 && isfinite(e) && e > 0.0 && e <= 1.0 && isfinite(b);
+    if (!ok) atomicOr(flag, 1);
+}
+
+__global__ void check_finite_kernel(long V, const double *x, int *flag)
+{
+    long v = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    if (!isfinite(x[v])) atomicOr(flag, 1);
+}
+
+
+// ------------------------------------------------------------------------------------------------
+// Batched launches: several independent problems (e.g. wavelengths on grids of different sizes) in
+// one launch per kernel.  Each block reads its problem's argument block; problems whose flag in
+// 'active' is zero return at once, which is how converged problems drop out of a replayed graph.
+// ------------------------------------------------------------------------------------------------
+
+struct BatchItem {
+    int member;
+    WorkItem item;
+};
+
+struct PlaneBlock {
+    int member, chunk, k, pad;
+};
+
+template <typename real, int NT, int LPT>
+__global__ __launch_bounds__(NT) void sweep_kernel_batch(const SweepArgs *args, const BatchItem *items,
+                                                         const int *active)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const BatchItem bi = items[blockIdx.x];
+    if (!active[bi.member]) return;
+    const SweepArgs a = args[bi.member];
+    sweep_body<real, NT, LPT, false>(a, bi.item, smem_raw);
+}
+
+template <typename real>
+__global__ __launch_bounds__(kPlaneThreads) void source_kernel_batch(const SourceArgs *args,
+                                                                     const PlaneBlock *blocks,
+                                                                     const int *active)
+{
+    const PlaneBlock b = blocks[blockIdx.x];
+    if (!active[b.member]) return;
+    const SourceArgs a = args[b.member];
+    source_body<real>(a, b.chunk * kPlaneThreads + threadIdx.x, b.k);
+}
+
+template <typename real>
+__global__ __launch_bounds__(kPlaneThreads) void reduce_kernel_batch(const ReduceArgs *args,
+                                                                     const PlaneBlock *blocks,
+                                                                     const int *active)
+{
+    const PlaneBlock b = blocks[blockIdx.x];
+    if (!active[b.member]) return;
+    const ReduceArgs a = args[b.member];
+    reduce_body<real>(a, b.chunk * kPlaneThreads + threadIdx.x, b.k);
+}
+
+template <typename coef>
+__global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel_batch(const JacobiArgs *args,
+                                                                     const PlaneBlock *blocks,
+                                                                     const int *active)
+{
+    const PlaneBlock b = blocks[blockIdx.x];
+    if (!active[b.member]) return;
+    const JacobiArgs a = args[b.member];
+    jacobi_body<coef>(a, b.chunk * kPlaneThreads + threadIdx.x, b.k);
+}
+
+// Clears the per-member convergence scalars (a kernel, not a memset, so it can sit in a graph).
+__global__ void clear_scalars_kernel(int n, unsigned long long *a, unsigned long long *b, int *flags)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        a[i] = 0ull;
+        b[i] = 0ull;
+        flags[i] = 0;
+    }
+}
+
+}  // namespace
