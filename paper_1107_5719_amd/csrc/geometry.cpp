@@ -140,7 +140,10 @@ void layer_segments(int nz, double mu, double ox, double oy, int k, LayerSegment
     std::vector<double> zx, zy;
     face_crossings(nz, 0.5, tx, z_in, z_out, zx);
     face_crossings(nz, 0.5, ty, z_in, z_out, zy);
-    // merge the two ordered crossing lists along the travel direction
+    // merge the two ordered crossing lists along the travel direction; crossings closer than
+    // kCornerTol in height are one crossing through a voxel edge (a line through an edge would
+    // otherwise leave a rounding-sized sliver between the x and the y crossing)
+    constexpr double kCornerTol = 1e-12;
     const bool down = z_out < z_in;
     std::vector<double> zb;
     zb.reserve(zx.size() + zy.size() + 2);
@@ -151,9 +154,11 @@ void layer_segments(int nz, double mu, double ox, double oy, int k, LayerSegment
         if (p == zx.size()) take_x = false;
         else if (q == zy.size()) take_x = true;
         else take_x = down ? (zx[p] >= zy[q]) : (zx[p] <= zy[q]);
-        zb.push_back(take_x ? zx[p++] : zy[q++]);
+        const double z = take_x ? zx[p++] : zy[q++];
+        if (std::fabs(z - zb.back()) > kCornerTol) zb.push_back(z);
     }
-    zb.push_back(z_out);
+    if (zb.size() > 1 && std::fabs(z_out - zb.back()) <= kCornerTol) zb.back() = z_out;
+    else zb.push_back(z_out);
     out.di.clear();
     out.dj.clear();
     out.len.clear();
@@ -166,6 +171,19 @@ void layer_segments(int nz, double mu, double ox, double oy, int k, LayerSegment
         out.dj.push_back(int(std::floor(0.5 + (zm - nz) * ty)));
         out.len.push_back(dz * inv_amu);
     }
+}
+
+void direction_segments(int nz, const AngleSet &A, int d, int k, LayerSegments &out)
+{
+    const int a = d / A.n_phi, b = d % A.n_phi;
+    const int bm = mirror_x(b, A.n_phi);
+    if (bm >= b) {
+        layer_segments(nz, A.mu[d], A.ox[d], A.oy[d], k, out);
+        return;
+    }
+    const int dm = a * A.n_phi + bm;
+    layer_segments(nz, A.mu[dm], A.ox[dm], A.oy[dm], k, out);
+    for (int &x : out.di) x = -x;
 }
 
 static int pos_mod(int a, int n)
@@ -199,7 +217,7 @@ bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int lines_per_w
     for (int d = 0; d < A.n_dir; ++d) {
         long nseg = 0;
         for (int k = 0; k < nz; ++k) {
-            layer_segments(nz, A.mu[d], A.ox[d], A.oy[d], k, L);
+            direction_segments(nz, A, d, k, L);
             const int n = int(L.di.size());
             const int bmin = *std::min_element(L.dj.begin(), L.dj.end());
             const int bmax = *std::max_element(L.dj.begin(), L.dj.end());

@@ -29,6 +29,12 @@ void layer_segments(int nz, double mu, double ox, double oy, int k, LayerSegment
 // Index of the azimuth mirrored in x (phi -> pi - phi).
 int mirror_x(int b, int n_phi);
 
+// The segments of direction d of an angle set inside layer k.  Of an x-mirrored pair of azimuths
+// the lower index is cut by layer_segments and the other is its exact mirror (columns negated):
+// lines that pass through voxel edges (every line when n_phi = 4) leave rounding-sized slivers whose
+// voxel would otherwise depend on the rounding of each direction separately.
+void direction_segments(int nz, const AngleSet &A, int d, int k, LayerSegments &out);
+
 // Per-direction metadata (plain old data, copied to the device).
 struct DirInfo {
     double wmu;        // W_d * |mu_d|

@@ -45,10 +45,27 @@ def test_quadrature_matches_oracle(R, orc, nt, nph):
         assert np.max(np.abs(a - b)) < 1e-15
 
 
-@pytest.mark.parametrize("shape,nt,nph", [((5, 6, 7), 8, 8), ((4, 3, 5), 16, 16), ((6, 9, 9), 16, 16)])
+def _merge_same_voxel(v, l, sliver=1e-12):
+    """Drop rounding-sized pieces (a line through a voxel edge touches the side voxels in a point;
+    rounding decides whether a 1e-15 piece appears there) and join consecutive pieces inside one voxel
+    (the exact integral over a voxel does not depend on how its path is split)."""
+    mv, ml = [], []
+    for a, b in zip(v, l):
+        if b <= sliver:
+            continue
+        if mv and mv[-1] == a:
+            ml[-1] += b
+        else:
+            mv.append(int(a))
+            ml.append(float(b))
+    return np.array(mv), np.array(ml)
+
+
+@pytest.mark.parametrize("shape,nt,nph", [((5, 6, 7), 8, 8), ((4, 3, 5), 16, 16), ((6, 9, 9), 16, 16),
+                                          ((5, 6, 7), 2, 4), ((5, 5, 5), 8, 4)])
 def test_segment_tables_match_oracle_lines(R, orc, shape, nt, nph):
     """The library's one table per (direction, layer), translated to line (i,j), equals the oracle's
-    own tracing of that line."""
+    own tracing of that line (n_phi = 4: every line runs through voxel edges)."""
     nz, ny, nx = shape
     desc = R._desc(nx, ny, nz, nt, nph)
     rng = np.random.default_rng(0)
@@ -58,10 +75,29 @@ def test_segment_tables_match_oracle_lines(R, orc, shape, nt, nph):
             assert abs(ln.sum() * abs(orc.quadrature(nt, nph)[0][d]) - 1) < 1e-13
             for _ in range(3):
                 i, j = int(rng.integers(nx)), int(rng.integers(ny))
-                v, l = orc.trace_layer(nx, ny, nz, nt, nph, d, i, j, k)
-                vv = (k * ny + (j + dj) % ny) * nx + (i + di) % nx
+                v, l = _merge_same_voxel(*orc.trace_layer(nx, ny, nz, nt, nph, d, i, j, k))
+                vv, ll = _merge_same_voxel((k * ny + (j + dj) % ny) * nx + (i + di) % nx, ln)
                 assert np.array_equal(v, vv)
-                assert np.max(np.abs(l - ln)) < 1e-12
+                assert np.max(np.abs(l - ll)) < 1e-12
+
+
+@pytest.mark.parametrize("nt,nph", [(2, 4), (8, 4), (8, 8), (4, 12)])
+def test_mirrored_directions_share_tables(R, nt, nph):
+    """Directions mirrored in x (phi -> pi - phi) have the same tables with negated columns, which is
+    what lets one sweep workgroup carry both (n_phi = 4 included, where lines pass through edges)."""
+    nz, ny, nx = 6, 5, 7
+    desc = R._desc(nx, ny, nz, nt, nph)
+    mu, ox, oy, _ = R.rt3d_quadrature(nt, nph)
+    for a in range(nt):
+        for b in range(nph):
+            d = a * nph + b
+            dm = [e for e in range(a * nph, (a + 1) * nph) if ox[e] == -ox[d] and oy[e] == oy[d]]
+            assert len(dm) == 1
+            for k in range(nz):
+                di, dj, ln = R.rt3d_segment_table(desc, d, k)
+                di2, dj2, ln2 = R.rt3d_segment_table(desc, dm[0], k)
+                assert np.array_equal(di, -di2) and np.array_equal(dj, dj2) and np.array_equal(ln, ln2)
+                assert (ln > 1e-9).all()
 
 
 def test_deposits_are_a_bijection_per_segment(R):

@@ -59,6 +59,8 @@ FS_CASES = [
     ((7, 5, 6), 8, 8, 4, 0.0, 1),        # zero light at the bottom
     ((4, 40, 33), 16, 16, 5, 0.1, 0),    # several bands per direction and a ragged last band
     ((6, 9, 131), 8, 8, 6, 0.0, 0),      # rows longer than two wavefronts
+    ((6, 5, 7), 2, 4, 7, 0.2, 0),        # smallest angle set; every line runs through voxel edges
+    ((5, 8, 6), 8, 4, 8, 0.0, 0),        # n_phi = 4 with steep and shallow directions
 ]
 
 
