@@ -163,6 +163,109 @@ const char *rt3d_status_str(int status);
 /* Last error message of a context ("" if none); valid until the next call on the context. */
 const char *rt3d_last_error(const rt3d_ctx *ctx);
 
+/* ---- sweep workgroup shape and its tuning -------------------------------------------------- */
+
+/* The sweep workgroup shapes: shape i runs threads[i] threads, each carrying lines[i] lines of
+ * both directions of an x-mirrored direction pair.  Fills min(count, max_n) entries of the arrays
+ * (either may be NULL) and returns the count.  Host-only. */
+int rt3d_sweep_shapes(int *threads, int *lines, int max_n);
+
+/* Rebuild the sweep plan (bands and work items) for a shape; medium, J and Lambda* are kept, and
+ * the results change only by the summation order of the partial planes.  Errors: RT3D_ERR_ARG
+ * (shape out of range, or its bands do not fit the grid; the context is unchanged), RT3D_ERR_OOM,
+ * RT3D_ERR_HIP (after these two the context cannot sweep -- RT3D_ERR_STATE -- until a later call
+ * succeeds). */
+int rt3d_set_sweep_shape(rt3d_ctx *ctx, int shape);
+
+/* Autotuner of the sweep shape.  Times `repeats` formal solutions (from the current J, in the
+ * context's precision) for every shape that fits the grid, installs the fastest and, when
+ * cache_path is neither NULL nor empty, records it in a JSON cache keyed by device, precision and
+ * grid.  When the cache already holds the key, its shape is installed without measuring.
+ * *shape_out (may be NULL) receives the shape; ms_out (may be NULL, one entry per shape) the
+ * milliseconds per formal solution, -1 where not measured.  Overwrites J_fs and the emergent
+ * intensities.  Errors: RT3D_ERR_STATE (no medium), RT3D_ERR_ARG (repeats < 1, unwritable
+ * cache), RT3D_ERR_OOM, RT3D_ERR_HIP. */
+int rt3d_autotune(rt3d_ctx *ctx, const char *cache_path, int repeats, int *shape_out, double *ms_out);
+
+/* ---- batched form: many problems in one launch per kernel ----------------------------------
+ * An extension of the method (the paper solves one wavelength at a time): a batch holds n members,
+ * independent problems with grid descriptors of their own (sizes and angle sets may differ), in one
+ * precision and one sweep shape -- for instance the wavelengths of a spectrum.  An outer iteration
+ * advances every member that has not stopped, with one launch per kernel for all of them; the
+ * iteration is captured once in a HIP graph and replayed.  Each member's stopping rule, FP32
+ * re-anchoring and Ng schedule are decided on the device with the rules of rt3d_os_step,
+ * rt3d_solve_to_convergence and rt3d_set_acceleration, and the arithmetic is that of a single
+ * context, so a member's iterates are bitwise those of solving it alone in a context with the same
+ * sweep shape.  Member buffers follow the layouts above. */
+typedef struct rt3d_batch rt3d_batch;
+
+enum {
+    RT3D_MEMBER_RUNNING = 0,     /* still iterating */
+    RT3D_MEMBER_CONVERGED = 1,   /* c < tol (in the FP32 form from a float64 formal solution) */
+    RT3D_MEMBER_MAX_ITER = 2,    /* stopped after max_iter steps; J and c are valid */
+    RT3D_MEMBER_NONFINITE = 3    /* NaN or Inf in dJ or J */
+};
+
+/* Create a batch of n_members >= 1 problems: descs[i] (host array) as for rt3d_create, precision
+ * and sweep_shape (rt3d_sweep_shapes) shared by all.  hip_stream: a hipStream_t other than the
+ * legacy default stream (graphs are captured from it), or NULL for a stream the batch creates (default
+ * priority) and destroys.  Errors: RT3D_ERR_ARG (any bad descriptor, n_members < 1, bad precision
+ * or shape, a shape whose bands do not fit a grid), RT3D_ERR_OOM, RT3D_ERR_HIP. */
+int rt3d_batch_create(rt3d_batch **out, int n_members, const rt3d_grid_desc *descs, int precision,
+                      int sweep_shape, void *hip_stream);
+
+/* Free the batch, its members and (if it created it) its stream.  NULL is ignored. */
+void rt3d_batch_destroy(rt3d_batch *b);
+
+/* Number of members (0 for NULL). */
+int rt3d_batch_size(const rt3d_batch *b);
+
+/* Last error message of the batch ("" if none), prefixed "member i:" when a member failed. */
+const char *rt3d_batch_last_error(const rt3d_batch *b);
+
+/* Per member, exactly as rt3d_set_medium / rt3d_set_J / rt3d_get_J of a context; member in
+ * [0, n).  rt3d_batch_get_Jfs copies the member's last formal solution J_fs out (RT3D_ERR_STATE
+ * before the first).  Errors as there, plus RT3D_ERR_ARG for a member out of range. */
+int rt3d_batch_set_medium(rt3d_batch *b, int member, const double *chi, const double *eps,
+                          const double *B, int ptr_kind);
+int rt3d_batch_set_J(rt3d_batch *b, int member, const double *J, int ptr_kind);
+int rt3d_batch_get_J(rt3d_batch *b, int member, double *J_out, int ptr_kind);
+int rt3d_batch_get_Jfs(rt3d_batch *b, int member, double *Jfs_out, int ptr_kind);
+
+/* Ng acceleration for every member, as rt3d_set_acceleration.  Errors as there. */
+int rt3d_batch_set_acceleration(rt3d_batch *b, int ng_order, int ng_every);
+
+/* Rebuild every member's plan for a shape, as rt3d_set_sweep_shape.  After RT3D_ERR_ARG from a
+ * member the batch cannot sweep (RT3D_ERR_STATE) until a shape change succeeds. */
+int rt3d_batch_set_sweep_shape(rt3d_batch *b, int shape);
+
+/* One formal solution of every member from its current J (S = eps B + (1-eps) J, boundary light
+ * as in its descriptor, float32 sweeps in the RT3D_FP32_SWEEP form, as rt3d_formal_solution), in
+ * one launch per kernel; read the results with rt3d_batch_get_Jfs.
+ * Errors: RT3D_ERR_STATE (a member without medium), RT3D_ERR_HIP. */
+int rt3d_batch_formal_solution(rt3d_batch *b);
+
+/* Iterate every member with OS steps of inner_sweeps Jacobi sweeps until it stops (see the member
+ * states above), replaying the captured iteration and reading the member states back every
+ * poll_every >= 1 replays; the iterates do not depend on poll_every.  Lambda* is built first where
+ * needed.  Per member (arrays of n entries, each may be NULL): iterations, last c (NaN for a
+ * non-finite member) and state.  Returns RT3D_OK when every member converged, else
+ * RT3D_ERR_NONFINITE if any member turned non-finite, else RT3D_ERR_NOT_CONVERGED; RT3D_ERR_ARG
+ * (tol <= 0, max_iter, inner_sweeps or poll_every < 1), RT3D_ERR_STATE (a member without medium),
+ * RT3D_ERR_OOM, RT3D_ERR_HIP. */
+int rt3d_batch_solve(rt3d_batch *b, double tol, int max_iter, int inner_sweeps, int poll_every,
+                     int *iters_out, double *final_rel_out, int *status_out);
+
+/* Autotuner of the batch's sweep shape: as rt3d_autotune, timing batched formal solutions; the
+ * cache key holds the device, the precision and the multiset of member grids. */
+int rt3d_batch_autotune(rt3d_batch *b, const char *cache_path, int repeats, int *shape_out,
+                        double *ms_out);
+
+/* Statistics of the batch and of its last solve as a NUL-terminated JSON object (members, voxels,
+ * voxel-angles, shape, replays, polls, solve milliseconds, iteration counts).
+ * Errors: RT3D_ERR_ARG (buffer too small or NULL). */
+int rt3d_batch_get_stats(rt3d_batch *b, char *json_buf, int buflen);
+
 /* ---- host-only helpers (no device needed) ------------------------------------------------- */
 
 /* The angle set: mu[d], ox[d], oy[d] (direction cosines) and weights w[d] for d = a*n_phi + b,

@@ -9,8 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librt3d.so")
-SOURCES = [os.path.join(CSRC, "geometry.cpp"), os.path.join(CSRC, "rt3d.hip")]
-HEADERS = [os.path.join(CSRC, h) for h in ("geometry.h", "context.h", "kernels.h")]
+SOURCES = [os.path.join(CSRC, f) for f in ("geometry.cpp", "tune_cache.cpp", "rt3d.hip", "batch.hip")]
+HEADERS = [os.path.join(CSRC, h) for h in ("geometry.h", "context.h", "kernels.h", "tune_cache.h")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -54,9 +54,10 @@ struct rt3d_ctx {
     // Ng acceleration
     int ng_order = 0, ng_every = 0;
     double *ng_hist = nullptr;          // [ng_order + 2][V] ring of iterates
-    double *ng_partial = nullptr;       // [kNgBlocks * kNgSums + kNgSums]
+    double *ng_work = nullptr;          // [kNgWork]: block partials, sums, coefficients
     size_t device_bytes = 0;
-    bool have_medium = false, have_lstar = false, have_fs = false;
+    size_t plan_bytes = 0;              // the part of device_bytes that belongs to the sweep plan
+    bool have_medium = false, have_lstar = false, have_fs = false, plan_ok = false;
     long outer_iters = 0, inner_sweeps = 0;
     // timing
     bool timing = false;
@@ -77,5 +78,48 @@ int sync(rt3d_ctx *c);
 int check_launch(rt3d_ctx *c, const char *what);
 int ensure_lstar(rt3d_ctx *c);
 int validate_desc(const rt3d_grid_desc *g, std::string &msg);
+int validate_medium_host(long V, const double *chi, const double *eps, const double *B, std::string &msg);
+hipMemcpyKind kind_in(int ptr_kind);
+hipMemcpyKind kind_out(int ptr_kind);
+int n_sweep_shapes();
+
+// New context with the given sweep shape (index into the shape table); stream may be null.
+int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream_t stream, int shape,
+               std::string &msg);
+// (Re)build the sweep plan for a shape and upload its tables; Lambda* and the state are kept.
+int install_plan(rt3d_ctx *c, int shape);
+// One formal solution from the current J (source, sweep, reduce; no residual), as the context's
+// precision sweeps it.
+int run_fs_plain(rt3d_ctx *c);
+// Key of a tuning-cache entry: device, precision and grid of a context.
+std::string device_key();
+
+#define HIP_TRY(ctx, expr, what)                                      \
+    do {                                                              \
+        hipError_t e_ = (expr);                                       \
+        if (e_ != hipSuccess) return rt3d_host::hip_fail(ctx, e_, what); \
+    } while (0)
+
+template <typename T>
+int dev_alloc(rt3d_ctx *c, T **p, size_t count)
+{
+    const size_t bytes = (count ? count : 1) * sizeof(T);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_fail(c, e, "hipMalloc");
+    }
+    c->device_bytes += bytes;
+    return RT3D_OK;
+}
+
+template <typename T>
+int upload(rt3d_ctx *c, T **p, const std::vector<T> &h)
+{
+    int rc = dev_alloc(c, p, h.size());
+    if (rc) return rc;
+    if (!h.empty()) HIP_TRY(c, hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+    return RT3D_OK;
+}
 
 }  // namespace rt3d_host

@@ -1,6 +1,7 @@
 // kernels.h -- HIP device code of the 3D radiative-transfer hot path (gfx950).  Included by the
-// single-problem ABI (rt3d.hip) and the batched ABI (batch.hip); every kernel body is a device
-// function with a single-problem wrapper and, where batching applies, a batched wrapper.
+// single-problem ABI (rt3d.hip) and the batched ABI (batch.hip).  The kernels that batching applies
+// to are device functions taking an argument struct, with a single-problem wrapper here and a
+// batched wrapper in batch.hip, so both run the same arithmetic.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -551,31 +552,46 @@ __global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel(JacobiArgs a)
 }
 
 // ------------------------------------------------------------------------------------------------
-// Ng acceleration: weighted dot products (fixed-order two-level reduction) and the combination
+// Ng acceleration: weighted dot products (fixed-order two-level reduction), the small normal
+// equations solved on the device, and the combination.  The iterates live in a ring of R = order + 2
+// vectors; with the newest at ring index m, iterate x_i (i = 0 newest) is entry (m - i) mod R.
 // ------------------------------------------------------------------------------------------------
 
 constexpr int kNgSums = 9;          // A00 A01 A02 A11 A12 A22 b0 b1 b2
-constexpr int kNgBlocks = 1024;
+constexpr int kNgBlocks = 512;      // blocks of the dot-product pass of one problem (fixes the order)
 constexpr int kNgThreads = 256;
+// layout of the Ng work buffer of one problem
+constexpr int kNgSumOff = kNgBlocks * kNgSums;   // the 9 sums
+constexpr int kNgCoefOff = kNgSumOff + kNgSums;  // c0..c3 (x_new = sum_i c_i x_i) and a valid flag
+constexpr int kNgWork = kNgCoefOff + 5;
 
 struct NgArgs {
     long V;
     int order;
-    const double *x[5];             // x[0] newest iterate, x[i] the i-th older one
-    double *partial;                // [kNgBlocks][kNgSums]
+    const double *hist;             // [order + 2][V]
+    double *work;                   // [kNgWork]
+    double *J;                      // receives the extrapolated iterate
 };
 
-__global__ __launch_bounds__(kNgThreads) void ng_dots_kernel(NgArgs a)
+__device__ inline const double *ng_x(const NgArgs &a, int m, int i)
 {
+    const int R = a.order + 2;
+    return a.hist + long((m - i + 4 * R) % R) * a.V;
+}
+
+// One block's share of the weighted dot products (weights 1/x_0^2).  Whole block.
+__device__ inline void ng_dots_body(const NgArgs &a, int m, int blk)
+{
+    const double *x0 = ng_x(a, m, 0), *x1 = ng_x(a, m, 1);
     double acc[kNgSums];
 #pragma unroll
     for (int q = 0; q < kNgSums; ++q) acc[q] = 0.0;
-    for (long v = long(blockIdx.x) * kNgThreads + threadIdx.x; v < a.V; v += long(kNgBlocks) * kNgThreads) {
-        const double x0 = a.x[0][v];
-        const double w = 1.0 / (x0 * x0);
-        const double d0 = x0 - a.x[1][v];
+    for (long v = long(blk) * kNgThreads + threadIdx.x; v < a.V; v += long(kNgBlocks) * kNgThreads) {
+        const double y0 = x0[v];
+        const double w = 1.0 / (y0 * y0);
+        const double d0 = y0 - x1[v];
         double Q[3] = {0.0, 0.0, 0.0};
-        for (int i = 1; i <= a.order; ++i) Q[i - 1] = d0 - (a.x[i][v] - a.x[i + 1][v]);
+        for (int i = 1; i <= a.order; ++i) Q[i - 1] = d0 - (ng_x(a, m, i)[v] - ng_x(a, m, i + 1)[v]);
         acc[0] += w * Q[0] * Q[0];
         acc[1] += w * Q[0] * Q[1];
         acc[2] += w * Q[0] * Q[2];
@@ -595,16 +611,18 @@ __global__ __launch_bounds__(kNgThreads) void ng_dots_kernel(NgArgs a)
             for (int q = 0; q < kNgSums; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x < kNgSums) a.partial[blockIdx.x * kNgSums + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < kNgSums) a.work[blk * kNgSums + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// one block: sums the per-block partials in a fixed order
-__global__ __launch_bounds__(kNgThreads) void ng_sum_kernel(const double *partial, double *out)
+// Sums the block partials in a fixed order (one block), then thread 0 solves the order x order
+// normal equations by Gaussian elimination with partial pivoting.  A singular system or a
+// non-finite solution clears the valid flag (the plain iterate is kept).
+__device__ inline void ng_solve_body(const NgArgs &a)
 {
     __shared__ double red[kNgSums][kNgThreads];
     for (int q = 0; q < kNgSums; ++q) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < kNgBlocks; b += kNgThreads) s += partial[b * kNgSums + q];
+        for (int b = threadIdx.x; b < kNgBlocks; b += kNgThreads) s += a.work[b * kNgSums + q];
         red[q][threadIdx.x] = s;
     }
     __syncthreads();
@@ -613,24 +631,67 @@ __global__ __launch_bounds__(kNgThreads) void ng_sum_kernel(const double *partia
             for (int q = 0; q < kNgSums; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x < kNgSums) out[threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x != 0) return;
+    double sums[kNgSums];
+    for (int q = 0; q < kNgSums; ++q) {
+        sums[q] = red[q][0];
+        a.work[kNgSumOff + q] = sums[q];
+    }
+    const int n = a.order;
+    double A[3][3] = {{sums[0], sums[1], sums[2]}, {sums[1], sums[3], sums[4]}, {sums[2], sums[4], sums[5]}};
+    double b[3] = {sums[6], sums[7], sums[8]}, c[3] = {0.0, 0.0, 0.0};
+    bool ok = true;
+    for (int col = 0; col < n && ok; ++col) {
+        int p = col;
+        for (int r = col + 1; r < n; ++r) if (fabs(A[r][col]) > fabs(A[p][col])) p = r;
+        if (!(fabs(A[p][col]) > 0.0)) { ok = false; break; }
+        if (p != col) {
+            for (int q = 0; q < n; ++q) { const double t = A[col][q]; A[col][q] = A[p][q]; A[p][q] = t; }
+            const double t = b[col]; b[col] = b[p]; b[p] = t;
+        }
+        for (int r = col + 1; r < n; ++r) {
+            const double f = A[r][col] / A[col][col];
+            for (int q = col; q < n; ++q) A[r][q] -= f * A[col][q];
+            b[r] -= f * b[col];
+        }
+    }
+    for (int r = n - 1; r >= 0 && ok; --r) {
+        double t = b[r];
+        for (int q = r + 1; q < n; ++q) t -= A[r][q] * c[q];
+        c[r] = t / A[r][r];
+        if (!isfinite(c[r])) ok = false;
+    }
+    double sa = 0.0;
+    for (int i = 0; i < n; ++i) sa += c[i];
+    a.work[kNgCoefOff + 0] = 1.0 - sa;
+    for (int i = 0; i < 3; ++i) a.work[kNgCoefOff + 1 + i] = c[i];
+    a.work[kNgCoefOff + 4] = ok ? 1.0 : 0.0;
 }
 
-struct NgCombineArgs {
-    long V;
-    int order;
-    double c0, c[3];                // x_new = c0 x[0] + sum_i c[i-1] x[i]
-    const double *x[4];
-    double *out;
-};
-
-__global__ void ng_combine_kernel(NgCombineArgs a)
+// J_v = c0 x_0 + sum_i c_i x_i (only when the solve succeeded)
+__device__ inline void ng_combine_body(const NgArgs &a, int m, long v)
 {
-    long v = long(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (v >= a.V) return;
-    double r = a.c0 * a.x[0][v];
-    for (int i = 1; i <= a.order; ++i) r += a.c[i - 1] * a.x[i][v];
-    a.out[v] = r;
+    const double *cf = a.work + kNgCoefOff;
+    if (cf[4] == 0.0) return;
+    double r = cf[0] * ng_x(a, m, 0)[v];
+    for (int i = 1; i <= a.order; ++i) r += cf[i] * ng_x(a, m, i)[v];
+    a.J[v] = r;
+}
+
+__global__ __launch_bounds__(kNgThreads) void ng_dots_kernel(NgArgs a, int m)
+{
+    ng_dots_body(a, m, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kNgThreads) void ng_solve_kernel(NgArgs a)
+{
+    ng_solve_body(a);
+}
+
+__global__ __launch_bounds__(256) void ng_combine_kernel(NgArgs a, int m)
+{
+    const long v = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v < a.V) ng_combine_body(a, m, v);
 }
 
 // finiteness / range check of a device medium
@@ -649,77 +710,6 @@ __global__ void check_finite_kernel(long V, const double *x, int *flag)
     long v = long(blockIdx.x) * blockDim.x + threadIdx.x;
     if (v >= V) return;
     if (!isfinite(x[v])) atomicOr(flag, 1);
-}
-
-
-// ------------------------------------------------------------------------------------------------
-// Batched launches: several independent problems (e.g. wavelengths on grids of different sizes) in
-// one launch per kernel.  Each block reads its problem's argument block; problems whose flag in
-// 'active' is zero return at once, which is how converged problems drop out of a replayed graph.
-// ------------------------------------------------------------------------------------------------
-
-struct BatchItem {
-    int member;
-    WorkItem item;
-};
-
-struct PlaneBlock {
-    int member, chunk, k, pad;
-};
-
-template <typename real, int NT, int LPT>
-__global__ __launch_bounds__(NT) void sweep_kernel_batch(const SweepArgs *args, const BatchItem *items,
-                                                         const int *active)
-{
-    extern __shared__ unsigned char smem_raw[];
-    const BatchItem bi = items[blockIdx.x];
-    if (!active[bi.member]) return;
-    const SweepArgs a = args[bi.member];
-    sweep_body<real, NT, LPT, false>(a, bi.item, smem_raw);
-}
-
-template <typename real>
-__global__ __launch_bounds__(kPlaneThreads) void source_kernel_batch(const SourceArgs *args,
-                                                                     const PlaneBlock *blocks,
-                                                                     const int *active)
-{
-    const PlaneBlock b = blocks[blockIdx.x];
-    if (!active[b.member]) return;
-    const SourceArgs a = args[b.member];
-    source_body<real>(a, b.chunk * kPlaneThreads + threadIdx.x, b.k);
-}
-
-template <typename real>
-__global__ __launch_bounds__(kPlaneThreads) void reduce_kernel_batch(const ReduceArgs *args,
-                                                                     const PlaneBlock *blocks,
-                                                                     const int *active)
-{
-    const PlaneBlock b = blocks[blockIdx.x];
-    if (!active[b.member]) return;
-    const ReduceArgs a = args[b.member];
-    reduce_body<real>(a, b.chunk * kPlaneThreads + threadIdx.x, b.k);
-}
-
-template <typename coef>
-__global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel_batch(const JacobiArgs *args,
-                                                                     const PlaneBlock *blocks,
-                                                                     const int *active)
-{
-    const PlaneBlock b = blocks[blockIdx.x];
-    if (!active[b.member]) return;
-    const JacobiArgs a = args[b.member];
-    jacobi_body<coef>(a, b.chunk * kPlaneThreads + threadIdx.x, b.k);
-}
-
-// Clears the per-member convergence scalars (a kernel, not a memset, so it can sit in a graph).
-__global__ void clear_scalars_kernel(int n, unsigned long long *a, unsigned long long *b, int *flags)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        a[i] = 0ull;
-        b[i] = 0ull;
-        flags[i] = 0;
-    }
 }
 
 }  // namespace

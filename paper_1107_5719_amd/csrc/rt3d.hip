@@ -34,6 +34,7 @@
 #include "context.h"
 #include "geometry.h"
 #include "kernels.h"
+#include "tune_cache.h"
 
 namespace rt3d_host {
 
@@ -48,34 +49,6 @@ int hip_fail(rt3d_ctx *c, hipError_t e, const char *what)
     std::string m = std::string(what) + ": " + hipGetErrorString(e);
     if (c) c->err = m;
     return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? RT3D_ERR_OOM : RT3D_ERR_HIP;
-}
-
-#define HIP_TRY(ctx, expr, what)                     \
-    do {                                             \
-        hipError_t e_ = (expr);                      \
-        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
-    } while (0)
-
-template <typename T>
-int dev_alloc(rt3d_ctx *c, T **p, size_t count)
-{
-    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), bytes);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        return hip_fail(c, e, "hipMalloc");
-    }
-    c->device_bytes += bytes;
-    return RT3D_OK;
-}
-
-template <typename T>
-int upload(rt3d_ctx *c, T **p, const std::vector<T> &h)
-{
-    int rc = dev_alloc(c, p, h.size());
-    if (rc) return rc;
-    if (!h.empty()) HIP_TRY(c, hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
-    return RT3D_OK;
 }
 
 hipEvent_t get_event(rt3d_ctx *c)
@@ -253,6 +226,7 @@ int launch_reduce(rt3d_ctx *c, bool with_residual, bool fp32, const double *base
 // S (given, or from J) -> J_fs (and r when with_residual), sweeps in float32 when fp32
 int run_fs(rt3d_ctx *c, const double *S_dev, bool with_residual, bool fp32)
 {
+    if (!c->plan_ok) return fail(c, RT3D_ERR_STATE, "no sweep plan (a shape change failed)");
     int rc = launch_source(c, S_dev, nullptr, fp32);
     if (!rc) rc = launch_sweep(c, fp32, false);
     if (!rc) rc = launch_reduce(c, with_residual, fp32, nullptr);
@@ -263,6 +237,7 @@ int run_fs(rt3d_ctx *c, const double *S_dev, bool with_residual, bool fp32)
 // FP32 form, difference step: J_fs = F_a + FS32((1 - eps)(J - Ja)) with no boundary light
 int run_fs_difference(rt3d_ctx *c)
 {
+    if (!c->plan_ok) return fail(c, RT3D_ERR_STATE, "no sweep plan (a shape change failed)");
     int rc = launch_source(c, nullptr, c->Ja, true);
     if (!rc) rc = launch_sweep(c, true, true);
     if (!rc) rc = launch_reduce(c, true, true, c->Fa);
@@ -288,6 +263,7 @@ int refresh_anchor(rt3d_ctx *c)
 int ensure_lstar(rt3d_ctx *c)
 {
     if (c->have_lstar) return RT3D_OK;
+    if (!c->plan_ok) return fail(c, RT3D_ERR_STATE, "no sweep plan (a shape change failed)");
     LstarArgs a;
     a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.n_dir = c->A.n_dir;
     a.early_exit = c->lstar_early_exit;
@@ -335,76 +311,34 @@ int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update)
     return check_launch(c, "jacobi_kernel");
 }
 
-// Solve the order x order normal equations of Ng's method (Gaussian elimination, partial
-// pivoting).  Returns false when the system is singular or the result is not finite.
-bool ng_solve_small(int n, double A[3][3], double b[3], double a[3])
-{
-    for (int col = 0; col < n; ++col) {
-        int p = col;
-        for (int r = col + 1; r < n; ++r) if (std::fabs(A[r][col]) > std::fabs(A[p][col])) p = r;
-        if (!(std::fabs(A[p][col]) > 0.0)) return false;
-        if (p != col) {
-            for (int q = 0; q < n; ++q) std::swap(A[col][q], A[p][q]);
-            std::swap(b[col], b[p]);
-        }
-        for (int r = col + 1; r < n; ++r) {
-            const double f = A[r][col] / A[col][col];
-            for (int q = col; q < n; ++q) A[r][q] -= f * A[col][q];
-            b[r] -= f * b[col];
-        }
-    }
-    for (int r = n - 1; r >= 0; --r) {
-        double t = b[r];
-        for (int q = r + 1; q < n; ++q) t -= A[r][q] * a[q];
-        a[r] = t / A[r][r];
-        if (!std::isfinite(a[r])) return false;
-    }
-    return true;
-}
-
-// Extrapolate J from the ring entries newest = index m (ring of ng_order + 2 vectors).
+// Extrapolate J from the ring entries, newest = index m (ring of ng_order + 2 vectors): dot
+// products, the small solve and the combination all run on the device, with no host round trip.
 int ng_step(rt3d_ctx *c, int m)
 {
-    const int R = c->ng_order + 2;
-    const long V = c->V;
     NgArgs a;
-    a.V = V;
+    a.V = c->V;
     a.order = c->ng_order;
-    for (int i = 0; i < 5; ++i) a.x[i] = c->ng_hist + long((m - std::min(i, c->ng_order + 1) + 4 * R) % R) * V;
-    a.partial = c->ng_partial;
-    hipLaunchKernelGGL(ng_dots_kernel, dim3(kNgBlocks), dim3(kNgThreads), 0, c->stream, a);
+    a.hist = c->ng_hist;
+    a.work = c->ng_work;
+    a.J = c->J;
+    hipLaunchKernelGGL(ng_dots_kernel, dim3(kNgBlocks), dim3(kNgThreads), 0, c->stream, a, m);
     int rc = check_launch(c, "ng_dots_kernel");
     if (rc) return rc;
-    double *sums_dev = c->ng_partial + kNgBlocks * kNgSums;
-    hipLaunchKernelGGL(ng_sum_kernel, dim3(1), dim3(kNgThreads), 0, c->stream, c->ng_partial, sums_dev);
-    rc = check_launch(c, "ng_sum_kernel");
+    hipLaunchKernelGGL(ng_solve_kernel, dim3(1), dim3(kNgThreads), 0, c->stream, a);
+    rc = check_launch(c, "ng_solve_kernel");
     if (rc) return rc;
-    double sums[kNgSums];
-    HIP_TRY(c, hipMemcpyAsync(sums, sums_dev, sizeof(sums), hipMemcpyDeviceToHost, c->stream), "ng sums");
-    rc = sync(c);
-    if (rc) return rc;
-    double A[3][3] = {{sums[0], sums[1], sums[2]}, {sums[1], sums[3], sums[4]}, {sums[2], sums[4], sums[5]}};
-    double b[3] = {sums[6], sums[7], sums[8]}, coef[3] = {0, 0, 0};
-    if (!ng_solve_small(c->ng_order, A, b, coef)) return RT3D_OK;   // keep the plain iterate
-    NgCombineArgs k;
-    k.V = V;
-    k.order = c->ng_order;
-    double sa = 0.0;
-    for (int i = 0; i < c->ng_order; ++i) { k.c[i] = coef[i]; sa += coef[i]; }
-    k.c0 = 1.0 - sa;
-    for (int i = 0; i < 4; ++i) k.x[i] = c->ng_hist + long((m - std::min(i, c->ng_order) + 4 * R) % R) * V;
-    k.out = c->J;
-    hipLaunchKernelGGL(ng_combine_kernel, dim3((V + 255) / 256), dim3(256), 0, c->stream, k);
+    hipLaunchKernelGGL(ng_combine_kernel, dim3((c->V + 255) / 256), dim3(256), 0, c->stream, a, m);
     return check_launch(c, "ng_combine_kernel");
 }
 
+void free_plan(rt3d_ctx *c);
+
 void free_all(rt3d_ctx *c)
 {
+    free_plan(c);
     void *ptrs[] = {c->chi, c->eps, c->B, c->J, c->Jfs, c->r, c->dJa, c->dJb, c->L, c->Kc, c->invD, c->Ecoef, c->Iem,
-                    c->Sbuf, c->cs, c->P, c->seg_len32, c->seg_len64, c->Ja, c->Fa, c->Iem_a, c->Kc32,
-                    c->d_maxdist, c->seg_off, c->seg_n, c->seg_a,
-                    c->seg_bb, c->seg_bm, c->seg_ai, c->seg_bi, c->row_min, c->dirs, c->items, c->pairs, c->pseg, c->player,
-                    c->d_maxrel, c->d_flag, c->ng_hist, c->ng_partial};
+                    c->Sbuf, c->cs, c->Ja, c->Fa, c->Iem_a, c->Kc32, c->d_maxdist, c->d_maxrel, c->d_flag,
+                    c->ng_hist, c->ng_work};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (auto &p : c->pending) {
@@ -412,6 +346,142 @@ void free_all(rt3d_ctx *c)
         hipEventDestroy(p.b);
     }
     for (auto e : c->event_pool) hipEventDestroy(e);
+}
+
+int n_sweep_shapes() { return int(sizeof(kSweepShapes) / sizeof(kSweepShapes[0])); }
+
+int run_fs_plain(rt3d_ctx *c) { return run_fs(c, nullptr, false, c->precision == RT3D_FP32_SWEEP); }
+
+std::string device_key()
+{
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string arch = p.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    return arch + "/" + std::to_string(p.multiProcessorCount) + "cu";
+}
+
+// the device tables built from the sweep plan (segment tables, pairs, work items, partial planes)
+void free_plan(rt3d_ctx *c)
+{
+    void **ptrs[] = {reinterpret_cast<void **>(&c->P), reinterpret_cast<void **>(&c->seg_len64),
+                     reinterpret_cast<void **>(&c->seg_len32), reinterpret_cast<void **>(&c->seg_off),
+                     reinterpret_cast<void **>(&c->seg_n), reinterpret_cast<void **>(&c->seg_a),
+                     reinterpret_cast<void **>(&c->seg_bb), reinterpret_cast<void **>(&c->seg_bm),
+                     reinterpret_cast<void **>(&c->seg_ai), reinterpret_cast<void **>(&c->seg_bi),
+                     reinterpret_cast<void **>(&c->row_min), reinterpret_cast<void **>(&c->dirs),
+                     reinterpret_cast<void **>(&c->items), reinterpret_cast<void **>(&c->pairs),
+                     reinterpret_cast<void **>(&c->pseg), reinterpret_cast<void **>(&c->player)};
+    for (void **p : ptrs) {
+        if (*p) hipFree(*p);
+        *p = nullptr;
+    }
+    c->device_bytes -= c->plan_bytes;
+    c->plan_bytes = 0;
+    c->plan_ok = false;
+}
+
+int install_plan(rt3d_ctx *c, int shape)
+{
+    if (shape < 0 || shape >= n_sweep_shapes()) return fail(c, RT3D_ERR_ARG, "sweep shape out of range");
+    const SweepShape sh = kSweepShapes[shape];
+    rt3d::SweepPlan plan;
+    std::string msg;
+    // one plan for both precisions: the LDS windows are budgeted for float64
+    if (!rt3d::build_sweep_plan(c->g.nx, c->g.ny, c->g.nz, c->A, sh.threads * sh.lines, 16 * sh.threads,
+                                kWindowBytes, int(sizeof(double)), plan, msg))
+        return fail(c, RT3D_ERR_ARG, msg);
+    int rc = sync(c);
+    if (rc) return rc;
+    free_plan(c);
+    c->plan = std::move(plan);
+    c->sweep_shape = shape;
+    const auto &P = c->plan;
+    const size_t before = c->device_bytes;
+    auto chk = [&](int r) { if (!rc) rc = r; };
+    {
+        double *Pp = nullptr;
+        chk(dev_alloc(c, &Pp, size_t(P.p_elems)));
+        c->P = Pp;
+    }
+    chk(upload(c, &c->seg_len64, P.seg_len));
+    chk(upload(c, &c->seg_len32, std::vector<float>(P.seg_len.begin(), P.seg_len.end())));
+    chk(upload(c, &c->seg_off, P.seg_off)); chk(upload(c, &c->seg_n, P.seg_n));
+    chk(upload(c, &c->seg_a, P.seg_a)); chk(upload(c, &c->seg_bb, P.seg_bb)); chk(upload(c, &c->seg_bm, P.seg_bm));
+    chk(upload(c, &c->seg_ai, P.seg_ai)); chk(upload(c, &c->seg_bi, P.seg_bi));
+    chk(upload(c, &c->row_min, P.row_min));
+    chk(upload(c, &c->dirs, P.dirs)); chk(upload(c, &c->items, P.items)); chk(upload(c, &c->pairs, P.pairs));
+    chk(upload(c, &c->pseg, P.pseg)); chk(upload(c, &c->player, P.player));
+    c->plan_bytes = c->device_bytes - before;
+    if (rc) {
+        free_plan(c);
+        return rc;
+    }
+    c->plan_ok = true;
+    return RT3D_OK;
+}
+
+int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream_t stream, int shape,
+               std::string &msg)
+{
+    *out = nullptr;
+    if (validate_desc(g, msg) != RT3D_OK) return RT3D_ERR_ARG;
+    if (precision != RT3D_FP64 && precision != RT3D_FP32_SWEEP) { msg = "bad precision"; return RT3D_ERR_ARG; }
+    if (shape < 0 || shape >= n_sweep_shapes()) { msg = "sweep shape out of range"; return RT3D_ERR_ARG; }
+    rt3d_ctx *c = new (std::nothrow) rt3d_ctx();
+    if (!c) { msg = "out of host memory"; return RT3D_ERR_OOM; }
+    c->g = *g;
+    c->precision = precision;
+    c->stream = stream;
+    c->real_size = (precision == RT3D_FP64) ? sizeof(double) : sizeof(float);
+    c->V = long(g->nx) * g->ny * g->nz;
+    if (!rt3d::make_angle_set(g->n_theta, g->n_phi, c->A)) { delete c; msg = "bad angle set"; return RT3D_ERR_ARG; }
+    // gathers of the next segment issued before the current one is computed (RT3D_SWEEP_PREFETCH=1;
+    // shapes 1 and 2 only; slower on MI355X because it costs occupancy)
+    if (const char *e = std::getenv("RT3D_SWEEP_PREFETCH")) c->sweep_prefetch = std::atoi(e) != 0;
+    if (const char *e = std::getenv("RT3D_JACOBI_XCD")) c->jacobi_xcd = std::atoi(e) != 0;
+    // Lambda* walk may stop at the first non-neighbour only if no line wraps back within two layers
+    {
+        double tmax_x = 0.0, tmax_y = 0.0;
+        for (int d = 0; d < c->A.n_dir; ++d) {
+            tmax_x = std::max(tmax_x, std::fabs(c->A.ox[d] / c->A.mu[d]));
+            tmax_y = std::max(tmax_y, std::fabs(c->A.oy[d] / c->A.mu[d]));
+        }
+        c->lstar_early_exit = (g->nx > 2.0 * tmax_x + 4.0 && g->ny > 2.0 * tmax_y + 4.0) ? 1 : 0;
+    }
+    const long V = c->V;
+    int rc = RT3D_OK;
+    auto chk = [&](int r) { if (!rc) rc = r; };
+    chk(dev_alloc(c, &c->chi, V)); chk(dev_alloc(c, &c->eps, V)); chk(dev_alloc(c, &c->B, V));
+    chk(dev_alloc(c, &c->J, V)); chk(dev_alloc(c, &c->Jfs, V)); chk(dev_alloc(c, &c->r, V));
+    chk(dev_alloc(c, &c->dJa, V)); chk(dev_alloc(c, &c->dJb, V)); chk(dev_alloc(c, &c->Sbuf, V));
+    chk(dev_alloc(c, &c->L, 27 * V));
+    chk(dev_alloc(c, &c->invD, V)); chk(dev_alloc(c, &c->Ecoef, V));
+    if (precision == RT3D_FP64) chk(dev_alloc(c, &c->Kc, 13 * V));
+    chk(dev_alloc(c, &c->Iem, size_t(c->A.n_dir / 2) * g->nx * g->ny));
+    {
+        double2 *cs = nullptr;
+        chk(dev_alloc(c, &cs, V));
+        c->cs = cs;
+    }
+    if (precision == RT3D_FP32_SWEEP) {
+        chk(dev_alloc(c, &c->Ja, V)); chk(dev_alloc(c, &c->Fa, V));
+        chk(dev_alloc(c, &c->Iem_a, size_t(c->A.n_dir / 2) * g->nx * g->ny));
+        chk(dev_alloc(c, &c->Kc32, 13 * V));
+    }
+    chk(dev_alloc(c, &c->d_maxdist, 1));
+    chk(dev_alloc(c, &c->d_maxrel, 1)); chk(dev_alloc(c, &c->d_flag, 1));
+    if (!rc) rc = install_plan(c, shape);
+    if (rc) {
+        msg = c->err;
+        free_all(c);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return RT3D_OK;
 }
 
 }  // namespace rt3d_host
@@ -459,7 +529,7 @@ int rt3d_segment_table(const rt3d_grid_desc *g, int d, int k, int *di, int *dj, 
     if (!rt3d::make_angle_set(g->n_theta, g->n_phi, A)) return RT3D_ERR_ARG;
     if (d < 0 || d >= A.n_dir || k < 0 || k >= g->nz) return RT3D_ERR_ARG;
     rt3d::LayerSegments L;
-    rt3d::layer_segments(g->nz, A.mu[d], A.ox[d], A.oy[d], k, L);
+    rt3d::direction_segments(g->nz, A, d, k, L);
     const int n = int(L.di.size());
     if (n > max_seg) return RT3D_ERR_ARG;
     for (int s = 0; s < n; ++s) {
@@ -482,81 +552,14 @@ int rt3d_create(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, void *hi
 {
     if (!out) return RT3D_ERR_ARG;
     *out = nullptr;
-    std::string msg;
-    if (validate_desc(g, msg) != RT3D_OK) return RT3D_ERR_ARG;
-    if (precision != RT3D_FP64 && precision != RT3D_FP32_SWEEP) return RT3D_ERR_ARG;
-    rt3d_ctx *c = new (std::nothrow) rt3d_ctx();
-    if (!c) return RT3D_ERR_OOM;
-    c->g = *g;
-    c->precision = precision;
-    c->stream = static_cast<hipStream_t>(hip_stream);
-    c->real_size = (precision == RT3D_FP64) ? sizeof(double) : sizeof(float);
-    c->V = long(g->nx) * g->ny * g->nz;
-    if (!rt3d::make_angle_set(g->n_theta, g->n_phi, c->A)) { delete c; return RT3D_ERR_ARG; }
-    // workgroup shape of the sweep: RT3D_SWEEP_SHAPE indexes kSweepShapes (default 512 threads x 2 lines)
+    // workgroup shape of the sweep: RT3D_SWEEP_SHAPE indexes the shape table (default 512 x 2)
+    int shape = 0;
     if (const char *e = std::getenv("RT3D_SWEEP_SHAPE")) {
         const int v = std::atoi(e);
-        if (v >= 0 && v < int(sizeof(kSweepShapes) / sizeof(kSweepShapes[0]))) c->sweep_shape = v;
+        if (v >= 0 && v < n_sweep_shapes()) shape = v;
     }
-    // gathers of the next segment issued before the current one is computed (RT3D_SWEEP_PREFETCH=1;
-    // shapes 1 and 2 only; slower on MI355X because it costs occupancy)
-    if (const char *e = std::getenv("RT3D_SWEEP_PREFETCH")) c->sweep_prefetch = std::atoi(e) != 0;
-    if (const char *e = std::getenv("RT3D_JACOBI_XCD")) c->jacobi_xcd = std::atoi(e) != 0;
-    const SweepShape shape = kSweepShapes[c->sweep_shape];
-    const int lines = shape.threads * shape.lines;
-    // one plan for both precisions: the LDS windows are budgeted for float64
-    if (!rt3d::build_sweep_plan(g->nx, g->ny, g->nz, c->A, lines, 16 * shape.threads, kWindowBytes,
-                                int(sizeof(double)), c->plan, msg)) {
-        delete c;
-        return RT3D_ERR_ARG;
-    }
-    // Lambda* walk may stop at the first non-neighbour only if no line wraps back within two layers
-    {
-        double tmax_x = 0.0, tmax_y = 0.0;
-        for (int d = 0; d < c->A.n_dir; ++d) {
-            tmax_x = std::max(tmax_x, std::fabs(c->A.ox[d] / c->A.mu[d]));
-            tmax_y = std::max(tmax_y, std::fabs(c->A.oy[d] / c->A.mu[d]));
-        }
-        c->lstar_early_exit = (g->nx > 2.0 * tmax_x + 4.0 && g->ny > 2.0 * tmax_y + 4.0) ? 1 : 0;
-    }
-    const long V = c->V;
-    const auto &P = c->plan;
-    int rc = RT3D_OK;
-    auto chk = [&](int r) { if (!rc) rc = r; };
-    chk(dev_alloc(c, &c->chi, V)); chk(dev_alloc(c, &c->eps, V)); chk(dev_alloc(c, &c->B, V));
-    chk(dev_alloc(c, &c->J, V)); chk(dev_alloc(c, &c->Jfs, V)); chk(dev_alloc(c, &c->r, V));
-    chk(dev_alloc(c, &c->dJa, V)); chk(dev_alloc(c, &c->dJb, V)); chk(dev_alloc(c, &c->Sbuf, V));
-    chk(dev_alloc(c, &c->L, 27 * V));
-    chk(dev_alloc(c, &c->invD, V)); chk(dev_alloc(c, &c->Ecoef, V));
-    if (precision == RT3D_FP64) chk(dev_alloc(c, &c->Kc, 13 * V));
-    chk(dev_alloc(c, &c->Iem, size_t(c->A.n_dir / 2) * g->nx * g->ny));
-    {
-        double2 *cs = nullptr; double *Pp = nullptr;
-        chk(dev_alloc(c, &cs, V)); chk(dev_alloc(c, &Pp, size_t(P.p_elems)));
-        c->cs = cs; c->P = Pp;
-    }
-    chk(upload(c, &c->seg_len64, P.seg_len));
-    chk(upload(c, &c->seg_len32, std::vector<float>(P.seg_len.begin(), P.seg_len.end())));
-    if (precision == RT3D_FP32_SWEEP) {
-        chk(dev_alloc(c, &c->Ja, V)); chk(dev_alloc(c, &c->Fa, V));
-        chk(dev_alloc(c, &c->Iem_a, size_t(c->A.n_dir / 2) * g->nx * g->ny));
-        chk(dev_alloc(c, &c->Kc32, 13 * V));
-    }
-    chk(dev_alloc(c, &c->d_maxdist, 1));
-    chk(upload(c, &c->seg_off, P.seg_off)); chk(upload(c, &c->seg_n, P.seg_n));
-    chk(upload(c, &c->seg_a, P.seg_a)); chk(upload(c, &c->seg_bb, P.seg_bb)); chk(upload(c, &c->seg_bm, P.seg_bm));
-    chk(upload(c, &c->seg_ai, P.seg_ai)); chk(upload(c, &c->seg_bi, P.seg_bi));
-    chk(upload(c, &c->row_min, P.row_min));
-    chk(upload(c, &c->dirs, P.dirs)); chk(upload(c, &c->items, P.items)); chk(upload(c, &c->pairs, P.pairs));
-    chk(upload(c, &c->pseg, P.pseg)); chk(upload(c, &c->player, P.player));
-    chk(dev_alloc(c, &c->d_maxrel, 1)); chk(dev_alloc(c, &c->d_flag, 1));
-    if (rc) {
-        free_all(c);
-        delete c;
-        return rc;
-    }
-    *out = c;
-    return RT3D_OK;
+    std::string msg;
+    return create_ctx(out, g, precision, static_cast<hipStream_t>(hip_stream), shape, msg);
 }
 
 void rt3d_destroy(rt3d_ctx *ctx)
@@ -790,12 +793,12 @@ int rt3d_set_acceleration(rt3d_ctx *c, int ng_order, int ng_every)
     int rc = sync(c);
     if (rc) return rc;
     if (c->ng_hist) { hipFree(c->ng_hist); c->ng_hist = nullptr; }
-    if (c->ng_partial) { hipFree(c->ng_partial); c->ng_partial = nullptr; }
+    if (c->ng_work) { hipFree(c->ng_work); c->ng_work = nullptr; }
     c->ng_order = 0;
     c->ng_every = 0;
     if (ng_order == 0) return RT3D_OK;
     rc = dev_alloc(c, &c->ng_hist, size_t(ng_order + 2) * c->V);
-    if (!rc) rc = dev_alloc(c, &c->ng_partial, size_t(kNgBlocks) * kNgSums + kNgSums);
+    if (!rc) rc = dev_alloc(c, &c->ng_work, size_t(kNgWork));
     if (rc) return rc;
     c->ng_order = ng_order;
     c->ng_every = ng_every;
@@ -835,11 +838,11 @@ int rt3d_get_stats(rt3d_ctx *c, char *buf, int buflen)
     std::snprintf(tmp, sizeof tmp,
                   "\"nx\":%d,\"ny\":%d,\"nz\":%d,\"n_dir\":%d,\"precision\":\"%s\",\"outer_iters\":%ld,"
                   "\"inner_sweeps\":%ld,\"fp64_sweeps\":%ld,\"fp32_sweeps\":%ld,\"device_bytes\":%zu,\"partial_plane_bytes\":%lld,"
-                  "\"sweep_workgroups\":%zu,\"sweep_threads\":%d,\"mean_segments\":%.6f,\"timing\":%s,\"kernels\":{",
+                  "\"sweep_workgroups\":%zu,\"sweep_shape\":%d,\"sweep_threads\":%d,\"sweep_lines\":%d,\"mean_segments\":%.6f,\"timing\":%s,\"kernels\":{",
                   c->g.nx, c->g.ny, c->g.nz, c->A.n_dir, c->precision == RT3D_FP64 ? "fp64" : "fp32_sweep",
                   c->outer_iters, c->inner_sweeps, c->fp64_sweeps, c->fp32_sweeps, c->device_bytes,
                   (long long)(c->plan.p_elems * (long long)sizeof(double)), c->plan.items.size(),
-                  kSweepShapes[c->sweep_shape].threads, c->plan.mean_segments, c->timing ? "true" : "false");
+                  c->sweep_shape, kSweepShapes[c->sweep_shape].threads, kSweepShapes[c->sweep_shape].lines, c->plan.mean_segments, c->timing ? "true" : "false");
     s += tmp;
     for (int k = 0; k < K_COUNT; ++k) {
         std::snprintf(tmp, sizeof tmp, "%s\"%s\":{\"launches\":%ld,\"total_ms\":%.6f}", k ? "," : "",
@@ -849,6 +852,90 @@ int rt3d_get_stats(rt3d_ctx *c, char *buf, int buflen)
     s += "}}";
     if (int(s.size()) + 1 > buflen) return fail(c, RT3D_ERR_ARG, "stats buffer too small");
     std::memcpy(buf, s.c_str(), s.size() + 1);
+    return RT3D_OK;
+}
+
+int rt3d_sweep_shapes(int *threads, int *lines, int max_n)
+{
+    const int n = n_sweep_shapes();
+    for (int i = 0; i < n && i < max_n; ++i) {
+        if (threads) threads[i] = kSweepShapes[i].threads;
+        if (lines) lines[i] = kSweepShapes[i].lines;
+    }
+    return n;
+}
+
+int rt3d_set_sweep_shape(rt3d_ctx *c, int shape)
+{
+    if (!c) return RT3D_ERR_ARG;
+    return install_plan(c, shape);
+}
+
+int rt3d_autotune(rt3d_ctx *c, const char *cache_path, int repeats, int *shape_out, double *ms_out)
+{
+    if (!c) return RT3D_ERR_ARG;
+    if (!c->have_medium) return fail(c, RT3D_ERR_STATE, "set the medium first");
+    if (repeats < 1) return fail(c, RT3D_ERR_ARG, "repeats must be >= 1");
+    const int ns = n_sweep_shapes();
+    char grid[96];
+    std::snprintf(grid, sizeof grid, "%dx%dx%d|%dx%d", c->g.nx, c->g.ny, c->g.nz, c->g.n_theta, c->g.n_phi);
+    const std::string key = device_key() + "|" + (c->precision == RT3D_FP64 ? "fp64" : "fp32_sweep") + "|" + grid;
+    int cached = -1;
+    if (cache_path && *cache_path && rt3d_tune::lookup(cache_path, key, cached) && cached >= 0 && cached < ns) {
+        if (cached != c->sweep_shape) {
+            const int rc = install_plan(c, cached);
+            if (rc) return rc;
+        }
+        if (shape_out) *shape_out = cached;
+        if (ms_out) for (int i = 0; i < ns; ++i) ms_out[i] = -1.0;
+        return RT3D_OK;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(c, hipEventCreate(&e0), "hipEventCreate");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(c, RT3D_ERR_HIP, "hipEventCreate");
+    }
+    std::vector<double> ms(ns, INFINITY);
+    int rc = RT3D_OK;
+    for (int s = 0; s < ns && !rc; ++s) {
+        const int r = install_plan(c, s);
+        if (r == RT3D_ERR_ARG) continue;      // the shape does not fit this grid
+        if (r) { rc = r; break; }
+        rc = run_fs_plain(c);                 // warm-up
+        if (!rc) rc = sync(c);
+        if (!rc && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(c, RT3D_ERR_HIP, "hipEventRecord");
+        for (int k = 0; k < repeats && !rc; ++k) rc = run_fs_plain(c);
+        if (!rc && hipEventRecord(e1, c->stream) != hipSuccess) rc = fail(c, RT3D_ERR_HIP, "hipEventRecord");
+        if (!rc) rc = sync(c);
+        float t = 0.f;
+        if (!rc && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms[s] = double(t) / repeats;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    int best = -1;
+    for (int s = 0; s < ns; ++s)
+        if (std::isfinite(ms[s]) && (best < 0 || ms[s] < ms[best])) best = s;
+    if (best < 0) return fail(c, RT3D_ERR_ARG, "no sweep shape fits this grid");
+    rc = install_plan(c, best);
+    if (rc) return rc;
+    if (shape_out) *shape_out = best;
+    if (ms_out) for (int i = 0; i < ns; ++i) ms_out[i] = std::isfinite(ms[i]) ? ms[i] : -1.0;
+    if (cache_path && *cache_path) {
+        std::string entry = "{\"shape\": " + std::to_string(best) + ", \"threads\": " +
+                            std::to_string(kSweepShapes[best].threads) + ", \"lines\": " +
+                            std::to_string(kSweepShapes[best].lines) + ", \"ms\": [";
+        for (int i = 0; i < ns; ++i) {
+            char t[32];
+            if (std::isfinite(ms[i])) std::snprintf(t, sizeof t, "%.4f", ms[i]);
+            else std::snprintf(t, sizeof t, "null");
+            entry += (i ? ", " : "") + std::string(t);
+        }
+        entry += "]}";
+        std::string err;
+        if (!rt3d_tune::store(cache_path, key, entry, err)) return fail(c, RT3D_ERR_ARG, err);
+    }
     return RT3D_OK;
 }
 

@@ -19,7 +19,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Workload", "WORKLOADS", "stratified_profile", "make_medium", "random_medium"]
+__all__ = ["Workload", "WORKLOADS", "stratified_profile", "make_medium", "random_medium", "wavelength_batch"]
 
 
 @dataclass(frozen=True)
@@ -134,3 +134,33 @@ def random_medium(nx: int, ny: int, nz: int, seed: int, chi_range=(1e-2, 1e2),
     eps = np.exp(rng.uniform(elo, ehi, shape))
     B = rng.uniform(b_range[0], b_range[1], shape)
     return {"chi": chi, "eps": eps, "B": B}
+
+
+def wavelength_batch(n: int = 64, sizes=(33, 65, 97), n_theta: int = 8, n_phi: int = 8, seed0: int = 1000,
+                     chi0_range=(1e-2, 1e2), eps_range=(1e-6, 1e-1), sigma: float = 0.05,
+                     decades: float = 7.0):
+    """Many wavelengths of one stratified atmosphere, each on a grid of its own.
+
+    Wavelength l uses the generator seeded with seed0 + l: it draws the grid edge N uniformly from
+    ``sizes`` (an N^3 grid), the opacity chi0 at the bottom plane log-uniformly from chi0_range and
+    a uniform epsilon log-uniformly from eps_range; then chi_k = chi0 exp(-(k + 1/2) / H) with
+    H = N / (decades ln 10) (the same fall-off over the column as the single-wavelength workloads),
+    times an i.i.d. log-normal perturbation of standard deviation sigma per voxel; B = 1.
+
+    Returns a list of dicts: grid (nx, ny, nz, n_theta, n_phi) and medium (chi, eps, B), plus the
+    drawn chi0 and eps."""
+    out = []
+    for lam in range(n):
+        rng = np.random.Generator(np.random.PCG64(seed0 + lam))
+        N = int(sizes[int(rng.integers(len(sizes)))])
+        chi0 = float(np.exp(rng.uniform(np.log(chi0_range[0]), np.log(chi0_range[1]))))
+        eps = float(np.exp(rng.uniform(np.log(eps_range[0]), np.log(eps_range[1]))))
+        H = N / (decades * math.log(10.0))
+        prof = chi0 * np.exp(-(np.arange(N, dtype=np.float64) + 0.5) / H)
+        chi = prof[:, None, None] * np.exp(sigma * rng.standard_normal((N, N, N)))
+        out.append({
+            "grid": {"nx": N, "ny": N, "nz": N, "n_theta": n_theta, "n_phi": n_phi},
+            "chi": np.ascontiguousarray(chi), "eps": np.full((N, N, N), eps), "B": np.ones((N, N, N)),
+            "chi0": chi0, "eps_value": eps,
+        })
+    return out

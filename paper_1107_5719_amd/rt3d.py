@@ -30,12 +30,21 @@ RT3D_HOST = 0
 RT3D_DEVICE = 1
 RT3D_FP64 = 0
 RT3D_FP32_SWEEP = 1
+RT3D_MEMBER_RUNNING = 0
+RT3D_MEMBER_CONVERGED = 1
+RT3D_MEMBER_MAX_ITER = 2
+RT3D_MEMBER_NONFINITE = 3
 
 EXPORTED = [
     "rt3d_create", "rt3d_destroy", "rt3d_set_medium", "rt3d_set_J", "rt3d_get_J",
     "rt3d_formal_solution", "rt3d_build_lstar", "rt3d_get_lstar", "rt3d_os_step",
     "rt3d_solve_to_convergence", "rt3d_set_acceleration", "rt3d_get_emergent_top", "rt3d_set_timing", "rt3d_get_stats",
     "rt3d_status_str", "rt3d_last_error", "rt3d_quadrature", "rt3d_segment_table", "rt3d_validate",
+    "rt3d_sweep_shapes", "rt3d_set_sweep_shape", "rt3d_autotune",
+    "rt3d_batch_create", "rt3d_batch_destroy", "rt3d_batch_size", "rt3d_batch_last_error",
+    "rt3d_batch_set_medium", "rt3d_batch_set_J", "rt3d_batch_get_J", "rt3d_batch_get_Jfs",
+    "rt3d_batch_set_acceleration", "rt3d_batch_set_sweep_shape", "rt3d_batch_formal_solution",
+    "rt3d_batch_solve", "rt3d_batch_autotune", "rt3d_batch_get_stats",
 ]
 
 
@@ -75,6 +84,23 @@ _sig = {
     "rt3d_quadrature": (_i, [_i, _i, _vp, _vp, _vp, _vp]),
     "rt3d_segment_table": (_i, [C.POINTER(GridDesc), _i, _i, _vp, _vp, _vp, _i]),
     "rt3d_validate": (_i, [C.POINTER(GridDesc), _vp, _vp, _vp]),
+    "rt3d_sweep_shapes": (_i, [_vp, _vp, _i]),
+    "rt3d_set_sweep_shape": (_i, [_vp, _i]),
+    "rt3d_autotune": (_i, [_vp, C.c_char_p, _i, C.POINTER(_i), _vp]),
+    "rt3d_batch_create": (_i, [C.POINTER(_vp), _i, _vp, _i, _i, _vp]),
+    "rt3d_batch_destroy": (None, [_vp]),
+    "rt3d_batch_size": (_i, [_vp]),
+    "rt3d_batch_last_error": (C.c_char_p, [_vp]),
+    "rt3d_batch_set_medium": (_i, [_vp, _i, _vp, _vp, _vp, _i]),
+    "rt3d_batch_set_J": (_i, [_vp, _i, _vp, _i]),
+    "rt3d_batch_get_J": (_i, [_vp, _i, _vp, _i]),
+    "rt3d_batch_get_Jfs": (_i, [_vp, _i, _vp, _i]),
+    "rt3d_batch_set_acceleration": (_i, [_vp, _i, _i]),
+    "rt3d_batch_set_sweep_shape": (_i, [_vp, _i]),
+    "rt3d_batch_formal_solution": (_i, [_vp]),
+    "rt3d_batch_solve": (_i, [_vp, _d, _i, _i, _i, _vp, _vp, _vp]),
+    "rt3d_batch_autotune": (_i, [_vp, C.c_char_p, _i, C.POINTER(_i), _vp]),
+    "rt3d_batch_get_stats": (_i, [_vp, C.c_char_p, _i]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -87,12 +113,12 @@ def library():
     return _lib
 
 
-def _raise(ctx, status: int, what: str):
+def _raise(ctx, status: int, what: str, last_error=None):
     if status == RT3D_OK:
         return status
     msg = ""
     if ctx:
-        m = _lib.rt3d_last_error(ctx)
+        m = (last_error or _lib.rt3d_last_error)(ctx)
         msg = m.decode() if m else ""
     if not msg:
         msg = _lib.rt3d_status_str(status).decode()
@@ -269,6 +295,126 @@ def rt3d_validate(desc: GridDesc, chi=None, eps=None, B=None) -> int:
     return _lib.rt3d_validate(C.byref(desc), *ptrs)
 
 
+def rt3d_sweep_shapes():
+    """[(threads, lines per thread), ...] of the sweep workgroup shapes."""
+    n = _lib.rt3d_sweep_shapes(None, None, 0)
+    t = np.zeros(n, dtype=np.int32)
+    l = np.zeros(n, dtype=np.int32)
+    _lib.rt3d_sweep_shapes(t.ctypes.data_as(_vp), l.ctypes.data_as(_vp), n)
+    return list(zip(t.tolist(), l.tolist()))
+
+
+def rt3d_set_sweep_shape(ctx, shape: int):
+    return _raise(ctx, _lib.rt3d_set_sweep_shape(ctx, int(shape)), "rt3d_set_sweep_shape")
+
+
+def _autotune(fn, errfn, handle, cache_path, repeats, what):
+    n = _lib.rt3d_sweep_shapes(None, None, 0)
+    shape = C.c_int(-1)
+    ms = np.zeros(n)
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _raise(handle, fn(handle, path, int(repeats), C.byref(shape), ms.ctypes.data_as(_vp)), what, errfn)
+    return shape.value, ms
+
+
+def rt3d_autotune(ctx, cache_path=None, repeats: int = 3):
+    """Returns (shape, ms per formal solution for every shape, -1 where not measured)."""
+    return _autotune(_lib.rt3d_autotune, None, ctx, cache_path, repeats, "rt3d_autotune")
+
+
+def rt3d_batch_create(descs, precision: int = RT3D_FP64, sweep_shape: int = 0, stream=None):
+    """descs: a sequence of GridDesc.  stream: a hipStream_t as int other than the legacy default
+    stream, or None for a stream the batch creates."""
+    arr = (GridDesc * len(descs))(*descs)
+    b = C.c_void_p()
+    st = _lib.rt3d_batch_create(C.byref(b), len(descs), C.cast(arr, _vp), int(precision), int(sweep_shape),
+                                C.c_void_p(stream or 0))
+    _raise(None, st, "rt3d_batch_create")
+    return b
+
+
+def rt3d_batch_destroy(b):
+    _lib.rt3d_batch_destroy(b)
+
+
+def rt3d_batch_size(b) -> int:
+    return _lib.rt3d_batch_size(b)
+
+
+def rt3d_batch_last_error(b) -> str:
+    m = _lib.rt3d_batch_last_error(b)
+    return m.decode() if m else ""
+
+
+def _braise(b, status, what):
+    return _raise(b, status, what, _lib.rt3d_batch_last_error)
+
+
+def rt3d_batch_set_medium(b, member: int, chi, eps, B):
+    ptrs, kinds, keep = [], [], []
+    for a in (chi, eps, B):
+        p, k, h = _arg(a)
+        ptrs.append(p)
+        kinds.append(k)
+        keep.append(h)
+    if len(set(kinds)) != 1:
+        raise ValueError("chi, eps and B must all be host arrays or all device tensors")
+    return _braise(b, _lib.rt3d_batch_set_medium(b, int(member), *ptrs, kinds[0]), "rt3d_batch_set_medium")
+
+
+def rt3d_batch_set_J(b, member: int, J):
+    p, k, h = _arg(J)
+    return _braise(b, _lib.rt3d_batch_set_J(b, int(member), p, k), "rt3d_batch_set_J")
+
+
+def rt3d_batch_get_J(b, member: int, out):
+    p, k, h = _arg(out, writable=True)
+    return _braise(b, _lib.rt3d_batch_get_J(b, int(member), p, k), "rt3d_batch_get_J")
+
+
+def rt3d_batch_get_Jfs(b, member: int, out):
+    p, k, h = _arg(out, writable=True)
+    return _braise(b, _lib.rt3d_batch_get_Jfs(b, int(member), p, k), "rt3d_batch_get_Jfs")
+
+
+def rt3d_batch_set_acceleration(b, ng_order: int, ng_every: int):
+    return _braise(b, _lib.rt3d_batch_set_acceleration(b, int(ng_order), int(ng_every)),
+                   "rt3d_batch_set_acceleration")
+
+
+def rt3d_batch_set_sweep_shape(b, shape: int):
+    return _braise(b, _lib.rt3d_batch_set_sweep_shape(b, int(shape)), "rt3d_batch_set_sweep_shape")
+
+
+def rt3d_batch_formal_solution(b):
+    return _braise(b, _lib.rt3d_batch_formal_solution(b), "rt3d_batch_formal_solution")
+
+
+def rt3d_batch_solve(b, tol: float, max_iter: int, inner_sweeps: int, poll_every: int = 4, check=True):
+    """Returns (status, iterations[n], last c[n], member states[n]); raises on any error except
+    RT3D_ERR_NOT_CONVERGED unless check is False."""
+    n = _lib.rt3d_batch_size(b)
+    it = np.zeros(n, dtype=np.int32)
+    c = np.zeros(n)
+    ms = np.zeros(n, dtype=np.int32)
+    st = _lib.rt3d_batch_solve(b, float(tol), int(max_iter), int(inner_sweeps), int(poll_every),
+                               it.ctypes.data_as(_vp), c.ctypes.data_as(_vp), ms.ctypes.data_as(_vp))
+    if check and st not in (RT3D_OK, RT3D_ERR_NOT_CONVERGED):
+        _braise(b, st, "rt3d_batch_solve")
+    return st, it, c, ms
+
+
+def rt3d_batch_autotune(b, cache_path=None, repeats: int = 3):
+    return _autotune(_lib.rt3d_batch_autotune, _lib.rt3d_batch_last_error, b, cache_path, repeats,
+                     "rt3d_batch_autotune")
+
+
+def rt3d_batch_get_stats(b) -> dict:
+    buf = C.create_string_buffer(4096)
+    _braise(b, _lib.rt3d_batch_get_stats(b, buf, len(buf)), "rt3d_batch_get_stats")
+    return json.loads(buf.value.decode())
+
+
 # ---- convenience wrapper ----------------------------------------------------------------------------
 
 class Solver:
@@ -341,3 +487,76 @@ class Solver:
 
     def stats(self):
         return rt3d_get_stats(self.ctx)
+
+    def set_sweep_shape(self, shape):
+        rt3d_set_sweep_shape(self.ctx, shape)
+
+    def autotune(self, cache_path=None, repeats=3):
+        return rt3d_autotune(self.ctx, cache_path, repeats)
+
+
+class Batch:
+    """Owns one batch of problems; methods map one-to-one onto the rt3d_batch_* calls.
+
+    grids: a sequence of dicts with keys nx, ny, nz, n_theta, n_phi (and optionally I_top,
+    bottom_bc)."""
+
+    def __init__(self, grids, precision=RT3D_FP64, sweep_shape=0, stream=None):
+        self.descs = [_desc(g["nx"], g["ny"], g["nz"], g["n_theta"], g["n_phi"], g.get("I_top", 0.0),
+                            g.get("bottom_bc", 0)) for g in grids]
+        self.shapes = [(d.nz, d.ny, d.nx) for d in self.descs]
+        self.b = rt3d_batch_create(self.descs, precision, sweep_shape, stream)
+
+    def close(self):
+        if self.b:
+            rt3d_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __len__(self):
+        return len(self.descs)
+
+    def set_medium(self, member, chi, eps, B):
+        rt3d_batch_set_medium(self.b, member, chi, eps, B)
+
+    def set_J(self, member, J):
+        rt3d_batch_set_J(self.b, member, J)
+
+    def get_J(self, member, out=None):
+        out = np.zeros(self.shapes[member]) if out is None else out
+        rt3d_batch_get_J(self.b, member, out)
+        return out
+
+    def get_Jfs(self, member, out=None):
+        out = np.zeros(self.shapes[member]) if out is None else out
+        rt3d_batch_get_Jfs(self.b, member, out)
+        return out
+
+    def set_acceleration(self, ng_order, ng_every):
+        rt3d_batch_set_acceleration(self.b, ng_order, ng_every)
+
+    def set_sweep_shape(self, shape):
+        rt3d_batch_set_sweep_shape(self.b, shape)
+
+    def formal_solution(self):
+        rt3d_batch_formal_solution(self.b)
+
+    def solve(self, tol, max_iter, inner_sweeps, poll_every=4, check=True):
+        return rt3d_batch_solve(self.b, tol, max_iter, inner_sweeps, poll_every, check)
+
+    def autotune(self, cache_path=None, repeats=3):
+        return rt3d_batch_autotune(self.b, cache_path, repeats)
+
+    def stats(self):
+        return rt3d_batch_get_stats(self.b)
