@@ -52,7 +52,7 @@ def measured_traffic(kernel: str):
     committed rocprofv3 summary, or None if the kernel source changed since it was measured."""
     import hashlib
 
-    src = os.path.join(ROOT, "paper_1107_5719_amd", "csrc", "rt3d.hip")
+    src = os.path.join(ROOT, "paper_1107_5719_amd", "csrc", "kernels.h")
     prof = os.path.join(ROOT, "profiles", "strat129_hbm_bytes.txt")
     if not os.path.exists(prof):
         return None
@@ -108,6 +108,99 @@ def _converge(rt3d, torch, w, d_med, prec, stream, M, ng_order, ng_every, tol, m
                "fp32_sweeps": st["fp32_sweeps"]}
 
 
+def _batched(rt3d, torch, n_wl, M, ng, tol, ref_tol, max_iter, cache):
+    """The many-wavelength form: n_wl wavelengths, grids drawn from {33, 65, 97}^3, 64 angles each.
+
+    Time to converged J of all of them (inputs resident, Lambda* builds included) for three forms:
+    the plain float64 path one wavelength at a time (one context each, shape autotuned per grid),
+    the batch in float64 and the batch with float32 sweeps; each against a float64 batch solved to
+    ref_tol.  Also the batched formal-solution rate."""
+    from paper_1107_5719_amd.inputs import wavelength_batch
+
+    mem = wavelength_batch(n_wl)
+    grids = [m["grid"] for m in mem]
+    dm = [{k: torch.from_numpy(m[k]).cuda() for k in ("chi", "eps", "B")} for m in mem]
+    torch.cuda.synchronize()
+    vox = sum(g["nx"] * g["ny"] * g["nz"] for g in grids)
+    vox_ang = sum(g["nx"] * g["ny"] * g["nz"] * g["n_theta"] * g["n_phi"] for g in grids)
+    sizes = {}
+    for g in grids:
+        sizes[g["nx"]] = sizes.get(g["nx"], 0) + 1
+
+    def fetch(getter, i):
+        J = torch.zeros(dm[i]["B"].shape, dtype=torch.float64, device="cuda")
+        getter(i, J)
+        return J
+
+    def run_batch(prec, tol_, fs_reps):
+        b = rt3d.Batch(grids, precision=prec)
+        for i, d in enumerate(dm):
+            b.set_medium(i, d["chi"], d["eps"], d["B"])
+        shape, ms = b.autotune(cache, repeats=3)
+        fs = None
+        if fs_reps:
+            b.formal_solution()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(fs_reps):
+                b.formal_solution()
+            dt = (time.perf_counter() - t0) / fs_reps
+            fs = {"ms": round(1e3 * dt, 3), "voxel_angle_updates_per_s": vox_ang / dt}
+        if ng[0]:
+            b.set_acceleration(*ng)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, iters, cs, states = b.solve(tol_, max_iter, M, poll_every=4, check=False)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        stats = b.stats()
+        Js = [fetch(b.get_J, i) for i in range(len(grids))]
+        b.close()
+        return Js, {"seconds": round(secs, 4), "converged": int((states == rt3d.RT3D_MEMBER_CONVERGED).sum()),
+                    "iters_max": int(iters.max()), "iters_sum": int(iters.sum()), "replays": stats["replays"],
+                    "graph_ms": round(stats["solve_ms"], 2), "sweep_shape": shape,
+                    "shape_ms": [round(x, 3) for x in ms.tolist()], "formal_solution": fs}
+
+    out = {"wavelengths": n_wl, "grids": {f"{n}^3": c for n, c in sorted(sizes.items())},
+           "angles": grids[0]["n_theta"] * grids[0]["n_phi"], "voxels": vox, "voxel_angles": vox_ang,
+           "tol": tol, "inner_sweeps": M, "ng_order": ng[0], "ng_every": ng[1]}
+    J_ref, ref = run_batch(rt3d.RT3D_FP64, ref_tol, 0)
+    out["reference"] = {"tol": ref_tol, **ref}
+
+    def err(Js):
+        return max(float(torch.max(torch.abs(a / r - 1)).item()) for a, r in zip(Js, J_ref))
+
+    for name, prec in (("batched_fp64", rt3d.RT3D_FP64), ("batched_fp32", rt3d.RT3D_FP32_SWEEP)):
+        Js, res = run_batch(prec, tol, 5)
+        res["max_rel_err_vs_reference"] = err(Js)
+        out[name] = res
+    # plain float64 path, one wavelength after another
+    singles = []
+    for i, g in enumerate(grids):
+        s = rt3d.Solver(g["nx"], g["ny"], g["nz"], g["n_theta"], g["n_phi"])
+        s.set_medium(dm[i]["chi"], dm[i]["eps"], dm[i]["B"])
+        s.autotune(cache, repeats=3)
+        if ng[0]:
+            s.set_acceleration(*ng)
+        singles.append(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for s in singles:
+        st, it, c = s.solve(tol, max_iter, M)
+        its.append(it)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    Js = [fetch(lambda i_, J_: singles[i_].get_J(J_), i) for i in range(len(grids))]
+    for s in singles:
+        s.close()
+    out["sequential_fp64"] = {"seconds": round(secs, 4), "iters_max": max(its), "iters_sum": sum(its),
+                              "max_rel_err_vs_reference": err(Js)}
+    out["batched_fp64_speedup"] = round(secs / out["batched_fp64"]["seconds"], 3)
+    out["batched_fp32_speedup"] = round(secs / out["batched_fp32"]["seconds"], 3)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,8 +216,13 @@ def main() -> int:
                     help="outer-iteration cap of the time-to-converged-J runs (0 skips them)")
     ap.add_argument("--reference-tol", type=float, default=1e-12,
                     help="tolerance of the float64 reference solve the converged forms are measured against")
+    ap.add_argument("--batch-wavelengths", type=int, default=64,
+                    help="wavelengths of the batched-form measurement (0 skips it)")
+    ap.add_argument("--batch-inner-sweeps", type=int, default=8)
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON cache of the sweep-shape autotuner (default: a file in the temp directory)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-every", type=int, default=8,
+    ap.add_argument("--cpu-sample-every", type=int, default=4,
                     help="the CPU oracle times every n-th direction of the full grid")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain elementwise copy of this many MiB (3 times) and exit: the "
@@ -219,6 +317,15 @@ def main() -> int:
             conv[name] = res
         conv["fp32_form_speedup"] = round(conv["fp64"]["seconds"] / conv["fp32"]["seconds"], 3)
 
+    # ---- many wavelengths on uneven grids: batched forms against one-at-a-time ------------------------
+    batched = None
+    if args.batch_wavelengths > 0:
+        import tempfile
+
+        cache = args.tune_cache or os.path.join(tempfile.gettempdir(), "rt3d_tune.json")
+        batched = _batched(rt3d, torch, args.batch_wavelengths, args.batch_inner_sweeps,
+                           (args.ng_order, args.ng_every), w.tol, args.reference_tol, 3000, cache)
+
     # ---- CPU oracle on a bounded sample of the same workload -------------------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -262,6 +369,7 @@ def main() -> int:
         "roofline_jacobi": roofline_jacobi,
         "cpu_baseline": cpu,
         "time_to_converged": conv,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
     return 0
