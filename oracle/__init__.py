@@ -7,6 +7,8 @@ links anything here, and nothing here imports the product path.
 The arithmetic lives in ``oracle.c`` (plain C, FP64, built with gcc); this module only builds and
 loads it and marshals numpy arrays.  ``dense_os_solution`` adds the plain definition of the converged
 result for tiny grids: the linear system (I - Lambda diag(1-eps)) J = Lambda (eps B) + J_bc.
+``loss_gradient_cs`` differentiates a loss on the emergent intensities of that converged result
+with respect to every voxel's chi and eps by complex step (tiny grids).
 
 Pins (closed forms, invariants, brute force) live in ``tests/test_oracle_*.py``.  Parity unpinned:
 the *number* of outer iterations to convergence (it depends on the readings of the Jacobi depth and
@@ -64,6 +66,8 @@ def lib():
                                    C.POINTER(C.c_int), C.POINTER(C.c_double), i]
         L.orc_ng_extrapolate.argtypes = [C.c_long, i, _dp, i, _dp]
         L.orc_pp1d.argtypes = [i, i, _dp, _dp, d, d, _dp]
+        L.orc_fs_complex.argtypes = [i, i, i, i, i, _dp, C.c_void_p, _dp, C.c_void_p, d, C.c_void_p,
+                                     _dp, _dp, C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -234,3 +238,84 @@ def dense_os_solution(chi, eps, B, n_theta, n_phi, I_top=0.0, bottom_from_B=True
     A = np.eye(V) - Lam * (1.0 - eps.ravel())[None, :]
     rhs = Lam @ (eps * B).ravel() + J_bc
     return np.linalg.solve(A, rhs).reshape(chi.shape)
+
+
+# ---- derivatives through the converged solution (complex step) ------------------------------------
+
+def fs_complex(chi, S, n_theta, n_phi, I_top=0.0, I_bot=None, want_emergent=False):
+    """The formal solution in complex arithmetic: chi and S may be complex (nz, ny, nx) arrays.
+    Returns J (complex) and, when asked for, the emergent top intensities [n_up, ny, nx] (complex)."""
+    chi = np.asarray(chi)
+    S = np.asarray(S)
+    nz, ny, nx = chi.shape
+    cr, ci = _f64(chi.real), _f64(chi.imag) if np.iscomplexobj(chi) else None
+    sr, si = _f64(S.real), _f64(S.imag) if np.iscomplexobj(S) else None
+    Jr, Ji = np.zeros(chi.shape), np.zeros(chi.shape)
+    nup = n_theta * n_phi // 2
+    Er = Ei = None
+    if want_emergent:
+        Er, Ei = np.zeros((nup, ny, nx)), np.zeros((nup, ny, nx))
+    Ib = None if I_bot is None else _f64(I_bot)
+    _check(lib().orc_fs_complex(nx, ny, nz, n_theta, n_phi, cr, _ptr(ci), sr, _ptr(si), float(I_top),
+                                _ptr(Ib), Jr, Ji, _ptr(Er), _ptr(Ei)), "fs_complex")
+    J = Jr + 1j * Ji
+    return (J, Er + 1j * Ei) if want_emergent else J
+
+
+def _converged_emergent(chi, eps, B, n_theta, n_phi, I_top, bottom_from_B, Lam=None):
+    """Converged J and emergent intensities by the plain definition, in complex arithmetic:
+    J = (I - Lambda diag(1-eps))^{-1} FS(eps B; boundary light), then I_em = FS_em(eps B + (1-eps) J)."""
+    V = chi.size
+    I_bot = B[0].real.copy() if bottom_from_B else None
+    if Lam is None:
+        Lam = np.zeros((V, V), dtype=complex)
+        for u in range(V):
+            e = np.zeros(V)
+            e[u] = 1.0
+            Lam[:, u] = fs_complex(chi, e.reshape(chi.shape), n_theta, n_phi).ravel()
+    rhs = fs_complex(chi, eps * B, n_theta, n_phi, I_top=I_top, I_bot=I_bot).ravel()
+    A = np.eye(V) - Lam * (1.0 - eps.ravel())[None, :]
+    J = np.linalg.solve(A, rhs).reshape(chi.shape)
+    S = eps * B + (1.0 - eps) * J
+    _, Iem = fs_complex(chi, S, n_theta, n_phi, I_top=I_top, I_bot=I_bot, want_emergent=True)
+    return J, Iem
+
+
+def emergent_loss(chi, eps, B, T, n_theta, n_phi, I_top=0.0, bottom_from_B=True):
+    """L = sum over the upward directions and top-plane lines of (I_em - T)^2 at the converged
+    solution (dense definition).  Returns (L, I_em, J)."""
+    chi, eps, B = _f64(chi), _f64(eps), _f64(B)
+    J, Iem = _converged_emergent(chi.astype(complex), eps.astype(complex), B.astype(complex), n_theta,
+                                 n_phi, I_top, bottom_from_B)
+    Iem = Iem.real
+    return float(np.sum((Iem - T) ** 2)), Iem, J.real
+
+
+def loss_gradient_cs(chi, eps, B, T, n_theta, n_phi, I_top=0.0, bottom_from_B=True, h=1e-30):
+    """dL/dchi_v and dL/deps_v of emergent_loss for every voxel, by complex step: one complex
+    evaluation of the converged solution per parameter with that parameter moved by i h; the
+    derivative is Im L / h.  Tiny grids only (a dense Lambda per chi parameter)."""
+    chi, eps, B = _f64(chi), _f64(eps), _f64(B)
+    T = _f64(T)
+    shape = chi.shape
+    V = chi.size
+    gchi = np.zeros(V)
+    geps = np.zeros(V)
+    chi_c, eps_c, B_c = chi.astype(complex), eps.astype(complex), B.astype(complex)
+    for v in range(V):
+        c = chi_c.copy().ravel()
+        c[v] += 1j * h
+        _, Iem = _converged_emergent(c.reshape(shape), eps_c, B_c, n_theta, n_phi, I_top, bottom_from_B)
+        gchi[v] = np.sum((Iem - T) ** 2).imag / h
+    Lam = np.zeros((V, V), dtype=complex)
+    for u in range(V):
+        e = np.zeros(V)
+        e[u] = 1.0
+        Lam[:, u] = fs_complex(chi_c, e.reshape(shape), n_theta, n_phi).ravel()
+    for v in range(V):
+        e_c = eps_c.copy().ravel()
+        e_c[v] += 1j * h
+        _, Iem = _converged_emergent(chi_c, e_c.reshape(shape), B_c, n_theta, n_phi, I_top, bottom_from_B,
+                                     Lam=Lam)
+        geps[v] = np.sum((Iem - T) ** 2).imag / h
+    return gchi.reshape(shape), geps.reshape(shape)
