@@ -163,6 +163,30 @@ const char *rt3d_status_str(int status);
 /* Last error message of a context ("" if none); valid until the next call on the context. */
 const char *rt3d_last_error(const rt3d_ctx *ctx);
 
+/* ---- adjoint: gradients through the converged solution ------------------------------------
+ * An extension of the method (the paper computes the forward solution only).  For a loss L of the
+ * emergent top intensities I_em (the layout of rt3d_get_emergent_top), given g_em = dL/dI_em
+ * ([n_theta/2 * n_phi][ny][nx]), computes dL/dchi and dL/deps per voxel ([nz][ny][nx]) through the
+ * fixed point J = Lambda(chi) (eps B + (1-eps) J) + J_bc(chi) at the context's current J, which should
+ * be converged (call after rt3d_solve_to_convergence; the gradient is that of the fixed point through
+ * the current J, so its accuracy follows that of J).  B, I_top and the bottom light are constants.
+ * Method: dL/dS by reverse-mode differentiation of the exact segment integration along the lines;
+ * the adjoint fixed point mu = dL/dS + Lambda^T (1-eps) mu, solved through reciprocity
+ * (chi_v Lambda_vu = chi_u Lambda_uv) as the forward-form system (1 - Lambda (1-eps)) nu = dL/dS / chi,
+ * nu = mu / chi, by the library's operator-splitting iteration (inner_sweeps Jacobi sweeps per step,
+ * stopped when max|d nu| < tol max|nu| or after max_iter steps); then dL/deps = mu (B - J) and dL/dchi
+ * from a second reverse-mode pass.  All of it runs in float64 (also in the RT3D_FP32_SWEEP form, whose
+ * float32 Jacobi coefficients only precondition).  Overwrites J_fs and the emergent intensities with
+ * those of the current J.  *iters_out and *final_rel_out (may be NULL) receive the adjoint steps and
+ * the last max|d nu| / max|nu|.  The first call allocates 2 n_dir V + 5 V + n_em float64 on the
+ * device (kept until rt3d_destroy).  Deterministic (fixed summation order).
+ * Errors: RT3D_ERR_STATE (no medium), RT3D_ERR_ARG (null arrays, non-finite host g_em, bad
+ * tol/max_iter/inner_sweeps), RT3D_ERR_NOT_CONVERGED (max_iter reached; the outputs hold the
+ * gradients of the last iterate), RT3D_ERR_NONFINITE, RT3D_ERR_OOM, RT3D_ERR_HIP. */
+int rt3d_adjoint_emergent(rt3d_ctx *ctx, const double *g_em, double tol, int max_iter, int inner_sweeps,
+                          double *dL_dchi, double *dL_deps, int ptr_kind, int *iters_out,
+                          double *final_rel_out);
+
 /* ---- sweep workgroup shape and its tuning -------------------------------------------------- */
 
 /* The sweep workgroup shapes: shape i runs threads[i] threads, each carrying lines[i] lines of

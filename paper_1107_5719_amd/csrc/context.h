@@ -51,6 +51,12 @@ struct rt3d_ctx {
     rt3d::WorkItem *items = nullptr;
     unsigned long long *d_maxrel = nullptr;
     int *d_flag = nullptr;
+    // adjoint (allocated by the first adjoint call): per (direction, layer, line) the intensity entering
+    // the layer and the adjoint variable leaving it; per voxel the adjoint iterate nu, its formal
+    // solution, residual, right-hand side and the pulled gradient terms
+    double *adj_Ient = nullptr, *adj_Qx = nullptr;
+    double *adj_nu = nullptr, *adj_fs = nullptr, *adj_r = nullptr, *adj_f = nullptr, *adj_pull = nullptr;
+    double *adj_g = nullptr;            // [n_up][ny][nx]: dL/dI_em
     // Ng acceleration
     int ng_order = 0, ng_every = 0;
     double *ng_hist = nullptr;          // [ng_order + 2][V] ring of iterates
@@ -91,6 +97,8 @@ int install_plan(rt3d_ctx *c, int shape);
 // One formal solution from the current J (source, sweep, reduce; no residual), as the context's
 // precision sweeps it.
 int run_fs_plain(rt3d_ctx *c);
+// S (given on the device, or from J when null) -> J_fs (and r = J_fs - J when with_residual).
+int run_fs(rt3d_ctx *c, const double *S_dev, bool with_residual, bool fp32);
 // Key of a tuning-cache entry: device, precision and grid of a context.
 std::string device_key();
 

@@ -18,6 +18,22 @@ struct SweepShape { int threads, lines; };
 // Measured on MI355X at 129^3 x 256: 512 x 2 is fastest (56 VGPRs, 8 waves/SIMD; the sweep is
 // latency-bound, so occupancy beats lines per thread and prefetching).
 constexpr SweepShape kSweepShapes[] = {{512, 2}, {512, 4}, {256, 8}, {1024, 2}, {256, 4}, {256, 2}};
+// Calls f(NT, LPT) (as integral constants) for the sweep shape with the given index.
+template <int NT, int LPT> struct ShapeTag {
+    static constexpr int threads = NT, lines = LPT;
+};
+template <typename F>
+inline void with_sweep_shape(int shape, F &&f)
+{
+    switch (shape) {
+    case 1: f(ShapeTag<512, 4>{}); break;
+    case 2: f(ShapeTag<256, 8>{}); break;
+    case 3: f(ShapeTag<1024, 2>{}); break;
+    case 4: f(ShapeTag<256, 4>{}); break;
+    case 5: f(ShapeTag<256, 2>{}); break;
+    default: f(ShapeTag<512, 2>{}); break;
+    }
+}
 constexpr size_t kWindowBytes = 48 * 1024;   // LDS for the two deposit windows of a band
 constexpr double kAnchorRatio = 1e-3;        // FP32 form: re-anchor when c < ratio * max|J - Ja|/|J|
 constexpr int kPlaneThreads = 256;   // voxel-parallel kernels: one thread per voxel of a k-plane
@@ -76,9 +92,11 @@ __device__ inline float expm1_nonpos(float x)
 // ------------------------------------------------------------------------------------------------
 
 // S_given: the source itself.  Ja (difference mode of the FP32 form): the source change since the
-// anchor iterate, (1 - eps)(J - Ja), whose formal solution is added to the anchor's.
+// anchor iterate, (1 - eps)(J - Ja), whose formal solution is added to the anchor's.  scatter_only:
+// the scattering part (1 - eps) J alone (the adjoint solve, whose thermal term enters as a base).
 struct SourceArgs {
     int nx, ny, nz;
+    int scatter_only;
     const double *chi, *eps, *B, *J, *S_given, *Ja;
     void *cs;                     // Vec2<real>
 };
@@ -91,6 +109,7 @@ __device__ inline void source_body(const SourceArgs &a, int p, int k)
     double S;
     if (a.S_given) S = a.S_given[v];
     else if (a.Ja) S = (1.0 - a.eps[v]) * (a.J[v] - a.Ja[v]);
+    else if (a.scatter_only) S = (1.0 - a.eps[v]) * a.J[v];
     else S = a.eps[v] * a.B[v] + (1.0 - a.eps[v]) * a.J[v];
     typename Vec2<real>::type c;
     c.x = real(a.chi[v]);
@@ -482,8 +501,9 @@ struct JacobiArgs {
     double *J;                   // last sweep: J += dJ (null otherwise)
     unsigned long long *maxrel;  // bits of max |dJ|/|J| (non-negative doubles order like integers)
     const double *Ja;            // anchor iterate of the FP32 form (may be null)
-    unsigned long long *maxdist; // bits of max |J - Ja|/|J| when Ja is given
+    unsigned long long *maxdist; // bits of max |J - Ja|/|J| when Ja is given, of max |J| when abs_measure
     int *nonfinite;
+    int abs_measure;             // 1: maxrel receives max |dJ| and maxdist max |J| (iterates that may vanish)
 };
 
 // Arithmetic is float64 for either coefficient type.
@@ -521,8 +541,13 @@ __device__ inline void jacobi_body(const JacobiArgs &a, int p, int k)
             const double dJ = acc * a.invD[v];
             const double Jn = a.J[v] + dJ;
             a.J[v] = Jn;
-            q = fabs(dJ) / fabs(Jn);
-            if (a.Ja) dist = fabs(Jn - a.Ja[v]) / fabs(Jn);
+            if (a.abs_measure) {
+                q = fabs(dJ);
+                dist = fabs(Jn);
+            } else {
+                q = fabs(dJ) / fabs(Jn);
+                if (a.Ja) dist = fabs(Jn - a.Ja[v]) / fabs(Jn);
+            }
             bad = !isfinite(Jn) || !isfinite(q);
         }
     }
@@ -541,7 +566,7 @@ __device__ inline void jacobi_body(const JacobiArgs &a, int p, int k)
         double m = wmax[0][0], md = wmax[1][0];
         for (int w = 1; w < kPlaneThreads / 64; ++w) { m = fmax(m, wmax[0][w]); md = fmax(md, wmax[1][w]); }
         atomicMax(a.maxrel, static_cast<unsigned long long>(__double_as_longlong(m)));
-        if (a.Ja) atomicMax(a.maxdist, static_cast<unsigned long long>(__double_as_longlong(md)));
+        if (a.Ja || a.abs_measure) atomicMax(a.maxdist, static_cast<unsigned long long>(__double_as_longlong(md)));
     }
 }
 

@@ -153,7 +153,7 @@ dim3 plane_grid_xcd(const rt3d_ctx *c)
 
 int launch_source(rt3d_ctx *c, const double *S_given, const double *Ja, bool fp32)
 {
-    SourceArgs a;
+    SourceArgs a{};
     a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
     a.chi = c->chi; a.eps = c->eps; a.B = c->B; a.J = c->J; a.S_given = S_given; a.Ja = Ja;
     a.cs = c->cs;
@@ -169,7 +169,7 @@ int launch_source(rt3d_ctx *c, const double *S_given, const double *Ja, bool fp3
 // anchor's)
 int launch_sweep(rt3d_ctx *c, bool fp32, bool diff)
 {
-    SweepArgs a;
+    SweepArgs a{};
     a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
     a.n_down = c->A.n_dir / 2;
     a.pseg = c->pseg; a.player = c->player;
@@ -211,7 +211,7 @@ int launch_sweep(rt3d_ctx *c, bool fp32, bool diff)
 
 int launch_reduce(rt3d_ctx *c, bool with_residual, bool fp32, const double *base)
 {
-    ReduceArgs a;
+    ReduceArgs a{};
     a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.n_pair = c->plan.n_pair;
     a.pairs = c->pairs; a.row_min = c->row_min; a.P = c->P; a.chi = c->chi;
     a.J = c->J; a.base = base; a.Jfs = c->Jfs; a.r = with_residual ? c->r : nullptr;
@@ -264,7 +264,7 @@ int ensure_lstar(rt3d_ctx *c)
 {
     if (c->have_lstar) return RT3D_OK;
     if (!c->plan_ok) return fail(c, RT3D_ERR_STATE, "no sweep plan (a shape change failed)");
-    LstarArgs a;
+    LstarArgs a{};
     a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.n_dir = c->A.n_dir;
     a.early_exit = c->lstar_early_exit;
     a.dirs = c->dirs; a.seg_off = c->seg_off; a.seg_n = c->seg_n; a.seg_ai = c->seg_ai;
@@ -292,7 +292,7 @@ int ensure_lstar(rt3d_ctx *c)
 
 int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update)
 {
-    JacobiArgs a;
+    JacobiArgs a{};
     const bool f32 = c->precision == RT3D_FP32_SWEEP;
     a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
     a.r = c->r; a.chi = c->chi; a.w_in = w_in; a.w_out = w_out;
@@ -315,7 +315,7 @@ int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update)
 // products, the small solve and the combination all run on the device, with no host round trip.
 int ng_step(rt3d_ctx *c, int m)
 {
-    NgArgs a;
+    NgArgs a{};
     a.V = c->V;
     a.order = c->ng_order;
     a.hist = c->ng_hist;
@@ -338,7 +338,8 @@ void free_all(rt3d_ctx *c)
     free_plan(c);
     void *ptrs[] = {c->chi, c->eps, c->B, c->J, c->Jfs, c->r, c->dJa, c->dJb, c->L, c->Kc, c->invD, c->Ecoef, c->Iem,
                     c->Sbuf, c->cs, c->Ja, c->Fa, c->Iem_a, c->Kc32, c->d_maxdist, c->d_maxrel, c->d_flag,
-                    c->ng_hist, c->ng_work};
+                    c->ng_hist, c->ng_work, c->adj_Ient, c->adj_Qx, c->adj_nu, c->adj_fs, c->adj_r,
+                    c->adj_f, c->adj_pull, c->adj_g};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (auto &p : c->pending) {

@@ -19,7 +19,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Workload", "WORKLOADS", "stratified_profile", "make_medium", "random_medium", "wavelength_batch"]
+__all__ = ["Workload", "WORKLOADS", "stratified_profile", "make_medium", "random_medium", "wavelength_batch",
+           "emergent_target"]
 
 
 @dataclass(frozen=True)
@@ -67,6 +68,9 @@ WORKLOADS = {
                       noise="grf", sigma=0.2, seed=2, tol=1e-8),
     "strat129": Workload("strat129", 129, 129, 129, 16, 16, tau_total=1e3, eps=1e-6, b_profile="const",
                          noise="iid", sigma=0.05, seed=3, tol=1e-8),
+    # differentiation workload: gradients of a loss on the emergent light through the converged solution
+    "strat65adj": Workload("strat65adj", 65, 65, 65, 8, 8, tau_total=1e3, eps=1e-2, b_profile="const",
+                           noise="iid", sigma=0.05, seed=5, tol=1e-14),
 }
 
 
@@ -164,3 +168,10 @@ def wavelength_batch(n: int = 64, sizes=(33, 65, 97), n_theta: int = 8, n_phi: i
             "chi0": chi0, "eps_value": eps,
         })
     return out
+
+
+def emergent_target(n_up: int, ny: int, nx: int, seed: int, lo: float = 0.2, hi: float = 0.8):
+    """Seeded target T for a loss sum (I_em - T)^2 on the emergent top intensities
+    ([n_up, ny, nx], uniform in [lo, hi])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(lo, hi, (n_up, ny, nx))

@@ -40,7 +40,7 @@ EXPORTED = [
     "rt3d_formal_solution", "rt3d_build_lstar", "rt3d_get_lstar", "rt3d_os_step",
     "rt3d_solve_to_convergence", "rt3d_set_acceleration", "rt3d_get_emergent_top", "rt3d_set_timing", "rt3d_get_stats",
     "rt3d_status_str", "rt3d_last_error", "rt3d_quadrature", "rt3d_segment_table", "rt3d_validate",
-    "rt3d_sweep_shapes", "rt3d_set_sweep_shape", "rt3d_autotune",
+    "rt3d_adjoint_emergent", "rt3d_sweep_shapes", "rt3d_set_sweep_shape", "rt3d_autotune",
     "rt3d_batch_create", "rt3d_batch_destroy", "rt3d_batch_size", "rt3d_batch_last_error",
     "rt3d_batch_set_medium", "rt3d_batch_set_J", "rt3d_batch_get_J", "rt3d_batch_get_Jfs",
     "rt3d_batch_set_acceleration", "rt3d_batch_set_sweep_shape", "rt3d_batch_formal_solution",
@@ -84,6 +84,7 @@ _sig = {
     "rt3d_quadrature": (_i, [_i, _i, _vp, _vp, _vp, _vp]),
     "rt3d_segment_table": (_i, [C.POINTER(GridDesc), _i, _i, _vp, _vp, _vp, _i]),
     "rt3d_validate": (_i, [C.POINTER(GridDesc), _vp, _vp, _vp]),
+    "rt3d_adjoint_emergent": (_i, [_vp, _vp, _d, _i, _i, _vp, _vp, _i, C.POINTER(_i), C.POINTER(_d)]),
     "rt3d_sweep_shapes": (_i, [_vp, _vp, _i]),
     "rt3d_set_sweep_shape": (_i, [_vp, _i]),
     "rt3d_autotune": (_i, [_vp, C.c_char_p, _i, C.POINTER(_i), _vp]),
@@ -295,6 +296,24 @@ def rt3d_validate(desc: GridDesc, chi=None, eps=None, B=None) -> int:
     return _lib.rt3d_validate(C.byref(desc), *ptrs)
 
 
+def rt3d_adjoint_emergent(ctx, g_em, dchi_out, deps_out, tol: float = 1e-12, max_iter: int = 2000,
+                          inner_sweeps: int = 30, check=True):
+    """dL/dchi and dL/deps (written into dchi_out, deps_out) for g_em = dL/dI_em; all arrays host
+    numpy or all device tensors.  Returns (status, adjoint steps, last max|d nu|/max|nu|)."""
+    pg, kg, hg = _arg(g_em)
+    pc, kc, hc = _arg(dchi_out, writable=True)
+    pe, ke, he = _arg(deps_out, writable=True)
+    if len({kg, kc, ke}) != 1:
+        raise ValueError("g_em and the outputs must all be host arrays or all device tensors")
+    it = C.c_int(0)
+    rel = C.c_double(0.0)
+    st = _lib.rt3d_adjoint_emergent(ctx, pg, float(tol), int(max_iter), int(inner_sweeps), pc, pe, kg,
+                                    C.byref(it), C.byref(rel))
+    if check and st not in (RT3D_OK, RT3D_ERR_NOT_CONVERGED):
+        _raise(ctx, st, "rt3d_adjoint_emergent")
+    return st, it.value, rel.value
+
+
 def rt3d_sweep_shapes():
     """[(threads, lines per thread), ...] of the sweep workgroup shapes."""
     n = _lib.rt3d_sweep_shapes(None, None, 0)
@@ -425,6 +444,7 @@ class Solver:
         self.desc = _desc(nx, ny, nz, n_theta, n_phi, I_top, bottom_bc)
         self.shape = (nz, ny, nx)
         self.n_dir = n_theta * n_phi
+        self._token = 0             # changes with every new medium (used by the autograd wrapper)
         self.ctx = rt3d_create(self.desc, precision, stream)
 
     def close(self):
@@ -446,6 +466,7 @@ class Solver:
 
     def set_medium(self, chi, eps, B):
         rt3d_set_medium(self.ctx, chi, eps, B)
+        self._token += 1
 
     def set_J(self, J):
         rt3d_set_J(self.ctx, J)
@@ -493,6 +514,14 @@ class Solver:
 
     def autotune(self, cache_path=None, repeats=3):
         return rt3d_autotune(self.ctx, cache_path, repeats)
+
+    def adjoint(self, g_em, tol=1e-12, max_iter=2000, inner_sweeps=30, dchi=None, deps=None):
+        """(dL/dchi, dL/deps, status, steps, last rel) for g_em = dL/dI_em (host numpy unless the
+        outputs given are device tensors)."""
+        dchi = np.zeros(self.shape) if dchi is None else dchi
+        deps = np.zeros(self.shape) if deps is None else deps
+        st, it, rel = rt3d_adjoint_emergent(self.ctx, g_em, dchi, deps, tol, max_iter, inner_sweeps)
+        return dchi, deps, st, it, rel
 
 
 class Batch:

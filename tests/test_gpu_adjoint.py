@@ -1,0 +1,182 @@
+"""GPU tests of the adjoint (gradients of a loss on the emergent light through the converged solution).
+
+* Against the oracle's complex-step gradient (exact to rounding) of the same loss on tiny grids, every
+  voxel's dL/dchi and dL/deps: FP64 within 1e-10 relative (+1e-13 of the largest entry).
+* Against central finite differences of the GPU's own forward solve at 65^3 x 64 (the differentiation
+  workload), h = 1e-6 relative on chi and absolute on eps, on seeded voxels.  The difference of two
+  losses carries their rounding, a few ulps of L, so the finite difference is only as good as
+  ulp(L) / h: the bar is 1e-4 |fd| + 1e-7 max|grad| + 32 ulp(L) / h, and enough of the checks must be
+  informative (that last term below a tenth of |fd|).
+* The torch.autograd.Function wrapper, error paths.
+"""
+import numpy as np
+import pytest
+
+from paper_1107_5719_amd.inputs import WORKLOADS, emergent_target, make_medium, random_medium
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.zeros(1, device="cuda")
+    from paper_1107_5719_amd import rt3d
+
+    return rt3d
+
+
+CASES = [
+    # (shape (nz, ny, nx), n_theta, n_phi, I_top, bottom_bc, seed)
+    ((3, 5, 4), 2, 4, 0.2, 0, 23),
+    ((4, 5, 6), 4, 8, 0.0, 0, 24),
+    ((5, 4, 4), 4, 4, 0.1, 1, 25),
+]
+
+
+def _gpu_gradient(R, m, nt, nph, T, I_top, bbc, precision=0):
+    nz, ny, nx = m["chi"].shape
+    with R.Solver(nx, ny, nz, nt, nph, I_top=I_top, bottom_bc=bbc, precision=precision) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        st, it, c = s.solve(1e-13, 20000, 10)
+        assert st == R.RT3D_OK
+        s.formal_solution()
+        I = s.emergent_top()
+        dchi, deps, st2, it2, rel = s.adjoint(2.0 * (I - T), tol=1e-14, max_iter=20000, inner_sweeps=10)
+        assert st2 == R.RT3D_OK and rel < 1e-14
+    return I, dchi, deps
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-{c[1]}x{c[2]}-bc{c[4]}" for c in CASES])
+def test_adjoint_matches_oracle_complex_step(R, orc, case):
+    shape, nt, nph, I_top, bbc, seed = case
+    nz, ny, nx = shape
+    m = random_medium(nx, ny, nz, seed=seed, chi_range=(1e-2, 3.0), eps_range=(0.05, 0.5))
+    T = emergent_target(nt * nph // 2, ny, nx, seed)
+    gchi, geps = orc.loss_gradient_cs(m["chi"], m["eps"], m["B"], T, nt, nph, I_top=I_top,
+                                      bottom_from_B=(bbc == 0))
+    _, Iem_o, _ = orc.emergent_loss(m["chi"], m["eps"], m["B"], T, nt, nph, I_top=I_top, bottom_from_B=(bbc == 0))
+    I, dchi, deps = _gpu_gradient(R, m, nt, nph, T, I_top, bbc)
+    np.testing.assert_allclose(I, Iem_o, rtol=1e-12)
+    for got, ref in ((dchi, gchi), (deps, geps)):
+        err = np.abs(got - ref)
+        assert (err <= 1e-10 * np.abs(ref) + 1e-13 * np.abs(ref).max()).all(), \
+            f"worst {np.max(err / (np.abs(ref) + 1e-300)):.3e} rel, {err.max() / np.abs(ref).max():.3e} of max"
+
+
+def test_adjoint_fp32_sweep_form(R, orc):
+    """The FP32 form's adjoint runs in float64 at its converged J; only the loss gradient fed in
+    (from float32-swept emergent light) carries float32 error."""
+    shape, nt, nph, I_top, bbc, seed = CASES[1]
+    nz, ny, nx = shape
+    m = random_medium(nx, ny, nz, seed=seed, chi_range=(1e-2, 3.0), eps_range=(0.05, 0.5))
+    T = emergent_target(nt * nph // 2, ny, nx, seed)
+    gchi, geps = orc.loss_gradient_cs(m["chi"], m["eps"], m["B"], T, nt, nph, I_top=I_top)
+    I, dchi, deps = _gpu_gradient(R, m, nt, nph, T, I_top, bbc, precision=1)
+    for got, ref in ((dchi, gchi), (deps, geps)):
+        assert np.max(np.abs(got - ref)) <= 1e-6 * np.abs(ref).max()
+
+
+def test_adjoint_finite_differences_strat65(R):
+    import torch
+
+    w = WORKLOADS["strat65adj"]
+    m = make_medium(w)
+    T = emergent_target(w.n_dir // 2, w.ny, w.nx, w.seed)
+    dm = {k: torch.from_numpy(v).cuda() for k, v in m.items()}
+    s = R.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi)
+    s.set_acceleration(3, 6)
+
+    def solve_loss(chi, eps, J0=None, steps=40):
+        # a fixed number of Ng-accelerated steps past the point where c stops falling, so the result
+        # sits at the rounding floor of the iteration rather than at a stopping tolerance
+        s.set_medium(chi, eps, dm["B"])
+        if J0 is not None:
+            s.set_J(J0)
+        s.solve(1e-300, steps, 30)
+        s.formal_solution()
+        I = s.emergent_top()
+        return float(np.sum((I - T) ** 2)), I
+
+    L0, I0 = solve_loss(dm["chi"], dm["eps"], steps=200)
+    Jst = torch.empty_like(dm["chi"])
+    s.get_J(Jst)
+    dchi, deps, st, it, rel = s.adjoint(2.0 * (I0 - T), tol=1e-13, max_iter=2000, inner_sweeps=30)
+    assert st == R.RT3D_OK
+    ulp = np.spacing(L0)
+    rng = np.random.Generator(np.random.PCG64(55))
+    vox = rng.choice(w.n_vox, 16, replace=False)
+    informative = {"chi": 0, "eps": 0}
+    report = []
+    for v in vox:
+        idx = np.unravel_index(v, (w.nz, w.ny, w.nx))
+        for name, g in (("chi", dchi), ("eps", deps)):
+            h = 1e-6 * float(dm[name][idx]) if name == "chi" else 1e-6
+            L = []
+            for sgn in (1.0, -1.0):
+                p = dm[name].clone()
+                p[idx] += sgn * h
+                L.append(solve_loss(p, dm["eps"], Jst)[0] if name == "chi" else solve_loss(dm["chi"], p, Jst)[0])
+            fd = (L[0] - L[1]) / (2 * h)
+            noise = 32 * ulp / h
+            bar = 1e-4 * abs(fd) + 1e-7 * np.abs(g).max() + noise
+            report.append(f"{name}{tuple(int(x) for x in idx)} adj {g[idx]:.6e} fd {fd:.6e} bar {bar:.2e}")
+            assert abs(g[idx] - fd) <= bar, report[-1]
+            if noise < 0.1 * abs(fd):
+                informative[name] += 1
+    print("\n".join(report), informative)
+    assert informative["eps"] >= 12 and informative["chi"] >= 6, (informative, report)
+    s.close()
+
+
+def test_autograd_function(R, orc):
+    import torch
+    from paper_1107_5719_amd.autograd import emergent_intensity
+
+    shape, nt, nph, I_top, bbc, seed = CASES[0]
+    nz, ny, nx = shape
+    m = random_medium(nx, ny, nz, seed=seed, chi_range=(1e-2, 3.0), eps_range=(0.05, 0.5))
+    T = emergent_target(nt * nph // 2, ny, nx, seed)
+    gchi, geps = orc.loss_gradient_cs(m["chi"], m["eps"], m["B"], T, nt, nph, I_top=I_top)
+    chi = torch.tensor(m["chi"], device="cuda", requires_grad=True)
+    eps = torch.tensor(m["eps"], device="cuda", requires_grad=True)
+    B = torch.tensor(m["B"], device="cuda")
+    Tt = torch.tensor(T, device="cuda")
+    s = R.Solver(nx, ny, nz, nt, nph, I_top=I_top)
+    I = emergent_intensity(chi, eps, B, s, tol=1e-13, max_iter=20000, inner_sweeps=10, adj_tol=1e-14)
+    loss = ((I - Tt) ** 2).sum()
+    # the solver is reused in between: backward restores its medium and converged J
+    s.set_medium(m["chi"] * 2.0, m["eps"], m["B"])
+    loss.backward()
+    np.testing.assert_allclose(chi.grad.cpu().numpy(), gchi, rtol=1e-9, atol=1e-13 * np.abs(gchi).max())
+    np.testing.assert_allclose(eps.grad.cpu().numpy(), geps, rtol=1e-9, atol=1e-13 * np.abs(geps).max())
+    s.close()
+
+
+def test_adjoint_error_paths(R):
+    m = random_medium(4, 5, 3, seed=3)
+    with R.Solver(4, 5, 3, 2, 4) as s:
+        g = np.ones((4, 5, 4))
+        with pytest.raises(R.Rt3dError) as e:
+            s.adjoint(g)
+        assert e.value.status == R.RT3D_ERR_STATE
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        s.solve(1e-12, 1000, 8)
+        for kw in ({"tol": 0.0}, {"max_iter": 0}, {"inner_sweeps": 0}):
+            with pytest.raises(R.Rt3dError) as e:
+                s.adjoint(g, **kw)
+            assert e.value.status == R.RT3D_ERR_ARG
+        bad = g.copy()
+        bad[0, 0, 0] = np.nan
+        with pytest.raises(R.Rt3dError) as e:
+            s.adjoint(bad)
+        assert e.value.status == R.RT3D_ERR_ARG
+        dchi, deps, st, it, rel = R.Solver.adjoint(s, g, tol=1e-15, max_iter=1)
+        assert st == R.RT3D_ERR_NOT_CONVERGED and it == 1
+        assert np.isfinite(dchi).all() and np.isfinite(deps).all()
+        # deterministic: two calls give the same bits
+        a1 = s.adjoint(g, tol=1e-13)
+        a2 = s.adjoint(g, tol=1e-13)
+        assert np.array_equal(a1[0], a2[0]) and np.array_equal(a1[1], a2[1])
