@@ -201,6 +201,84 @@ def _batched(rt3d, torch, n_wl, M, ng, tol, ref_tol, max_iter, cache):
     return out
 
 
+def _adjoint(rt3d, torch, n_fd, M):
+    """The differentiation form on the 65^3 x 64 workload: loss L = sum (I_em - T)^2 of the emergent
+    top intensities against a seeded target.  Time of the forward solve (to 3e-13 with Ng), of the
+    adjoint (rt3d_adjoint_emergent to 1e-12, Ng as for the forward solve), and agreement with central
+    finite differences of the forward solve (h = 1e-6 relative on chi, absolute on eps; and 1e-4
+    relative on chi, where the rounding of L matters less) on n_fd seeded voxels."""
+    import numpy as np
+    from paper_1107_5719_amd.inputs import WORKLOADS, emergent_target, make_medium
+
+    w = WORKLOADS["strat65adj"]
+    m = make_medium(w)
+    T = emergent_target(w.n_dir // 2, w.ny, w.nx, w.seed)
+    dm = {k: torch.from_numpy(v).cuda() for k, v in m.items()}
+    s = rt3d.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi)
+    s.set_acceleration(3, 6)
+    s.set_medium(dm["chi"], dm["eps"], dm["B"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, it, c = s.solve(3e-13, 2000, M)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    s.solve(1e-300, 100, M)             # on to the rounding floor of the iteration for the checks
+    J = torch.empty_like(dm["chi"])
+    s.get_J(J)
+    s.formal_solution()
+    I0 = s.emergent_top()
+    L0 = float(np.sum((I0 - T) ** 2))
+    g = 2.0 * (I0 - T)
+    s.adjoint(g, tol=1e-12, max_iter=2000, inner_sweeps=M)       # warm-up (allocates)
+    s.set_J(J)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dchi, deps, st2, it2, rel = s.adjoint(g, tol=1e-12, max_iter=2000, inner_sweeps=M)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    out = {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} voxels x {w.n_dir} angles, eps={w.eps:g}, "
+                       f"tau_total={w.tau_total:g}, target uniform [0.2, 0.8] seed {w.seed}",
+           "loss": L0, "inner_sweeps": M,
+           "forward_solve": {"seconds": round(t_fwd, 4), "iterations": it, "tol": 3e-13},
+           "adjoint": {"seconds": round(t_adj, 4), "iterations": it2, "tol": 1e-12, "final_rel": rel},
+           "adjoint_over_forward": round(t_adj / t_fwd, 3)}
+    if n_fd > 0:
+        rng = np.random.Generator(np.random.PCG64(55))
+        vox = rng.choice(w.n_vox, n_fd, replace=False)
+        ulp = float(np.spacing(L0))
+        stats = {}
+        for key, name, grad, hrel in (("chi", "chi", dchi, 1e-6), ("eps", "eps", deps, 1e-6),
+                                      ("chi_h1e-4", "chi", dchi, 1e-4)):
+            rels, informative = [], 0
+            for v in vox:
+                idx = np.unravel_index(v, (w.nz, w.ny, w.nx))
+                h = hrel * float(dm[name][idx]) if name == "chi" else hrel
+                L = []
+                for sgn in (1.0, -1.0):
+                    p = dm[name].clone()
+                    p[idx] += sgn * h
+                    if name == "chi":
+                        s.set_medium(p, dm["eps"], dm["B"])
+                    else:
+                        s.set_medium(dm["chi"], p, dm["B"])
+                    s.set_J(J)
+                    s.solve(1e-300, 40, M)
+                    s.formal_solution()
+                    L.append(float(np.sum((s.emergent_top() - T) ** 2)))
+                fd = (L[0] - L[1]) / (2 * h)
+                if 32 * ulp / h < 0.1 * abs(fd):          # the difference stands above rounding of L
+                    informative += 1
+                    rels.append(abs(grad[idx] - fd) / abs(fd))
+            stats[key] = {"voxels": int(n_fd), "informative": informative,
+                           "median_rel_diff": float(np.median(rels)) if rels else None,
+                           "max_rel_diff": float(np.max(rels)) if rels else None}
+        out["finite_differences"] = {"h": "1e-6 relative on chi, 1e-6 absolute on eps; chi_h1e-4: 1e-4 relative",
+                                     "note": "a check is informative when 32 ulp(L)/h < |fd|/10",
+                                     **stats}
+    s.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +297,9 @@ def main() -> int:
     ap.add_argument("--batch-wavelengths", type=int, default=64,
                     help="wavelengths of the batched-form measurement (0 skips it)")
     ap.add_argument("--batch-inner-sweeps", type=int, default=8)
+    ap.add_argument("--adjoint-fd-voxels", type=int, default=50,
+                    help="finite-difference checks of the adjoint at 65^3 x 64 (0 skips them; -1 skips "
+                         "the adjoint measurement)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON cache of the sweep-shape autotuner (default: a file in the temp directory)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -326,6 +407,11 @@ def main() -> int:
         batched = _batched(rt3d, torch, args.batch_wavelengths, args.batch_inner_sweeps,
                            (args.ng_order, args.ng_every), w.tol, args.reference_tol, 3000, cache)
 
+    # ---- gradients through the converged solution (adjoint) ----------------------------------------
+    adjoint = None
+    if args.adjoint_fd_voxels >= 0:
+        adjoint = _adjoint(rt3d, torch, args.adjoint_fd_voxels, 30)
+
     # ---- CPU oracle on a bounded sample of the same workload -------------------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -370,6 +456,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "time_to_converged": conv,
         "batched": batched,
+        "adjoint": adjoint,
     }
     print(json.dumps(out), flush=True)
     return 0

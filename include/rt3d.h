@@ -174,7 +174,8 @@ const char *rt3d_last_error(const rt3d_ctx *ctx);
  * the adjoint fixed point mu = dL/dS + Lambda^T (1-eps) mu, solved through reciprocity
  * (chi_v Lambda_vu = chi_u Lambda_uv) as the forward-form system (1 - Lambda (1-eps)) nu = dL/dS / chi,
  * nu = mu / chi, by the library's operator-splitting iteration (inner_sweeps Jacobi sweeps per step,
- * stopped when max|d nu| < tol max|nu| or after max_iter steps); then dL/deps = mu (B - J) and dL/dchi
+ * Ng acceleration as set by rt3d_set_acceleration but with unit weights, stopped when
+ * max|d nu| < tol max|nu| or after max_iter steps); then dL/deps = mu (B - J) and dL/dchi
  * from a second reverse-mode pass.  All of it runs in float64 (also in the RT3D_FP32_SWEEP form, whose
  * float32 Jacobi coefficients only precondition).  Overwrites J_fs and the emergent intensities with
  * those of the current J.  *iters_out and *final_rel_out (may be NULL) receive the adjoint steps and

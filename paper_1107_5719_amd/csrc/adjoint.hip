@@ -353,6 +353,17 @@ int rt3d_adjoint_emergent(rt3d_ctx *c, const double *g_em, double tol, int max_i
     // (I - Lambda D) nu = f by operator splitting from nu = 0, until max|dnu| < tol max|nu|
     hipLaunchKernelGGL(adj_zero_kernel, dim3((V + 255) / 256), dim3(256), 0, c->stream, V, c->adj_nu);
     if ((rc = check_launch(c, "adj_zero_kernel"))) return rc;
+    // Ng acceleration as configured for the forward solve, with unit weights (nu may vanish)
+    const int R = c->ng_order + 2;
+    const size_t vbytes = size_t(V) * sizeof(double);
+    NgArgs ng{};
+    ng.V = V; ng.order = c->ng_order; ng.hist = c->ng_hist; ng.work = c->ng_work; ng.J = c->adj_nu;
+    ng.unit_weights = 1;
+    int nh = 0;
+    if (c->ng_order > 0) {
+        HIP_TRY(c, hipMemcpyAsync(c->ng_hist, c->adj_nu, vbytes, hipMemcpyDeviceToDevice, c->stream), "ng hist");
+        nh = 1;
+    }
     int it = 0;
     double rel = INFINITY;
     while (it < max_iter) {
@@ -364,6 +375,21 @@ int rt3d_adjoint_emergent(rt3d_ctx *c, const double *g_em, double tol, int max_i
         if (bad) return fail(c, RT3D_ERR_NONFINITE, "NaN or Inf in the adjoint iterate");
         rel = numax > 0.0 ? dmax / numax : 0.0;
         if (rel < tol) break;
+        if (c->ng_order > 0) {
+            HIP_TRY(c, hipMemcpyAsync(c->ng_hist + long(nh % R) * V, c->adj_nu, vbytes, hipMemcpyDeviceToDevice,
+                                      c->stream), "ng hist");
+            ++nh;
+            if (nh - 1 >= c->ng_every) {
+                const int m = (nh - 1) % R;
+                hipLaunchKernelGGL(ng_dots_kernel, dim3(kNgBlocks), dim3(kNgThreads), 0, c->stream, ng, m);
+                hipLaunchKernelGGL(ng_solve_kernel, dim3(1), dim3(kNgThreads), 0, c->stream, ng);
+                hipLaunchKernelGGL(ng_combine_kernel, dim3((V + 255) / 256), dim3(256), 0, c->stream, ng, m);
+                if ((rc = check_launch(c, "ng kernels (adjoint)"))) return rc;
+                HIP_TRY(c, hipMemcpyAsync(c->ng_hist, c->adj_nu, vbytes, hipMemcpyDeviceToDevice, c->stream),
+                        "ng hist");
+                nh = 1;
+            }
+        }
     }
     if (iters_out) *iters_out = it;
     if (final_rel_out) *final_rel_out = rel;

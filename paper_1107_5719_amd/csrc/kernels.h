@@ -596,6 +596,7 @@ struct NgArgs {
     const double *hist;             // [order + 2][V]
     double *work;                   // [kNgWork]
     double *J;                      // receives the extrapolated iterate
+    int unit_weights;               // 1: weights 1 instead of 1/x_0^2 (iterates that may vanish)
 };
 
 __device__ inline const double *ng_x(const NgArgs &a, int m, int i)
@@ -604,7 +605,7 @@ __device__ inline const double *ng_x(const NgArgs &a, int m, int i)
     return a.hist + long((m - i + 4 * R) % R) * a.V;
 }
 
-// One block's share of the weighted dot products (weights 1/x_0^2).  Whole block.
+// One block's share of the weighted dot products (weights 1/x_0^2, or 1).  Whole block.
 __device__ inline void ng_dots_body(const NgArgs &a, int m, int blk)
 {
     const double *x0 = ng_x(a, m, 0), *x1 = ng_x(a, m, 1);
@@ -613,7 +614,7 @@ __device__ inline void ng_dots_body(const NgArgs &a, int m, int blk)
     for (int q = 0; q < kNgSums; ++q) acc[q] = 0.0;
     for (long v = long(blk) * kNgThreads + threadIdx.x; v < a.V; v += long(kNgBlocks) * kNgThreads) {
         const double y0 = x0[v];
-        const double w = 1.0 / (y0 * y0);
+        const double w = a.unit_weights ? 1.0 : 1.0 / (y0 * y0);
         const double d0 = y0 - x1[v];
         double Q[3] = {0.0, 0.0, 0.0};
         for (int i = 1; i <= a.order; ++i) Q[i - 1] = d0 - (ng_x(a, m, i)[v] - ng_x(a, m, i + 1)[v]);
