@@ -65,6 +65,16 @@ def measured_traffic(kernel: str):
     return None
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip() + f" ({os.cpu_count()} logical CPUs visible)"
+    except OSError:
+        pass
+    return f"unknown ({os.cpu_count()} logical CPUs visible)"
+
+
 def _timed_steps(rt3d, torch, w, d_med, prec, stream, steps, warmup, M):
     """K timed OS steps after W warm-up steps; per-kernel HIP-event times from the library."""
     s = rt3d.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi, I_top=w.I_top, precision=prec, stream=stream)
@@ -397,6 +407,19 @@ def main() -> int:
             res["max_rel_err_vs_reference"] = float(torch.max(torch.abs(J / J_ref - 1)).item())
             conv[name] = res
         conv["fp32_form_speedup"] = round(conv["fp64"]["seconds"] / conv["fp32"]["seconds"], 3)
+        # equal accuracy: the time each form needs to come within 1e-5 and within 1e-8 of the reference
+        # (stopping at c < target / 100; the error reached is reported beside the time)
+        conv["accuracy_targets"] = {}
+        for target in (1e-5, 1e-8):
+            row = {"stop_tol": target / 100}
+            for name, prec in forms.items():
+                J, res = _converge(rt3d, torch, w, d_med, prec, stream, M, args.ng_order, args.ng_every,
+                                   target / 100, 20 * args.converge_max_iter)
+                err = float(torch.max(torch.abs(J / J_ref - 1)).item())
+                row[name] = {"seconds": res["seconds"], "outer_iterations": res["outer_iterations"],
+                             "max_rel_err_vs_reference": err, "within_target": err <= target}
+            row["fp32_form_speedup"] = round(row["fp64"]["seconds"] / row["fp32"]["seconds"], 3)
+            conv["accuracy_targets"][f"{target:g}"] = row
 
     # ---- many wavelengths on uneven grids: batched forms against one-at-a-time ------------------------
     batched = None
@@ -429,6 +452,16 @@ def main() -> int:
                "sample": f"FP64 oracle formal solution of {len(dirs)} of the {n_dir} directions "
                          f"(every {args.cpu_sample_every}th) on the full {w.nx}x{w.ny}x{w.nz} grid, "
                          f"{tcpu:.2f} s wall"}
+        # one thread (the serial analogue), on a smaller share of the directions
+        dirs1 = list(range(0, n_dir, 8 * args.cpu_sample_every))
+        t0 = time.perf_counter()
+        oracle.formal_solution_dirs(med["chi"], S, w.n_theta, w.n_phi, dirs1, I_top=w.I_top,
+                                    I_bot=med["B"][0], n_threads=1)
+        t1 = time.perf_counter() - t0
+        cpu["single_thread"] = {"value": V * len(dirs1) / t1, "cores": 1,
+                                "sample": f"{len(dirs1)} directions (every {8 * args.cpu_sample_every}th), "
+                                          f"{t1:.2f} s wall"}
+        cpu["host_cpu"] = _cpu_model()
 
     out = {
         "metric": METRIC,
