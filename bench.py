@@ -289,6 +289,28 @@ def _adjoint(rt3d, torch, n_fd, M):
     return out
 
 
+def _paper_grids(rt3d, torch, stream, steps, M, ng, max_iter):
+    """The paper's slab on its two timing grids (65^3 and 129^2 x 193, 256 angles): OS-step rate and
+    time to converged J (tol 1e-8, Lambda* included), both forms."""
+    from paper_1107_5719_amd.inputs import WORKLOADS, make_medium
+
+    out = {}
+    for name in ("slab65", "slab193"):
+        w = WORKLOADS[name]
+        med = make_medium(w)
+        d_med = {k: torch.from_numpy(v).cuda() for k, v in med.items()}
+        row = {"grid": f"{w.nx}x{w.ny}x{w.nz} x {w.n_dir} angles"}
+        for form, prec in (("fp64", rt3d.RT3D_FP64), ("fp32", rt3d.RT3D_FP32_SWEEP)):
+            elapsed, per_launch, lstar_s, st = _timed_steps(rt3d, torch, w, d_med, prec, stream, steps, 1, M)
+            J, conv = _converge(rt3d, torch, w, d_med, prec, stream, M, ng[0], ng[1], w.tol, max_iter)
+            row[form] = {"ms_per_step": round(1e3 * elapsed / steps, 3),
+                         "voxel_angle_updates_per_s": w.n_vox * w.n_dir * steps / elapsed,
+                         "sweep_ms": per_launch["sweep"], "time_to_converged": conv}
+        out[name] = row
+        del d_med
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -310,6 +332,8 @@ def main() -> int:
     ap.add_argument("--adjoint-fd-voxels", type=int, default=50,
                     help="finite-difference checks of the adjoint at 65^3 x 64 (0 skips them; -1 skips "
                          "the adjoint measurement)")
+    ap.add_argument("--paper-grids", type=int, default=1,
+                    help="also measure the paper's slab on its 65^3 and 129^2 x 193 grids (0 skips)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON cache of the sweep-shape autotuner (default: a file in the temp directory)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -430,6 +454,12 @@ def main() -> int:
         batched = _batched(rt3d, torch, args.batch_wavelengths, args.batch_inner_sweeps,
                            (args.ng_order, args.ng_every), w.tol, args.reference_tol, 3000, cache)
 
+    # ---- the paper's slab on the paper's grids ------------------------------------------------------
+    paper_grids = None
+    if args.paper_grids:
+        paper_grids = _paper_grids(rt3d, torch, stream, 3, M, (args.ng_order, args.ng_every),
+                                   args.converge_max_iter)
+
     # ---- gradients through the converged solution (adjoint) ----------------------------------------
     adjoint = None
     if args.adjoint_fd_voxels >= 0:
@@ -490,6 +520,7 @@ def main() -> int:
         "time_to_converged": conv,
         "batched": batched,
         "adjoint": adjoint,
+        "paper_grids": paper_grids,
     }
     print(json.dumps(out), flush=True)
     return 0

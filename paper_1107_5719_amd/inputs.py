@@ -19,7 +19,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Workload", "WORKLOADS", "stratified_profile", "make_medium", "random_medium", "wavelength_batch",
+__all__ = ["Workload", "WORKLOADS", "stratified_profile", "paper_slab_profile", "make_medium", "random_medium", "wavelength_batch",
            "emergent_target"]
 
 
@@ -68,6 +68,13 @@ WORKLOADS = {
                       noise="grf", sigma=0.2, seed=2, tol=1e-8),
     "strat129": Workload("strat129", 129, 129, 129, 16, 16, tau_total=1e3, eps=1e-6, b_profile="const",
                          noise="iid", sigma=0.05, seed=3, tol=1e-8),
+    # the paper's timing grids ("Timing results": 65^3 and 129^2 x 193 voxels) with its slab
+    # ("Test case setup": continuum optical depth a power law from 1e-4 at the outer boundary to 1e8 at
+    # the inner one, isothermal, eps = 1e-2); plane-parallel in structure, so no perturbation
+    "slab65": Workload("slab65", 65, 65, 65, 16, 16, tau_total=1e8, eps=1e-2, b_profile="const",
+                       noise="none", sigma=0.0, seed=0, tol=1e-8, extra={"profile": "paper_slab"}),
+    "slab193": Workload("slab193", 129, 129, 193, 16, 16, tau_total=1e8, eps=1e-2, b_profile="const",
+                        noise="none", sigma=0.0, seed=0, tol=1e-8, extra={"profile": "paper_slab"}),
     # differentiation workload: gradients of a loss on the emergent light through the converged solution
     "strat65adj": Workload("strat65adj", 65, 65, 65, 8, 8, tau_total=1e3, eps=1e-2, b_profile="const",
                            noise="iid", sigma=0.05, seed=5, tol=1e-14),
@@ -80,6 +87,16 @@ def stratified_profile(nz: int, tau_total: float, decades: float = 7.0) -> np.nd
     zc = np.arange(nz, dtype=np.float64) + 0.5
     prof = np.exp(-zc / H)
     return prof * (tau_total / prof.sum())
+
+
+def paper_slab_profile(nz: int, tau_min: float = 1e-4, tau_max: float = 1e8) -> np.ndarray:
+    """The paper's slab: the continuum optical depth at height z (unit voxels, z = nz outside) is the
+    power law tau(z) = tau_min (tau_max / tau_min)^((nz - z) / nz), so layer k has the opacity
+    chi_k = tau(k) - tau(k + 1) (its optical thickness); tau(nz) = tau_min is the optical depth of the
+    medium above the grid, which carries no opacity here."""
+    z = np.arange(nz + 1, dtype=np.float64)
+    tau = tau_min * (tau_max / tau_min) ** ((nz - z) / nz)
+    return tau[:-1] - tau[1:]
 
 
 def _grf(rng: np.random.Generator, nz: int, ny: int, nx: int, corr_len: float) -> np.ndarray:
@@ -105,7 +122,10 @@ def make_medium(w: Workload | str):
     if isinstance(w, str):
         w = WORKLOADS[w]
     rng = np.random.Generator(np.random.PCG64(w.seed))
-    prof = stratified_profile(w.nz, w.tau_total)
+    if w.extra.get("profile") == "paper_slab":
+        prof = paper_slab_profile(w.nz)
+    else:
+        prof = stratified_profile(w.nz, w.tau_total)
     if w.noise == "iid":
         g = rng.standard_normal(w.shape)
     elif w.noise == "grf":

@@ -206,6 +206,34 @@ def test_fs_parity_strat129(R, orc):
     _close(J, J_orc)
 
 
+def test_paper_slab_grids_parity(R, orc):
+    """The paper's slab (continuum optical depth 1e-4 .. 1e8, isothermal, eps = 1e-2) on its two timing
+    grids: at 65^3 x 256 J_fs, Lambda* and one OS step; at 129^2 x 193 x 256 every voxel of J_fs for a
+    seeded source (the slab has no horizontal structure, the source does)."""
+    w = WORKLOADS["slab65"]
+    m = make_medium(w)
+    L_orc = orc.lstar(m["chi"], w.n_theta, w.n_phi)
+    J1_orc, c_orc = orc.os_step(m["chi"], m["eps"], m["B"], L_orc, m["B"], w.n_theta, w.n_phi, M=4)
+    S = np.random.default_rng(65).uniform(0.5, 1.5, w.shape)
+    J_fs_orc = orc.formal_solution(m["chi"], S, w.n_theta, w.n_phi, I_bot=m["B"][0])
+    with R.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        _close(s.formal_solution(S), J_fs_orc)
+        s.build_lstar()
+        _close_rows(s.get_lstar(), L_orc)
+        c = s.os_step(4)
+        _close(s.get_J(), J1_orc)
+        assert abs(c - c_orc) <= 1e-8 * c_orc
+    w = WORKLOADS["slab193"]
+    m = make_medium(w)
+    S = np.random.default_rng(193).uniform(0.5, 1.5, w.shape)
+    J_orc = orc.formal_solution(m["chi"], S, w.n_theta, w.n_phi, I_bot=m["B"][0])
+    with R.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        J = s.formal_solution(S)
+    _close(J, J_orc)
+
+
 def test_error_paths(R):
     import torch
 
