@@ -65,9 +65,12 @@ def lib():
         L.orc_solve_ng.argtypes = [i, i, i, i, i, _dp, _dp, _dp, d, i, C.c_void_p, _dp, d, i, i, i, i,
                                    C.POINTER(C.c_int), C.POINTER(C.c_double), i]
         L.orc_ng_extrapolate.argtypes = [C.c_long, i, _dp, i, _dp]
-        L.orc_pp1d.argtypes = [i, i, _dp, _dp, d, d, _dp]
+        L.orc_pp1d.argtypes = [i, i, _dp, _dp, d, d, d, _dp]
         L.orc_fs_complex.argtypes = [i, i, i, i, i, _dp, C.c_void_p, _dp, C.c_void_p, d, C.c_void_p,
-                                     _dp, _dp, C.c_void_p, C.c_void_p]
+                                     C.c_void_p, C.c_void_p, _dp, _dp, C.c_void_p, C.c_void_p]
+        L.orc_formal_solution_slope.argtypes = [i, i, i, i, i, _dp, _dp, d, C.c_void_p, _dp, _dp,
+                                                C.c_void_p, C.c_void_p, i]
+        L.orc_diffusion_slope.argtypes = [i, i, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -110,9 +113,23 @@ def trace_layer(nx, ny, nz, n_theta, n_phi, d, i, j, k, max_seg=64):
     return v[:n].copy(), ln[:n].copy()
 
 
+def _bottom_mode(bottom_from_B):
+    """True / 1: B of the entry voxel; False / 0: zero; "diffusion" / 2: LTE diffusion."""
+    if bottom_from_B == "diffusion":
+        return 2
+    return int(bottom_from_B)
+
+
+def diffusion_slope(chi, B):
+    """dB/dtau at the inner boundary per column: (B_0 - B_1) / ((chi_0 + chi_1) / 2) (works for
+    complex chi too)."""
+    return (B[0] - B[1]) / (0.5 * (chi[0] + chi[1]))
+
+
 def formal_solution(chi, S, n_theta, n_phi, I_top=0.0, I_bot=None, want_emergent=False,
-                    want_ibar=False, n_threads=0):
-    """J = FS(S).  chi, S: (nz, ny, nx).  I_bot: (ny, nx) or None (zero).
+                    want_ibar=False, n_threads=0, I_slope=None):
+    """J = FS(S).  chi, S: (nz, ny, nx).  I_bot: (ny, nx) or None (zero); I_slope: (ny, nx) or None,
+    the LTE-diffusion gradient (an upward line of direction cosine mu enters with I_bot + mu I_slope).
 
     Returns J (and the top-plane emergent intensities [n_up, ny, nx] and the per-direction voxel
     intensities [n_dir, nz, ny, nx] when asked for)."""
@@ -124,8 +141,14 @@ def formal_solution(chi, S, n_theta, n_phi, I_top=0.0, I_bot=None, want_emergent
     Iem = np.zeros((nd // 2, ny, nx)) if want_emergent else None
     Ibar = np.zeros((nd,) + chi.shape) if want_ibar else None
     ib = None if I_bot is None else _f64(np.broadcast_to(I_bot, (ny, nx)))
-    _check(lib().orc_formal_solution(nx, ny, nz, n_theta, n_phi, chi, S, float(I_top), _ptr(ib), J,
-                                     _ptr(Iem), _ptr(Ibar), n_threads), "formal_solution")
+    if I_slope is None:
+        _check(lib().orc_formal_solution(nx, ny, nz, n_theta, n_phi, chi, S, float(I_top), _ptr(ib), J,
+                                         _ptr(Iem), _ptr(Ibar), n_threads), "formal_solution")
+    else:
+        sl = _f64(np.broadcast_to(I_slope, (ny, nx)))
+        ib = np.zeros((ny, nx)) if ib is None else ib
+        _check(lib().orc_formal_solution_slope(nx, ny, nz, n_theta, n_phi, chi, S, float(I_top), _ptr(ib),
+                                               sl, J, _ptr(Iem), _ptr(Ibar), n_threads), "formal_solution")
     out = [J]
     if want_emergent:
         out.append(Iem)
@@ -174,7 +197,7 @@ def os_step(chi, eps, B, Lstar, J, n_theta, n_phi, M, I_top=0.0, bottom_from_B=T
     Jn = _f64(J).copy()
     c = C.c_double(0.0)
     Jfs = np.zeros_like(chi) if want_jfs else None
-    _check(lib().orc_os_step(nx, ny, nz, n_theta, n_phi, chi, eps, B, float(I_top), int(bottom_from_B),
+    _check(lib().orc_os_step(nx, ny, nz, n_theta, n_phi, chi, eps, B, float(I_top), _bottom_mode(bottom_from_B),
                              Lstar, Jn, int(M), C.byref(c), _ptr(Jfs), n_threads), "os_step")
     return (Jn, c.value, Jfs) if want_jfs else (Jn, c.value)
 
@@ -189,7 +212,7 @@ def solve(chi, eps, B, n_theta, n_phi, tol, max_iter, M, J0=None, Lstar=None, I_
     it = C.c_int(0)
     c = C.c_double(0.0)
     rc = _check(lib().orc_solve(nx, ny, nz, n_theta, n_phi, chi, eps, B, float(I_top),
-                                int(bottom_from_B), _ptr(Ls), J, float(tol), int(max_iter), int(M),
+                                _bottom_mode(bottom_from_B), _ptr(Ls), J, float(tol), int(max_iter), int(M),
                                 C.byref(it), C.byref(c), n_threads), "solve")
     return J, it.value, c.value, rc == 0
 
@@ -205,7 +228,7 @@ def solve_ng(chi, eps, B, n_theta, n_phi, tol, max_iter, M, ng_order, ng_every, 
     it = C.c_int(0)
     c = C.c_double(0.0)
     rc = _check(lib().orc_solve_ng(nx, ny, nz, n_theta, n_phi, chi, eps, B, float(I_top),
-                                   int(bottom_from_B), _ptr(Ls), J, float(tol), int(max_iter), int(M),
+                                   _bottom_mode(bottom_from_B), _ptr(Ls), J, float(tol), int(max_iter), int(M),
                                    int(ng_order), int(ng_every), C.byref(it), C.byref(c), n_threads),
                 "solve_ng")
     return J, it.value, c.value, rc == 0
@@ -219,11 +242,13 @@ def ng_extrapolate(hist, order):
     return out.reshape(np.shape(hist[0])), rc == 0
 
 
-def pp1d(dtau, S, n_theta, I_top=0.0, I_bot=0.0):
-    """Plane-parallel J_k for layer thicknesses dtau[k] (k = 0 bottom) and sources S[k]."""
+def pp1d(dtau, S, n_theta, I_top=0.0, I_bot=0.0, I_slope=0.0):
+    """Plane-parallel J_k for layer thicknesses dtau[k] (k = 0 bottom) and sources S[k]; upward light
+    enters the bottom with I_bot + mu I_slope."""
     dtau, S = _f64(dtau), _f64(S)
     J = np.zeros_like(dtau)
-    _check(lib().orc_pp1d(dtau.size, n_theta, dtau, S, float(I_top), float(I_bot), J), "pp1d")
+    _check(lib().orc_pp1d(dtau.size, n_theta, dtau, S, float(I_top), float(I_bot), float(I_slope), J),
+           "pp1d")
     return J
 
 
@@ -233,8 +258,10 @@ def dense_os_solution(chi, eps, B, n_theta, n_phi, I_top=0.0, bottom_from_B=True
     chi, eps, B = _f64(chi), _f64(eps), _f64(B)
     Lam = lambda_bruteforce(chi, n_theta, n_phi, n_threads)
     V = chi.size
+    mode = _bottom_mode(bottom_from_B)
     J_bc = formal_solution(chi, np.zeros_like(chi), n_theta, n_phi, I_top=I_top,
-                           I_bot=(B[0] if bottom_from_B else None), n_threads=n_threads).ravel()
+                           I_bot=(B[0] if mode else None), n_threads=n_threads,
+                           I_slope=(diffusion_slope(chi, B) if mode == 2 else None)).ravel()
     A = np.eye(V) - Lam * (1.0 - eps.ravel())[None, :]
     rhs = Lam @ (eps * B).ravel() + J_bc
     return np.linalg.solve(A, rhs).reshape(chi.shape)
@@ -242,9 +269,10 @@ def dense_os_solution(chi, eps, B, n_theta, n_phi, I_top=0.0, bottom_from_B=True
 
 # ---- derivatives through the converged solution (complex step) ------------------------------------
 
-def fs_complex(chi, S, n_theta, n_phi, I_top=0.0, I_bot=None, want_emergent=False):
-    """The formal solution in complex arithmetic: chi and S may be complex (nz, ny, nx) arrays.
-    Returns J (complex) and, when asked for, the emergent top intensities [n_up, ny, nx] (complex)."""
+def fs_complex(chi, S, n_theta, n_phi, I_top=0.0, I_bot=None, want_emergent=False, I_slope=None):
+    """The formal solution in complex arithmetic: chi and S may be complex (nz, ny, nx) arrays, and
+    the LTE-diffusion gradient I_slope (ny, nx) too.  Returns J (complex) and, when asked for, the
+    emergent top intensities [n_up, ny, nx] (complex)."""
     chi = np.asarray(chi)
     S = np.asarray(S)
     nz, ny, nx = chi.shape
@@ -256,8 +284,13 @@ def fs_complex(chi, S, n_theta, n_phi, I_top=0.0, I_bot=None, want_emergent=Fals
     if want_emergent:
         Er, Ei = np.zeros((nup, ny, nx)), np.zeros((nup, ny, nx))
     Ib = None if I_bot is None else _f64(I_bot)
+    slr = sli = None
+    if I_slope is not None:
+        sl = np.asarray(I_slope)
+        slr = _f64(sl.real)
+        sli = _f64(sl.imag) if np.iscomplexobj(sl) else None
     _check(lib().orc_fs_complex(nx, ny, nz, n_theta, n_phi, cr, _ptr(ci), sr, _ptr(si), float(I_top),
-                                _ptr(Ib), Jr, Ji, _ptr(Er), _ptr(Ei)), "fs_complex")
+                                _ptr(Ib), _ptr(slr), _ptr(sli), Jr, Ji, _ptr(Er), _ptr(Ei)), "fs_complex")
     J = Jr + 1j * Ji
     return (J, Er + 1j * Ei) if want_emergent else J
 
@@ -266,24 +299,28 @@ def _converged_emergent(chi, eps, B, n_theta, n_phi, I_top, bottom_from_B, Lam=N
     """Converged J and emergent intensities by the plain definition, in complex arithmetic:
     J = (I - Lambda diag(1-eps))^{-1} FS(eps B; boundary light), then I_em = FS_em(eps B + (1-eps) J)."""
     V = chi.size
-    I_bot = B[0].real.copy() if bottom_from_B else None
+    mode = _bottom_mode(bottom_from_B)
+    I_bot = B[0].real.copy() if mode else None
+    I_slope = diffusion_slope(chi, B) if mode == 2 else None
     if Lam is None:
         Lam = np.zeros((V, V), dtype=complex)
         for u in range(V):
             e = np.zeros(V)
             e[u] = 1.0
             Lam[:, u] = fs_complex(chi, e.reshape(chi.shape), n_theta, n_phi).ravel()
-    rhs = fs_complex(chi, eps * B, n_theta, n_phi, I_top=I_top, I_bot=I_bot).ravel()
+    rhs = fs_complex(chi, eps * B, n_theta, n_phi, I_top=I_top, I_bot=I_bot, I_slope=I_slope).ravel()
     A = np.eye(V) - Lam * (1.0 - eps.ravel())[None, :]
     J = np.linalg.solve(A, rhs).reshape(chi.shape)
     S = eps * B + (1.0 - eps) * J
-    _, Iem = fs_complex(chi, S, n_theta, n_phi, I_top=I_top, I_bot=I_bot, want_emergent=True)
+    _, Iem = fs_complex(chi, S, n_theta, n_phi, I_top=I_top, I_bot=I_bot, want_emergent=True,
+                        I_slope=I_slope)
     return J, Iem
 
 
 def emergent_loss(chi, eps, B, T, n_theta, n_phi, I_top=0.0, bottom_from_B=True):
     """L = sum over the upward directions and top-plane lines of (I_em - T)^2 at the converged
-    solution (dense definition).  Returns (L, I_em, J)."""
+    solution (dense definition).  bottom_from_B as for solve (True, False or "diffusion").
+    Returns (L, I_em, J)."""
     chi, eps, B = _f64(chi), _f64(eps), _f64(B)
     J, Iem = _converged_emergent(chi.astype(complex), eps.astype(complex), B.astype(complex), n_theta,
                                  n_phi, I_top, bottom_from_B)

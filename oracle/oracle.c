@@ -219,8 +219,8 @@ int orc_trace_layer(int nx, int ny, int nz, int n_theta, int n_phi, int d, int i
  *   D_s   = S_v dtau - (I_in - S_v) em1.
  * Dsum[v] receives sum_s D_s; Iem (optional) receives I at the top plane of upward lines. */
 static void fs_direction(const Geom *g, int d, const double *chi, const double *S, double I_top,
-                         const double *I_bot, double *Dsum, double *Iem, double *fbuf,
-                         int *seg_v, double *seg_len)
+                         const double *I_bot, const double *I_slope, double *Dsum, double *Iem,
+                         double *fbuf, int *seg_v, double *seg_len)
 {
     const double mu = g->mu[d];
     for (int j = 0; j < g->ny; ++j) {
@@ -230,9 +230,11 @@ static void fs_direction(const Geom *g, int d, const double *chi, const double *
                 int k = (mu < 0.0) ? g->nz - 1 - step : step;
                 int ns = trace_layer(g, d, i, j, k, fbuf, seg_v, seg_len);
                 if (mu > 0.0 && step == 0) {
-                    /* upward line: boundary intensity of the bottom voxel it enters */
-                    /* in layer 0 the voxel index equals the column index j*nx + i */
+                    /* upward line: boundary intensity of the bottom voxel it enters (in layer 0
+                     * the voxel index equals the column index j*nx + i), plus mu times the slope
+                     * of the LTE-diffusion condition when one is given */
                     I = I_bot ? I_bot[seg_v[0]] : 0.0;
+                    if (I_slope) I += mu * I_slope[seg_v[0]];
                 }
                 for (int s = 0; s < ns; ++s) {
                     int v = seg_v[s];
@@ -265,17 +267,28 @@ static int n_threads_of(int req)
  * direction order.  Ibar (optional): [n_dir][V] per-direction voxel intensities.
  * Threads split the directions; each thread sums its own directions in order, and the threads'
  * partial sums are added in thread order. */
-int orc_formal_solution_dirs(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi,
-                             const double *S, double I_top, const double *I_bot, double *J,
-                             double *Iem, double *Ibar, int n_threads, const int *dir_list,
-                             int n_list);
+static int fs_dirs(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi, const double *S,
+                   double I_top, const double *I_bot, const double *I_slope, double *J, double *Iem,
+                   double *Ibar, int n_threads, const int *dir_list, int n_list);
 
 int orc_formal_solution(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi,
                         const double *S, double I_top, const double *I_bot, double *J,
                         double *Iem, double *Ibar, int n_threads)
 {
-    return orc_formal_solution_dirs(nx, ny, nz, n_theta, n_phi, chi, S, I_top, I_bot, J, Iem, Ibar,
-                                    n_threads, NULL, 0);
+    return fs_dirs(nx, ny, nz, n_theta, n_phi, chi, S, I_top, I_bot, NULL, J, Iem, Ibar, n_threads,
+                   NULL, 0);
+}
+
+/* As orc_formal_solution with the LTE-diffusion inner condition: an upward line of direction cosine
+ * mu enters with I_bot + mu * I_slope of the bottom voxel it enters (I_slope: [ny][nx], the
+ * gradient dB/dtau at the inner boundary). */
+int orc_formal_solution_slope(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi,
+                              const double *S, double I_top, const double *I_bot,
+                              const double *I_slope, double *J, double *Iem, double *Ibar,
+                              int n_threads)
+{
+    return fs_dirs(nx, ny, nz, n_theta, n_phi, chi, S, I_top, I_bot, I_slope, J, Iem, Ibar, n_threads,
+                   NULL, 0);
 }
 
 /* As orc_formal_solution, restricted to the directions in dir_list[0..n_list-1] (all directions
@@ -284,6 +297,14 @@ int orc_formal_solution_dirs(int nx, int ny, int nz, int n_theta, int n_phi, con
                              const double *S, double I_top, const double *I_bot, double *J,
                              double *Iem, double *Ibar, int n_threads, const int *dir_list,
                              int n_list)
+{
+    return fs_dirs(nx, ny, nz, n_theta, n_phi, chi, S, I_top, I_bot, NULL, J, Iem, Ibar, n_threads,
+                   dir_list, n_list);
+}
+
+static int fs_dirs(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi, const double *S,
+                   double I_top, const double *I_bot, const double *I_slope, double *J, double *Iem,
+                   double *Ibar, int n_threads, const int *dir_list, int n_list)
 {
     Geom g;
     int rc = geom_init(&g, nx, ny, nz, n_theta, n_phi);
@@ -317,7 +338,7 @@ int orc_formal_solution_dirs(int nx, int ny, int nz, int n_theta, int n_phi, con
                 if (d < 0 || d >= g.n_dir) continue;
                 memset(Dsum, 0, sizeof(double) * V);
                 double *Iem_d = (Iem && g.mu[d] > 0.0) ? Iem + (size_t)(d - n_down) * nx * ny : NULL;
-                fs_direction(&g, d, chi, S, I_top, I_bot, Dsum, Iem_d, fbuf, seg_v, seg_len);
+                fs_direction(&g, d, chi, S, I_top, I_bot, I_slope, Dsum, Iem_d, fbuf, seg_v, seg_len);
                 const double amu = fabs(g.mu[d]);
                 for (long v = 0; v < V; ++v) {
                     double ib = amu / chi[v] * Dsum[v];
@@ -487,13 +508,23 @@ int orc_lambda_bruteforce(int nx, int ny, int nz, int n_theta, int n_phi, const 
  * Operator splitting.
  * --------------------------------------------------------------------------------------------- */
 
+/* The gradient of B at the inner boundary for the LTE-diffusion condition, per column:
+ * (B_0 - B_1) / ((chi_0 + chi_1) / 2), layer 0 the bottom voxel and layer 1 the one above it. */
+void orc_diffusion_slope(int nx, int ny, const double *chi, const double *B, double *slope)
+{
+    const long nxy = (long)nx * ny;
+    for (long c = 0; c < nxy; ++c) slope[c] = (B[c] - B[nxy + c]) / (0.5 * (chi[c] + chi[nxy + c]));
+}
+
 /* One OS step ("Implementation of the operator splitting step"):
  *   S = eps B + (1-eps) J;  J_fs = FS(S);  r = J_fs - J;
  *   M Jacobi sweeps from dJ^0 = 0 of
  *     dJ^{m+1}_v = (r_v + sum_{u != v} Lstar_vu (1-eps_u) dJ^m_u) / (1 - Lstar_vv (1-eps_v));
  *   J <- J + dJ^M;  c = max_v |dJ_v| / |J_v|.
- * Boundary light: I_top at the top; at the bottom I_bot = B of the bottom layer if bottom_from_B,
- * else zero.  Jfs_out (optional) receives J_fs. */
+ * Boundary light: I_top at the top; at the bottom (bottom_from_B) 0: zero, 1: I_bot = B of the
+ * bottom voxel a line enters, 2: LTE diffusion, I_bot = B + mu dB/dtau with
+ * dB/dtau = (B_0 - B_1) / ((chi_0 + chi_1) / 2) from the bottom voxel and the one above it (the
+ * optical distance between their centres; tau grows inwards).  Jfs_out (optional) receives J_fs. */
 int orc_os_step(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi, const double *eps,
                 const double *B, double I_top, int bottom_from_B, const double *Lstar, double *J,
                 int M, double *c_out, double *Jfs_out, int n_threads)
@@ -510,8 +541,16 @@ int orc_os_step(int nx, int ny, int nz, int n_theta, int n_phi, const double *ch
         return ORC_ENOMEM;
     }
     for (long v = 0; v < V; ++v) S[v] = eps[v] * B[v] + (1.0 - eps[v]) * J[v];
-    int rc = orc_formal_solution(nx, ny, nz, n_theta, n_phi, chi, S, I_top,
-                                 bottom_from_B ? B : NULL, Jfs, NULL, NULL, n_threads);
+    double *slope = NULL;
+    if (bottom_from_B == 2) {
+        if (nz < 2) { free(S); free(Jfs); free(r); free(dJ); free(dJn); return ORC_EARG; }
+        slope = (double *)malloc(sizeof(double) * nx * ny);
+        if (!slope) { free(S); free(Jfs); free(r); free(dJ); free(dJn); return ORC_ENOMEM; }
+        orc_diffusion_slope(nx, ny, chi, B, slope);
+    }
+    int rc = fs_dirs(nx, ny, nz, n_theta, n_phi, chi, S, I_top, bottom_from_B ? B : NULL, slope, Jfs,
+                     NULL, NULL, n_threads, NULL, 0);
+    free(slope);
     if (rc == ORC_OK) {
         for (long v = 0; v < V; ++v) r[v] = Jfs[v] - J[v];
         for (int m = 0; m < M; ++m) {
@@ -708,7 +747,7 @@ int orc_solve(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi,
  * of an exactly integrated constant-source layer is  Ibar = S - (I_in - S) em1 / (dtau/|mu|),
  * and J_k = sum_a (w_a / 2) Ibar_k(mu_a). */
 int orc_pp1d(int nz, int n_theta, const double *dtau, const double *S, double I_top, double I_bot,
-             double *J)
+             double I_slope, double *J)
 {
     if (nz < 1 || n_theta < 2 || (n_theta & 1)) return ORC_EARG;
     double *x = (double *)malloc(sizeof(double) * n_theta);
@@ -718,7 +757,8 @@ int orc_pp1d(int nz, int n_theta, const double *dtau, const double *S, double I_
     for (int k = 0; k < nz; ++k) J[k] = 0.0;
     for (int a = 0; a < n_theta; ++a) {
         double amu = fabs(x[a]);
-        double I = (x[a] < 0.0) ? I_top : I_bot;
+        /* upward light at the bottom: I_bot + mu I_slope (I_slope = 0 except for LTE diffusion) */
+        double I = (x[a] < 0.0) ? I_top : I_bot + x[a] * I_slope;
         for (int step = 0; step < nz; ++step) {
             int k = (x[a] < 0.0) ? nz - 1 - step : step;
             double t = dtau[k] / amu;
@@ -771,11 +811,13 @@ static cplx c_expm1(cplx z)
 
 /* Complex formal solution: chi = chi_re + i chi_im, S = S_re + i S_im (any imaginary part may be
  * NULL = zero).  I_top is real; I_bot ([ny][nx], real, NULL = zero) is the light entering the bottom
- * plane.  Outputs J ([V], real and imaginary parts) and, optionally, the emergent top intensities
+ * plane, to which an upward line adds mu times slope ([ny][nx], complex, NULL = none: the
+ * LTE-diffusion gradient dB/dtau, which depends on chi).  Outputs J ([V], real and imaginary parts) and, optionally, the emergent top intensities
  * of the upward directions Iem ([n_up][ny][nx], real and imaginary parts).  Single-threaded. */
 int orc_fs_complex(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi_re,
                    const double *chi_im, const double *S_re, const double *S_im, double I_top,
-                   const double *I_bot, double *J_re, double *J_im, double *Iem_re, double *Iem_im)
+                   const double *I_bot, const double *slope_re, const double *slope_im,
+                   double *J_re, double *J_im, double *Iem_re, double *Iem_im)
 {
     Geom g;
     int rc = geom_init(&g, nx, ny, nz, n_theta, n_phi);
@@ -805,6 +847,10 @@ int orc_fs_complex(int nx, int ny, int nz, int n_theta, int n_phi, const double 
                     if (mu > 0.0 && step == 0) {
                         In.re = I_bot ? I_bot[seg_v[0]] : 0.0;
                         In.im = 0.0;
+                        if (slope_re) {   /* LTE diffusion: + mu dB/dtau (complex through chi) */
+                            In.re += mu * slope_re[seg_v[0]];
+                            In.im += slope_im ? mu * slope_im[seg_v[0]] : 0.0;
+                        }
                     }
                     for (int s = 0; s < ns; ++s) {
                         const int v = seg_v[s];

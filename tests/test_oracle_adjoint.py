@@ -97,3 +97,21 @@ def test_loss_gradient_matches_finite_differences(orc):
                 L.append(orc.emergent_loss(p["chi"], p["eps"], p["B"], T, nt, nph, I_top=0.2)[0])
             fd = (L[0] - L[1]) / (2 * step)
             assert abs(g[idx] - fd) <= 1e-6 * abs(fd) + 1e-9 * np.abs(g).max(), (name, idx, g[idx], fd)
+
+
+def test_loss_gradient_with_lte_diffusion_boundary_matches_fd(orc):
+    """With the LTE-diffusion inner condition the bottom light depends on chi of the two bottom
+    layers; the complex-step gradient carries that dependence (checked on bottom-layer voxels)."""
+    m = random_medium(4, 4, 3, seed=29, chi_range=(0.05, 2.0), eps_range=(0.05, 0.5))
+    nt, nph = 2, 4
+    T = np.random.default_rng(4).uniform(0.5, 1.5, (nt * nph // 2, 4, 4))
+    gchi, geps = orc.loss_gradient_cs(m["chi"], m["eps"], m["B"], T, nt, nph, bottom_from_B="diffusion")
+    for idx in ((0, 1, 2), (1, 3, 0), (2, 0, 1)):
+        step = 1e-5 * m["chi"][idx]
+        L = []
+        for sign in (1.0, -1.0):
+            c = m["chi"].copy()
+            c[idx] += sign * step
+            L.append(orc.emergent_loss(c, m["eps"], m["B"], T, nt, nph, bottom_from_B="diffusion")[0])
+        fd = (L[0] - L[1]) / (2 * step)
+        assert abs(gchi[idx] - fd) <= 1e-6 * abs(fd) + 1e-9 * np.abs(gchi).max(), (idx, gchi[idx], fd)

@@ -173,3 +173,43 @@ def test_threads_do_not_change_result_beyond_rounding(orc):
     J1 = orc.formal_solution(m["chi"], m["B"], 8, 8, n_threads=1)
     J4 = orc.formal_solution(m["chi"], m["B"], 8, 8, n_threads=4)
     assert np.max(np.abs(J4 / J1 - 1)) < 1e-14
+
+
+def test_lte_diffusion_boundary_pins(orc):
+    """The LTE-diffusion inner condition I = B_0 + mu (B_0 - B_1) / ((chi_0 + chi_1) / 2):
+    * with isothermal B it is the B condition, exactly;
+    * through an almost transparent slab the emergent light of every upward line is that boundary
+      light of the column the line enters;
+    * for a horizontally homogeneous slab the 3D formal solution equals the 1D plane-parallel one
+      with the same boundary (a separate code path with no 3D geometry)."""
+    nz, ny, nx = 4, 5, 6
+    rng = np.random.default_rng(7)
+    chi = np.exp(rng.uniform(np.log(0.05), np.log(3.0), (nz, ny, nx)))
+    eps = rng.uniform(0.1, 0.9, (nz, ny, nx))
+    B1 = np.full((nz, ny, nx), 1.7)
+    assert np.array_equal(orc.dense_os_solution(chi, eps, B1, 4, 4, bottom_from_B="diffusion"),
+                          orc.dense_os_solution(chi, eps, B1, 4, 4, bottom_from_B=True))
+    # almost transparent: I_em = B_0 + mu slope of the entry column
+    B = rng.uniform(0.5, 2.0, (nz, ny, nx))
+    chi_t = np.full((nz, ny, nx), 1e-13)
+    slope = orc.diffusion_slope(chi_t * 0 + 1.0, B)       # any slope field will do
+    _, Iem = orc.formal_solution(chi_t, np.zeros_like(B), 4, 8, I_bot=B[0], I_slope=slope,
+                                 want_emergent=True)
+    mu, ox, oy, _ = orc.quadrature(4, 8)
+    for q, d in enumerate(range(16, 32)):
+        for j in range(ny):
+            for i in range(nx):
+                v, _ = orc.trace_layer(nx, ny, nz, 4, 8, d, i, j, 0)
+                c = v[0]
+                assert abs(Iem[q, j, i] - (B[0].ravel()[c] + mu[d] * slope.ravel()[c])) < 1e-10
+    # horizontally homogeneous: 3D = 1D with the same boundary
+    chi_k = np.array([2.5, 0.8, 0.3, 0.05])
+    B_k = np.array([3.0, 2.2, 1.5, 1.0])
+    S_k = np.array([2.0, 1.5, 1.1, 0.6])
+    chi3 = np.broadcast_to(chi_k[:, None, None], (nz, ny, nx)).copy()
+    B3 = np.broadcast_to(B_k[:, None, None], (nz, ny, nx)).copy()
+    S3 = np.broadcast_to(S_k[:, None, None], (nz, ny, nx)).copy()
+    sl = orc.diffusion_slope(chi3, B3)
+    J3 = orc.formal_solution(chi3, S3, 8, 8, I_top=0.2, I_bot=B3[0], I_slope=sl)
+    J1 = orc.pp1d(chi_k, S_k, 8, I_top=0.2, I_bot=B_k[0], I_slope=(B_k[0] - B_k[1]) / (0.5 * (chi_k[0] + chi_k[1])))
+    np.testing.assert_allclose(J3, np.broadcast_to(J1[:, None, None], J3.shape), rtol=1e-13)
