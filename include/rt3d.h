@@ -69,7 +69,10 @@ typedef struct {
     int n_theta, n_phi;    /* n_theta even >= 2; n_phi >= 4 and a multiple of 4 */
     double I_top;          /* intensity entering through the top plane (outer boundary), >= 0 */
     int bottom_bc;         /* 0: an upward line enters with I = B of the bottom voxel it enters;
-                              1: I = 0 at the bottom plane */
+                              1: I = 0 at the bottom plane;
+                              2: LTE diffusion, I = B_0 + mu (B_0 - B_1) / ((chi_0 + chi_1) / 2) with B_0,
+                                 chi_0 of that voxel and B_1, chi_1 of the voxel above it (the inner
+                                 condition of the paper's test; = case 0 for an isothermal slab) */
 } rt3d_grid_desc;
 
 typedef struct rt3d_ctx rt3d_ctx;

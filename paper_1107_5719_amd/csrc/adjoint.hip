@@ -48,11 +48,13 @@ struct AdjLineArgs {
     const double *seg_len;
     const double *chi, *S;        // opacity and the converged source
     const double *Ibot;           // light entering the bottom plane ([ny][nx]) or null
+    const double *Islope;         // LTE-diffusion gradient ([ny][nx]): upward lines add mu * Islope
     double I_top;
     double *Ient;                 // [n_dir][nz][ny*nx]: I entering layer k along line p
     const double *g;              // [n_up][ny*nx]: dL/dI_em at the top end of the upward lines
     const double *nu, *eps;       // weights c = (1 - eps) nu W|mu| of the deposits, or nu == null
     double *Qx;                   // [n_dir][nz][ny*nx]: adjoint q leaving layer k along line p
+    double *Qstart;               // [n_up][ny*nx]: q at the start of the upward lines (or null)
 };
 
 __device__ inline int wrap_any(int a, int n)
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(kLineThreads) void adj_record_kernel(AdjLineArgs a)
     double I = a.I_top;
     if (!down) {
         const long v0 = seg_voxel(a, i0, j0, 0, a.seg_off[d * a.nz]);
-        I = a.Ibot ? a.Ibot[v0] : 0.0;
+        I = a.Ibot ? a.Ibot[v0] + (a.Islope ? a.dirs[d].mu * a.Islope[v0] : 0.0) : 0.0;
     }
     for (int step = 0; step < a.nz; ++step) {
         const int k = down ? a.nz - 1 - step : step;
@@ -122,6 +124,30 @@ __global__ __launch_bounds__(kLineThreads) void adj_back_kernel(AdjLineArgs a)
             q = q - (c - q) * em1;                           // q e + c (1 - e)
         }
     }
+    if (!down && a.Qstart) a.Qstart[long(d - a.n_dir / 2) * nxy + p] = q;   // sensitivity to the entry light
+}
+
+// LTE-diffusion inner condition: the entry light B_0 + mu (B_0 - B_1) / dtau of an upward line
+// depends on chi_0 and chi_1 of its entry column through dtau = (chi_0 + chi_1) / 2.  Per bottom
+// column, the lines of every upward direction that enter there add q_start mu d(slope)/d(chi) to
+// both voxels' chi gradient.
+__global__ void adj_bc_kernel(AdjLineArgs a, const double *B, double *pull)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nxy = a.nx * a.ny;
+    if (c >= nxy) return;
+    const int i = c % a.nx, j = c / a.nx;
+    double acc = 0.0;
+    for (int d = a.n_dir / 2; d < a.n_dir; ++d) {
+        const int t = a.seg_off[d * a.nz];                  // first segment of layer 0
+        const int i0 = wrap_any(i - a.seg_ai[t], a.nx);
+        const int j0 = wrap_any(j - a.seg_bi[t], a.ny);
+        acc += a.Qstart[long(d - a.n_dir / 2) * nxy + long(j0) * a.nx + i0] * a.dirs[d].mu;
+    }
+    const double dtau = 0.5 * (a.chi[c] + a.chi[nxy + c]);
+    const double dslope = -0.5 * (B[c] - B[nxy + c]) / (dtau * dtau);   // d(slope)/d(chi_0) = d/d(chi_1)
+    pull[c] += acc * dslope;
+    pull[nxy + c] += acc * dslope;
 }
 
 // Per voxel, over all directions and the segments of its layer that lie in it:
@@ -206,7 +232,9 @@ AdjLineArgs line_args(rt3d_ctx *c)
     a.dirs = c->dirs; a.seg_off = c->seg_off; a.seg_n = c->seg_n; a.seg_ai = c->seg_ai; a.seg_bi = c->seg_bi;
     a.seg_len = c->seg_len64;
     a.chi = c->chi; a.S = c->Sbuf;
-    a.Ibot = c->g.bottom_bc == 0 ? c->B : nullptr;
+    a.Ibot = c->g.bottom_bc != 1 ? c->B : nullptr;
+    a.Islope = c->g.bottom_bc == 2 ? c->bot_slope : nullptr;
+    a.Qstart = c->g.bottom_bc == 2 ? c->adj_qs : nullptr;
     a.I_top = c->g.I_top;
     a.Ient = c->adj_Ient; a.Qx = c->adj_Qx;
     a.g = c->adj_g;
@@ -224,9 +252,10 @@ int ensure_adjoint_buffers(rt3d_ctx *c)
     chk(dev_alloc(c, &c->adj_nu, c->V)); chk(dev_alloc(c, &c->adj_fs, c->V)); chk(dev_alloc(c, &c->adj_r, c->V));
     chk(dev_alloc(c, &c->adj_f, c->V)); chk(dev_alloc(c, &c->adj_pull, c->V));
     chk(dev_alloc(c, &c->adj_g, size_t(c->A.n_dir / 2) * c->g.nx * c->g.ny));
+    if (c->g.bottom_bc == 2) chk(dev_alloc(c, &c->adj_qs, size_t(c->A.n_dir / 2) * c->g.nx * c->g.ny));
     if (rc) {
         double **ptrs[] = {&c->adj_Ient, &c->adj_Qx, &c->adj_nu, &c->adj_fs, &c->adj_r, &c->adj_f, &c->adj_pull,
-                           &c->adj_g};
+                           &c->adj_g, &c->adj_qs};
         for (double **p : ptrs) {
             if (*p) hipFree(*p);
             *p = nullptr;
@@ -399,6 +428,10 @@ int rt3d_adjoint_emergent(rt3d_ctx *c, const double *g_em, double tol, int max_i
     if ((rc = check_launch(c, "adj_back_kernel"))) return rc;
     hipLaunchKernelGGL(adj_pull_kernel, planes(c), dim3(kPlaneThreads), 0, c->stream, la, 1, c->adj_pull);
     if ((rc = check_launch(c, "adj_pull_kernel"))) return rc;
+    if (c->g.bottom_bc == 2) {
+        hipLaunchKernelGGL(adj_bc_kernel, dim3((nxy + 255) / 256), dim3(256), 0, c->stream, la, c->B, c->adj_pull);
+        if ((rc = check_launch(c, "adj_bc_kernel"))) return rc;
+    }
     AdjFinalArgs fa{};
     fa.V = V;
     fa.chi = c->chi; fa.eps = c->eps; fa.B = c->B; fa.J = c->J; fa.Jfs = c->Jfs; fa.nu = c->adj_nu;

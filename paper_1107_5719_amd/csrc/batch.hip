@@ -385,7 +385,8 @@ int build_tables(rt3d_batch *b)
             s.n_down = c->A.n_dir / 2;
             s.pseg = c->pseg; s.player = c->player; s.pairs = c->pairs; s.items = c->items;
             s.cs = c->cs;
-            s.Ibot = (c->g.bottom_bc == 0 && !diff) ? c->B : nullptr;
+            s.Ibot = (c->g.bottom_bc != 1 && !diff) ? c->B : nullptr;
+            s.Islope = (c->g.bottom_bc == 2 && !diff) ? c->bot_slope : nullptr;
             s.I_top = diff ? 0.0 : c->g.I_top;
             s.P = c->P;
             s.Iem = c->Iem;

@@ -32,6 +32,7 @@ struct rt3d_ctx {
     double *dJa = nullptr, *dJb = nullptr, *L = nullptr, *Iem = nullptr;
     double *Kc = nullptr, *invD = nullptr, *Ecoef = nullptr;   // Jacobi coefficients (float64 form)
     double *Sbuf = nullptr;
+    double *bot_slope = nullptr;        // [ny][nx] LTE-diffusion gradient (bottom_bc 2)
     void *cs = nullptr, *P = nullptr;       // sized for float64; float sweeps use the first half
     double *seg_len64 = nullptr;
     float *seg_len32 = nullptr;
@@ -57,6 +58,7 @@ struct rt3d_ctx {
     double *adj_Ient = nullptr, *adj_Qx = nullptr;
     double *adj_nu = nullptr, *adj_fs = nullptr, *adj_r = nullptr, *adj_f = nullptr, *adj_pull = nullptr;
     double *adj_g = nullptr;            // [n_up][ny][nx]: dL/dI_em
+    double *adj_qs = nullptr;           // [n_up][ny][nx]: adjoint at the start of upward lines (bottom_bc 2)
     // Ng acceleration
     int ng_order = 0, ng_every = 0;
     double *ng_hist = nullptr;          // [ng_order + 2][V] ring of iterates

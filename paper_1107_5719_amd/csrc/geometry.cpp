@@ -242,6 +242,7 @@ bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int lines_per_w
         P.dirs[d].wmu = A.w[d] * std::fabs(A.mu[d]);
         P.dirs[d].down = A.mu[d] < 0.0 ? 1 : 0;
         P.dirs[d].pad = 0;
+        P.dirs[d].mu = A.mu[d];
     }
     P.mean_segments = double(total_segments) / (double(A.n_dir) * nz);
     // pairs mirrored in x: the partner's tables must equal the owner's up to negated columns
@@ -270,6 +271,7 @@ bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int lines_per_w
             pi.dA = dA;
             pi.dB = dB;
             pi.down = P.dirs[dA].down;
+            pi.mu = A.mu[dA];
             // Band height: about target_seg_per_wg line-segments per layer for the two directions,
             // never thinner than the window's halo, within the line and LDS budgets.
             int rows = int(std::lround(target_seg_per_wg / (2.0 * nx * seg_per_layer[dA])));

@@ -40,6 +40,7 @@ struct DirInfo {
     double wmu;        // W_d * |mu_d|
     int down;          // 1 if mu < 0 (sweep from the top layer down)
     int pad;
+    double mu;         // direction cosine with the z axis
 };
 
 // A pair of directions mirrored in x, (mu, phi) and (mu, pi - phi).  Their lines cross the same
@@ -56,6 +57,7 @@ struct PairInfo {
     int last_rows;     // rows of the last band: ny - (nb - 1) * Bj
     float inv_rows;    // 1 / Bj (band lookup; corrected exactly in the kernel)
     int64_t p_off;     // element offset of this pair's partial planes in P
+    double mu;         // direction cosine with the z axis (the same for both)
 };
 
 // Segment s of a pair in one layer, packed for one scalar load: column offsets of both directions

@@ -135,6 +135,7 @@ struct SweepArgs {
     const WorkItem *items;
     const void *cs;               // Vec2<real>
     const double *Ibot;           // [ny][nx] intensities at the bottom plane, or null (zero)
+    const double *Islope;         // [ny][nx] LTE-diffusion gradient: upward lines add mu * Islope (or null)
     double I_top;
     void *P;                      // real
     double *Iem;                  // [n_up][ny][nx] or null
@@ -203,8 +204,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
                 const unsigned row = wrap_once(grow0[t] + unsigned(g.smnx), plane);
                 const unsigned cA = wrap_once(unsigned(li[t] + g.saA), nx);
                 const unsigned cB = wrap_once(unsigned(li[t] + g.saB), nx);
-                IA[t] = a.Ibot ? real(a.Ibot[row + cA]) : real(0);
-                IB[t] = a.Ibot ? real(a.Ibot[row + cB]) : real(0);
+                const double sA = a.Islope ? pi.mu * a.Islope[row + cA] : 0.0;
+                const double sB = a.Islope ? pi.mu * a.Islope[row + cB] : 0.0;
+                IA[t] = a.Ibot ? real(a.Ibot[row + cA] + sA) : real(0);
+                IB[t] = a.Ibot ? real(a.Ibot[row + cB] + sB) : real(0);
             }
         }
         // gathers of segment s (prefetch variant: segment s+1's are issued before s is computed)
@@ -729,6 +732,14 @@ __global__ void check_medium_kernel(long V, const double *chi, const double *eps
     const double c = chi[v], e = eps[v], b = B[v];
     const bool ok = isfinite(c) && c > 0.0 && isfinite(e) && e > 0.0 && e <= 1.0 && isfinite(b);
     if (!ok) atomicOr(flag, 1);
+}
+
+// LTE-diffusion inner condition: dB/dtau per bottom column, (B_0 - B_1) / ((chi_0 + chi_1) / 2) from
+// the bottom voxel and the one above it (the optical distance between their centres)
+__global__ void diffusion_slope_kernel(int nxy, const double *chi, const double *B, double *slope)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nxy) slope[c] = (B[c] - B[nxy + c]) / (0.5 * (chi[c] + chi[nxy + c]));
 }
 
 __global__ void check_finite_kernel(long V, const double *x, int *flag)

@@ -119,7 +119,7 @@ int validate_desc(const rt3d_grid_desc *g, std::string &msg)
     if (g->n_theta < 2 || (g->n_theta % 2) != 0) { msg = "n_theta must be even and >= 2"; return RT3D_ERR_ARG; }
     if (g->n_phi < 4 || (g->n_phi % 4) != 0) { msg = "n_phi must be a positive multiple of 4"; return RT3D_ERR_ARG; }
     if (!std::isfinite(g->I_top) || g->I_top < 0.0) { msg = "I_top must be finite and >= 0"; return RT3D_ERR_ARG; }
-    if (g->bottom_bc != 0 && g->bottom_bc != 1) { msg = "bottom_bc must be 0 or 1"; return RT3D_ERR_ARG; }
+    if (g->bottom_bc < 0 || g->bottom_bc > 2) { msg = "bottom_bc must be 0, 1 or 2"; return RT3D_ERR_ARG; }
     return RT3D_OK;
 }
 
@@ -175,7 +175,8 @@ int launch_sweep(rt3d_ctx *c, bool fp32, bool diff)
     a.pseg = c->pseg; a.player = c->player;
     a.pairs = c->pairs; a.items = c->items;
     a.cs = c->cs;
-    a.Ibot = (c->g.bottom_bc == 0 && !diff) ? c->B : nullptr;
+    a.Ibot = (c->g.bottom_bc != 1 && !diff) ? c->B : nullptr;
+    a.Islope = (c->g.bottom_bc == 2 && !diff) ? c->bot_slope : nullptr;
     a.I_top = diff ? 0.0 : c->g.I_top;
     a.P = c->P;
     a.Iem = c->Iem;
@@ -337,9 +338,9 @@ void free_all(rt3d_ctx *c)
 {
     free_plan(c);
     void *ptrs[] = {c->chi, c->eps, c->B, c->J, c->Jfs, c->r, c->dJa, c->dJb, c->L, c->Kc, c->invD, c->Ecoef, c->Iem,
-                    c->Sbuf, c->cs, c->Ja, c->Fa, c->Iem_a, c->Kc32, c->d_maxdist, c->d_maxrel, c->d_flag,
+                    c->Sbuf, c->bot_slope, c->cs, c->Ja, c->Fa, c->Iem_a, c->Kc32, c->d_maxdist, c->d_maxrel, c->d_flag,
                     c->ng_hist, c->ng_work, c->adj_Ient, c->adj_Qx, c->adj_nu, c->adj_fs, c->adj_r,
-                    c->adj_f, c->adj_pull, c->adj_g};
+                    c->adj_f, c->adj_pull, c->adj_g, c->adj_qs};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (auto &p : c->pending) {
@@ -474,6 +475,7 @@ int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream
     }
     chk(dev_alloc(c, &c->d_maxdist, 1));
     chk(dev_alloc(c, &c->d_maxrel, 1)); chk(dev_alloc(c, &c->d_flag, 1));
+    if (g->bottom_bc == 2) chk(dev_alloc(c, &c->bot_slope, size_t(g->nx) * g->ny));
     if (!rc) rc = install_plan(c, shape);
     if (rc) {
         msg = c->err;
@@ -599,6 +601,13 @@ int rt3d_set_medium(rt3d_ctx *c, const double *chi, const double *eps, const dou
     std::swap(c->chi, c->dJa);
     std::swap(c->eps, c->dJb);
     std::swap(c->B, c->Sbuf);
+    if (c->g.bottom_bc == 2) {
+        const int nxy = c->g.nx * c->g.ny;
+        hipLaunchKernelGGL(diffusion_slope_kernel, dim3((nxy + 255) / 256), dim3(256), 0, c->stream, nxy, c->chi,
+                           c->B, c->bot_slope);
+        int rc = check_launch(c, "diffusion_slope_kernel");
+        if (rc) return rc;
+    }
     HIP_TRY(c, hipMemcpyAsync(c->J, c->B, V * 8, hipMemcpyDeviceToDevice, c->stream), "J = B");
     c->have_medium = true;
     c->have_lstar = false;

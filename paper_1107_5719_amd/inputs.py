@@ -19,7 +19,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Workload", "WORKLOADS", "stratified_profile", "paper_slab_profile", "make_medium", "random_medium", "wavelength_batch",
+__all__ = ["Workload", "WORKLOADS", "stratified_profile", "paper_slab_profile", "make_medium", "random_medium",
+           "diffusion_medium", "wavelength_batch",
            "emergent_target"]
 
 
@@ -145,6 +146,18 @@ def make_medium(w: Workload | str):
         raise ValueError(f"unknown B profile {w.b_profile!r}")
     return {"chi": np.ascontiguousarray(chi), "eps": np.ascontiguousarray(eps),
             "B": np.ascontiguousarray(B)}
+
+
+def diffusion_medium(nx: int, ny: int, nz: int, seed: int, chi_range=(1e-2, 3.0), eps_range=(0.05, 0.5)):
+    """Small random medium for the LTE-diffusion inner condition, which assumes an optically thick
+    bottom and B varying slowly with depth: as random_medium, but the two bottom layers have
+    chi >= 1 and B falls linearly from 1.5 (bottom) to 1 (top) with a 5 % perturbation."""
+    m = random_medium(nx, ny, nz, seed, chi_range=chi_range, eps_range=eps_range)
+    m["chi"][:2] = np.maximum(m["chi"][:2], 1.0)
+    rng = np.random.Generator(np.random.PCG64(seed + 7919))
+    prof = 1.5 - 0.5 * np.arange(nz) / max(nz - 1, 1)
+    m["B"] = prof[:, None, None] * (1.0 + 0.05 * rng.uniform(-1.0, 1.0, (nz, ny, nx)))
+    return m
 
 
 def random_medium(nx: int, ny: int, nz: int, seed: int, chi_range=(1e-2, 1e2),

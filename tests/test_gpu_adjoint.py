@@ -12,7 +12,7 @@
 import numpy as np
 import pytest
 
-from paper_1107_5719_amd.inputs import WORKLOADS, emergent_target, make_medium, random_medium
+from paper_1107_5719_amd.inputs import WORKLOADS, diffusion_medium, emergent_target, make_medium, random_medium
 
 pytestmark = pytest.mark.gpu
 
@@ -33,6 +33,7 @@ CASES = [
     ((3, 5, 4), 2, 4, 0.2, 0, 23),
     ((4, 5, 6), 4, 8, 0.0, 0, 24),
     ((5, 4, 4), 4, 4, 0.1, 1, 25),
+    ((4, 4, 5), 4, 4, 0.0, 2, 26),       # LTE-diffusion inner condition (depends on chi)
 ]
 
 
@@ -53,11 +54,12 @@ def _gpu_gradient(R, m, nt, nph, T, I_top, bbc, precision=0):
 def test_adjoint_matches_oracle_complex_step(R, orc, case):
     shape, nt, nph, I_top, bbc, seed = case
     nz, ny, nx = shape
-    m = random_medium(nx, ny, nz, seed=seed, chi_range=(1e-2, 3.0), eps_range=(0.05, 0.5))
+    make = diffusion_medium if bbc == 2 else random_medium
+    m = make(nx, ny, nz, seed=seed, chi_range=(1e-2, 3.0), eps_range=(0.05, 0.5))
     T = emergent_target(nt * nph // 2, ny, nx, seed)
-    gchi, geps = orc.loss_gradient_cs(m["chi"], m["eps"], m["B"], T, nt, nph, I_top=I_top,
-                                      bottom_from_B=(bbc == 0))
-    _, Iem_o, _ = orc.emergent_loss(m["chi"], m["eps"], m["B"], T, nt, nph, I_top=I_top, bottom_from_B=(bbc == 0))
+    bottom = {0: True, 1: False, 2: "diffusion"}[bbc]
+    gchi, geps = orc.loss_gradient_cs(m["chi"], m["eps"], m["B"], T, nt, nph, I_top=I_top, bottom_from_B=bottom)
+    _, Iem_o, _ = orc.emergent_loss(m["chi"], m["eps"], m["B"], T, nt, nph, I_top=I_top, bottom_from_B=bottom)
     I, dchi, deps = _gpu_gradient(R, m, nt, nph, T, I_top, bbc)
     np.testing.assert_allclose(I, Iem_o, rtol=1e-12)
     for got, ref in ((dchi, gchi), (deps, geps)):

@@ -10,7 +10,7 @@ import json
 import numpy as np
 import pytest
 
-from paper_1107_5719_amd.inputs import random_medium, wavelength_batch
+from paper_1107_5719_amd.inputs import diffusion_medium, random_medium, wavelength_batch
 
 pytestmark = pytest.mark.gpu
 
@@ -31,11 +31,12 @@ def R():
 def _members(seed=0):
     """Ragged members: different sizes, angle sets, boundary light and media."""
     out = []
-    specs = [((6, 7, 9), 4, 8, 0.2, 0), ((9, 12, 10), 8, 8, 0.0, 0), ((5, 5, 5), 4, 4, 0.0, 1),
+    specs = [((6, 7, 9), 4, 8, 0.2, 0), ((9, 12, 10), 8, 8, 0.0, 2), ((5, 5, 5), 4, 4, 0.0, 1),
              ((8, 33, 20), 8, 16, 0.1, 0)]
     for i, (shape, nt, nph, I_top, bbc) in enumerate(specs):
         nz, ny, nx = shape
-        m = random_medium(nx, ny, nz, seed=100 + seed + i, chi_range=(1e-3, 3e1), eps_range=(1e-3, 0.5))
+        make = diffusion_medium if bbc == 2 else random_medium
+        m = make(nx, ny, nz, seed=100 + seed + i, chi_range=(1e-3, 3e1), eps_range=(1e-3, 0.5))
         out.append({"grid": {"nx": nx, "ny": ny, "nz": nz, "n_theta": nt, "n_phi": nph, "I_top": I_top,
                              "bottom_bc": bbc}, "chi": m["chi"], "eps": m["eps"], "B": m["B"]})
     return out

@@ -7,7 +7,7 @@ J.  The oracle never sees anything the GPU produced: both sides get the same see
 import numpy as np
 import pytest
 
-from paper_1107_5719_amd.inputs import WORKLOADS, make_medium, random_medium
+from paper_1107_5719_amd.inputs import WORKLOADS, diffusion_medium, make_medium, random_medium
 
 pytestmark = pytest.mark.gpu
 
@@ -61,6 +61,7 @@ FS_CASES = [
     ((6, 9, 131), 8, 8, 6, 0.0, 0),      # rows longer than two wavefronts
     ((6, 5, 7), 2, 4, 7, 0.2, 0),        # smallest angle set; every line runs through voxel edges
     ((5, 8, 6), 8, 4, 8, 0.0, 0),        # n_phi = 4 with steep and shallow directions
+    ((6, 7, 5), 8, 8, 9, 0.1, 2),        # LTE-diffusion inner condition
 ]
 
 
@@ -68,10 +69,12 @@ FS_CASES = [
 def test_formal_solution_parity(R, orc, case):
     shape, nt, nph, seed, I_top, bbc = case
     nz, ny, nx = shape
-    m = random_medium(nx, ny, nz, seed=seed, chi_range=(1e-4, 1e2))
+    m = (diffusion_medium(nx, ny, nz, seed=seed, chi_range=(1e-4, 1e2)) if bbc == 2 else
+         random_medium(nx, ny, nz, seed=seed, chi_range=(1e-4, 1e2)))
     S = np.random.default_rng(seed).uniform(0.1, 3.0, shape)
     J_orc, Iem_orc = orc.formal_solution(m["chi"], S, nt, nph, I_top=I_top,
-                                         I_bot=(m["B"][0] if bbc == 0 else None), want_emergent=True)
+                                         I_bot=(m["B"][0] if bbc != 1 else None), want_emergent=True,
+                                         I_slope=(orc.diffusion_slope(m["chi"], m["B"]) if bbc == 2 else None))
     with R.Solver(nx, ny, nz, nt, nph, I_top=I_top, bottom_bc=bbc) as s:
         s.set_medium(m["chi"], m["eps"], m["B"])
         J = s.formal_solution(S)
@@ -232,6 +235,24 @@ def test_paper_slab_grids_parity(R, orc):
         s.set_medium(m["chi"], m["eps"], m["B"])
         J = s.formal_solution(S)
     _close(J, J_orc)
+
+
+def test_solve_parity_lte_diffusion(R, orc):
+    """A converged solve with the LTE-diffusion inner condition (B varying with depth, so the
+    condition differs from I = B) against the oracle's: same iteration count, J within 1e-10."""
+    nz, ny, nx = 6, 5, 7
+    m = diffusion_medium(nx, ny, nz, seed=31, chi_range=(0.05, 5.0), eps_range=(0.01, 0.3))
+    J_orc, it_o, c_o, ok = orc.solve(m["chi"], m["eps"], m["B"], 8, 8, 1e-10, 3000, 6,
+                                     bottom_from_B="diffusion")
+    assert ok
+    J_dense = orc.dense_os_solution(m["chi"], m["eps"], m["B"], 8, 8, bottom_from_B="diffusion")
+    with R.Solver(nx, ny, nz, 8, 8, bottom_bc=2) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        st, it, c = s.solve(1e-10, 3000, 6)
+        J = s.get_J()
+    assert st == R.RT3D_OK and it == it_o
+    _close(J, J_orc)
+    np.testing.assert_allclose(J, J_dense, rtol=1e-8)
 
 
 def test_error_paths(R):
