@@ -422,12 +422,16 @@ int build_tables(rt3d_batch *b)
         for (int z = 0; z < nz; ++z)
             for (int ch = 0; ch < chunks; ++ch) planes.push_back(PlaneBlock{i, ch, z, 0});
         // XCD-aware order (as in the single-problem Jacobi grid): each member starts on a multiple of
-        // 8 blocks and its planes are padded to a multiple of 8 chunks, so a chunk of every plane
-        // lands on the same XCD; padding blocks have no voxels
+        // 8 blocks; block b of the member runs on XCD b % 8, which takes the contiguous chunk range
+        // [xcd * G, (xcd + 1) * G) of every plane (G = chunks padded to 8, / 8); padding blocks have
+        // no voxels
         while (planes_xcd.size() % 8) planes_xcd.push_back(PlaneBlock{i, chunks, 0, 0});
-        const int padded = (chunks + 7) / 8 * 8;
-        for (int z = 0; z < nz; ++z)
-            for (int ch = 0; ch < padded; ++ch) planes_xcd.push_back(PlaneBlock{i, ch, z, 0});
+        const int group = (chunks + 7) / 8;
+        for (int bl = 0; bl < 8 * group * nz; ++bl) {
+            const int xcd = bl & 7, slot = bl >> 3;
+            const int z = slot / group;
+            planes_xcd.push_back(PlaneBlock{i, xcd * group + (slot - z * group), z, 0});
+        }
     }
     // dispatch the most expensive bands of all members first
     std::stable_sort(work.begin(), work.end(), [](const std::pair<double, BatchItem> &x,

@@ -26,7 +26,8 @@ struct rt3d_ctx {
     int lstar_early_exit = 0;
     int sweep_shape = 0;       // index into kSweepShapes
     int sweep_prefetch = 0;
-    int jacobi_xcd = 1;        // XCD-aware Jacobi grid (RT3D_JACOBI_XCD=0 disables)
+    int jacobi_xcd = 2;        // Jacobi grid: 0 plain, 1 chunks padded to 8 per plane, 2 contiguous chunk
+                               // ranges per XCD (default), 3 2D tiles (RT3D_JACOBI_XCD)
     // device buffers (owned)
     double *chi = nullptr, *eps = nullptr, *B = nullptr, *J = nullptr, *Jfs = nullptr, *r = nullptr;
     double *dJa = nullptr, *dJb = nullptr, *L = nullptr, *Iem = nullptr;

@@ -512,32 +512,34 @@ struct JacobiArgs {
 // Arithmetic is float64 for either coefficient type.
 // The whole block must call this (it ends with a block reduction when J is updated).
 template <typename coef>
-__device__ inline void jacobi_body(const JacobiArgs &a, int p, int k)
+__device__ inline void jacobi_core(const JacobiArgs &a, int i, int j, int k, bool valid)
 {
     const coef *Kc = static_cast<const coef *>(a.Kc);
     double dist = 0.0;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const bool valid = p < nx * ny;
     double q = 0.0;
     bool bad = false;
     if (valid) {
-        const int j = p / nx, i = p - j * nx;
-        const long plane = long(nx) * ny, V = plane * nz, v = k * plane + p;
+        const long plane = long(nx) * ny, V = plane * nz, v = k * plane + long(j) * nx + i;
         double acc = a.chi[v] * a.r[v];
         if (a.w_in) {
             const int im = (i == 0) ? nx - 1 : i - 1, ip = (i == nx - 1) ? 0 : i + 1;
             const int jm = (j == 0) ? ny - 1 : j - 1, jp = (j == ny - 1) ? 0 : j + 1;
             const int cols[3] = {im, i, ip};
             const int rows[3] = {jm, j, jp};
+            // Branch-free over the planes so that all loads can be in flight together: the plane
+            // below is clamped at the bottom and its sum masked; the plane above needs no mask, its
+            // coefficients are stored as zero in the top layer.
+            const int planes[3] = {k > 0 ? k - 1 : 0, k, k < nz - 1 ? k + 1 : k};
+            double part[3] = {0.0, 0.0, 0.0};
 #pragma unroll
             for (int o = 0; o < 27; ++o) {
                 if (o == 13) continue;
-                const int kk = k + o / 9 - 1;
-                if (kk < 0 || kk >= nz) continue;
-                const long u = kk * plane + long(rows[(o / 3) % 3]) * nx + cols[o % 3];
+                const long u = planes[o / 9] * plane + long(rows[(o / 3) % 3]) * nx + cols[o % 3];
                 const double K = (o > 13) ? double(Kc[(o - 14) * V + v]) : double(Kc[(12 - o) * V + u]);
-                acc += K * a.w_in[u];
+                part[o / 9] += K * a.w_in[u];
             }
+            acc += (k > 0 ? part[0] : 0.0) + part[1] + part[2];
         }
         if (a.w_out) a.w_out[v] = acc * a.E[v];
         if (a.J) {
@@ -574,9 +576,51 @@ __device__ inline void jacobi_body(const JacobiArgs &a, int p, int k)
 }
 
 template <typename coef>
+__device__ inline void jacobi_body(const JacobiArgs &a, int p, int k)
+{
+    const bool valid = p < a.nx * a.ny;
+    const int j = valid ? p / a.nx : 0;
+    jacobi_core<coef>(a, valid ? p - j * a.nx : 0, j, k, valid);
+}
+
+template <typename coef>
 __global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel(JacobiArgs a)
 {
     jacobi_body<coef>(a, blockIdx.x * kPlaneThreads + threadIdx.x, blockIdx.y);
+}
+
+// The same sweep on a 1D grid whose blocks are dealt to the 8 XCDs (each with its own L2) in
+// contiguous ranges: workgroups go round-robin over the XCDs in launch order, so block b runs on XCD
+// b % 8; here that XCD takes the chunks [xcd * G, (xcd + 1) * G) of every plane, G = padded chunks / 8.
+// A voxel's mirrored coefficients and iterates sit in the row above (mostly the same or the previous
+// chunk) and in the plane below (the same chunk, G * 8 blocks earlier), so they are in that XCD's L2.
+// Chunks beyond the plane are padding (no voxels).
+template <typename coef>
+__global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel_grouped(JacobiArgs a, int group)
+{
+    const int b = blockIdx.x;
+    const int xcd = b & 7, slot = b >> 3;
+    const int k = slot / group;
+    const int chunk = xcd * group + (slot - k * group);
+    jacobi_body<coef>(a, chunk * kPlaneThreads + threadIdx.x, k);
+}
+
+// 2D tiles of kTileX x kTileY columns (a wavefront spans two rows of 32), dealt to the XCDs in
+// contiguous ranges of tiles per plane as above: the row above a voxel is mostly in its own tile, so
+// its iterates and mirrored coefficients come from this workgroup's recent reads.
+constexpr int kTileX = 32, kTileY = kPlaneThreads / kTileX;
+template <typename coef>
+__global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel_tiled(JacobiArgs a, int tiles_x, int group)
+{
+    const int b = blockIdx.x;
+    const int xcd = b & 7, slot = b >> 3;
+    const int k = slot / group;
+    const int tile = xcd * group + (slot - k * group);
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int i = tx * kTileX + (threadIdx.x % kTileX);
+    const int j = ty * kTileY + (threadIdx.x / kTileX);
+    const bool valid = i < a.nx && j < a.ny;
+    jacobi_core<coef>(a, valid ? i : 0, valid ? j : 0, k, valid);
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -304,6 +304,26 @@ int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update)
     a.Ja = (f32 && update) ? c->Ja : nullptr;
     a.maxdist = c->d_maxdist;
     TimedLaunch t(c, K_JACOBI);
+    if (c->jacobi_xcd == 3) {
+        const int tiles_x = (c->g.nx + kTileX - 1) / kTileX, tiles_y = (c->g.ny + kTileY - 1) / kTileY;
+        const int group = (tiles_x * tiles_y + 7) / 8;
+        const dim3 grid(unsigned(8 * group) * unsigned(c->g.nz));
+        if (f32)
+            hipLaunchKernelGGL(jacobi_kernel_tiled<float>, grid, dim3(kPlaneThreads), 0, c->stream, a, tiles_x, group);
+        else
+            hipLaunchKernelGGL(jacobi_kernel_tiled<double>, grid, dim3(kPlaneThreads), 0, c->stream, a, tiles_x, group);
+        return check_launch(c, "jacobi_kernel");
+    }
+    if (c->jacobi_xcd == 2) {
+        const int chunks = (c->g.nx * c->g.ny + kPlaneThreads - 1) / kPlaneThreads;
+        const int group = (chunks + 7) / 8;
+        const dim3 grid(unsigned(8 * group) * unsigned(c->g.nz));
+        if (f32)
+            hipLaunchKernelGGL(jacobi_kernel_grouped<float>, grid, dim3(kPlaneThreads), 0, c->stream, a, group);
+        else
+            hipLaunchKernelGGL(jacobi_kernel_grouped<double>, grid, dim3(kPlaneThreads), 0, c->stream, a, group);
+        return check_launch(c, "jacobi_kernel");
+    }
     const dim3 grid = c->jacobi_xcd ? plane_grid_xcd(c) : plane_grid(c);
     if (f32)
         hipLaunchKernelGGL(jacobi_kernel<float>, grid, dim3(kPlaneThreads), 0, c->stream, a);
@@ -443,7 +463,7 @@ int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream
     // gathers of the next segment issued before the current one is computed (RT3D_SWEEP_PREFETCH=1;
     // shapes 1 and 2 only; slower on MI355X because it costs occupancy)
     if (const char *e = std::getenv("RT3D_SWEEP_PREFETCH")) c->sweep_prefetch = std::atoi(e) != 0;
-    if (const char *e = std::getenv("RT3D_JACOBI_XCD")) c->jacobi_xcd = std::atoi(e) != 0;
+    if (const char *e = std::getenv("RT3D_JACOBI_XCD")) c->jacobi_xcd = std::max(0, std::min(3, std::atoi(e)));
     // Lambda* walk may stop at the first non-neighbour only if no line wraps back within two layers
     {
         double tmax_x = 0.0, tmax_y = 0.0;
