@@ -30,7 +30,7 @@ ALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 # adds) ~ 140 FP64 or ~80 FP32 vector operations, each priced as an FMA (2 flops).
 SWEEP_OPS_PER_UPDATE = {"fp64": 140, "fp32": 80}
 SWEEP_KERNEL = {"fp64": "sweep_kernel<double,512,2>", "fp32": "sweep_kernel<float,512,2>"}
-JACOBI_KERNEL = {"fp64": "jacobi_kernel<double>", "fp32": "jacobi_kernel<float>"}
+JACOBI_KERNEL = {"fp64": "jacobi_kernel_grouped<double>", "fp32": "jacobi_kernel_grouped<float>"}
 
 
 def sweep_bytes_per_update(precision: str) -> int:
@@ -302,7 +302,9 @@ def _paper_grids(rt3d, torch, stream, steps, M, ng, max_iter):
         row = {"grid": f"{w.nx}x{w.ny}x{w.nz} x {w.n_dir} angles"}
         for form, prec in (("fp64", rt3d.RT3D_FP64), ("fp32", rt3d.RT3D_FP32_SWEEP)):
             elapsed, per_launch, lstar_s, st = _timed_steps(rt3d, torch, w, d_med, prec, stream, steps, 1, M)
-            J, conv = _converge(rt3d, torch, w, d_med, prec, stream, M, ng[0], ng[1], w.tol, max_iter)
+            conv = None
+            if max_iter > 0:
+                J, conv = _converge(rt3d, torch, w, d_med, prec, stream, M, ng[0], ng[1], w.tol, max_iter)
             row[form] = {"ms_per_step": round(1e3 * elapsed / steps, 3),
                          "voxel_angle_updates_per_s": w.n_vox * w.n_dir * steps / elapsed,
                          "sweep_ms": per_launch["sweep"], "time_to_converged": conv}
