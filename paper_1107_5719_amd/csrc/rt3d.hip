@@ -272,7 +272,8 @@ int ensure_lstar(rt3d_ctx *c)
     a.seg_bi = c->seg_bi; a.seg_len = c->seg_len64; a.chi = c->chi; a.L = c->L;
     {
         TimedLaunch t(c, K_LSTAR);
-        hipLaunchKernelGGL(lstar_kernel, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
+        const dim3 grid((c->g.nx * c->g.ny + kLstarThreads - 1) / kLstarThreads, c->g.nz);
+        hipLaunchKernelGGL(lstar_kernel, grid, dim3(kLstarThreads), 0, c->stream, a);
     }
     int rc = check_launch(c, "lstar_kernel");
     if (rc) return rc;
