@@ -155,6 +155,13 @@ int rt3d_get_emergent_top(rt3d_ctx *ctx, double *out, int ptr_kind);
  * durations are accumulated (read with rt3d_get_stats).  Errors: RT3D_ERR_ARG. */
 int rt3d_set_timing(rt3d_ctx *ctx, int enable);
 
+/* The per-step record since the last rt3d_set_medium, rt3d_set_J or start of
+ * rt3d_solve_to_convergence (at most 100000 steps): max |dJ|/|J| (c_out), host wall milliseconds of the
+ * step (ms_out) and flags (flags_out: 1 = the step's formal solution was float64, 2 = Ng extrapolated
+ * after it).  Fills the first min(n, max_n) entries of the arrays (any may be NULL) and returns n, the
+ * number of records.  Errors: RT3D_ERR_ARG. */
+int rt3d_get_history(rt3d_ctx *ctx, double *c_out, double *ms_out, int *flags_out, int max_n);
+
 /* Statistics as a NUL-terminated JSON object: grid, angles, precision, outer iterations, inner
  * sweeps, device bytes, and per-kernel {launches, total_ms} when timing is enabled.
  * Errors: RT3D_ERR_ARG (buffer too small or NULL). */

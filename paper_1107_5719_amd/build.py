@@ -17,6 +17,8 @@ HIPCC_FLAGS = [
     # never let the compiler emit packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
+    # roctx ranges around the entry points (rocprofv3 --marker-trace)
+    "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
 ]
 
 

@@ -348,6 +348,7 @@ int rt3d_adjoint_emergent(rt3d_ctx *c, const double *g_em, double tol, int max_i
                           double *dL_dchi, double *dL_deps, int ptr_kind, int *iters_out, double *final_rel_out)
 {
     if (!c) return RT3D_ERR_ARG;
+    TraceRange tr("rt3d_adjoint_emergent");
     if (!c->have_medium) return fail(c, RT3D_ERR_STATE, "set the medium first");
     if (!g_em || !dL_dchi || !dL_deps || (ptr_kind != RT3D_HOST && ptr_kind != RT3D_DEVICE))
         return fail(c, RT3D_ERR_ARG, "null array or bad ptr_kind");

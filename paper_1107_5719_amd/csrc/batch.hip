@@ -767,6 +767,7 @@ int rt3d_batch_set_sweep_shape(rt3d_batch *b, int shape)
 int rt3d_batch_formal_solution(rt3d_batch *b)
 {
     if (!b) return RT3D_ERR_ARG;
+    TraceRange tr("rt3d_batch_formal_solution");
     for (int i = 0; i < b->n; ++i)
         if (!b->m[i]->have_medium) return bfail(b, RT3D_ERR_STATE, "member " + std::to_string(i) + " has no medium");
     int rc = ensure_tables(b);
@@ -799,6 +800,7 @@ int rt3d_batch_solve(rt3d_batch *b, double tol, int max_iter, int inner_sweeps, 
                      double *final_rel_out, int *status_out)
 {
     if (!b) return RT3D_ERR_ARG;
+    TraceRange tr("rt3d_batch_solve");
     if (!(tol > 0.0) || max_iter < 1 || inner_sweeps < 1 || poll_every < 1)
         return bfail(b, RT3D_ERR_ARG, "bad tol/max_iter/inner_sweeps/poll_every");
     const int n = b->n;

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cmath>
 #include <string>
@@ -13,6 +14,7 @@
 
 
 enum KernelId { K_SOURCE, K_SWEEP, K_REDUCE, K_LSTAR, K_COEF, K_JACOBI, K_COUNT };
+constexpr size_t kHistoryMax = 100000;   // step records kept per context
 static const char *kKernelNames[K_COUNT] = {"source", "sweep", "reduce", "lstar", "coef", "jacobi"};
 
 struct rt3d_ctx {
@@ -68,6 +70,10 @@ struct rt3d_ctx {
     size_t plan_bytes = 0;              // the part of device_bytes that belongs to the sweep plan
     bool have_medium = false, have_lstar = false, have_fs = false, plan_ok = false;
     long outer_iters = 0, inner_sweeps = 0;
+    // per OS step since the last new medium, new J or start of a solve: max |dJ|/|J|, wall ms,
+    // flags (1: float64 formal solution, 2: Ng extrapolation after the step)
+    struct StepRecord { double c, ms; int flags; };
+    std::vector<StepRecord> history;
     // timing
     bool timing = false;
     struct Pending { int kid; hipEvent_t a, b; };
@@ -80,6 +86,14 @@ struct rt3d_ctx {
 
 
 namespace rt3d_host {
+
+// A roctx range for the lifetime of the object (shown by rocprofv3 --marker-trace).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 int fail(rt3d_ctx *c, int code, const std::string &msg);
 int hip_fail(rt3d_ctx *c, hipError_t e, const char *what);

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -633,6 +634,7 @@ int rt3d_set_medium(rt3d_ctx *c, const double *chi, const double *eps, const dou
     c->have_medium = true;
     c->have_lstar = false;
     c->have_fs = false;
+    c->history.clear();
     c->anchor_valid = false;
     c->c_last = INFINITY;
     c->outer_iters = 0;
@@ -652,6 +654,7 @@ int rt3d_set_J(rt3d_ctx *c, const double *J, int ptr_kind)
         HIP_TRY(c, hipMemcpyAsync(c->J, J, V * 8, hipMemcpyHostToDevice, c->stream), "copy J");
         c->anchor_valid = false;
         c->c_last = INFINITY;
+        c->history.clear();
         return sync(c);
     }
     HIP_TRY(c, hipMemcpyAsync(c->dJa, J, V * 8, hipMemcpyDeviceToDevice, c->stream), "copy J");
@@ -666,6 +669,7 @@ int rt3d_set_J(rt3d_ctx *c, const double *J, int ptr_kind)
     std::swap(c->J, c->dJa);
     c->anchor_valid = false;
     c->c_last = INFINITY;
+    c->history.clear();
     return sync(c);
 }
 
@@ -681,6 +685,7 @@ int rt3d_get_J(rt3d_ctx *c, double *J_out, int ptr_kind)
 int rt3d_formal_solution(rt3d_ctx *c, const double *S_or_null, double *J_fs_out, int ptr_kind)
 {
     if (!c) return RT3D_ERR_ARG;
+    TraceRange tr("rt3d_formal_solution");
     if (!c->have_medium) return fail(c, RT3D_ERR_STATE, "set the medium first");
     if (!J_fs_out || (ptr_kind != RT3D_HOST && ptr_kind != RT3D_DEVICE)) return fail(c, RT3D_ERR_ARG, "bad output");
     const double *S_dev = nullptr;
@@ -701,6 +706,7 @@ int rt3d_formal_solution(rt3d_ctx *c, const double *S_or_null, double *J_fs_out,
 int rt3d_build_lstar(rt3d_ctx *c)
 {
     if (!c) return RT3D_ERR_ARG;
+    TraceRange tr("rt3d_build_lstar");
     if (!c->have_medium) return fail(c, RT3D_ERR_STATE, "set the medium first");
     int rc = ensure_lstar(c);
     if (rc) return rc;
@@ -719,6 +725,8 @@ int rt3d_get_lstar(rt3d_ctx *c, double *out, int ptr_kind)
 int rt3d_os_step(rt3d_ctx *c, int inner_sweeps, double *max_rel_dJ_out)
 {
     if (!c) return RT3D_ERR_ARG;
+    TraceRange tr("rt3d_os_step");
+    const auto t0 = std::chrono::steady_clock::now();
     if (!c->have_medium) return fail(c, RT3D_ERR_STATE, "set the medium first");
     if (inner_sweeps < 1) return fail(c, RT3D_ERR_ARG, "inner_sweeps must be >= 1");
     int rc = ensure_lstar(c);
@@ -764,6 +772,10 @@ int rt3d_os_step(rt3d_ctx *c, int inner_sweeps, double *max_rel_dJ_out)
     c->c_last = cval;
     c->da_last = dval;
     c->last_step_anchored = anchored;
+    if (c->history.size() < kHistoryMax) {
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        c->history.push_back({cval, ms, anchored ? 1 : 0});
+    }
     if (flag) {
         if (max_rel_dJ_out) *max_rel_dJ_out = NAN;
         return fail(c, RT3D_ERR_NONFINITE, "NaN or Inf in dJ or J");
@@ -777,6 +789,8 @@ int rt3d_solve_to_convergence(rt3d_ctx *c, double tol, int max_iter, int inner_s
 {
     if (!c) return RT3D_ERR_ARG;
     if (!(tol > 0.0) || max_iter < 1 || inner_sweeps < 1) return fail(c, RT3D_ERR_ARG, "bad tol/max_iter/inner_sweeps");
+    TraceRange tr("rt3d_solve_to_convergence");
+    c->history.clear();
     double cval = INFINITY;
     int n = 0, rc = RT3D_OK;
     const int R = c->ng_order + 2;
@@ -803,6 +817,7 @@ int rt3d_solve_to_convergence(rt3d_ctx *c, double tol, int max_iter, int inner_s
             if (nh - 1 >= c->ng_every) {
                 rc = ng_step(c, (nh - 1) % R);
                 if (rc) break;
+                if (!c->history.empty()) c->history.back().flags |= 2;
                 HIP_TRY(c, hipMemcpyAsync(c->ng_hist, c->J, vbytes, hipMemcpyDeviceToDevice, c->stream),
                         "ng hist");
                 nh = 1;
@@ -859,6 +874,18 @@ int rt3d_set_timing(rt3d_ctx *c, int enable)
     return RT3D_OK;
 }
 
+int rt3d_get_history(rt3d_ctx *c, double *c_out, double *ms_out, int *flags_out, int max_n)
+{
+    if (!c || max_n < 0) return RT3D_ERR_ARG;
+    const int n = int(c->history.size());
+    for (int q = 0; q < n && q < max_n; ++q) {
+        if (c_out) c_out[q] = c->history[q].c;
+        if (ms_out) ms_out[q] = c->history[q].ms;
+        if (flags_out) flags_out[q] = c->history[q].flags;
+    }
+    return n;
+}
+
 int rt3d_get_stats(rt3d_ctx *c, char *buf, int buflen)
 {
     if (!c || !buf || buflen < 2) return RT3D_ERR_ARG;
@@ -905,6 +932,7 @@ int rt3d_set_sweep_shape(rt3d_ctx *c, int shape)
 int rt3d_autotune(rt3d_ctx *c, const char *cache_path, int repeats, int *shape_out, double *ms_out)
 {
     if (!c) return RT3D_ERR_ARG;
+    TraceRange tr("rt3d_autotune");
     if (!c->have_medium) return fail(c, RT3D_ERR_STATE, "set the medium first");
     if (repeats < 1) return fail(c, RT3D_ERR_ARG, "repeats must be >= 1");
     const int ns = n_sweep_shapes();

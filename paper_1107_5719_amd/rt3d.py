@@ -40,7 +40,7 @@ EXPORTED = [
     "rt3d_formal_solution", "rt3d_build_lstar", "rt3d_get_lstar", "rt3d_os_step",
     "rt3d_solve_to_convergence", "rt3d_set_acceleration", "rt3d_get_emergent_top", "rt3d_set_timing", "rt3d_get_stats",
     "rt3d_status_str", "rt3d_last_error", "rt3d_quadrature", "rt3d_segment_table", "rt3d_validate",
-    "rt3d_adjoint_emergent", "rt3d_sweep_shapes", "rt3d_set_sweep_shape", "rt3d_autotune",
+    "rt3d_adjoint_emergent", "rt3d_get_history", "rt3d_sweep_shapes", "rt3d_set_sweep_shape", "rt3d_autotune",
     "rt3d_batch_create", "rt3d_batch_destroy", "rt3d_batch_size", "rt3d_batch_last_error",
     "rt3d_batch_set_medium", "rt3d_batch_set_J", "rt3d_batch_get_J", "rt3d_batch_get_Jfs",
     "rt3d_batch_set_acceleration", "rt3d_batch_set_sweep_shape", "rt3d_batch_formal_solution",
@@ -84,6 +84,7 @@ _sig = {
     "rt3d_quadrature": (_i, [_i, _i, _vp, _vp, _vp, _vp]),
     "rt3d_segment_table": (_i, [C.POINTER(GridDesc), _i, _i, _vp, _vp, _vp, _i]),
     "rt3d_validate": (_i, [C.POINTER(GridDesc), _vp, _vp, _vp]),
+    "rt3d_get_history": (_i, [_vp, _vp, _vp, _vp, _i]),
     "rt3d_adjoint_emergent": (_i, [_vp, _vp, _d, _i, _i, _vp, _vp, _i, C.POINTER(_i), C.POINTER(_d)]),
     "rt3d_sweep_shapes": (_i, [_vp, _vp, _i]),
     "rt3d_set_sweep_shape": (_i, [_vp, _i]),
@@ -260,6 +261,27 @@ def rt3d_get_stats(ctx) -> dict:
     buf = C.create_string_buffer(8192)
     _raise(ctx, _lib.rt3d_get_stats(ctx, buf, len(buf)), "rt3d_get_stats")
     return json.loads(buf.value.decode())
+
+
+def rt3d_get_history(ctx) -> dict:
+    """The per-step record (see include/rt3d.h): arrays max_rel_dJ, ms, float64_fs, ng."""
+    n = _lib.rt3d_get_history(ctx, None, None, None, 0)
+    _raise(ctx, min(n, 0), "rt3d_get_history")
+    c = np.zeros(n)
+    ms = np.zeros(n)
+    fl = np.zeros(n, dtype=np.int32)
+    _lib.rt3d_get_history(ctx, c.ctypes.data_as(_vp), ms.ctypes.data_as(_vp), fl.ctypes.data_as(_vp), n)
+    return {"max_rel_dJ": c, "ms": ms, "float64_fs": (fl & 1) != 0, "ng": (fl & 2) != 0}
+
+
+def write_history_jsonl(path, history: dict, **extra):
+    """One JSON object per step ({"step", "max_rel_dJ", "ms", "float64_fs", "ng", **extra}), appended."""
+    with open(path, "a") as f:
+        for q in range(len(history["max_rel_dJ"])):
+            rec = {"step": q + 1, "max_rel_dJ": float(history["max_rel_dJ"][q]), "ms": float(history["ms"][q]),
+                   "float64_fs": bool(history["float64_fs"][q]), "ng": bool(history["ng"][q])}
+            rec.update(extra)
+            f.write(json.dumps(rec) + "\n")
 
 
 def rt3d_status_str(status: int) -> str:
@@ -492,8 +514,15 @@ class Solver:
     def os_step(self, inner_sweeps):
         return rt3d_os_step(self.ctx, inner_sweeps)
 
-    def solve(self, tol, max_iter, inner_sweeps):
-        return rt3d_solve_to_convergence(self.ctx, tol, max_iter, inner_sweeps)
+    def solve(self, tol, max_iter, inner_sweeps, log_path=None):
+        """rt3d_solve_to_convergence; with log_path the per-step record is appended there as JSONL."""
+        out = rt3d_solve_to_convergence(self.ctx, tol, max_iter, inner_sweeps)
+        if log_path is not None:
+            write_history_jsonl(log_path, self.history(), inner_sweeps=int(inner_sweeps))
+        return out
+
+    def history(self):
+        return rt3d_get_history(self.ctx)
 
     def set_acceleration(self, ng_order, ng_every):
         rt3d_set_acceleration(self.ctx, ng_order, ng_every)

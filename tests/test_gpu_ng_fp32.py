@@ -153,3 +153,29 @@ def test_fp32_form_reaches_fp64_accuracy(R, orc, eps0):
     assert e32 < 1e-8
     assert e32 < 20 * e64 + 1e-10
     assert st32["fp32_sweeps"] > st32["fp64_sweeps"]
+
+
+def test_step_history_and_jsonl_log(R, tmp_path):
+    """The per-step record of a solve: one entry per step, the float64-anchored steps of the FP32
+    form flagged (as many as the context counted), Ng extrapolations flagged, the last entry's c the
+    solve's, and the JSONL log one line per step."""
+    import json
+
+    from paper_1107_5719_amd.inputs import random_medium
+
+    m = random_medium(9, 8, 7, seed=41, chi_range=(1e-2, 10.0), eps_range=(1e-3, 0.1))
+    log = tmp_path / "steps.jsonl"
+    with R.Solver(9, 8, 7, 4, 8, precision=R.RT3D_FP32_SWEEP) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        s.set_acceleration(2, 4)
+        before = s.stats()["fp64_sweeps"]
+        st, it, c = s.solve(1e-10, 2000, 6, log_path=str(log))
+        h = s.history()
+        stats = s.stats()
+    assert st == R.RT3D_OK
+    assert len(h["max_rel_dJ"]) == it and h["max_rel_dJ"][-1] == c
+    assert int(h["float64_fs"].sum()) == stats["fp64_sweeps"] - before >= 1
+    assert h["float64_fs"][0] and h["float64_fs"][-1]         # the first step anchors; the last is accepted
+    assert h["ng"].sum() >= 1 and (h["ms"] > 0).all()
+    lines = [json.loads(x) for x in log.read_text().splitlines()]
+    assert len(lines) == it and lines[-1]["max_rel_dJ"] == c and lines[0]["inner_sweeps"] == 6
