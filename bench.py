@@ -30,7 +30,7 @@ ALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 # adds) ~ 140 FP64 or ~80 FP32 vector operations, each priced as an FMA (2 flops).
 SWEEP_OPS_PER_UPDATE = {"fp64": 140, "fp32": 80}
 SWEEP_KERNEL = {"fp64": "sweep_kernel<double,512,2>", "fp32": "sweep_kernel<float,512,2>"}
-JACOBI_KERNEL = {"fp64": "jacobi_kernel_grouped<double>", "fp32": "jacobi_kernel_grouped<float>"}
+JACOBI_KERNEL = {"fp64": "jacobi_kernel_column<double>", "fp32": "jacobi_kernel_column<float>"}
 
 
 def sweep_bytes_per_update(precision: str) -> int:
@@ -42,9 +42,10 @@ def sweep_bytes_per_update(precision: str) -> int:
 
 
 def jacobi_bytes_per_voxel(precision: str) -> int:
-    """Algorithmic HBM bytes of one Jacobi sweep per voxel: 13 stored coefficients (the other 13 are
-    their mirrors), chi, r, 1/D, E, the previous (1-eps) dJ and the new one."""
-    return 13 * (8 if precision == "fp64" else 4) + 6 * 8
+    """Algorithmic HBM bytes of one intermediate Jacobi sweep per voxel: 13 stored coefficients (the
+    other 13 are their mirrors), the right-hand side chi (J_fs - J), E = (1 - eps)/D, the previous
+    (1 - eps) dJ and the new one (float64 but for the coefficients of the FP32 form)."""
+    return 13 * (8 if precision == "fp64" else 4) + 4 * 8
 
 
 def measured_traffic(kernel: str):

@@ -289,6 +289,7 @@ int adjoint_os_step(rt3d_ctx *c, int M, double *dmax, double *numax, int *bad)
     w.P = c->P;
     w.Iem = nullptr;
     w.Iem_base = nullptr;
+    w.xtab = c->xtab;
     const size_t smem = 2 * size_t(c->plan.max_win_rows) * c->g.nx * sizeof(double);
     const dim3 grid(c->plan.items.size());
     with_sweep_shape(c->sweep_shape, [&](auto tag) {
@@ -300,7 +301,7 @@ int adjoint_os_step(rt3d_ctx *c, int M, double *dmax, double *numax, int *bad)
     ReduceArgs ra{};
     ra.nx = c->g.nx; ra.ny = c->g.ny; ra.nz = c->g.nz; ra.n_pair = c->plan.n_pair;
     ra.pairs = c->pairs; ra.row_min = c->row_min; ra.P = c->P; ra.chi = c->chi;
-    ra.J = c->adj_nu; ra.base = c->adj_f; ra.Jfs = c->adj_fs; ra.r = c->adj_r;
+    ra.J = c->adj_nu; ra.base = c->adj_f; ra.Jfs = c->adj_fs; ra.rb = c->adj_r;
     hipLaunchKernelGGL(reduce_kernel<double>, planes(c), dim3(kPlaneThreads), 0, c->stream, ra);
     if ((rc = check_launch(c, "reduce_kernel (adjoint)"))) return rc;
     HIP_TRY(c, hipMemsetAsync(c->d_maxrel, 0, sizeof(unsigned long long), c->stream), "memset");
@@ -313,7 +314,7 @@ int adjoint_os_step(rt3d_ctx *c, int M, double *dmax, double *numax, int *bad)
         const bool last = m == M - 1;
         JacobiArgs ja{};
         ja.nx = c->g.nx; ja.ny = c->g.ny; ja.nz = c->g.nz;
-        ja.r = c->adj_r; ja.chi = c->chi;
+        ja.b = c->adj_r;
         ja.Kc = f32 ? static_cast<const void *>(c->Kc32) : static_cast<const void *>(c->Kc);
         ja.invD = c->invD; ja.E = c->Ecoef;
         ja.w_in = in;
@@ -321,10 +322,7 @@ int adjoint_os_step(rt3d_ctx *c, int M, double *dmax, double *numax, int *bad)
         ja.J = last ? c->adj_nu : nullptr;
         ja.maxrel = c->d_maxrel; ja.maxdist = c->d_maxdist; ja.nonfinite = c->d_flag;
         ja.abs_measure = 1;
-        if (f32)
-            hipLaunchKernelGGL(jacobi_kernel<float>, planes(c), dim3(kPlaneThreads), 0, c->stream, ja);
-        else
-            hipLaunchKernelGGL(jacobi_kernel<double>, planes(c), dim3(kPlaneThreads), 0, c->stream, ja);
+        launch_jacobi_sweep(ja, c->jacobi_xcd, f32, c->stream);
         if ((rc = check_launch(c, "jacobi_kernel (adjoint)"))) return rc;
         in = ja.w_out;
     }

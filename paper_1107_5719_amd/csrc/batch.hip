@@ -146,14 +146,16 @@ __global__ void clear_scalars_kernel(int n, const MemberScalars *sc)
     *sc[m].flag = 0;
 }
 
+// Jacobi sweep of the members, column form (b.k is the column layer of kJacCol planes)
 template <typename coef>
-__global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel_batch(const JacobiArgs *args, const PlaneBlock *blocks,
-                                                                     const MemberState *st)
+__global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel_batch_column(const JacobiArgs *args,
+                                                                            const PlaneBlock *blocks,
+                                                                            const MemberState *st)
 {
     const PlaneBlock b = blocks[blockIdx.x];
     if (st[b.member].mode == 0) return;
     const JacobiArgs a = args[b.member];
-    jacobi_body<coef>(a, b.chunk * kPlaneThreads + threadIdx.x, b.k);
+    jacobi_column_body<coef>(a, b.chunk * kPlaneThreads + threadIdx.x, b.k);
 }
 
 // The stopping rule of the single-problem solve, per member: a step whose max |dJ|/|J| is below tol
@@ -277,8 +279,8 @@ struct rt3d_batch {
     JacobiArgs *d_jac = nullptr;       // [M][n]
     int jac_M = 0;
     BatchItem *d_items = nullptr;
-    PlaneBlock *d_planes = nullptr, *d_planes_xcd = nullptr;
-    int n_items = 0, n_planes = 0, n_planes_xcd = 0;
+    PlaneBlock *d_planes = nullptr, *d_columns = nullptr;
+    int n_items = 0, n_planes = 0, n_columns = 0;
     size_t smem64 = 0, smem32 = 0;
     long max_V = 0;
     bool tables_ok = false;            // argument arrays and block tables match the members
@@ -337,7 +339,7 @@ void free_tables(rt3d_batch *b)
     drop_graph(b);
     bfree(b->d_state); bfree(b->d_params); bfree(b->d_scalars);
     bfree(b->d_src); bfree(b->d_sw); bfree(b->d_red); bfree(b->d_copy); bfree(b->d_ng); bfree(b->d_jac);
-    bfree(b->d_items); bfree(b->d_planes); bfree(b->d_planes_xcd);
+    bfree(b->d_items); bfree(b->d_planes); bfree(b->d_columns);
     b->jac_M = 0;
     b->tables_ok = false;
 }
@@ -364,7 +366,7 @@ int build_tables(rt3d_batch *b)
     std::vector<NgArgs> ng(n);
     std::vector<MemberScalars> sc(n);
     std::vector<std::pair<double, BatchItem>> work;
-    std::vector<PlaneBlock> planes, planes_xcd;
+    std::vector<PlaneBlock> planes, columns;
     const SweepShape sh = kSweepShapes[b->shape];
     b->smem64 = b->smem32 = 0;
     b->max_V = 0;
@@ -391,6 +393,7 @@ int build_tables(rt3d_batch *b)
             s.P = c->P;
             s.Iem = c->Iem;
             s.Iem_base = diff ? c->Iem_a : nullptr;
+            s.xtab = c->xtab;
         }
         for (int v = 0; v < 3; ++v) {
             ReduceArgs &a = red[v * n + i];
@@ -398,7 +401,7 @@ int build_tables(rt3d_batch *b)
             a.pairs = c->pairs; a.row_min = c->row_min; a.P = c->P; a.chi = c->chi;
             a.J = c->J; a.Jfs = c->Jfs;
             a.base = v == 1 ? c->Fa : nullptr;
-            a.r = v == 2 ? nullptr : c->r;
+            a.rb = v == 2 ? nullptr : c->r;
         }
         CopyArgs &k = cp[i];
         k.V = c->V;
@@ -421,16 +424,17 @@ int build_tables(rt3d_batch *b)
         const int chunks = (nx * ny + kPlaneThreads - 1) / kPlaneThreads;
         for (int z = 0; z < nz; ++z)
             for (int ch = 0; ch < chunks; ++ch) planes.push_back(PlaneBlock{i, ch, z, 0});
-        // XCD-aware order (as in the single-problem Jacobi grid): each member starts on a multiple of
-        // 8 blocks; block b of the member runs on XCD b % 8, which takes the contiguous chunk range
-        // [xcd * G, (xcd + 1) * G) of every plane (G = chunks padded to 8, / 8); padding blocks have
-        // no voxels
-        while (planes_xcd.size() % 8) planes_xcd.push_back(PlaneBlock{i, chunks, 0, 0});
+        // the Jacobi sweep's column layers, XCD-aware as in the single-problem grid: each member starts
+        // on a multiple of 8 blocks; block b of the member runs on XCD b % 8, which takes the contiguous
+        // chunk range [xcd * G, (xcd + 1) * G) of every column layer (G = chunks padded to 8, / 8);
+        // padding blocks have no voxels
         const int group = (chunks + 7) / 8;
-        for (int bl = 0; bl < 8 * group * nz; ++bl) {
+        while (columns.size() % 8) columns.push_back(PlaneBlock{i, chunks, 0, 0});
+        const int layers = (nz + kJacCol - 1) / kJacCol;
+        for (int bl = 0; bl < 8 * group * layers; ++bl) {
             const int xcd = bl & 7, slot = bl >> 3;
-            const int z = slot / group;
-            planes_xcd.push_back(PlaneBlock{i, xcd * group + (slot - z * group), z, 0});
+            const int kc = slot / group;
+            columns.push_back(PlaneBlock{i, xcd * group + (slot - kc * group), kc, 0});
         }
     }
     // dispatch the most expensive bands of all members first
@@ -444,13 +448,13 @@ int build_tables(rt3d_batch *b)
     chk(bupload(b, b->d_src, src)); chk(bupload(b, b->d_sw, sw)); chk(bupload(b, b->d_red, red));
     chk(bupload(b, b->d_copy, cp)); chk(bupload(b, b->d_ng, ng)); chk(bupload(b, b->d_scalars, sc));
     chk(bupload(b, b->d_items, items)); chk(bupload(b, b->d_planes, planes));
-    chk(bupload(b, b->d_planes_xcd, planes_xcd));
+    chk(bupload(b, b->d_columns, columns));
     if (rc) return rc;
     if (!b->d_state) BHIP_TRY(b, hipMalloc(reinterpret_cast<void **>(&b->d_state), n * sizeof(MemberState)), "hipMalloc");
     if (!b->d_params) BHIP_TRY(b, hipMalloc(reinterpret_cast<void **>(&b->d_params), sizeof(BatchParams)), "hipMalloc");
     b->n_items = int(items.size());
     b->n_planes = int(planes.size());
-    b->n_planes_xcd = int(planes_xcd.size());
+    b->n_columns = int(columns.size());
     bfree(b->d_jac);
     b->jac_M = 0;
     b->tables_ok = true;
@@ -488,7 +492,7 @@ int build_jacobi_args(rt3d_batch *b, int M)
             double *out = last ? nullptr : bufs[s & 1];
             JacobiArgs &a = ja[size_t(s) * n + i];
             a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
-            a.r = c->r; a.chi = c->chi; a.w_in = in; a.w_out = out;
+            a.b = c->r; a.w_in = in; a.w_out = out;
             a.Kc = f32 ? static_cast<const void *>(c->Kc32) : static_cast<const void *>(c->Kc);
             a.invD = c->invD; a.E = c->Ecoef;
             a.J = last ? c->J : nullptr;
@@ -571,11 +575,11 @@ int enqueue_iteration(rt3d_batch *b, int M)
     for (int s = 0; s < M; ++s) {
         const JacobiArgs *args = b->d_jac + size_t(s) * n;
         if (f32)
-            hipLaunchKernelGGL(jacobi_kernel_batch<float>, dim3(b->n_planes_xcd), dim3(kPlaneThreads), 0,
-                               b->stream, args, b->d_planes_xcd, b->d_state);
+            hipLaunchKernelGGL(jacobi_kernel_batch_column<float>, dim3(b->n_columns), dim3(kPlaneThreads), 0,
+                               b->stream, args, b->d_columns, b->d_state);
         else
-            hipLaunchKernelGGL(jacobi_kernel_batch<double>, dim3(b->n_planes_xcd), dim3(kPlaneThreads), 0,
-                               b->stream, args, b->d_planes_xcd, b->d_state);
+            hipLaunchKernelGGL(jacobi_kernel_batch_column<double>, dim3(b->n_columns), dim3(kPlaneThreads), 0,
+                               b->stream, args, b->d_columns, b->d_state);
         if ((rc = launch_check(b, "jacobi_kernel_batch"))) return rc;
     }
     hipLaunchKernelGGL(ctl_post_kernel, ctl, ctl_t, 0, b->stream, n, b->d_state, b->d_params, b->d_scalars);

@@ -28,14 +28,15 @@ struct rt3d_ctx {
     int lstar_early_exit = 0;
     int sweep_shape = 0;       // index into kSweepShapes
     int sweep_prefetch = 0;
-    int jacobi_xcd = 2;        // Jacobi grid: 0 plain, 1 chunks padded to 8 per plane, 2 contiguous chunk
-                               // ranges per XCD (default), 3 2D tiles (RT3D_JACOBI_XCD)
+    int jacobi_xcd = 4;        // Jacobi grid: 0 plain, 1 chunks padded to 8 per plane, 2 contiguous chunk
+                               // ranges per XCD, 3 2D tiles, 4 columns (default) (RT3D_JACOBI_XCD)
     // device buffers (owned)
     double *chi = nullptr, *eps = nullptr, *B = nullptr, *J = nullptr, *Jfs = nullptr, *r = nullptr;
     double *dJa = nullptr, *dJb = nullptr, *L = nullptr, *Iem = nullptr;
     double *Kc = nullptr, *invD = nullptr, *Ecoef = nullptr;   // Jacobi coefficients (float64 form)
     double *Sbuf = nullptr;
     double *bot_slope = nullptr;        // [ny][nx] LTE-diffusion gradient (bottom_bc 2)
+    double *xtab = nullptr;             // [64] 2^(j/64) for the float64 exponential of the sweep
     void *cs = nullptr, *P = nullptr;       // sized for float64; float sweeps use the first half
     double *seg_len64 = nullptr;
     float *seg_len32 = nullptr;

@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "geometry.h"
 
 using rt3d::DirInfo;
@@ -42,33 +44,36 @@ template <typename real> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
 
-// e^x - 1 for x <= 0 (the argument is always -dtau).  Write x = k ln2 + r with |r| <= ln2/2; then
-// e^x - 1 = 2^k (e^r - 1) + (2^k - 1), and e^r - 1 is its Taylor series (through r^13 in float64,
-// truncation below 2e-17 relative; through r^8 in float32, below 1e-9).  ln2 is split into a high part
-// whose product with k is exact and a low part.  No range branches: x is clamped where e^x vanishes.
-__device__ inline double expm1_nonpos(double x)
+// e^x - 1 for x <= 0 (the argument is always -dtau).  No range branches: x is clamped where e^x
+// vanishes.  ln2 is split into a high part whose product with the reduction multiple is exact and a
+// low part.
+//
+// float64, Tang's table method: x = (64 k + j) ln2/64 + r with 0 <= j < 64 and |r| <= ln2/128, so
+// e^x - 1 = 2^k T_j (1 + r p(r)) - 1 with T_j = 2^(j/64) read from a table and p the Taylor polynomial
+// of (e^r - 1)/r through r^5 (truncation below 1e-17 relative).  2^k T_j - 1 is exact when
+// 2^k T_j >= 1/2 and is far from zero otherwise; the rounding of T_j bounds the relative error by
+// about 5e-15 where the result is small (|x| just above ln2/128), and below ln2/128 the result is
+// r p(r) itself.
+constexpr int kExpTab = 64;
+__device__ inline double expm1_nonpos_tab(double x, const double *tab)
 {
     x = fmax(x, -708.0);
-    const double kf = rint(x * 1.4426950408889634);
-    double r = fma(-kf, 6.93147180369123816490e-01, x);
-    r = fma(-kf, 1.90821492927058770002e-10, r);
-    double p = 1.0 / 6227020800.0;
-    p = fma(p, r, 1.0 / 479001600.0);
-    p = fma(p, r, 1.0 / 39916800.0);
-    p = fma(p, r, 1.0 / 3628800.0);
-    p = fma(p, r, 1.0 / 362880.0);
-    p = fma(p, r, 1.0 / 40320.0);
-    p = fma(p, r, 1.0 / 5040.0);
-    p = fma(p, r, 1.0 / 720.0);
+    const double kf = rint(x * 92.332482616893656877);          // 64 / ln2
+    double r = fma(-kf, 6.93147180369123816490e-01 / 64, x);
+    r = fma(-kf, 1.90821492927058770002e-10 / 64, r);
+    const int n = int(kf);
+    double p = 1.0 / 720.0;
     p = fma(p, r, 1.0 / 120.0);
     p = fma(p, r, 1.0 / 24.0);
     p = fma(p, r, 1.0 / 6.0);
     p = fma(p, r, 0.5);
     p = fma(p, r, 1.0);
-    const double two_k = ldexp(1.0, int(kf));
-    return fma(two_k, p * r, two_k - 1.0);
+    const double s = ldexp(tab[n & (kExpTab - 1)], n >> 6);
+    return fma(s, p * r, s - 1.0);
 }
 
+// float32: x = k ln2 + r with |r| <= ln2/2; e^x - 1 = 2^k (e^r - 1) + (2^k - 1), and e^r - 1 is its
+// Taylor series through r^8 (truncation below 1e-9 relative).
 __device__ inline float expm1_nonpos(float x)
 {
     x = fmaxf(x, -87.0f);
@@ -140,7 +145,11 @@ struct SweepArgs {
     void *P;                      // real
     double *Iem;                  // [n_up][ny][nx] or null
     const double *Iem_base;       // added to Iem in difference mode (or null)
+    const double *xtab;           // [kExpTab] 2^(j/64), the float64 exponential's table
 };
+
+__device__ inline double expm1_sweep(double x, const double *tab) { return expm1_nonpos_tab(x, tab); }
+__device__ inline float expm1_sweep(float x, const double *) { return expm1_nonpos(x); }
 
 // One workgroup sweeps the lines of one band for both directions of an x-mirrored pair.  Thread t
 // owns lines q = t + i*NT (i < LPT) of the band, for both directions.  Per layer and segment index s
@@ -168,6 +177,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
     real *P = static_cast<real *>(a.P) + pi.p_off + long(it.band) * nz * wsize;
 
     for (int e = threadIdx.x; e < 2 * wsize; e += NT) winA[e] = real(0);
+    __shared__ double xtab[kExpTab];
+    if (std::is_same<real, double>::value && threadIdx.x < kExpTab) xtab[threadIdx.x] = a.xtab[threadIdx.x];
 
     real IA[LPT], IB[LPT];
     int li[LPT], lj[LPT];
@@ -246,14 +257,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
                 const unsigned wrow = lbase[t] + unsigned(g.sbnx);
                 {
                     const real dtau = cA[t].x * len;
-                    const real em1 = expm1_nonpos(-dtau);          // e^{-dtau} - 1
+                    const real em1 = expm1_sweep(-dtau, xtab);     // e^{-dtau} - 1
                     const real dI = (IA[t] - cA[t].y) * em1;
                     IA[t] += dI;
                     winA[wrow + colA[t]] += cA[t].y * dtau - dI;   // chi * integral of I
                 }
                 {
                     const real dtau = cB[t].x * len;
-                    const real em1 = expm1_nonpos(-dtau);
+                    const real em1 = expm1_sweep(-dtau, xtab);
                     const real dI = (IB[t] - cB[t].y) * em1;
                     IB[t] += dI;
                     winB[wrow + colB[t]] += cB[t].y * dtau - dI;
@@ -304,7 +315,7 @@ struct ReduceArgs {
     const double *J;          // for r = J_fs - J (may be null)
     const double *base;       // difference mode: J_fs of the anchor, added (may be null)
     double *Jfs;
-    double *r;                // may be null
+    double *rb;               // chi (J_fs - J), the right-hand side of the OS step (may be null)
 };
 
 // J_fs(v) = (1/chi_v) sum_pairs W|mu| sum over the bands whose deposit windows cover v.  The band of
@@ -353,7 +364,7 @@ __device__ inline void reduce_body(const ReduceArgs &a, int p, int k)
     const long v = long(k) * nx * ny + p;
     const double Jfs = a.base ? a.base[v] + acc / a.chi[v] : acc / a.chi[v];
     a.Jfs[v] = Jfs;
-    if (a.r) a.r[v] = Jfs - a.J[v];
+    if (a.rb) a.rb[v] = a.chi[v] * (Jfs - a.J[v]);
 }
 
 template <typename real>
@@ -500,7 +511,7 @@ __global__ __launch_bounds__(kPlaneThreads) void coef_kernel(int nx, int ny, int
 // evaluated as (chi_v r_v + sum_u K_vu w_u) invD_v with w = (1 - eps) dJ carried between sweeps.
 struct JacobiArgs {
     int nx, ny, nz;
-    const double *r, *chi;
+    const double *b;             // chi (J_fs - J_old): the right-hand side of the chi-scaled system
     const void *Kc;              // [13][V] upper coefficients (double, or float in the FP32 form)
     const double *invD, *E;
     const double *w_in;          // (1 - eps) dJ of the previous sweep; null: dJ^0 = 0 (first sweep)
@@ -513,19 +524,61 @@ struct JacobiArgs {
     int abs_measure;             // 1: maxrel receives max |dJ| and maxdist max |J| (iterates that may vanish)
 };
 
+// Block max of q and of the anchor distance into maxrel / maxdist (as integer bits: non-negative
+// doubles order like integers); NaN/Inf raise the flag.  The whole block must call this.
+__device__ inline void jacobi_block_max(const JacobiArgs &a, double q, double dist, bool bad)
+{
+    if (bad) { atomicOr(a.nonfinite, 1); q = 0.0; dist = 0.0; }
+    for (int offs = 32; offs > 0; offs >>= 1) {
+        q = fmax(q, __shfl_xor(q, offs));
+        dist = fmax(dist, __shfl_xor(dist, offs));
+    }
+    __shared__ double wmax[2][kPlaneThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { wmax[0][wid] = q; wmax[1][wid] = dist; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = wmax[0][0], md = wmax[1][0];
+        for (int w = 1; w < kPlaneThreads / 64; ++w) { m = fmax(m, wmax[0][w]); md = fmax(md, wmax[1][w]); }
+        atomicMax(a.maxrel, static_cast<unsigned long long>(__double_as_longlong(m)));
+        if (a.Ja || a.abs_measure) atomicMax(a.maxdist, static_cast<unsigned long long>(__double_as_longlong(md)));
+    }
+}
+
+// The last sweep of a step: J += dJ, and the convergence measures of voxel v folded into q / dist.
+__device__ inline void jacobi_update(const JacobiArgs &a, long v, double acc, double &q, double &dist, bool &bad)
+{
+    const double dJ = acc * a.invD[v];
+    const double Jn = a.J[v] + dJ;
+    a.J[v] = Jn;
+    double qv, dv = 0.0;
+    if (a.abs_measure) {
+        qv = fabs(dJ);
+        dv = fabs(Jn);
+    } else {
+        qv = fabs(dJ) / fabs(Jn);
+        if (a.Ja) dv = fabs(Jn - a.Ja[v]) / fabs(Jn);
+    }
+    if (!isfinite(Jn) || !isfinite(qv)) {
+        bad = true;
+    } else {
+        q = fmax(q, qv);
+        dist = fmax(dist, dv);
+    }
+}
+
 // Arithmetic is float64 for either coefficient type.
 // The whole block must call this (it ends with a block reduction when J is updated).
 template <typename coef>
 __device__ inline void jacobi_core(const JacobiArgs &a, int i, int j, int k, bool valid)
 {
     const coef *Kc = static_cast<const coef *>(a.Kc);
-    double dist = 0.0;
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    double q = 0.0;
+    double q = 0.0, dist = 0.0;
     bool bad = false;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
     if (valid) {
         const long plane = long(nx) * ny, V = plane * nz, v = k * plane + long(j) * nx + i;
-        double acc = a.chi[v] * a.r[v];
+        double acc = a.b[v];
         if (a.w_in) {
             const int im = (i == 0) ? nx - 1 : i - 1, ip = (i == nx - 1) ? 0 : i + 1;
             const int jm = (j == 0) ? ny - 1 : j - 1, jp = (j == ny - 1) ? 0 : j + 1;
@@ -546,37 +599,9 @@ __device__ inline void jacobi_core(const JacobiArgs &a, int i, int j, int k, boo
             acc += (k > 0 ? part[0] : 0.0) + part[1] + part[2];
         }
         if (a.w_out) a.w_out[v] = acc * a.E[v];
-        if (a.J) {
-            const double dJ = acc * a.invD[v];
-            const double Jn = a.J[v] + dJ;
-            a.J[v] = Jn;
-            if (a.abs_measure) {
-                q = fabs(dJ);
-                dist = fabs(Jn);
-            } else {
-                q = fabs(dJ) / fabs(Jn);
-                if (a.Ja) dist = fabs(Jn - a.Ja[v]) / fabs(Jn);
-            }
-            bad = !isfinite(Jn) || !isfinite(q);
-        }
+        if (a.J) jacobi_update(a, v, acc, q, dist, bad);
     }
-    if (!a.J) return;
-    // block max of q (and of the anchor distance); NaN/Inf raise the flag
-    if (bad) { atomicOr(a.nonfinite, 1); q = 0.0; dist = 0.0; }
-    for (int offs = 32; offs > 0; offs >>= 1) {
-        q = fmax(q, __shfl_xor(q, offs));
-        dist = fmax(dist, __shfl_xor(dist, offs));
-    }
-    __shared__ double wmax[2][kPlaneThreads / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) { wmax[0][wid] = q; wmax[1][wid] = dist; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = wmax[0][0], md = wmax[1][0];
-        for (int w = 1; w < kPlaneThreads / 64; ++w) { m = fmax(m, wmax[0][w]); md = fmax(md, wmax[1][w]); }
-        atomicMax(a.maxrel, static_cast<unsigned long long>(__double_as_longlong(m)));
-        if (a.Ja || a.abs_measure) atomicMax(a.maxdist, static_cast<unsigned long long>(__double_as_longlong(md)));
-    }
+    if (a.J) jacobi_block_max(a, q, dist, bad);
 }
 
 template <typename coef>
@@ -625,6 +650,108 @@ __global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel_tiled(JacobiArgs 
     const int j = ty * kTileY + (threadIdx.x / kTileX);
     const bool valid = i < a.nx && j < a.ny;
     jacobi_core<coef>(a, valid ? i : 0, valid ? j : 0, k, valid);
+}
+
+// Column form: a thread takes kJacCol voxels (i, j, k0 .. k0 + kJacCol - 1) and marches up them,
+// keeping the previous iterates of three planes in registers, so each voxel loads one new plane of
+// nine iterates instead of 26 neighbours (the coefficient streams and the per-voxel sums are those of
+// jacobi_core, in the same order).  Blocks are dealt to the XCDs in contiguous ranges of chunks per
+// column layer, as in jacobi_kernel_grouped.
+constexpr int kJacCol = 4;
+// Column layer kc of the columns p (p = j nx + i; p >= nx ny: no voxels).  The whole block must call
+// this (it ends with a block reduction when J is updated).
+template <typename coef>
+__device__ inline void jacobi_column_body(const JacobiArgs &a, int p, int kc)
+{
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const bool valid = p < nx * ny;
+    const coef *Kc = static_cast<const coef *>(a.Kc);
+    double q = 0.0, dist = 0.0;
+    bool bad = false;
+    if (valid) {
+        const int j = p / nx, i = p - j * nx, k0 = kc * kJacCol;
+        const long plane = long(nx) * ny, V = plane * nz;
+        const int im = (i == 0) ? nx - 1 : i - 1, ip = (i == nx - 1) ? 0 : i + 1;
+        const int jm = (j == 0) ? ny - 1 : j - 1, jp = (j == ny - 1) ? 0 : j + 1;
+        long off[9];              // the 3 x 3 columns around (i, j), in the stencil's order
+#pragma unroll
+        for (int m = 0; m < 9; ++m)
+            off[m] = long(m < 3 ? jm : (m < 6 ? j : jp)) * nx + (m % 3 == 0 ? im : (m % 3 == 1 ? i : ip));
+        double Wm[9], W0[9], Wp[9];   // iterates of the planes k - 1 (clamped), k, k + 1 (clamped)
+        if (a.w_in) {
+            const long km = k0 > 0 ? k0 - 1 : 0;
+#pragma unroll
+            for (int m = 0; m < 9; ++m) {
+                Wm[m] = a.w_in[km * plane + off[m]];
+                W0[m] = a.w_in[long(k0) * plane + off[m]];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < kJacCol; ++t) {
+            const int k = k0 + t;
+            if (k >= nz) break;
+            const long kp = k < nz - 1 ? k + 1 : k;
+            const long v = k * plane + off[4];
+            double acc = a.b[v];
+            if (a.w_in) {
+#pragma unroll
+                for (int m = 0; m < 9; ++m) Wp[m] = a.w_in[kp * plane + off[m]];
+                const long pls[3] = {(k > 0 ? k - 1 : 0) * plane, long(k) * plane, kp * plane};
+                double part[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int o = 0; o < 27; ++o) {
+                    if (o == 13) continue;
+                    const long u = pls[o / 9] + off[o % 9];
+                    const double K = (o > 13) ? double(Kc[(o - 14) * V + v]) : double(Kc[(12 - o) * V + u]);
+                    const double w = o < 9 ? Wm[o % 9] : (o < 18 ? W0[o % 9] : Wp[o % 9]);
+                    part[o / 9] += K * w;
+                }
+                acc += (k > 0 ? part[0] : 0.0) + part[1] + part[2];
+#pragma unroll
+                for (int m = 0; m < 9; ++m) { Wm[m] = W0[m]; W0[m] = Wp[m]; }
+            }
+            if (a.w_out) a.w_out[v] = acc * a.E[v];
+            if (a.J) jacobi_update(a, v, acc, q, dist, bad);
+        }
+    }
+    if (a.J) jacobi_block_max(a, q, dist, bad);
+}
+
+template <typename coef>
+__global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel_column(JacobiArgs a, int group)
+{
+    const int blk = blockIdx.x;
+    const int xcd = blk & 7, slot = blk >> 3;
+    const int kc = slot / group;
+    jacobi_column_body<coef>(a, (xcd * group + (slot - kc * group)) * kPlaneThreads + threadIdx.x, kc);
+}
+
+// One Jacobi sweep in the given grid layout: 0 one block per chunk of a plane, 1 the same padded to
+// a multiple of 8 chunks per plane, 2 contiguous chunk ranges per XCD, 3 2D tiles, 4 columns.
+inline void launch_jacobi_sweep(const JacobiArgs &a, int layout, bool f32, hipStream_t stream)
+{
+    const int chunks = (a.nx * a.ny + kPlaneThreads - 1) / kPlaneThreads;
+    const int group = (chunks + 7) / 8;
+    const dim3 blk(kPlaneThreads);
+    if (layout == 4) {
+        const dim3 grid(unsigned(8 * group) * unsigned((a.nz + kJacCol - 1) / kJacCol));
+        if (f32) hipLaunchKernelGGL(jacobi_kernel_column<float>, grid, blk, 0, stream, a, group);
+        else hipLaunchKernelGGL(jacobi_kernel_column<double>, grid, blk, 0, stream, a, group);
+    } else if (layout == 3) {
+        const int tiles_x = (a.nx + kTileX - 1) / kTileX, tiles_y = (a.ny + kTileY - 1) / kTileY;
+        const int tgroup = (tiles_x * tiles_y + 7) / 8;
+        const dim3 grid(unsigned(8 * tgroup) * unsigned(a.nz));
+        if (f32) hipLaunchKernelGGL(jacobi_kernel_tiled<float>, grid, blk, 0, stream, a, tiles_x, tgroup);
+        else hipLaunchKernelGGL(jacobi_kernel_tiled<double>, grid, blk, 0, stream, a, tiles_x, tgroup);
+    } else if (layout == 2) {
+        const dim3 grid(unsigned(8 * group) * unsigned(a.nz));
+        if (f32) hipLaunchKernelGGL(jacobi_kernel_grouped<float>, grid, blk, 0, stream, a, group);
+        else hipLaunchKernelGGL(jacobi_kernel_grouped<double>, grid, blk, 0, stream, a, group);
+    } else {
+        const dim3 grid(layout == 1 ? unsigned(group * 8) : unsigned(chunks), a.nz);
+        if (f32) hipLaunchKernelGGL(jacobi_kernel<float>, grid, blk, 0, stream, a);
+        else hipLaunchKernelGGL(jacobi_kernel<double>, grid, blk, 0, stream, a);
+    }
 }
 
 // ------------------------------------------------------------------------------------------------

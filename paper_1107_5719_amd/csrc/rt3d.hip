@@ -182,6 +182,7 @@ int launch_sweep(rt3d_ctx *c, bool fp32, bool diff)
     a.P = c->P;
     a.Iem = c->Iem;
     a.Iem_base = diff ? c->Iem_a : nullptr;
+    a.xtab = c->xtab;
     const size_t smem = 2 * size_t(c->plan.max_win_rows) * c->g.nx * (fp32 ? sizeof(float) : sizeof(double));
     const dim3 grid(c->plan.items.size());
     TimedLaunch t(c, K_SWEEP);
@@ -216,7 +217,7 @@ int launch_reduce(rt3d_ctx *c, bool with_residual, bool fp32, const double *base
     ReduceArgs a{};
     a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.n_pair = c->plan.n_pair;
     a.pairs = c->pairs; a.row_min = c->row_min; a.P = c->P; a.chi = c->chi;
-    a.J = c->J; a.base = base; a.Jfs = c->Jfs; a.r = with_residual ? c->r : nullptr;
+    a.J = c->J; a.base = base; a.Jfs = c->Jfs; a.rb = with_residual ? c->r : nullptr;
     TimedLaunch t(c, K_REDUCE);
     if (!fp32)
         hipLaunchKernelGGL(reduce_kernel<double>, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
@@ -293,12 +294,14 @@ int ensure_lstar(rt3d_ctx *c)
     return RT3D_OK;
 }
 
+int launch_jacobi_args(rt3d_ctx *c, const JacobiArgs &a);
+
 int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update)
 {
     JacobiArgs a{};
     const bool f32 = c->precision == RT3D_FP32_SWEEP;
     a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
-    a.r = c->r; a.chi = c->chi; a.w_in = w_in; a.w_out = w_out;
+    a.b = c->r; a.w_in = w_in; a.w_out = w_out;
     a.Kc = f32 ? static_cast<const void *>(c->Kc32) : static_cast<const void *>(c->Kc);
     a.invD = c->invD; a.E = c->Ecoef;
     a.J = update ? c->J : nullptr;
@@ -306,31 +309,12 @@ int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update)
     a.Ja = (f32 && update) ? c->Ja : nullptr;
     a.maxdist = c->d_maxdist;
     TimedLaunch t(c, K_JACOBI);
-    if (c->jacobi_xcd == 3) {
-        const int tiles_x = (c->g.nx + kTileX - 1) / kTileX, tiles_y = (c->g.ny + kTileY - 1) / kTileY;
-        const int group = (tiles_x * tiles_y + 7) / 8;
-        const dim3 grid(unsigned(8 * group) * unsigned(c->g.nz));
-        if (f32)
-            hipLaunchKernelGGL(jacobi_kernel_tiled<float>, grid, dim3(kPlaneThreads), 0, c->stream, a, tiles_x, group);
-        else
-            hipLaunchKernelGGL(jacobi_kernel_tiled<double>, grid, dim3(kPlaneThreads), 0, c->stream, a, tiles_x, group);
-        return check_launch(c, "jacobi_kernel");
-    }
-    if (c->jacobi_xcd == 2) {
-        const int chunks = (c->g.nx * c->g.ny + kPlaneThreads - 1) / kPlaneThreads;
-        const int group = (chunks + 7) / 8;
-        const dim3 grid(unsigned(8 * group) * unsigned(c->g.nz));
-        if (f32)
-            hipLaunchKernelGGL(jacobi_kernel_grouped<float>, grid, dim3(kPlaneThreads), 0, c->stream, a, group);
-        else
-            hipLaunchKernelGGL(jacobi_kernel_grouped<double>, grid, dim3(kPlaneThreads), 0, c->stream, a, group);
-        return check_launch(c, "jacobi_kernel");
-    }
-    const dim3 grid = c->jacobi_xcd ? plane_grid_xcd(c) : plane_grid(c);
-    if (f32)
-        hipLaunchKernelGGL(jacobi_kernel<float>, grid, dim3(kPlaneThreads), 0, c->stream, a);
-    else
-        hipLaunchKernelGGL(jacobi_kernel<double>, grid, dim3(kPlaneThreads), 0, c->stream, a);
+    return launch_jacobi_args(c, a);
+}
+
+int launch_jacobi_args(rt3d_ctx *c, const JacobiArgs &a)
+{
+    launch_jacobi_sweep(a, c->jacobi_xcd, c->precision == RT3D_FP32_SWEEP, c->stream);
     return check_launch(c, "jacobi_kernel");
 }
 
@@ -360,7 +344,7 @@ void free_all(rt3d_ctx *c)
 {
     free_plan(c);
     void *ptrs[] = {c->chi, c->eps, c->B, c->J, c->Jfs, c->r, c->dJa, c->dJb, c->L, c->Kc, c->invD, c->Ecoef, c->Iem,
-                    c->Sbuf, c->bot_slope, c->cs, c->Ja, c->Fa, c->Iem_a, c->Kc32, c->d_maxdist, c->d_maxrel, c->d_flag,
+                    c->Sbuf, c->bot_slope, c->xtab, c->cs, c->Ja, c->Fa, c->Iem_a, c->Kc32, c->d_maxdist, c->d_maxrel, c->d_flag,
                     c->ng_hist, c->ng_work, c->adj_Ient, c->adj_Qx, c->adj_nu, c->adj_fs, c->adj_r,
                     c->adj_f, c->adj_pull, c->adj_g, c->adj_qs};
     for (void *p : ptrs)
@@ -465,7 +449,7 @@ int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream
     // gathers of the next segment issued before the current one is computed (RT3D_SWEEP_PREFETCH=1;
     // shapes 1 and 2 only; slower on MI355X because it costs occupancy)
     if (const char *e = std::getenv("RT3D_SWEEP_PREFETCH")) c->sweep_prefetch = std::atoi(e) != 0;
-    if (const char *e = std::getenv("RT3D_JACOBI_XCD")) c->jacobi_xcd = std::max(0, std::min(3, std::atoi(e)));
+    if (const char *e = std::getenv("RT3D_JACOBI_XCD")) c->jacobi_xcd = std::max(0, std::min(4, std::atoi(e)));
     // Lambda* walk may stop at the first non-neighbour only if no line wraps back within two layers
     {
         double tmax_x = 0.0, tmax_y = 0.0;
@@ -498,6 +482,14 @@ int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream
     chk(dev_alloc(c, &c->d_maxdist, 1));
     chk(dev_alloc(c, &c->d_maxrel, 1)); chk(dev_alloc(c, &c->d_flag, 1));
     if (g->bottom_bc == 2) chk(dev_alloc(c, &c->bot_slope, size_t(g->nx) * g->ny));
+    chk(dev_alloc(c, &c->xtab, kExpTab));
+    if (!rc) {
+        // 2^(j/64) rounded to float64 from the 64-bit-mantissa long double exp2
+        double tab[kExpTab];
+        for (int j = 0; j < kExpTab; ++j) tab[j] = double(std::exp2(static_cast<long double>(j) / kExpTab));
+        if (hipMemcpy(c->xtab, tab, sizeof(tab), hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail(c, RT3D_ERR_HIP, "upload of the exponential table");
+    }
     if (!rc) rc = install_plan(c, shape);
     if (rc) {
         msg = c->err;
