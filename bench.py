@@ -26,9 +26,13 @@ METRIC = "voxel·angle FS updates/s + time-to-converged J, 129³×256 angles, FP
 HBM_PEAK_GBS = 8000.0
 # MI355X vector peaks: 256 CUs x 2.4 GHz; FP64 78.6 TFLOP/s, FP32 157.3 TFLOP/s (FMA = 2 flops)
 ALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
-# Arithmetic per voxel-angle update of the sweep: about 4 segments x (one exponential + ~10 multiply-
-# adds) ~ 140 FP64 or ~80 FP32 vector operations, each priced as an FMA (2 flops).
-SWEEP_OPS_PER_UPDATE = {"fp64": 140, "fp32": 80}
+# Arithmetic per voxel-angle update of the sweep, counted per segment and multiplied by the mean
+# segments per voxel-angle of the 16 x 16 angle set (4.05): dtau = chi l (1); e^-dtau - 1 (float64 by
+# the 64-entry table: clamp, scale, round, 2 reduction FMAs, convert, 5 Horner FMAs, scale by 2^k,
+# r p, s - 1, final FMA = 15; float32 with 8 Horner FMAs and no table = 17); (I - S) em1 (2); I += dI
+# (1); D = S dtau - dI (1); window += D (1): 21 (float64) / 23 (float32) per segment, i.e. 85 / 93
+# vector operations per update, each priced as an FMA issue slot (2 flops).
+SWEEP_OPS_PER_UPDATE = {"fp64": 85, "fp32": 93}
 SWEEP_KERNEL = {"fp64": "sweep_kernel<double,512,2>", "fp32": "sweep_kernel<float,512,2>"}
 JACOBI_KERNEL = {"fp64": "jacobi_kernel_column<double>", "fp32": "jacobi_kernel_column<float>"}
 

@@ -120,7 +120,7 @@ int rt3d_get_lstar(rt3d_ctx *ctx, double *out, int ptr_kind);
  * solution F_a; a step sweeps the source change (1-eps)(J - Ja) in float32 with no boundary light and
  * uses J_fs = F_a + that sweep, summed in float64, so the float32 error scales with |J - Ja| rather
  * than with J.  A float64 sweep re-anchors at the current J on the first step, after rt3d_set_J or
- * rt3d_set_medium, and whenever the last step's c fell below 1e-3 of max_v |J_v - Ja_v| / |J_v|.  The
+ * rt3d_set_medium, and whenever the last step's c fell below 1e-2 of max_v |J_v - Ja_v| / |J_v|.  The
  * Jacobi coefficients are stored in float32 in this form (they only precondition; the fixed point is
  * set by the residual); the Jacobi arithmetic is float64.
  * Errors: RT3D_ERR_STATE, RT3D_ERR_ARG, RT3D_ERR_NONFINITE (J is then not trustworthy),

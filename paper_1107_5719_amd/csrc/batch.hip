@@ -85,7 +85,7 @@ __global__ void ctl_pre_kernel(int n, MemberState *st, const BatchParams *prm)
     MemberState &s = st[m];
     if (!s.active) { s.mode = 0; return; }
     if (!prm->fp32) { s.mode = 1; return; }
-    const bool refresh = !s.anchor_valid || s.force_refresh || s.c_last < kAnchorRatio * s.da_last;
+    const bool refresh = !s.anchor_valid || s.force_refresh || s.c_last < kAnchorRatioDefault * s.da_last;
     s.mode = refresh ? 1 : 2;
 }
 

@@ -15,6 +15,9 @@
 
 enum KernelId { K_SOURCE, K_SWEEP, K_REDUCE, K_LSTAR, K_COEF, K_JACOBI, K_COUNT };
 constexpr size_t kHistoryMax = 100000;   // step records kept per context
+// FP32 form: a float64 sweep re-anchors when c < ratio * max|J - Ja|/|J| (the float32 error of a
+// difference step scales with the distance travelled since the anchor)
+constexpr double kAnchorRatioDefault = 1e-2;
 static const char *kKernelNames[K_COUNT] = {"source", "sweep", "reduce", "lstar", "coef", "jacobi"};
 
 struct rt3d_ctx {
@@ -28,6 +31,7 @@ struct rt3d_ctx {
     int lstar_early_exit = 0;
     int sweep_shape = 0;       // index into kSweepShapes
     int sweep_prefetch = 0;
+    double anchor_ratio = kAnchorRatioDefault;   // FP32 form: re-anchor when c < ratio * max|J - Ja|/|J|
     int jacobi_xcd = 4;        // Jacobi grid: 0 plain, 1 chunks padded to 8 per plane, 2 contiguous chunk
                                // ranges per XCD, 3 2D tiles, 4 columns (default) (RT3D_JACOBI_XCD)
     // device buffers (owned)

@@ -37,7 +37,6 @@ inline void with_sweep_shape(int shape, F &&f)
     }
 }
 constexpr size_t kWindowBytes = 48 * 1024;   // LDS for the two deposit windows of a band
-constexpr double kAnchorRatio = 1e-3;        // FP32 form: re-anchor when c < ratio * max|J - Ja|/|J|
 constexpr int kPlaneThreads = 256;   // voxel-parallel kernels: one thread per voxel of a k-plane
 
 template <typename real> struct Vec2;

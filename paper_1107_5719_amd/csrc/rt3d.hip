@@ -450,6 +450,7 @@ int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream
     // shapes 1 and 2 only; slower on MI355X because it costs occupancy)
     if (const char *e = std::getenv("RT3D_SWEEP_PREFETCH")) c->sweep_prefetch = std::atoi(e) != 0;
     if (const char *e = std::getenv("RT3D_JACOBI_XCD")) c->jacobi_xcd = std::max(0, std::min(4, std::atoi(e)));
+    if (const char *e = std::getenv("RT3D_ANCHOR_RATIO")) c->anchor_ratio = std::max(0.0, std::atof(e));
     // Lambda* walk may stop at the first non-neighbour only if no line wraps back within two layers
     {
         double tmax_x = 0.0, tmax_y = 0.0;
@@ -728,7 +729,7 @@ int rt3d_os_step(rt3d_ctx *c, int inner_sweeps, double *max_rel_dJ_out)
         // float32 sweeps of the source change since the anchor; a float64 sweep re-anchors when the
         // step has become small next to the distance travelled since the anchor (the float32 error
         // of a difference step scales with that distance), or when asked to
-        const bool refresh = !c->anchor_valid || c->force_refresh || c->c_last < kAnchorRatio * c->da_last;
+        const bool refresh = !c->anchor_valid || c->force_refresh || c->c_last < c->anchor_ratio * c->da_last;
         rc = refresh ? refresh_anchor(c) : run_fs_difference(c);
         anchored = refresh;
     } else {

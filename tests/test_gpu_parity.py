@@ -315,3 +315,23 @@ def test_determinism_and_resume(R):
         for _ in range(3):
             s.os_step(5)
         assert np.array_equal(s.get_J(), runs[0])
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32_sweep"])
+def test_jacobi_grid_layouts_agree_bitwise(R, precision, monkeypatch):
+    """Every launch layout of the Jacobi sweep (one block per plane chunk, padded, XCD-grouped, 2D
+    tiles, columns marched in z) computes each voxel's sum in the same order, so OS steps agree
+    bitwise; the grid (nz = 10, not a multiple of the column height; 37 x 9 columns, a ragged last
+    chunk) also checks the column form's ends.  The layout is read from RT3D_JACOBI_XCD when a context
+    is created."""
+    m = random_medium(37, 9, 10, seed=77, chi_range=(1e-3, 3e1), eps_range=(1e-4, 0.3))
+    out = {}
+    for layout in range(5):
+        monkeypatch.setenv("RT3D_JACOBI_XCD", str(layout))
+        with R.Solver(37, 9, 10, 4, 8, precision=precision) as s:
+            s.set_medium(m["chi"], m["eps"], m["B"])
+            cs = [s.os_step(7) for _ in range(3)]
+            out[layout] = (s.get_J(), cs)
+    for layout in range(1, 5):
+        assert np.array_equal(out[layout][0], out[0][0]), f"layout {layout}"
+        assert out[layout][1] == out[0][1]
