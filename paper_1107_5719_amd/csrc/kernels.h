@@ -250,23 +250,35 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
             } else {
                 gather(g, cA, cB, colA, colB);
             }
+            // At one segment index the lines of a direction deposit into distinct cells (and the two
+            // directions into separate windows), so the window cells are read first, ahead of the
+            // exponentials, and written after: one LDS wait per segment index, not one per deposit.
+            real oA[LPT], oB[LPT];
+            unsigned wA[LPT], wB[LPT];
+#pragma unroll
+            for (int t = 0; t < LPT; ++t) {
+                const unsigned wrow = lbase[t] + unsigned(g.sbnx);
+                wA[t] = wrow + colA[t];
+                wB[t] = wrow + colB[t];
+                oA[t] = li[t] >= 0 ? winA[wA[t]] : real(0);
+                oB[t] = li[t] >= 0 ? winB[wB[t]] : real(0);
+            }
 #pragma unroll
             for (int t = 0; t < LPT; ++t) {
                 if (li[t] < 0) continue;
-                const unsigned wrow = lbase[t] + unsigned(g.sbnx);
                 {
                     const real dtau = cA[t].x * len;
                     const real em1 = expm1_sweep(-dtau, xtab);     // e^{-dtau} - 1
                     const real dI = (IA[t] - cA[t].y) * em1;
                     IA[t] += dI;
-                    winA[wrow + colA[t]] += cA[t].y * dtau - dI;   // chi * integral of I
+                    winA[wA[t]] = oA[t] + (cA[t].y * dtau - dI);    // chi * integral of I
                 }
                 {
                     const real dtau = cB[t].x * len;
                     const real em1 = expm1_sweep(-dtau, xtab);
                     const real dI = (IB[t] - cB[t].y) * em1;
                     IB[t] += dI;
-                    winB[wrow + colB[t]] += cB[t].y * dtau - dI;
+                    winB[wB[t]] = oB[t] + (cB[t].y * dtau - dI);
                 }
             }
             __syncthreads();
