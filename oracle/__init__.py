@@ -60,6 +60,10 @@ def lib():
         L.orc_lambda_bruteforce.argtypes = [i, i, i, i, i, _dp, _dp, i]
         L.orc_os_step.argtypes = [i, i, i, i, i, _dp, _dp, _dp, d, i, _dp, _dp, i,
                                   C.POINTER(C.c_double), C.c_void_p, i]
+        L.orc_os_step_method.argtypes = [i, i, i, i, i, _dp, _dp, _dp, d, i, _dp, _dp, i, i,
+                                         C.POINTER(C.c_double), C.c_void_p, i]
+        L.orc_os_inner.argtypes = [i, i, i, _dp, _dp, _dp, i, i, _dp]
+        L.orc_gs_colour.argtypes = [i, i, i, C.POINTER(C.c_int)]
         L.orc_solve.argtypes = [i, i, i, i, i, _dp, _dp, _dp, d, i, C.c_void_p, _dp, d, i, i,
                                 C.POINTER(C.c_int), C.POINTER(C.c_double), i]
         L.orc_solve_ng.argtypes = [i, i, i, i, i, _dp, _dp, _dp, d, i, C.c_void_p, _dp, d, i, i, i, i,
@@ -189,17 +193,39 @@ def lambda_bruteforce(chi, n_theta, n_phi, n_threads=0):
     return Lam
 
 
+OS_JACOBI, OS_GAUSS_SEIDEL = 0, 1
+
+
 def os_step(chi, eps, B, Lstar, J, n_theta, n_phi, M, I_top=0.0, bottom_from_B=True, n_threads=0,
-            want_jfs=False):
-    """One operator-splitting step.  Returns (J_new, c) (and J_fs when asked for)."""
+            want_jfs=False, method=OS_JACOBI):
+    """One operator-splitting step (M Jacobi or multicolour Gauss-Seidel sweeps).  Returns (J_new, c)
+    (and J_fs when asked for)."""
     chi, eps, B, Lstar = _f64(chi), _f64(eps), _f64(B), _f64(Lstar)
     nz, ny, nx = chi.shape
     Jn = _f64(J).copy()
     c = C.c_double(0.0)
     Jfs = np.zeros_like(chi) if want_jfs else None
-    _check(lib().orc_os_step(nx, ny, nz, n_theta, n_phi, chi, eps, B, float(I_top), _bottom_mode(bottom_from_B),
-                             Lstar, Jn, int(M), C.byref(c), _ptr(Jfs), n_threads), "os_step")
+    _check(lib().orc_os_step_method(nx, ny, nz, n_theta, n_phi, chi, eps, B, float(I_top),
+                                    _bottom_mode(bottom_from_B), Lstar, Jn, int(M), int(method), C.byref(c),
+                                    _ptr(Jfs), n_threads), "os_step")
     return (Jn, c.value, Jfs) if want_jfs else (Jn, c.value)
+
+
+def os_inner(eps, Lstar, r, M, method):
+    """The inner solve alone: M sweeps (Jacobi or multicolour Gauss-Seidel) of the OS equations
+    (1 - Lstar (1 - eps)) dJ = r from dJ = 0.  Returns dJ."""
+    eps, Lstar, r = _f64(eps), _f64(Lstar), _f64(r)
+    nz, ny, nx = eps.shape
+    dJ = np.zeros_like(eps)
+    _check(lib().orc_os_inner(nx, ny, nz, eps, Lstar, r, int(M), int(method), dJ), "os_inner")
+    return dJ
+
+
+def gs_colour(n, periodic, i):
+    """(colour of index i, colours on the axis) in the Gauss-Seidel ordering."""
+    nc = C.c_int(0)
+    col = lib().orc_gs_colour(int(n), int(periodic), int(i), C.byref(nc))
+    return col, nc.value
 
 
 def solve(chi, eps, B, n_theta, n_phi, tol, max_iter, M, J0=None, Lstar=None, I_top=0.0,

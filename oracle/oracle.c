@@ -26,7 +26,9 @@
  *             direction's lines inside v; every voxel holds exactly 1/|mu| of path per direction;
  *   Lambda*   the 27-point band of the exact Lambda operator (S -> J with zero boundary light);
  *   OS        dJ^0 = 0, a fixed number M of Jacobi sweeps, J <- J + dJ^M,
- *             convergence measure c = max_v |dJ_v| / |J_v^new|, initial guess J^0 = B.
+ *             convergence measure c = max_v |dJ_v| / |J_v^new|, initial guess J^0 = B;
+ *             alternatively M Gauss-Seidel sweeps in a multicolour order (the Fortran code's other
+ *             choice, named in the same subsection): see orc_gs_colour.
  *
  * Layout: every per-voxel field is [k][j][i] with i fastest; Lambda* is [27][V] with neighbour
  * offset index o = 9 (dk+1) + 3 (dj+1) + (di+1), u = v + (di, dj, dk), periodic in i and j.
@@ -525,15 +527,81 @@ void orc_diffusion_slope(int nx, int ny, const double *chi, const double *B, dou
  * bottom voxel a line enters, 2: LTE diffusion, I_bot = B + mu dB/dtau with
  * dB/dtau = (B_0 - B_1) / ((chi_0 + chi_1) / 2) from the bottom voxel and the one above it (the
  * optical distance between their centres; tau grows inwards).  Jfs_out (optional) receives J_fs. */
-int orc_os_step(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi, const double *eps,
-                const double *B, double I_top, int bottom_from_B, const double *Lstar, double *J,
-                int M, double *c_out, double *Jfs_out, int n_threads)
+/* Colour of index i (0 <= i < n) in the multicolour ordering of the Gauss-Seidel sweep.  Two voxels
+ * are 27-point neighbours when every coordinate differs by at most one (cyclically in x and y), so a
+ * colouring per axis in which adjacent indices differ gives, as the triple (cx, cy, cz), a colouring
+ * in which no two voxels of a colour are neighbours: along z (not periodic) k mod 2; along a periodic
+ * axis i mod 2 when n is even, and when n is odd i mod 2 except colour 2 for i = n - 1 (its
+ * neighbours n - 2 and 0 are odd and even).  The number of colours per axis is returned through
+ * *n_colours.  The colours are swept in the order c = (cz * ncy + cy) * ncx + cx. */
+int orc_gs_colour(int n, int periodic, int i, int *n_colours)
 {
-    if (M < 1) return ORC_EARG;
+    if (!periodic || n % 2 == 0) {
+        if (n_colours) *n_colours = 2;
+        return i % 2;
+    }
+    if (n_colours) *n_colours = 3;
+    return i == n - 1 ? 2 : i % 2;
+}
+
+/* The inner solve of the OS step: M sweeps of
+ *   dJ_v <- (r_v + sum_{u != v} Lstar_vu (1-eps_u) dJ_u) / (1 - Lstar_vv (1-eps_v))  from dJ = 0,
+ * Jacobi (method 0: every voxel from the previous sweep's dJ) or Gauss-Seidel (method 1: in place,
+ * colour after colour in the order of orc_gs_colour, so each voxel sees the newest dJ of every
+ * neighbour of an earlier colour). */
+static void os_inner(int nx, int ny, int nz, const double *eps, const double *Lstar, const double *r,
+                     int M, int method, double *dJ, double *dJn)
+{
+    const long V = (long)nx * ny * nz;
+    int ncx, ncy, ncz;
+    orc_gs_colour(nx, 1, 0, &ncx);
+    orc_gs_colour(ny, 1, 0, &ncy);
+    orc_gs_colour(nz, 0, 0, &ncz);
+    const int n_pass = method == 1 ? ncx * ncy * ncz : 1;
+    for (int m = 0; m < M; ++m) {
+        /* Jacobi reads the previous sweep (dJ) and writes dJn; Gauss-Seidel reads and writes dJ */
+        const double *src = dJ;
+        double *dst = method == 1 ? dJ : dJn;
+        for (int pass = 0; pass < n_pass; ++pass)
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        if (method == 1) {
+                            int c = (orc_gs_colour(nz, 0, k, NULL) * ncy + orc_gs_colour(ny, 1, j, NULL)) * ncx
+                                    + orc_gs_colour(nx, 1, i, NULL);
+                            if (c != pass) continue;
+                        }
+                        long v = ((long)k * ny + j) * nx + i;
+                        double acc = r[v];
+                        for (int dk = -1; dk <= 1; ++dk) {
+                            if (k + dk < 0 || k + dk >= nz) continue;
+                            for (int dj = -1; dj <= 1; ++dj)
+                                for (int di = -1; di <= 1; ++di) {
+                                    int o = 9 * (dk + 1) + 3 * (dj + 1) + (di + 1);
+                                    if (o == 13) continue;
+                                    long u = ((long)(k + dk) * ny + imod(j + dj, ny)) * nx
+                                             + imod(i + di, nx);
+                                    acc += Lstar[(size_t)o * V + v] * (1.0 - eps[u]) * src[u];
+                                }
+                        }
+                        dst[v] = acc / (1.0 - Lstar[13 * V + v] * (1.0 - eps[v]));
+                    }
+        if (method != 1) memcpy(dJ, dJn, sizeof(double) * V);
+    }
+}
+
+/* One OS step with the inner solve of os_inner (method 0 Jacobi, 1 Gauss-Seidel); otherwise as
+ * orc_os_step. */
+int orc_os_step_method(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi,
+                       const double *eps, const double *B, double I_top, int bottom_from_B,
+                       const double *Lstar, double *J, int M, int method, double *c_out,
+                       double *Jfs_out, int n_threads)
+{
+    if (M < 1 || method < 0 || method > 1) return ORC_EARG;
     const long V = (long)nx * ny * nz;
     double *S = (double *)malloc(sizeof(double) * V);
     double *Jfs = (double *)malloc(sizeof(double) * V);
-    double *r = (double *)malloc(sizeof(double) * V);
+    double *r = (double *)calloc(V, sizeof(double));
     double *dJ = (double *)calloc(V, sizeof(double));
     double *dJn = (double *)malloc(sizeof(double) * V);
     if (!S || !Jfs || !r || !dJ || !dJn) {
@@ -553,27 +621,7 @@ int orc_os_step(int nx, int ny, int nz, int n_theta, int n_phi, const double *ch
     free(slope);
     if (rc == ORC_OK) {
         for (long v = 0; v < V; ++v) r[v] = Jfs[v] - J[v];
-        for (int m = 0; m < M; ++m) {
-            for (int k = 0; k < nz; ++k)
-                for (int j = 0; j < ny; ++j)
-                    for (int i = 0; i < nx; ++i) {
-                        long v = ((long)k * ny + j) * nx + i;
-                        double acc = r[v];
-                        for (int dk = -1; dk <= 1; ++dk) {
-                            if (k + dk < 0 || k + dk >= nz) continue;
-                            for (int dj = -1; dj <= 1; ++dj)
-                                for (int di = -1; di <= 1; ++di) {
-                                    int o = 9 * (dk + 1) + 3 * (dj + 1) + (di + 1);
-                                    if (o == 13) continue;
-                                    long u = ((long)(k + dk) * ny + imod(j + dj, ny)) * nx
-                                             + imod(i + di, nx);
-                                    acc += Lstar[(size_t)o * V + v] * (1.0 - eps[u]) * dJ[u];
-                                }
-                        }
-                        dJn[v] = acc / (1.0 - Lstar[13 * V + v] * (1.0 - eps[v]));
-                    }
-            double *t = dJ; dJ = dJn; dJn = t;
-        }
+        os_inner(nx, ny, nz, eps, Lstar, r, M, method, dJ, dJn);
         double c = 0.0;
         for (long v = 0; v < V; ++v) {
             J[v] += dJ[v];
@@ -585,6 +633,29 @@ int orc_os_step(int nx, int ny, int nz, int n_theta, int n_phi, const double *ch
     }
     free(S); free(Jfs); free(r); free(dJ); free(dJn);
     return rc;
+}
+
+int orc_os_step(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi, const double *eps,
+                const double *B, double I_top, int bottom_from_B, const double *Lstar, double *J,
+                int M, double *c_out, double *Jfs_out, int n_threads)
+{
+    return orc_os_step_method(nx, ny, nz, n_theta, n_phi, chi, eps, B, I_top, bottom_from_B, Lstar, J, M,
+                              0, c_out, Jfs_out, n_threads);
+}
+
+/* The inner solve alone, for the pins: M sweeps (method 0 Jacobi, 1 Gauss-Seidel) of the OS
+ * equations with right-hand side r; dJ ([V]) receives the result. */
+int orc_os_inner(int nx, int ny, int nz, const double *eps, const double *Lstar, const double *r, int M,
+                 int method, double *dJ)
+{
+    if (M < 1 || method < 0 || method > 1) return ORC_EARG;
+    const long V = (long)nx * ny * nz;
+    double *tmp = (double *)malloc(sizeof(double) * V);
+    if (!tmp) return ORC_ENOMEM;
+    memset(dJ, 0, sizeof(double) * V);
+    os_inner(nx, ny, nz, eps, Lstar, r, M, method, dJ, tmp);
+    free(tmp);
+    return ORC_OK;
 }
 
 /* Ng acceleration of the outer iteration (named among the host-side parts of the method in the

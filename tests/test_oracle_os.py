@@ -157,3 +157,88 @@ def test_ng_reaches_the_same_fixed_point_faster(orc):
     assert it2 < it0 and it3 < it0
     for J in (J0, J2, J3):
         assert np.max(np.abs(J / Jd - 1)) < 1e-9
+
+
+# ---- Gauss-Seidel inner solve ------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [3, 4, 5, 6, 7, 9, 129])
+@pytest.mark.parametrize("periodic", [0, 1])
+def test_gs_colouring_is_proper(orc, n, periodic):
+    """Neighbouring indices (cyclically when periodic) never share a colour; 2 colours unless the
+    axis is periodic with an odd length (3)."""
+    cols = [orc.gs_colour(n, periodic, i) for i in range(n)]
+    nc = cols[0][1]
+    assert nc == (3 if periodic and n % 2 else 2)
+    c = [x[0] for x in cols]
+    assert set(c) == set(range(nc))
+    for i in range(n - 1):
+        assert c[i] != c[i + 1]
+    if periodic:
+        assert c[n - 1] != c[0]
+
+
+def _os_system(orc, shape, seed, eps_range=(1e-3, 0.5)):
+    nz, ny, nx = shape
+    m = random_medium(nx, ny, nz, seed=seed, chi_range=(1e-2, 1e1), eps_range=eps_range)
+    L = orc.lstar(m["chi"], 4, 8)
+    r = np.random.default_rng(seed).uniform(-1.0, 1.0, m["chi"].shape)
+    # the OS matrix (1 - Lstar (1 - eps)) written out densely from the 27 bands
+    V = m["chi"].size
+    A = np.eye(V)
+    idx = np.arange(V).reshape(shape)
+    for o in range(27):
+        dk, dj, di = o // 9 - 1, (o // 3) % 3 - 1, o % 3 - 1
+        for k in range(nz):
+            if not 0 <= k + dk < nz:
+                continue
+            for j in range(ny):
+                for i in range(nx):
+                    v, u = idx[k, j, i], idx[k + dk, (j + dj) % ny, (i + di) % nx]
+                    A[v, u] -= L[o].ravel()[v] * (1 - m["eps"].ravel()[u])
+    return m, L, r, A
+
+
+@pytest.mark.parametrize("shape", [(4, 5, 6), (5, 3, 7), (3, 4, 4)])
+def test_gs_inner_solve_reaches_the_dense_solution(orc, shape):
+    """Both inner solves converge to the solution of the dense OS system (numpy solve); on an axis of
+    length 3 every column is its own colour."""
+    m, L, r, A = _os_system(orc, shape, seed=11)
+    x = np.linalg.solve(A, r.ravel()).reshape(shape)
+    for method in (orc.OS_JACOBI, orc.OS_GAUSS_SEIDEL):
+        dJ = orc.os_inner(m["eps"], L, r, 400, method)
+        assert np.max(np.abs(dJ - x)) < 1e-12 * np.max(np.abs(x)), method
+
+
+def test_gs_converges_faster_than_jacobi(orc):
+    """The Jacobi iteration matrix of the OS system is non-negative (Lambda* >= 0, 1 - eps >= 0), so by
+    the Stein-Rosenberg theorem Gauss-Seidel (in any order) has the smaller spectral radius: after the
+    same number of sweeps its error is smaller, and the ratio of successive errors is below Jacobi's."""
+    shape = (6, 5, 7)
+    m, L, r, A = _os_system(orc, shape, seed=12, eps_range=(1e-4, 1e-3))
+    x = np.linalg.solve(A, r.ravel()).reshape(shape)
+    err = {}
+    for method in (orc.OS_JACOBI, orc.OS_GAUSS_SEIDEL):
+        err[method] = [np.max(np.abs(orc.os_inner(m["eps"], L, r, M, method) - x)) for M in (10, 11, 20)]
+    assert err[orc.OS_GAUSS_SEIDEL][2] < err[orc.OS_JACOBI][2]
+    rate = {k: (v[2] / v[0]) ** 0.1 for k, v in err.items()}
+    assert rate[orc.OS_GAUSS_SEIDEL] < rate[orc.OS_JACOBI] < 1.0
+
+
+def test_gs_single_colour_pass_is_jacobi_on_that_colour(orc):
+    """One Gauss-Seidel sweep from dJ = 0: the first colour sees only zeros, so it equals one Jacobi
+    sweep there (r / diagonal); every later colour sees the earlier colours' new values."""
+    shape = (4, 4, 4)
+    m, L, r, A = _os_system(orc, shape, seed=13)
+    j1 = orc.os_inner(m["eps"], L, r, 1, orc.OS_JACOBI)
+    g1 = orc.os_inner(m["eps"], L, r, 1, orc.OS_GAUSS_SEIDEL)
+    first = np.zeros(shape, dtype=bool)
+    first[0::2, 0::2, 0::2] = True            # colour (0, 0, 0) on even axes
+    assert np.array_equal(g1[first], j1[first])
+    assert not np.allclose(g1[~first], j1[~first])
+    # the last colour's values are the Jacobi update from the other colours' Gauss-Seidel values
+    last = np.zeros(shape, dtype=bool)
+    last[1::2, 1::2, 1::2] = True
+    D = np.diag(A).reshape(shape)
+    off = (A - np.diag(np.diag(A))) @ np.where(last, 0.0, g1).ravel()
+    ref = ((r.ravel() - off) / D.ravel()).reshape(shape)
+    assert np.max(np.abs(g1[last] - ref[last])) < 1e-13 * np.max(np.abs(ref))
