@@ -103,10 +103,11 @@ def _timed_steps(rt3d, torch, w, d_med, prec, stream, steps, warmup, M):
     return elapsed, per_launch, lstar_s, st
 
 
-def _converge(rt3d, torch, w, d_med, prec, stream, M, ng_order, ng_every, tol, max_iter):
+def _converge(rt3d, torch, w, d_med, prec, stream, M, ng_order, ng_every, tol, max_iter, os_method=0):
     """Time from resident inputs (Lambda* build included) to max rel dJ < tol."""
     s = rt3d.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi, I_top=w.I_top, precision=prec, stream=stream)
     s.set_medium(d_med["chi"], d_med["eps"], d_med["B"])
+    s.set_os_method(os_method)
     if ng_order:
         s.set_acceleration(ng_order, ng_every)
     torch.cuda.synchronize()
@@ -329,6 +330,8 @@ def main() -> int:
     ap.add_argument("--inner-sweeps", type=int, default=30, help="Jacobi sweeps per OS step (M)")
     ap.add_argument("--ng-order", type=int, default=3)
     ap.add_argument("--ng-every", type=int, default=6)
+    ap.add_argument("--gs-inner-sweeps", type=int, default=15,
+                    help="Gauss-Seidel sweeps per OS step for its time to converged J (0: skip)")
     ap.add_argument("--converge-max-iter", type=int, default=600,
                     help="outer-iteration cap of the time-to-converged-J runs (0 skips them)")
     ap.add_argument("--reference-tol", type=float, default=1e-12,
@@ -438,6 +441,13 @@ def main() -> int:
             res["max_rel_err_vs_reference"] = float(torch.max(torch.abs(J / J_ref - 1)).item())
             conv[name] = res
         conv["fp32_form_speedup"] = round(conv["fp64"]["seconds"] / conv["fp32"]["seconds"], 3)
+        # the Fortran code's other inner solve: multicolour Gauss-Seidel, float64, half the sweeps
+        if args.gs_inner_sweeps > 0:
+            J, res = _converge(rt3d, torch, w, d_med, rt3d.RT3D_FP64, stream, args.gs_inner_sweeps,
+                               args.ng_order, args.ng_every, w.tol, args.converge_max_iter,
+                               os_method=rt3d.RT3D_OS_GAUSS_SEIDEL)
+            res["max_rel_err_vs_reference"] = float(torch.max(torch.abs(J / J_ref - 1)).item())
+            conv["gauss_seidel_fp64"] = {"inner_sweeps": args.gs_inner_sweeps, **res}
         # equal accuracy: the time each form needs to come within 1e-5 and within 1e-8 of the reference
         # (stopping at c < target / 100; the error reached is reported beside the time)
         conv["accuracy_targets"] = {}

@@ -145,6 +145,19 @@ int rt3d_solve_to_convergence(rt3d_ctx *ctx, double tol, int max_iter, int inner
  * Errors: RT3D_ERR_ARG, RT3D_ERR_OOM, RT3D_ERR_HIP. */
 int rt3d_set_acceleration(rt3d_ctx *ctx, int ng_order, int ng_every);
 
+/* Inner solve of the OS step (section "Implementation of the operator splitting step": the Fortran
+ * code solves the OS equations by Jordan (Jacobi) or Gauss-Seidel iterations; its GPU version uses
+ * Jacobi).  RT3D_OS_JACOBI (the default): inner_sweeps Jacobi sweeps from dJ = 0.
+ * RT3D_OS_GAUSS_SEIDEL: inner_sweeps multicolour Gauss-Seidel sweeps from dJ = 0, in place.  The
+ * colouring is per axis: index i has colour i mod 2, except on x or y (periodic) of odd length, where
+ * the last index has colour 2; z (not periodic) has two colours; a sweep visits the colours in the
+ * order (cz * ncy + cy) * ncx + cx (8, 12 or 18 passes, one launch each), and every voxel uses the
+ * newest dJ of all its neighbours.  Applies to rt3d_os_step and rt3d_solve_to_convergence of this
+ * context (either precision); the batched form and the adjoint solve use Jacobi.
+ * Errors: RT3D_ERR_ARG (unknown method). */
+enum { RT3D_OS_JACOBI = 0, RT3D_OS_GAUSS_SEIDEL = 1 };
+int rt3d_set_os_method(rt3d_ctx *ctx, int method);
+
 /* Top-plane intensities of the upward lines from the last formal solution, [n_theta/2 * n_phi][ny][nx]
  * in direction order (the upward directions are d = n_dir/2 .. n_dir-1); entry (j,i) belongs to the
  * line through (i+1/2, j+1/2, nz).  Errors: RT3D_ERR_STATE (no FS yet), RT3D_ERR_ARG, RT3D_ERR_HIP. */

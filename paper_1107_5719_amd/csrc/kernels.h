@@ -737,6 +737,37 @@ __global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel_column(JacobiArgs
     jacobi_column_body<coef>(a, (xcd * group + (slot - kc * group)) * kPlaneThreads + threadIdx.x, kc);
 }
 
+// Gauss-Seidel colour pass.  The voxels are coloured per axis so that no two 27-point neighbours share
+// a colour: index i has colour i mod 2, except on a periodic axis of odd length, where the last index
+// has colour 2 (its neighbours n-2 and 0 are odd and even); z (not periodic) always has two.  A pass
+// updates the voxels of one colour (cx, cy, cz) in place: none of them reads another's value, and
+// each reads the newest value of every neighbour.  Member q of colour c on an axis is 2q + c, or
+// n - 1 for colour 2; cnt holds the members per axis.
+__device__ inline int colour_member(int c, int q, int n) { return c == 2 ? n - 1 : 2 * q + c; }
+
+template <typename coef>
+__global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel_colour(JacobiArgs a, int3 col, int3 cnt)
+{
+    const long t = long(blockIdx.x) * kPlaneThreads + threadIdx.x;
+    const bool valid = t < long(cnt.x) * cnt.y * cnt.z;
+    int i = 0, j = 0, k = 0;
+    if (valid) {
+        const long rest = t / cnt.x;
+        i = colour_member(col.x, int(t - rest * cnt.x), a.nx);
+        j = colour_member(col.y, int(rest % cnt.y), a.ny);
+        k = colour_member(col.z, int(rest / cnt.y), a.nz);
+    }
+    jacobi_core<coef>(a, i, j, k, valid);
+}
+
+// Colours on an axis of length n (periodic or not) and the members of colour c.
+inline int axis_colours(int n, bool periodic) { return periodic && (n % 2) ? 3 : 2; }
+inline int colour_count(int c, int n, bool periodic)
+{
+    if (periodic && (n % 2)) return c == 2 ? 1 : (n - 1) / 2;
+    return c == 0 ? (n + 1) / 2 : n / 2;
+}
+
 // One Jacobi sweep in the given grid layout: 0 one block per chunk of a plane, 1 the same padded to
 // a multiple of 8 chunks per plane, 2 contiguous chunk ranges per XCD, 3 2D tiles, 4 columns.
 inline void launch_jacobi_sweep(const JacobiArgs &a, int layout, bool f32, hipStream_t stream)

@@ -295,6 +295,7 @@ int ensure_lstar(rt3d_ctx *c)
 }
 
 int launch_jacobi_args(rt3d_ctx *c, const JacobiArgs &a);
+int gauss_seidel_sweeps(rt3d_ctx *c, int M);
 
 int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update)
 {
@@ -310,6 +311,45 @@ int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update)
     a.maxdist = c->d_maxdist;
     TimedLaunch t(c, K_JACOBI);
     return launch_jacobi_args(c, a);
+}
+
+// M multicolour Gauss-Seidel sweeps from dJ = 0, colour after colour in the order
+// (cz * ncy + cy) * ncx + cx, with (1 - eps) dJ kept in place in dJa; the colour passes of the last
+// sweep also update J and fold in the convergence measures.
+int gauss_seidel_sweeps(rt3d_ctx *c, int M)
+{
+    const bool f32 = c->precision == RT3D_FP32_SWEEP;
+    HIP_TRY(c, hipMemsetAsync(c->dJa, 0, size_t(c->V) * sizeof(double), c->stream), "memset");
+    JacobiArgs a{};
+    a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
+    a.b = c->r; a.w_in = c->dJa; a.w_out = c->dJa;
+    a.Kc = f32 ? static_cast<const void *>(c->Kc32) : static_cast<const void *>(c->Kc);
+    a.invD = c->invD; a.E = c->Ecoef;
+    a.maxrel = c->d_maxrel; a.nonfinite = c->d_flag;
+    a.maxdist = c->d_maxdist;
+    const int ncx = axis_colours(c->g.nx, true), ncy = axis_colours(c->g.ny, true), ncz = axis_colours(c->g.nz, false);
+    for (int m = 0; m < M; ++m) {
+        TimedLaunch t(c, K_JACOBI);      // one record per sweep (all its colour passes)
+        const bool last = m == M - 1;
+        a.J = last ? c->J : nullptr;
+        a.Ja = (f32 && last) ? c->Ja : nullptr;
+        for (int cz = 0; cz < ncz; ++cz)
+            for (int cy = 0; cy < ncy; ++cy)
+                for (int cx = 0; cx < ncx; ++cx) {
+                    const int3 col = make_int3(cx, cy, cz);
+                    const int3 cnt = make_int3(colour_count(cx, c->g.nx, true), colour_count(cy, c->g.ny, true),
+                                               colour_count(cz, c->g.nz, false));
+                    const long total = long(cnt.x) * cnt.y * cnt.z;
+                    const dim3 grid(unsigned((total + kPlaneThreads - 1) / kPlaneThreads));
+                    if (f32)
+                        hipLaunchKernelGGL(jacobi_kernel_colour<float>, grid, dim3(kPlaneThreads), 0, c->stream, a, col, cnt);
+                    else
+                        hipLaunchKernelGGL(jacobi_kernel_colour<double>, grid, dim3(kPlaneThreads), 0, c->stream, a, col, cnt);
+                    int rc = check_launch(c, "jacobi_kernel_colour");
+                    if (rc) return rc;
+                }
+    }
+    return RT3D_OK;
 }
 
 int launch_jacobi_args(rt3d_ctx *c, const JacobiArgs &a)
@@ -739,16 +779,21 @@ int rt3d_os_step(rt3d_ctx *c, int inner_sweeps, double *max_rel_dJ_out)
     HIP_TRY(c, hipMemsetAsync(c->d_maxdist, 0, sizeof(unsigned long long), c->stream), "memset");
     HIP_TRY(c, hipMemsetAsync(c->d_maxrel, 0, sizeof(unsigned long long), c->stream), "memset");
     HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream), "memset");
-    // sweep 1 from dJ = 0; sweeps 2..M from the previous one (carried as (1 - eps) dJ); the last
-    // also updates J
-    const double *in = nullptr;
-    double *bufs[2] = {c->dJa, c->dJb};
-    for (int m = 0; m < inner_sweeps; ++m) {
-        const bool last = (m == inner_sweeps - 1);
-        double *out = last ? nullptr : bufs[m & 1];
-        rc = launch_jacobi(c, in, out, last);
+    if (c->os_method == RT3D_OS_GAUSS_SEIDEL) {
+        rc = gauss_seidel_sweeps(c, inner_sweeps);
         if (rc) return rc;
-        in = out;
+    } else {
+        // sweep 1 from dJ = 0; sweeps 2..M from the previous one (carried as (1 - eps) dJ); the last
+        // also updates J
+        const double *in = nullptr;
+        double *bufs[2] = {c->dJa, c->dJb};
+        for (int m = 0; m < inner_sweeps; ++m) {
+            const bool last = (m == inner_sweeps - 1);
+            double *out = last ? nullptr : bufs[m & 1];
+            rc = launch_jacobi(c, in, out, last);
+            if (rc) return rc;
+            in = out;
+        }
     }
     unsigned long long bits = 0, dbits = 0;
     int flag = 0;
@@ -844,6 +889,15 @@ int rt3d_set_acceleration(rt3d_ctx *c, int ng_order, int ng_every)
     return RT3D_OK;
 }
 
+int rt3d_set_os_method(rt3d_ctx *c, int method)
+{
+    if (!c) return RT3D_ERR_ARG;
+    if (method != RT3D_OS_JACOBI && method != RT3D_OS_GAUSS_SEIDEL)
+        return fail(c, RT3D_ERR_ARG, "method must be RT3D_OS_JACOBI or RT3D_OS_GAUSS_SEIDEL");
+    c->os_method = method;
+    return RT3D_OK;
+}
+
 int rt3d_get_emergent_top(rt3d_ctx *c, double *out, int ptr_kind)
 {
     if (!c) return RT3D_ERR_ARG;
@@ -889,11 +943,13 @@ int rt3d_get_stats(rt3d_ctx *c, char *buf, int buflen)
     std::snprintf(tmp, sizeof tmp,
                   "\"nx\":%d,\"ny\":%d,\"nz\":%d,\"n_dir\":%d,\"precision\":\"%s\",\"outer_iters\":%ld,"
                   "\"inner_sweeps\":%ld,\"fp64_sweeps\":%ld,\"fp32_sweeps\":%ld,\"device_bytes\":%zu,\"partial_plane_bytes\":%lld,"
-                  "\"sweep_workgroups\":%zu,\"sweep_shape\":%d,\"sweep_threads\":%d,\"sweep_lines\":%d,\"mean_segments\":%.6f,\"timing\":%s,\"kernels\":{",
+                  "\"sweep_workgroups\":%zu,\"sweep_shape\":%d,\"sweep_threads\":%d,\"sweep_lines\":%d,\"mean_segments\":%.6f,"
+                  "\"os_method\":\"%s\",\"timing\":%s,\"kernels\":{",
                   c->g.nx, c->g.ny, c->g.nz, c->A.n_dir, c->precision == RT3D_FP64 ? "fp64" : "fp32_sweep",
                   c->outer_iters, c->inner_sweeps, c->fp64_sweeps, c->fp32_sweeps, c->device_bytes,
                   (long long)(c->plan.p_elems * (long long)sizeof(double)), c->plan.items.size(),
-                  c->sweep_shape, kSweepShapes[c->sweep_shape].threads, kSweepShapes[c->sweep_shape].lines, c->plan.mean_segments, c->timing ? "true" : "false");
+                  c->sweep_shape, kSweepShapes[c->sweep_shape].threads, kSweepShapes[c->sweep_shape].lines, c->plan.mean_segments,
+                  c->os_method == RT3D_OS_GAUSS_SEIDEL ? "gauss_seidel" : "jacobi", c->timing ? "true" : "false");
     s += tmp;
     for (int k = 0; k < K_COUNT; ++k) {
         std::snprintf(tmp, sizeof tmp, "%s\"%s\":{\"launches\":%ld,\"total_ms\":%.6f}", k ? "," : "",

@@ -335,3 +335,20 @@ def test_jacobi_grid_layouts_agree_bitwise(R, precision, monkeypatch):
     for layout in range(1, 5):
         assert np.array_equal(out[layout][0], out[0][0]), f"layout {layout}"
         assert out[layout][1] == out[0][1]
+
+
+def test_formal_solution_parity_extreme_optical_depths(R, orc):
+    """Segment optical depths from ~1e-10 to ~1e6 (chi log-uniform over 16 decades): the float64
+    exponential's reduction, table and clamp at both ends, against the oracle's libm expm1."""
+    nz, ny, nx = 6, 7, 9
+    rng = np.random.default_rng(31)
+    chi = np.exp(rng.uniform(np.log(1e-10), np.log(1e6), (nz, ny, nx)))
+    S = rng.uniform(0.1, 3.0, (nz, ny, nx))
+    B = rng.uniform(0.5, 2.0, (nz, ny, nx))
+    J_orc, Iem_orc = orc.formal_solution(chi, S, 8, 8, I_top=0.2, I_bot=B[0], want_emergent=True)
+    with R.Solver(nx, ny, nz, 8, 8, I_top=0.2) as s:
+        s.set_medium(chi, np.full_like(chi, 0.5), B)
+        J = s.formal_solution(S)
+        Iem = s.emergent_top()
+    _close(J, J_orc)
+    _close(Iem, Iem_orc)
