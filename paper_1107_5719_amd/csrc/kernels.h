@@ -71,6 +71,28 @@ __device__ inline double expm1_nonpos_tab(double x, const double *tab)
     return fma(s, p * r, s - 1.0);
 }
 
+// Both e^x and e^x - 1 for x <= 0 from one table evaluation: with s = 2^k T_j and q = r p(r),
+// e^x = s (1 + q) and e^x - 1 = s q + (s - 1), each to a few ulps relative (the first also for
+// thick segments, where 1 + (e^x - 1) would lose all of it).
+__device__ inline void exp_pair_tab(double x, const double *tab, double &e, double &em1)
+{
+    x = fmax(x, -708.0);
+    const double kf = rint(x * 92.332482616893656877);          // 64 / ln2
+    double r = fma(-kf, 6.93147180369123816490e-01 / 64, x);
+    r = fma(-kf, 1.90821492927058770002e-10 / 64, r);
+    const int n = int(kf);
+    double p = 1.0 / 720.0;
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    const double s = ldexp(tab[n & (kExpTab - 1)], n >> 6);
+    const double q = p * r;
+    e = fma(s, q, s);
+    em1 = fma(s, q, s - 1.0);
+}
+
 // float32: x = k ln2 + r with |r| <= ln2/2; e^x - 1 = 2^k (e^r - 1) + (2^k - 1), and e^r - 1 is its
 // Taylor series through r^8 (truncation below 1e-9 relative).
 __device__ inline float expm1_nonpos(float x)
@@ -396,13 +418,15 @@ struct LstarArgs {
     const double *seg_len;
     const double *chi;
     double *L;                      // [27][V]
+    const double *xtab;             // [kExpTab] 2^(j/64), the float64 exponential's table
 };
 
-// x + expm1(-x) = e^{-x} - 1 + x for x >= 0; below 1/2 by Horner on x^2 (1/2! - x/3! + x^2/4! - ...)
-// through x^15/17!, which avoids the cancellation of the direct form for thin segments.
-__device__ inline double self_term(double x)
+// x + expm1(-x) = e^{-x} - 1 + x for x >= 0 (em1 = e^{-x} - 1 given); below 1/2 by Horner on x^2
+// (1/2! - x/3! + x^2/4! - ...) through x^15/17!, which avoids the cancellation of the direct form for
+// thin segments.
+__device__ inline double self_term(double x, double em1)
 {
-    if (x >= 0.5) return x + expm1(-x);
+    if (x >= 0.5) return x + em1;
     constexpr double inv_fact[18] = {
         1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720, 1.0 / 5040, 1.0 / 40320,
         1.0 / 362880, 1.0 / 3628800, 1.0 / 39916800, 1.0 / 479001600, 1.0 / 6227020800.0,
@@ -434,6 +458,8 @@ constexpr int kLstarThreads = 64;
 __global__ __launch_bounds__(kLstarThreads) void lstar_kernel(LstarArgs a)
 {
     __shared__ double acc[27][kLstarThreads];
+    __shared__ double xtab[kExpTab];
+    for (int q = threadIdx.x; q < kExpTab; q += kLstarThreads) xtab[q] = a.xtab[q];
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y;
@@ -443,6 +469,7 @@ __global__ __launch_bounds__(kLstarThreads) void lstar_kernel(LstarArgs a)
     const long V = plane * nz;
     const long v = k * plane + long(j) * nx + i;
     for (int o = 0; o < 27; ++o) acc[o][threadIdx.x] = 0.0;
+    __syncthreads();
     const double chiv = a.chi[v];
     for (int d = 0; d < a.n_dir; ++d) {
         const DirInfo di = a.dirs[d];
@@ -456,8 +483,8 @@ __global__ __launch_bounds__(kLstarThreads) void lstar_kernel(LstarArgs a)
         for (int s = 0; s < n; ++s) {
             const int as = a.seg_ai[off + s], bs = a.seg_bi[off + s];
             const double dtau = chiv * a.seg_len[off + s];
-            const double em1 = expm1(-dtau);
-            acc[13][threadIdx.x] += fac * self_term(dtau);
+            const double em1 = expm1_nonpos_tab(-dtau, xtab);
+            acc[13][threadIdx.x] += fac * self_term(dtau, em1);
             const double g = -fac * em1;
             double prod = 1.0;
             // walk back: current layer s-1 .. 0, then the previous layer from its last segment
@@ -468,18 +495,22 @@ __global__ __launch_bounds__(kLstarThreads) void lstar_kernel(LstarArgs a)
                 else { idx = offu + nu - 1 - (w - s); dkk = ku - k; }
                 const int dA = a.seg_ai[idx] - as, dB = a.seg_bi[idx] - bs;
                 if (a.early_exit && (dA > 1 || dA < -1 || dB > 1 || dB < -1)) break;
-                const int mA = wrap_small(dA, nx), mB = wrap_small(dB, ny);
+                // with early exit the offsets are -1, 0 or 1 here
+                const int mA = a.early_exit ? dA + (dA < 0 ? nx : 0) : wrap_small(dA, nx);
+                const int mB = a.early_exit ? dB + (dB < 0 ? ny : 0) : wrap_small(dB, ny);
                 int col = i + mA;
                 col -= (col >= nx) ? nx : 0;
                 int row = j + mB;
                 row -= (row >= ny) ? ny : 0;
                 const long u = long(k + dkk) * plane + long(row) * nx + col;
                 const double tau_u = a.chi[u] * a.seg_len[idx];
-                const double c = -expm1(-tau_u) * prod;
+                double e_u, em1_u;
+                exp_pair_tab(-tau_u, xtab, e_u, em1_u);
+                const double c = -em1_u * prod;
                 const int oi = (mA == 0) ? 1 : (mA == 1) ? 2 : (mA == nx - 1) ? 0 : -1;
                 const int oj = (mB == 0) ? 1 : (mB == 1) ? 2 : (mB == ny - 1) ? 0 : -1;
                 if (oi >= 0 && oj >= 0) acc[9 * (dkk + 1) + 3 * oj + oi][threadIdx.x] += g * c;
-                prod *= exp(-tau_u);   // not 1 + expm1: keeps relative accuracy for thick segments
+                prod *= e_u;
             }
         }
     }

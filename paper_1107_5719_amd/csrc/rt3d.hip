@@ -272,6 +272,7 @@ int ensure_lstar(rt3d_ctx *c)
     a.early_exit = c->lstar_early_exit;
     a.dirs = c->dirs; a.seg_off = c->seg_off; a.seg_n = c->seg_n; a.seg_ai = c->seg_ai;
     a.seg_bi = c->seg_bi; a.seg_len = c->seg_len64; a.chi = c->chi; a.L = c->L;
+    a.xtab = c->xtab;
     {
         TimedLaunch t(c, K_LSTAR);
         const dim3 grid((c->g.nx * c->g.ny + kLstarThreads - 1) / kLstarThreads, c->g.nz);
