@@ -146,6 +146,13 @@ __global__ void clear_scalars_kernel(int n, const MemberScalars *sc)
     *sc[m].flag = 0;
 }
 
+// Lambda* of several members in one launch (small grids alone would leave most of the chip idle)
+__global__ __launch_bounds__(kLstarThreads) void lstar_kernel_batch(const LstarArgs *args, const PlaneBlock *blocks)
+{
+    const PlaneBlock b = blocks[blockIdx.x];
+    lstar_body(args[b.member], b.chunk * kLstarThreads + threadIdx.x, b.k);
+}
+
 // Jacobi sweep of the members, column form (b.k is the column layer of kJacCol planes)
 template <typename coef>
 __global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel_batch_column(const JacobiArgs *args,
@@ -350,6 +357,66 @@ int bupload(rt3d_batch *b, T *&d, const std::vector<T> &h)
     bfree(d);
     BHIP_TRY(b, hipMalloc(reinterpret_cast<void **>(&d), std::max<size_t>(h.size(), 1) * sizeof(T)), "hipMalloc");
     if (!h.empty()) BHIP_TRY(b, hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+    return RT3D_OK;
+}
+
+int launch_check(rt3d_batch *b, const char *what);
+
+// Lambda* of every member that lacks it, in one launch over all their planes (64-column blocks,
+// the largest members first), then each member's Jacobi coefficients.
+int build_lstar_batched(rt3d_batch *b)
+{
+    std::vector<LstarArgs> args;
+    std::vector<PlaneBlock> blocks;
+    std::vector<int> who;
+    for (int i = 0; i < b->n; ++i) {
+        rt3d_ctx *c = b->m[i];
+        if (c->have_lstar) continue;
+        if (!c->plan_ok) return bfail(b, RT3D_ERR_STATE, "member " + std::to_string(i) + " has no sweep plan");
+        LstarArgs a{};
+        a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.n_dir = c->A.n_dir;
+        a.early_exit = c->lstar_early_exit;
+        a.dirs = c->dirs; a.seg_off = c->seg_off; a.seg_n = c->seg_n; a.seg_ai = c->seg_ai;
+        a.seg_bi = c->seg_bi; a.seg_len = c->seg_len64; a.chi = c->chi; a.L = c->L;
+        a.xtab = c->xtab;
+        args.push_back(a);
+        who.push_back(i);
+    }
+    if (who.empty()) return RT3D_OK;
+    std::vector<int> order(who.size());
+    for (size_t q = 0; q < order.size(); ++q) order[q] = int(q);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return long(args[x].nx) * args[x].ny * args[x].nz * args[x].n_dir >
+               long(args[y].nx) * args[y].ny * args[y].nz * args[y].n_dir;
+    });
+    for (int q : order) {
+        const int chunks = (args[q].nx * args[q].ny + kLstarThreads - 1) / kLstarThreads;
+        for (int k = 0; k < args[q].nz; ++k)
+            for (int ch = 0; ch < chunks; ++ch) blocks.push_back(PlaneBlock{q, ch, k, 0});
+    }
+    LstarArgs *d_args = nullptr;
+    PlaneBlock *d_blocks = nullptr;
+    int rc = RT3D_OK;
+    if (hipMalloc(reinterpret_cast<void **>(&d_args), args.size() * sizeof(LstarArgs)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&d_blocks), blocks.size() * sizeof(PlaneBlock)) != hipSuccess) {
+        rc = bfail(b, RT3D_ERR_OOM, "hipMalloc (Lambda* tables)");
+    } else if (hipMemcpy(d_args, args.data(), args.size() * sizeof(LstarArgs), hipMemcpyHostToDevice) != hipSuccess ||
+               hipMemcpy(d_blocks, blocks.data(), blocks.size() * sizeof(PlaneBlock), hipMemcpyHostToDevice) !=
+                   hipSuccess) {
+        rc = bfail(b, RT3D_ERR_HIP, "upload (Lambda* tables)");
+    } else {
+        hipLaunchKernelGGL(lstar_kernel_batch, dim3(unsigned(blocks.size())), dim3(kLstarThreads), 0, b->stream,
+                           d_args, d_blocks);
+        rc = launch_check(b, "lstar_kernel_batch");
+        if (!rc && hipStreamSynchronize(b->stream) != hipSuccess) rc = bfail(b, RT3D_ERR_HIP, "sync (Lambda*)");
+    }
+    bfree(d_args);
+    bfree(d_blocks);
+    if (rc) return rc;
+    for (int i : who) {
+        rc = finish_lstar(b->m[i]);
+        if (rc) return member_fail(b, i, rc);
+    }
     return RT3D_OK;
 }
 
@@ -809,11 +876,11 @@ int rt3d_batch_solve(rt3d_batch *b, double tol, int max_iter, int inner_sweeps, 
         return bfail(b, RT3D_ERR_ARG, "bad tol/max_iter/inner_sweeps/poll_every");
     const int n = b->n;
     const bool f32 = b->precision == RT3D_FP32_SWEEP;
-    for (int i = 0; i < n; ++i) {
-        rt3d_ctx *c = b->m[i];
-        if (!c->have_medium) return bfail(b, RT3D_ERR_STATE, "member " + std::to_string(i) + " has no medium");
-        const int rc = ensure_lstar(c);
-        if (rc) return member_fail(b, i, rc);
+    for (int i = 0; i < n; ++i)
+        if (!b->m[i]->have_medium) return bfail(b, RT3D_ERR_STATE, "member " + std::to_string(i) + " has no medium");
+    {
+        const int rc = build_lstar_batched(b);
+        if (rc) return rc;
     }
     // the Ng ring starts from the current iterate; control state from each member's context
     std::vector<MemberState> h(n);

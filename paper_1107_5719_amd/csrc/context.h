@@ -106,6 +106,7 @@ int hip_fail(rt3d_ctx *c, hipError_t e, const char *what);
 int sync(rt3d_ctx *c);
 int check_launch(rt3d_ctx *c, const char *what);
 int ensure_lstar(rt3d_ctx *c);
+int finish_lstar(rt3d_ctx *c);
 int validate_desc(const rt3d_grid_desc *g, std::string &msg);
 int validate_medium_host(long V, const double *chi, const double *eps, const double *B, std::string &msg);
 hipMemcpyKind kind_in(int ptr_kind);

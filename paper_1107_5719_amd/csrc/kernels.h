@@ -455,14 +455,13 @@ __device__ inline int wrap_small(int a, int n)
 // and small workgroups let many of them share a CU to hide the latency of the gathers along the
 // lines (measured at 129^3 x 256: 31.7 ms with 256 threads, 29.2 ms with 128, 26.4 ms with 64).
 constexpr int kLstarThreads = 64;
-__global__ __launch_bounds__(kLstarThreads) void lstar_kernel(LstarArgs a)
+// Columns p (p = j nx + i; p >= nx ny: none) of plane k; the whole block calls this.
+__device__ inline void lstar_body(const LstarArgs &a, int p, int k)
 {
     __shared__ double acc[27][kLstarThreads];
     __shared__ double xtab[kExpTab];
     for (int q = threadIdx.x; q < kExpTab; q += kLstarThreads) xtab[q] = a.xtab[q];
     const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
     const bool valid = p < nx * ny;
     const int j = valid ? p / nx : 0, i = valid ? p - (p / nx) * nx : 0;
     const long plane = long(nx) * ny;
@@ -516,6 +515,11 @@ __global__ __launch_bounds__(kLstarThreads) void lstar_kernel(LstarArgs a)
     }
     if (valid)
         for (int o = 0; o < 27; ++o) a.L[o * V + v] = acc[o][threadIdx.x];
+}
+
+__global__ __launch_bounds__(kLstarThreads) void lstar_kernel(LstarArgs a)
+{
+    lstar_body(a, blockIdx.x * kLstarThreads + threadIdx.x, blockIdx.y);
 }
 
 // Jacobi coefficients.  K_vu = chi_v Lambda*_vu is symmetric (reciprocity: lines for Omega and -Omega

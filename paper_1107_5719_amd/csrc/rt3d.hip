@@ -280,6 +280,13 @@ int ensure_lstar(rt3d_ctx *c)
     }
     int rc = check_launch(c, "lstar_kernel");
     if (rc) return rc;
+    return finish_lstar(c);
+}
+
+// The Jacobi coefficients from Lambda* (after it was built into c->L)
+int finish_lstar(rt3d_ctx *c)
+{
+    int rc;
     {
         TimedLaunch t(c, K_COEF);
         if (c->precision == RT3D_FP32_SWEEP)
