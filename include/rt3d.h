@@ -13,6 +13,11 @@
  *     setup").
  * All state lives on the device; only opacities/eps/B go in and J comes out (section "Method").
  *
+ * Environment variables read when a context is created (tuning experiments; the defaults are the
+ * measured best): RT3D_SWEEP_SHAPE (index into rt3d_sweep_shapes), RT3D_JACOBI_XCD (Jacobi launch
+ * layout 0..4; all give bitwise the same iterates), RT3D_ANCHOR_RATIO (re-anchoring ratio of the
+ * RT3D_FP32_SWEEP form, default 1e-2).
+ *
  * Discretisation (the paper defers it to earlier papers of its series; these are the readings):
  *   voxels    unit cubes (i,j,k), i fastest; k = 0 is the bottom (inner boundary), k = nz-1 the top;
  *   angles    n_theta-point Gauss-Legendre in mu (n_theta even) x n_phi uniform azimuths
