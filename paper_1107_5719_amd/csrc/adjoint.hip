@@ -294,7 +294,7 @@ int adjoint_os_step(rt3d_ctx *c, int M, double *dmax, double *numax, int *bad)
     const dim3 grid(c->plan.items.size());
     with_sweep_shape(c->sweep_shape, [&](auto tag) {
         using Tag = decltype(tag);
-        hipLaunchKernelGGL((sweep_kernel<double, Tag::threads, Tag::lines, false>), grid, dim3(Tag::threads), smem,
+        hipLaunchKernelGGL((sweep_kernel<double, Tag::threads, Tag::lines>), grid, dim3(Tag::threads), smem,
                            c->stream, w);
     });
     if ((rc = check_launch(c, "sweep_kernel (adjoint)"))) return rc;

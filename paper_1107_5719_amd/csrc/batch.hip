@@ -108,7 +108,7 @@ __global__ __launch_bounds__(NT) void sweep_kernel_batch(const SweepArgs *args, 
     const BatchItem bi = items[blockIdx.x];
     if (st && st[bi.member].mode != want) return;
     const SweepArgs a = args[bi.member];
-    sweep_body<real, NT, LPT, false>(a, bi.item, smem_raw);
+    sweep_body<real, NT, LPT>(a, bi.item, smem_raw);
 }
 
 template <typename real>

@@ -30,7 +30,6 @@ struct rt3d_ctx {
     size_t real_size = 8;
     int lstar_early_exit = 0;
     int sweep_shape = 0;       // index into kSweepShapes
-    int sweep_prefetch = 0;
     int os_method = RT3D_OS_JACOBI;   // inner solve of the OS step
     double anchor_ratio = kAnchorRatioDefault;   // FP32 form: re-anchor when c < ratio * max|J - Ja|/|J|
     int jacobi_xcd = 4;        // Jacobi grid: 0 plain, 1 chunks padded to 8 per plane, 2 contiguous chunk

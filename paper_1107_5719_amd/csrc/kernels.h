@@ -183,7 +183,7 @@ template <> __device__ inline float seg_length<float>(const rt3d::PairSeg &g) { 
 // x mod n for 0 <= x < 2n, as min(x, x - n) on unsigned integers (x - n wraps when x < n)
 __device__ inline unsigned wrap_once(unsigned x, unsigned n) { return min(x, x - n); }
 
-template <typename real, int NT, int LPT, bool PF>
+template <typename real, int NT, int LPT>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &it, unsigned char *smem_raw)
 {
     using real2 = typename Vec2<real>::type;
@@ -242,35 +242,21 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
                 IB[t] = a.Ibot ? real(a.Ibot[row + cB] + sB) : real(0);
             }
         }
-        // gathers of segment s (prefetch variant: segment s+1's are issued before s is computed)
-        real2 nA[LPT], nB[LPT];
-        unsigned ncA[LPT], ncB[LPT];
-        auto gather = [&](const rt3d::PairSeg &g, real2 *dA, real2 *dB, unsigned *cA_, unsigned *cB_) {
-#pragma unroll
-            for (int t = 0; t < LPT; ++t) {
-                const unsigned grow = wrap_once(grow0[t] + unsigned(g.smnx), plane);
-                cA_[t] = wrap_once(unsigned(li[t] + g.saA), nx);
-                cB_[t] = wrap_once(unsigned(li[t] + g.saB), nx);
-                if (li[t] >= 0) {
-                    dA[t] = csk[grow + cA_[t]];
-                    dB[t] = csk[grow + cB_[t]];
-                }
-            }
-        };
-        if (PF && L.ns > 0) gather(a.pseg[L.off], nA, nB, ncA, ncB);
         for (int s = 0; s < L.ns; ++s) {
             const rt3d::PairSeg g = a.pseg[L.off + s];
             const real len = seg_length<real>(g);
+            // gathers of segment s: the voxel of each line in the chi,S plane
             real2 cA[LPT], cB[LPT];
             unsigned colA[LPT], colB[LPT];
-            if (PF) {
 #pragma unroll
-                for (int t = 0; t < LPT; ++t) {
-                    cA[t] = nA[t]; cB[t] = nB[t]; colA[t] = ncA[t]; colB[t] = ncB[t];
+            for (int t = 0; t < LPT; ++t) {
+                const unsigned grow = wrap_once(grow0[t] + unsigned(g.smnx), plane);
+                colA[t] = wrap_once(unsigned(li[t] + g.saA), nx);
+                colB[t] = wrap_once(unsigned(li[t] + g.saB), nx);
+                if (li[t] >= 0) {
+                    cA[t] = csk[grow + colA[t]];
+                    cB[t] = csk[grow + colB[t]];
                 }
-                if (s + 1 < L.ns) gather(a.pseg[L.off + s + 1], nA, nB, ncA, ncB);
-            } else {
-                gather(g, cA, cB, colA, colB);
             }
             // At one segment index the lines of a direction deposit into distinct cells (and the two
             // directions into separate windows), so the window cells are read first, ahead of the
@@ -328,11 +314,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
     }
 }
 
-template <typename real, int NT, int LPT, bool PF>
+template <typename real, int NT, int LPT>
 __global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs a)
 {
     extern __shared__ unsigned char smem_raw[];
-    sweep_body<real, NT, LPT, PF>(a, a.items[blockIdx.x], smem_raw);
+    sweep_body<real, NT, LPT>(a, a.items[blockIdx.x], smem_raw);
 }
 
 // ------------------------------------------------------------------------------------------------

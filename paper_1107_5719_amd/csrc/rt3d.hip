@@ -187,26 +187,20 @@ int launch_sweep(rt3d_ctx *c, bool fp32, bool diff)
     const dim3 grid(c->plan.items.size());
     TimedLaunch t(c, K_SWEEP);
     if (fp32) c->fp32_sweeps += 1; else c->fp64_sweeps += 1;
-#define RT3D_LAUNCH_SWEEP(NT_, LPT_, PF_)                                                      \
+#define RT3D_LAUNCH_SWEEP(NT_, LPT_)                                                           \
     do {                                                                                          \
         if (!fp32)                                                                                \
-            hipLaunchKernelGGL((sweep_kernel<double, NT_, LPT_, PF_>), grid, dim3(NT_), smem,     \
-                               c->stream, a);                                                     \
+            hipLaunchKernelGGL((sweep_kernel<double, NT_, LPT_>), grid, dim3(NT_), smem, c->stream, a); \
         else                                                                                      \
-            hipLaunchKernelGGL((sweep_kernel<float, NT_, LPT_, PF_>), grid, dim3(NT_), smem,      \
-                               c->stream, a);                                                     \
+            hipLaunchKernelGGL((sweep_kernel<float, NT_, LPT_>), grid, dim3(NT_), smem, c->stream, a);  \
     } while (0)
     switch (c->sweep_shape) {
-    case 1:
-        if (c->sweep_prefetch) RT3D_LAUNCH_SWEEP(512, 4, true); else RT3D_LAUNCH_SWEEP(512, 4, false);
-        break;
-    case 2:
-        if (c->sweep_prefetch) RT3D_LAUNCH_SWEEP(256, 8, true); else RT3D_LAUNCH_SWEEP(256, 8, false);
-        break;
-    case 3: RT3D_LAUNCH_SWEEP(1024, 2, false); break;
-    case 4: RT3D_LAUNCH_SWEEP(256, 4, false); break;
-    case 5: RT3D_LAUNCH_SWEEP(256, 2, false); break;
-    default: RT3D_LAUNCH_SWEEP(512, 2, false); break;
+    case 1: RT3D_LAUNCH_SWEEP(512, 4); break;
+    case 2: RT3D_LAUNCH_SWEEP(256, 8); break;
+    case 3: RT3D_LAUNCH_SWEEP(1024, 2); break;
+    case 4: RT3D_LAUNCH_SWEEP(256, 4); break;
+    case 5: RT3D_LAUNCH_SWEEP(256, 2); break;
+    default: RT3D_LAUNCH_SWEEP(512, 2); break;
     }
 #undef RT3D_LAUNCH_SWEEP
     return check_launch(c, "sweep_kernel");
@@ -494,9 +488,6 @@ int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream
     c->real_size = (precision == RT3D_FP64) ? sizeof(double) : sizeof(float);
     c->V = long(g->nx) * g->ny * g->nz;
     if (!rt3d::make_angle_set(g->n_theta, g->n_phi, c->A)) { delete c; msg = "bad angle set"; return RT3D_ERR_ARG; }
-    // gathers of the next segment issued before the current one is computed (RT3D_SWEEP_PREFETCH=1;
-    // shapes 1 and 2 only; slower on MI355X because it costs occupancy)
-    if (const char *e = std::getenv("RT3D_SWEEP_PREFETCH")) c->sweep_prefetch = std::atoi(e) != 0;
     if (const char *e = std::getenv("RT3D_JACOBI_XCD")) c->jacobi_xcd = std::max(0, std::min(4, std::atoi(e)));
     if (const char *e = std::getenv("RT3D_ANCHOR_RATIO")) c->anchor_ratio = std::max(0.0, std::atof(e));
     // Lambda* walk may stop at the first non-neighbour only if no line wraps back within two layers
