@@ -304,9 +304,7 @@ int adjoint_os_step(rt3d_ctx *c, int M, double *dmax, double *numax, int *bad)
     ra.J = c->adj_nu; ra.base = c->adj_f; ra.Jfs = c->adj_fs; ra.rb = c->adj_r;
     hipLaunchKernelGGL(reduce_kernel<double>, planes(c), dim3(kPlaneThreads), 0, c->stream, ra);
     if ((rc = check_launch(c, "reduce_kernel (adjoint)"))) return rc;
-    HIP_TRY(c, hipMemsetAsync(c->d_maxrel, 0, sizeof(unsigned long long), c->stream), "memset");
-    HIP_TRY(c, hipMemsetAsync(c->d_maxdist, 0, sizeof(unsigned long long), c->stream), "memset");
-    HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream), "memset");
+    HIP_TRY(c, hipMemsetAsync(c->d_scal, 0, kScalarBytes, c->stream), "memset");
     const bool f32 = c->precision == RT3D_FP32_SWEEP;
     const double *in = nullptr;
     double *bufs[2] = {c->dJa, c->dJb};
@@ -326,12 +324,12 @@ int adjoint_os_step(rt3d_ctx *c, int M, double *dmax, double *numax, int *bad)
         if ((rc = check_launch(c, "jacobi_kernel (adjoint)"))) return rc;
         in = ja.w_out;
     }
-    unsigned long long b1 = 0, b2 = 0;
-    HIP_TRY(c, hipMemcpyAsync(&b1, c->d_maxrel, sizeof(b1), hipMemcpyDeviceToHost, c->stream), "maxrel");
-    HIP_TRY(c, hipMemcpyAsync(&b2, c->d_maxdist, sizeof(b2), hipMemcpyDeviceToHost, c->stream), "maxdist");
-    HIP_TRY(c, hipMemcpyAsync(bad, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream), "flag");
+    unsigned long long scal[3] = {0, 0, 0};
+    HIP_TRY(c, hipMemcpyAsync(scal, c->d_scal, kScalarBytes, hipMemcpyDeviceToHost, c->stream), "scalars");
     rc = sync(c);
     if (rc) return rc;
+    const unsigned long long b1 = scal[0], b2 = scal[1];
+    std::memcpy(bad, &scal[2], sizeof(int));
     std::memcpy(dmax, &b1, sizeof(double));
     std::memcpy(numax, &b2, sizeof(double));
     return RT3D_OK;

@@ -15,6 +15,7 @@
 
 enum KernelId { K_SOURCE, K_SWEEP, K_REDUCE, K_LSTAR, K_COEF, K_JACOBI, K_COUNT };
 constexpr size_t kHistoryMax = 100000;   // step records kept per context
+constexpr size_t kScalarBytes = 3 * sizeof(unsigned long long);   // max rel dJ, max distance, flag
 // FP32 form: a float64 sweep re-anchors when c < ratio * max|J - Ja|/|J| (the float32 error of a
 // difference step scales with the distance travelled since the anchor)
 constexpr double kAnchorRatioDefault = 1e-2;
@@ -60,6 +61,7 @@ struct rt3d_ctx {
     rt3d::WorkItem *items = nullptr;
     unsigned long long *d_maxrel = nullptr;
     int *d_flag = nullptr;
+    unsigned long long *d_scal = nullptr;   // owns d_maxrel, d_maxdist, d_flag (in that order)
     // adjoint (allocated by the first adjoint call): per (direction, layer, line) the intensity entering
     // the layer and the adjoint variable leaving it; per voxel the adjoint iterate nu, its formal
     // solution, residual, right-hand side and the pulled gradient terms

@@ -386,7 +386,7 @@ void free_all(rt3d_ctx *c)
 {
     free_plan(c);
     void *ptrs[] = {c->chi, c->eps, c->B, c->J, c->Jfs, c->r, c->dJa, c->dJb, c->L, c->Kc, c->invD, c->Ecoef, c->Iem,
-                    c->Sbuf, c->bot_slope, c->xtab, c->cs, c->Ja, c->Fa, c->Iem_a, c->Kc32, c->d_maxdist, c->d_maxrel, c->d_flag,
+                    c->Sbuf, c->bot_slope, c->xtab, c->cs, c->Ja, c->Fa, c->Iem_a, c->Kc32, c->d_scal,
                     c->ng_hist, c->ng_work, c->adj_Ient, c->adj_Qx, c->adj_nu, c->adj_fs, c->adj_r,
                     c->adj_f, c->adj_pull, c->adj_g, c->adj_qs};
     for (void *p : ptrs)
@@ -519,8 +519,12 @@ int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream
         chk(dev_alloc(c, &c->Iem_a, size_t(c->A.n_dir / 2) * g->nx * g->ny));
         chk(dev_alloc(c, &c->Kc32, 13 * V));
     }
-    chk(dev_alloc(c, &c->d_maxdist, 1));
-    chk(dev_alloc(c, &c->d_maxrel, 1)); chk(dev_alloc(c, &c->d_flag, 1));
+    chk(dev_alloc(c, &c->d_scal, kScalarBytes / sizeof(unsigned long long)));
+    if (!rc) {
+        c->d_maxrel = c->d_scal;
+        c->d_maxdist = c->d_scal + 1;
+        c->d_flag = reinterpret_cast<int *>(c->d_scal + 2);
+    }
     if (g->bottom_bc == 2) chk(dev_alloc(c, &c->bot_slope, size_t(g->nx) * g->ny));
     chk(dev_alloc(c, &c->xtab, kExpTab));
     if (!rc) {
@@ -775,9 +779,8 @@ int rt3d_os_step(rt3d_ctx *c, int inner_sweeps, double *max_rel_dJ_out)
         rc = run_fs(c, nullptr, true, false);
     }
     if (rc) return rc;
-    HIP_TRY(c, hipMemsetAsync(c->d_maxdist, 0, sizeof(unsigned long long), c->stream), "memset");
-    HIP_TRY(c, hipMemsetAsync(c->d_maxrel, 0, sizeof(unsigned long long), c->stream), "memset");
-    HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream), "memset");
+    // the three convergence scalars share one allocation: one clear, one read-back per step
+    HIP_TRY(c, hipMemsetAsync(c->d_scal, 0, kScalarBytes, c->stream), "memset");
     if (c->os_method == RT3D_OS_GAUSS_SEIDEL) {
         rc = gauss_seidel_sweeps(c, inner_sweeps);
         if (rc) return rc;
@@ -794,13 +797,13 @@ int rt3d_os_step(rt3d_ctx *c, int inner_sweeps, double *max_rel_dJ_out)
             in = out;
         }
     }
-    unsigned long long bits = 0, dbits = 0;
-    int flag = 0;
-    HIP_TRY(c, hipMemcpyAsync(&bits, c->d_maxrel, sizeof(bits), hipMemcpyDeviceToHost, c->stream), "maxrel");
-    HIP_TRY(c, hipMemcpyAsync(&dbits, c->d_maxdist, sizeof(dbits), hipMemcpyDeviceToHost, c->stream), "maxdist");
-    HIP_TRY(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream), "flag");
+    unsigned long long scal[3] = {0, 0, 0};
+    HIP_TRY(c, hipMemcpyAsync(scal, c->d_scal, kScalarBytes, hipMemcpyDeviceToHost, c->stream), "scalars");
     rc = sync(c);
     if (rc) return rc;
+    const unsigned long long bits = scal[0], dbits = scal[1];
+    int flag = 0;
+    std::memcpy(&flag, &scal[2], sizeof(flag));
     c->outer_iters += 1;
     c->inner_sweeps += inner_sweeps;
     double cval, dval;
