@@ -168,9 +168,14 @@ int rt3d_set_os_method(rt3d_ctx *ctx, int method);
  * line through (i+1/2, j+1/2, nz).  Errors: RT3D_ERR_STATE (no FS yet), RT3D_ERR_ARG, RT3D_ERR_HIP. */
 int rt3d_get_emergent_top(rt3d_ctx *ctx, double *out, int ptr_kind);
 
-/* Enable (1) or disable (0) per-kernel timing with HIP events on the context stream.  While enabled
- * every launch of the sweep, reduce, Lambda* and Jacobi kernels is bracketed by events and the
- * durations are accumulated (read with rt3d_get_stats).  Errors: RT3D_ERR_ARG. */
+/* Per-kernel timing with HIP events on the context stream: 0 off; 1 every launch of the source,
+ * sweep, reduce, Lambda*, coefficient and Jacobi kernels is bracketed by events; 2 sampled: the same
+ * except for the inner sweeps of an OS step, of which the intermediate ones (all but the first, from
+ * dJ = 0, and the last, which updates J) are timed as one group by a single pair of events (with two
+ * or fewer sweeps the first is timed; Gauss-Seidel: its second sweep).  Mode 2 keeps the events' own
+ * cost (about 4% of a step with mode 1) out of the timed work.  Durations are accumulated with the
+ * number of launches they cover (rt3d_get_stats: per kernel "launches", "timed", "total_ms");
+ * changing the mode clears them.  Errors: RT3D_ERR_ARG. */
 int rt3d_set_timing(rt3d_ctx *ctx, int enable);
 
 /* The per-step record since the last rt3d_set_medium, rt3d_set_J or start of

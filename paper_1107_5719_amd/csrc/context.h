@@ -82,12 +82,13 @@ struct rt3d_ctx {
     struct StepRecord { double c, ms; int flags; };
     std::vector<StepRecord> history;
     // timing
-    bool timing = false;
+    int timing = 0;                    // 0 off, 1 every launch, 2 sampled (see rt3d_set_timing)
     struct Pending { int kid; hipEvent_t a, b; };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> event_pool;
     double kernel_ms[K_COUNT] = {0};
     long kernel_launches[K_COUNT] = {0};
+    long kernel_timed[K_COUNT] = {0};  // launches bracketed by events
     std::string err;
 };
 

@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <optional>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -68,9 +69,12 @@ struct TimedLaunch {
     rt3d_ctx *c;
     int kid;
     hipEvent_t a = nullptr, b = nullptr;
-    TimedLaunch(rt3d_ctx *ctx, int id) : c(ctx), kid(id)
+    bool on;
+    // chosen: in sampled timing (mode 2) only the chosen launches are bracketed by events
+    TimedLaunch(rt3d_ctx *ctx, int id, bool chosen = true)
+        : c(ctx), kid(id), on(ctx->timing == 1 || (ctx->timing == 2 && chosen))
     {
-        if (c->timing) {
+        if (on) {
             a = get_event(c);
             b = get_event(c);
             if (a) hipEventRecord(a, c->stream);
@@ -78,12 +82,39 @@ struct TimedLaunch {
     }
     ~TimedLaunch()
     {
-        if (c->timing && a && b) {
+        if (on && a && b) {
             hipEventRecord(b, c->stream);
             c->pending.push_back({kid, a, b});
+            c->kernel_timed[kid] += 1;
         }
         c->kernel_launches[kid] += 1;
     }
+};
+
+// Sampled timing of n consecutive launches of one kernel as a group (one pair of events): the
+// launches are counted by their own TimedLaunch objects, constructed with chosen = false.
+struct TimedGroup {
+    rt3d_ctx *c;
+    int kid, n;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedGroup(rt3d_ctx *ctx, int id, int count) : c(ctx), kid(id), n(count)
+    {
+        if (c->timing == 2 && n > 0) {
+            a = get_event(c);
+            b = get_event(c);
+            if (a) hipEventRecord(a, c->stream);
+        }
+    }
+    void end()
+    {
+        if (a && b) {
+            hipEventRecord(b, c->stream);
+            c->pending.push_back({kid, a, b});
+            c->kernel_timed[kid] += n;
+        }
+        a = b = nullptr;
+    }
+    ~TimedGroup() { end(); }
 };
 
 // Resolve pending timing events (call after the stream has been synchronised).
@@ -299,7 +330,7 @@ int finish_lstar(rt3d_ctx *c)
 int launch_jacobi_args(rt3d_ctx *c, const JacobiArgs &a);
 int gauss_seidel_sweeps(rt3d_ctx *c, int M);
 
-int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update)
+int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update, bool chosen)
 {
     JacobiArgs a{};
     const bool f32 = c->precision == RT3D_FP32_SWEEP;
@@ -311,7 +342,7 @@ int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update)
     a.maxrel = c->d_maxrel; a.nonfinite = c->d_flag;
     a.Ja = (f32 && update) ? c->Ja : nullptr;
     a.maxdist = c->d_maxdist;
-    TimedLaunch t(c, K_JACOBI);
+    TimedLaunch t(c, K_JACOBI, chosen);
     return launch_jacobi_args(c, a);
 }
 
@@ -331,7 +362,7 @@ int gauss_seidel_sweeps(rt3d_ctx *c, int M)
     a.maxdist = c->d_maxdist;
     const int ncx = axis_colours(c->g.nx, true), ncy = axis_colours(c->g.ny, true), ncz = axis_colours(c->g.nz, false);
     for (int m = 0; m < M; ++m) {
-        TimedLaunch t(c, K_JACOBI);      // one record per sweep (all its colour passes)
+        TimedLaunch t(c, K_JACOBI, m == std::min(1, M - 1));   // one record per sweep (all its passes)
         const bool last = m == M - 1;
         a.J = last ? c->J : nullptr;
         a.Ja = (f32 && last) ? c->Ja : nullptr;
@@ -789,10 +820,15 @@ int rt3d_os_step(rt3d_ctx *c, int inner_sweeps, double *max_rel_dJ_out)
         // also updates J
         const double *in = nullptr;
         double *bufs[2] = {c->dJa, c->dJb};
+        std::optional<TimedGroup> group;
         for (int m = 0; m < inner_sweeps; ++m) {
             const bool last = (m == inner_sweeps - 1);
             double *out = last ? nullptr : bufs[m & 1];
-            rc = launch_jacobi(c, in, out, last);
+            // sampled timing: the intermediate sweeps 1 .. M-2 as one group (the first sweep, from
+            // dJ = 0, and the last, which updates J, are cheaper and dearer); with M <= 2 the first
+            if (m == 1 && inner_sweeps > 2) group.emplace(c, K_JACOBI, inner_sweeps - 2);
+            rc = launch_jacobi(c, in, out, last, inner_sweeps <= 2 && m == 0);
+            if (m == inner_sweeps - 2 && group) group->end();
             if (rc) return rc;
             in = out;
         }
@@ -912,13 +948,14 @@ int rt3d_get_emergent_top(rt3d_ctx *c, double *out, int ptr_kind)
 
 int rt3d_set_timing(rt3d_ctx *c, int enable)
 {
-    if (!c || (enable != 0 && enable != 1)) return RT3D_ERR_ARG;
+    if (!c || enable < 0 || enable > 2) return RT3D_ERR_ARG;
     int rc = sync(c);
     if (rc) return rc;
-    c->timing = enable != 0;
+    c->timing = enable;
     for (int k = 0; k < K_COUNT; ++k) {
         c->kernel_ms[k] = 0.0;
         c->kernel_launches[k] = 0;
+        c->kernel_timed[k] = 0;
     }
     return RT3D_OK;
 }
@@ -946,16 +983,16 @@ int rt3d_get_stats(rt3d_ctx *c, char *buf, int buflen)
                   "\"nx\":%d,\"ny\":%d,\"nz\":%d,\"n_dir\":%d,\"precision\":\"%s\",\"outer_iters\":%ld,"
                   "\"inner_sweeps\":%ld,\"fp64_sweeps\":%ld,\"fp32_sweeps\":%ld,\"device_bytes\":%zu,\"partial_plane_bytes\":%lld,"
                   "\"sweep_workgroups\":%zu,\"sweep_shape\":%d,\"sweep_threads\":%d,\"sweep_lines\":%d,\"mean_segments\":%.6f,"
-                  "\"os_method\":\"%s\",\"timing\":%s,\"kernels\":{",
+                  "\"os_method\":\"%s\",\"timing\":%d,\"kernels\":{",
                   c->g.nx, c->g.ny, c->g.nz, c->A.n_dir, c->precision == RT3D_FP64 ? "fp64" : "fp32_sweep",
                   c->outer_iters, c->inner_sweeps, c->fp64_sweeps, c->fp32_sweeps, c->device_bytes,
                   (long long)(c->plan.p_elems * (long long)sizeof(double)), c->plan.items.size(),
                   c->sweep_shape, kSweepShapes[c->sweep_shape].threads, kSweepShapes[c->sweep_shape].lines, c->plan.mean_segments,
-                  c->os_method == RT3D_OS_GAUSS_SEIDEL ? "gauss_seidel" : "jacobi", c->timing ? "true" : "false");
+                  c->os_method == RT3D_OS_GAUSS_SEIDEL ? "gauss_seidel" : "jacobi", c->timing);
     s += tmp;
     for (int k = 0; k < K_COUNT; ++k) {
-        std::snprintf(tmp, sizeof tmp, "%s\"%s\":{\"launches\":%ld,\"total_ms\":%.6f}", k ? "," : "",
-                      kKernelNames[k], c->kernel_launches[k], c->kernel_ms[k]);
+        std::snprintf(tmp, sizeof tmp, "%s\"%s\":{\"launches\":%ld,\"timed\":%ld,\"total_ms\":%.6f}", k ? "," : "",
+                      kKernelNames[k], c->kernel_launches[k], c->kernel_timed[k], c->kernel_ms[k]);
         s += tmp;
     }
     s += "}}";

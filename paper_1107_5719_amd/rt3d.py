@@ -260,8 +260,10 @@ def rt3d_get_emergent_top(ctx, out):
     return _raise(ctx, _lib.rt3d_get_emergent_top(ctx, p, k), "rt3d_get_emergent_top")
 
 
-def rt3d_set_timing(ctx, enable: bool):
-    return _raise(ctx, _lib.rt3d_set_timing(ctx, 1 if enable else 0), "rt3d_set_timing")
+def rt3d_set_timing(ctx, enable):
+    """0 / False: off; 1 / True: every launch timed; 2: sampled (see include/rt3d.h)."""
+    mode = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
+    return _raise(ctx, _lib.rt3d_set_timing(ctx, mode), "rt3d_set_timing")
 
 
 def rt3d_get_stats(ctx) -> dict:
