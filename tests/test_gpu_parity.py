@@ -352,3 +352,30 @@ def test_formal_solution_parity_extreme_optical_depths(R, orc):
         Iem = s.emergent_top()
     _close(J, J_orc)
     _close(Iem, Iem_orc)
+
+
+def test_sampled_timing_counts(R):
+    """Timing mode 2 (the benchmark's): per OS step one timed source, sweep and reduction launch and
+    the M - 2 intermediate Jacobi sweeps as one group; mode 1 times every launch; results unchanged."""
+    m = random_medium(9, 8, 7, seed=51)
+    J = {}
+    for mode in (0, 1, 2):
+        with R.Solver(9, 8, 7, 4, 8) as s:
+            s.set_medium(m["chi"], m["eps"], m["B"])
+            s.build_lstar()
+            s.set_timing(mode)
+            for _ in range(3):
+                s.os_step(6)
+            st = s.stats()
+            J[mode] = s.get_J()
+        k = st["kernels"]
+        assert st["timing"] == mode
+        assert k["sweep"]["launches"] == 3 and k["jacobi"]["launches"] == 18
+        if mode == 1:
+            assert k["sweep"]["timed"] == 3 and k["jacobi"]["timed"] == 18
+        elif mode == 2:
+            assert k["sweep"]["timed"] == 3 and k["reduce"]["timed"] == 3 and k["jacobi"]["timed"] == 3 * 4
+            assert k["jacobi"]["total_ms"] > 0
+        else:
+            assert k["sweep"]["timed"] == 0 and k["jacobi"]["total_ms"] == 0
+    assert np.array_equal(J[0], J[1]) and np.array_equal(J[0], J[2])
