@@ -7,19 +7,23 @@
 // Kernels
 //   source_kernel   S = eps B + (1-eps) J packed with chi as {chi, S} per voxel (one 16-byte gather
 //                   per segment in the sweep).
-//   sweep_kernel    one workgroup per (direction, band of line rows): every thread owns a few lines
-//                   and carries their intensity down (or up) through all layers.  All lines of a
-//                   direction share one segment table, so segment s of every line in a layer lands
-//                   in a distinct voxel: the deposits D_s go into an LDS window without atomics, one
-//                   segment index at a time, and each layer's window is written once to a per-band
-//                   partial plane P.  Deterministic; no float atomics.
+//   sweep_kernel    one workgroup per (x-mirrored direction pair, band of line rows): every thread
+//                   owns a few lines and carries their intensity down (or up) through all layers.
+//                   All lines of a direction share one segment table, so segment s of every line in
+//                   a layer lands in a distinct voxel: the deposits D_s go into an LDS window without
+//                   atomics, one segment index at a time, and each layer's window is written once to
+//                   a per-band partial plane P.  Deterministic; no float atomics.  The float64
+//                   exponential uses a 64-entry table of 2^(j/64) (per context, copied to LDS).
 //   reduce_kernel   per voxel, sums the partial planes of all directions in a fixed order:
-//                   J_fs = (1/chi) sum_d W_d |mu_d| sum_bands P, and r = J_fs - J.
+//                   J_fs = (1/chi) sum_d W_d |mu_d| sum_bands P, and the OS right-hand side
+//                   chi (J_fs - J).
 //   lstar_kernel    per voxel, the 27 derivatives dJ_v/dS_u along the lines through v (exact band).
 //   coef_kernel     the Jacobi coefficients: chi_v Lambda*_vu for the 13 upper neighbours (the
 //                   lower ones follow by reciprocity) and the per-voxel scalings.
-//   jacobi_kernel   one Jacobi sweep of the OS equations (27-point stencil); the last sweep also
-//                   updates J and reduces max |dJ|/|J| (and flags NaN/Inf).
+//   jacobi_kernel_column  one Jacobi sweep of the OS equations (27-point stencil), a thread marching
+//                   up a column of 4 voxels; the last sweep also updates J and reduces max |dJ|/|J|
+//                   (and flags NaN/Inf).  jacobi_kernel_colour: one colour pass of the multicolour
+//                   Gauss-Seidel alternative.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
