@@ -302,7 +302,9 @@ int adjoint_os_step(rt3d_ctx *c, int M, double *dmax, double *numax, int *bad)
     ra.nx = c->g.nx; ra.ny = c->g.ny; ra.nz = c->g.nz; ra.n_pair = c->plan.n_pair;
     ra.pairs = c->pairs; ra.row_min = c->row_min; ra.P = c->P; ra.chi = c->chi;
     ra.J = c->adj_nu; ra.base = c->adj_f; ra.Jfs = c->adj_fs; ra.rb = c->adj_r;
-    hipLaunchKernelGGL(reduce_kernel<double>, planes(c), dim3(kPlaneThreads), 0, c->stream, ra);
+    hipLaunchKernelGGL(reduce_kernel_pair<double>,
+                       dim3(((c->g.nx + 1) / 2 * c->g.ny + kPlaneThreads - 1) / kPlaneThreads, c->g.nz),
+                       dim3(kPlaneThreads), 0, c->stream, ra);
     if ((rc = check_launch(c, "reduce_kernel (adjoint)"))) return rc;
     HIP_TRY(c, hipMemsetAsync(c->d_scal, 0, kScalarBytes, c->stream), "memset");
     const bool f32 = c->precision == RT3D_FP32_SWEEP;

@@ -386,11 +386,71 @@ __device__ inline void reduce_body(const ReduceArgs &a, int p, int k)
     if (a.rb) a.rb[v] = a.chi[v] * (Jfs - a.J[v]);
 }
 
+// The same sum for two neighbouring voxels of one row per thread (p2 indexes the (ny, (nx + 1) / 2)
+// voxel pairs of plane k): the band lookup is shared and the partials of both are read together,
+// the per-voxel sums in the order of reduce_body (so the results are bitwise those of reduce_body).
+// Measured at 129^3 x 256: 0.69 against 0.74 ms (float64), 0.51 against 0.59 ms (float32).
 template <typename real>
-__global__ __launch_bounds__(kPlaneThreads) void reduce_kernel(ReduceArgs a)
+__device__ inline void reduce_body_pair(const ReduceArgs &a, int p2, int k)
 {
-    reduce_body<real>(a, blockIdx.x * kPlaneThreads + threadIdx.x, blockIdx.y);
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int hx = (nx + 1) / 2;
+    if (p2 >= hx * ny) return;
+    const int j = p2 / hx, i0 = 2 * (p2 - j * hx);
+    const bool two = i0 + 1 < nx;
+    const int d1 = two ? 1 : 0;          // the second voxel's offset (0: none, reads the first again)
+    const real *P = static_cast<const real *>(a.P);
+    double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll 4
+    for (int q = 0; q < a.n_pair; ++q) {
+        const rt3d::PairInfo pi = a.pairs[q];
+        const int rows = pi.band_rows, nb = pi.n_bands, Hw = pi.win_rows;
+        const int rmin = a.row_min[pi.dA * nz + k];
+        int jj = j - rmin;
+        jj += (jj < 0) ? ny : 0;
+        int b = min(int((float(jj) + 0.5f) * pi.inv_rows), nb - 1);
+        b -= (b * rows > jj) ? 1 : 0;
+        b += (b < nb - 1 && (b + 1) * rows <= jj) ? 1 : 0;
+        const int off0 = jj - b * rows;
+        const long plane = long(Hw) * nx;
+        const long band_stride = long(nz) * plane;
+        const real *Pq = P + pi.p_off + long(k) * plane + i0;
+        const int b1 = (b == 0) ? nb - 1 : b - 1;
+        const int off1 = off0 + ((b1 == nb - 1) ? pi.last_rows : rows);
+        const long o0 = long(b) * band_stride + long(off0) * nx;
+        const long o1 = long(b1) * band_stride + long(off1) * nx;
+        double s0 = double(Pq[o0]), s1 = double(Pq[o0 + d1]);
+        if (off1 < Hw) {
+            s0 += double(Pq[o1]);
+            s1 += double(Pq[o1 + d1]);
+            int bb = b1, off = off1;
+            while (true) {
+                bb = (bb == 0) ? nb - 1 : bb - 1;
+                off += (bb == nb - 1) ? pi.last_rows : rows;
+                if (off >= Hw) break;
+                const long o = long(bb) * band_stride + long(off) * nx;
+                s0 += double(Pq[o]);
+                s1 += double(Pq[o + d1]);
+            }
+        }
+        acc0 += pi.wmu * s0;
+        acc1 += pi.wmu * s1;
+    }
+    for (int t = 0; t < (two ? 2 : 1); ++t) {
+        const long v = long(k) * nx * ny + long(j) * nx + i0 + t;
+        const double acc = t ? acc1 : acc0;
+        const double Jfs = a.base ? a.base[v] + acc / a.chi[v] : acc / a.chi[v];
+        a.Jfs[v] = Jfs;
+        if (a.rb) a.rb[v] = a.chi[v] * (Jfs - a.J[v]);
+    }
 }
+
+template <typename real>
+__global__ __launch_bounds__(kPlaneThreads) void reduce_kernel_pair(ReduceArgs a)
+{
+    reduce_body_pair<real>(a, blockIdx.x * kPlaneThreads + threadIdx.x, blockIdx.y);
+}
+
 
 // ------------------------------------------------------------------------------------------------
 // Lambda*

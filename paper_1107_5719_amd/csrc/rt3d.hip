@@ -14,9 +14,9 @@
 //                   atomics, one segment index at a time, and each layer's window is written once to
 //                   a per-band partial plane P.  Deterministic; no float atomics.  The float64
 //                   exponential uses a 64-entry table of 2^(j/64) (per context, copied to LDS).
-//   reduce_kernel   per voxel, sums the partial planes of all directions in a fixed order:
-//                   J_fs = (1/chi) sum_d W_d |mu_d| sum_bands P, and the OS right-hand side
-//                   chi (J_fs - J).
+//   reduce_kernel_pair  per voxel (two neighbours of a row per thread), sums the partial planes of
+//                   all directions in a fixed order: J_fs = (1/chi) sum_d W_d |mu_d| sum_bands P, and
+//                   the OS right-hand side chi (J_fs - J).
 //   lstar_kernel    per voxel, the 27 derivatives dJ_v/dS_u along the lines through v (exact band).
 //   coef_kernel     the Jacobi coefficients: chi_v Lambda*_vu for the 13 upper neighbours (the
 //                   lower ones follow by reciprocity) and the per-voxel scalings.
@@ -181,6 +181,12 @@ dim3 plane_grid(const rt3d_ctx *c)
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2) in linear order.
 // Padding the chunks of a plane to a multiple of 8 sends a chunk's blocks of every plane to the same
 // XCD, so the plane-below data a Jacobi sweep re-reads is in that XCD's L2.  Padding blocks exit.
+// the reduction's grid: one thread per pair of neighbouring voxels of a row
+dim3 pair_grid(const rt3d_ctx *c)
+{
+    return dim3(((c->g.nx + 1) / 2 * c->g.ny + kPlaneThreads - 1) / kPlaneThreads, c->g.nz);
+}
+
 dim3 plane_grid_xcd(const rt3d_ctx *c)
 {
     const unsigned chunks = (c->g.nx * c->g.ny + kPlaneThreads - 1) / kPlaneThreads;
@@ -249,9 +255,9 @@ int launch_reduce(rt3d_ctx *c, bool with_residual, bool fp32, const double *base
     a.J = c->J; a.base = base; a.Jfs = c->Jfs; a.rb = with_residual ? c->r : nullptr;
     TimedLaunch t(c, K_REDUCE);
     if (!fp32)
-        hipLaunchKernelGGL(reduce_kernel<double>, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(reduce_kernel_pair<double>, pair_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
     else
-        hipLaunchKernelGGL(reduce_kernel<float>, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(reduce_kernel_pair<float>, pair_grid(c), dim3(kPlaneThreads), 0, c->stream, a);
     return check_launch(c, "reduce_kernel");
 }
 
