@@ -28,11 +28,11 @@ HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 # Arithmetic per voxel-angle update of the sweep, counted per segment and multiplied by the mean
 # segments per voxel-angle of the 16 x 16 angle set (4.05): dtau = chi l (1); e^-dtau - 1 (float64 by
-# the 64-entry table: clamp, scale, round, 2 reduction FMAs, convert, 5 Horner FMAs, scale by 2^k,
-# r p, s - 1, final FMA = 15; float32 with 8 Horner FMAs and no table = 17); (I - S) em1 (2); I += dI
-# (1); D = S dtau - dI (1); window += D (1): 21 (float64) / 23 (float32) per segment, i.e. 85 / 93
-# vector operations per update, each priced as an FMA issue slot (2 flops).
-SWEEP_OPS_PER_UPDATE = {"fp64": 85, "fp32": 93}
+# the 128-entry table: clamp, scale-and-round FMA, subtract, 1 reduction FMA, 4 Horner FMAs, r p,
+# scale by 2^k, s - 1, final FMA = 12; float32 with 8 Horner FMAs and no table = 17); (I - S) em1 (2);
+# I += dI (1); D = S dtau - dI (1); window += D (1): 18 (float64) / 23 (float32) per segment, i.e.
+# 73 / 93 vector operations per update, each priced as an FMA issue slot (2 flops).
+SWEEP_OPS_PER_UPDATE = {"fp64": 73, "fp32": 93}
 SWEEP_KERNEL = {"fp64": "sweep_kernel<double,512,2>", "fp32": "sweep_kernel<float,512,2>"}
 JACOBI_KERNEL = {"fp64": "jacobi_kernel_column<double>", "fp32": "jacobi_kernel_column<float>"}
 

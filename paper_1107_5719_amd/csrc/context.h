@@ -41,7 +41,7 @@ struct rt3d_ctx {
     double *Kc = nullptr, *invD = nullptr, *Ecoef = nullptr;   // Jacobi coefficients (float64 form)
     double *Sbuf = nullptr;
     double *bot_slope = nullptr;        // [ny][nx] LTE-diffusion gradient (bottom_bc 2)
-    double *xtab = nullptr;             // [64] 2^(j/64) for the float64 exponential of the sweep
+    double *xtab = nullptr;             // [kExpTab] 2^(j/kExpTab) for the float64 exponential of the sweep
     void *cs = nullptr, *P = nullptr;       // sized for float64; float sweeps use the first half
     double *seg_len64 = nullptr;
     float *seg_len32 = nullptr;

@@ -44,31 +44,46 @@ template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
 
 // e^x - 1 for x <= 0 (the argument is always -dtau).  No range branches: x is clamped where e^x
-// vanishes.  ln2 is split into a high part whose product with the reduction multiple is exact and a
-// low part.
+// vanishes.
 //
-// float64, Tang's table method: x = (64 k + j) ln2/64 + r with 0 <= j < 64 and |r| <= ln2/128, so
-// e^x - 1 = 2^k T_j (1 + r p(r)) - 1 with T_j = 2^(j/64) read from a table and p the Taylor polynomial
-// of (e^r - 1)/r through r^5 (truncation below 1e-17 relative).  2^k T_j - 1 is exact when
-// 2^k T_j >= 1/2 and is far from zero otherwise; the rounding of T_j bounds the relative error by
-// about 5e-15 where the result is small (|x| just above ln2/128), and below ln2/128 the result is
-// r p(r) itself.
-constexpr int kExpTab = 64;
-__device__ inline double expm1_nonpos_tab(double x, const double *tab)
+// float64, Tang's table method: x = (128 k + j) ln2/128 + r with 0 <= j < 128 and |r| <= ln2/256, so
+// e^x - 1 = 2^k T_j (1 + r p(r)) - 1 with T_j = 2^(j/128) read from a table and p the Taylor
+// polynomial of (e^r - 1)/r through r^4 (truncation below 3e-17 relative).  The multiple n = 128 k + j
+// is the nearest integer to x 128/ln2, taken from the rounding of x 128/ln2 + 1.5 * 2^52 (the spacing
+// of doubles there is 1, so the low word of the sum is n in two's complement).  2^k T_j - 1 is exact
+// when 2^k T_j >= 1/2 and is far from zero otherwise; the rounding of T_j bounds the relative error
+// by about 4e-15 where the result is small (|x| a few times ln2/256), and below ln2/256 the result is
+// r p(r) itself.  The sweep reduces with one fma on the rounded ln2/128: its error in r, |n| times
+// half an ulp of ln2/128, moves e^x by at most 1e-16 |x| e^x relative (below 3e-17 absolute).
+// exp_pair_tab splits ln2/128 into a high part whose product with n is exact and a low part, so that
+// e^x itself stays accurate to a few ulps for thick segments.
+constexpr int kExpTabLog2 = 7;
+constexpr int kExpTab = 1 << kExpTabLog2;
+constexpr double kExpInvStep = 184.66496523378731;                // 128 / ln2
+constexpr double kExpStep = 0.0054152123481245725;                 // ln2 / 128
+constexpr double kExpStepHi = 6.93147180369123816490e-01 / 128;   // 21 trailing zero bits
+constexpr double kExpStepLo = 1.90821492927058770002e-10 / 128;
+constexpr double kExpRound = 6755399441055744.0;                   // 1.5 * 2^52
+
+__device__ inline double expm1_poly(double r)
 {
-    x = fmax(x, -708.0);
-    const double kf = rint(x * 92.332482616893656877);          // 64 / ln2
-    double r = fma(-kf, 6.93147180369123816490e-01 / 64, x);
-    r = fma(-kf, 1.90821492927058770002e-10 / 64, r);
-    const int n = int(kf);
-    double p = 1.0 / 720.0;
-    p = fma(p, r, 1.0 / 120.0);
+    double p = 1.0 / 120.0;
     p = fma(p, r, 1.0 / 24.0);
     p = fma(p, r, 1.0 / 6.0);
     p = fma(p, r, 0.5);
     p = fma(p, r, 1.0);
-    const double s = ldexp(tab[n & (kExpTab - 1)], n >> 6);
-    return fma(s, p * r, s - 1.0);
+    return p * r;
+}
+
+__device__ inline double expm1_nonpos_tab(double x, const double *tab)
+{
+    x = fmax(x, -708.0);
+    const double kr = fma(x, kExpInvStep, kExpRound);
+    const double kf = kr - kExpRound;
+    const int n = __double2loint(kr);
+    const double q = expm1_poly(fma(-kf, kExpStep, x));
+    const double s = ldexp(tab[n & (kExpTab - 1)], n >> kExpTabLog2);
+    return fma(s, q, s - 1.0);
 }
 
 // Both e^x and e^x - 1 for x <= 0 from one table evaluation: with s = 2^k T_j and q = r p(r),
@@ -77,18 +92,11 @@ __device__ inline double expm1_nonpos_tab(double x, const double *tab)
 __device__ inline void exp_pair_tab(double x, const double *tab, double &e, double &em1)
 {
     x = fmax(x, -708.0);
-    const double kf = rint(x * 92.332482616893656877);          // 64 / ln2
-    double r = fma(-kf, 6.93147180369123816490e-01 / 64, x);
-    r = fma(-kf, 1.90821492927058770002e-10 / 64, r);
-    const int n = int(kf);
-    double p = 1.0 / 720.0;
-    p = fma(p, r, 1.0 / 120.0);
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
-    p = fma(p, r, 0.5);
-    p = fma(p, r, 1.0);
-    const double s = ldexp(tab[n & (kExpTab - 1)], n >> 6);
-    const double q = p * r;
+    const double kr = fma(x, kExpInvStep, kExpRound);
+    const double kf = kr - kExpRound;
+    const int n = __double2loint(kr);
+    const double q = expm1_poly(fma(-kf, kExpStepLo, fma(-kf, kExpStepHi, x)));
+    const double s = ldexp(tab[n & (kExpTab - 1)], n >> kExpTabLog2);
     e = fma(s, q, s);
     em1 = fma(s, q, s - 1.0);
 }
@@ -166,7 +174,7 @@ struct SweepArgs {
     void *P;                      // real
     double *Iem;                  // [n_up][ny][nx] or null
     const double *Iem_base;       // added to Iem in difference mode (or null)
-    const double *xtab;           // [kExpTab] 2^(j/64), the float64 exponential's table
+    const double *xtab;           // [kExpTab] 2^(j/kExpTab), the float64 exponential's table
 };
 
 __device__ inline double expm1_sweep(double x, const double *tab) { return expm1_nonpos_tab(x, tab); }
@@ -464,7 +472,7 @@ struct LstarArgs {
     const double *seg_len;
     const double *chi;
     double *L;                      // [27][V]
-    const double *xtab;             // [kExpTab] 2^(j/64), the float64 exponential's table
+    const double *xtab;             // [kExpTab] 2^(j/kExpTab), the float64 exponential's table
 };
 
 // x + expm1(-x) = e^{-x} - 1 + x for x >= 0 (em1 = e^{-x} - 1 given); below 1/2 by Horner on x^2

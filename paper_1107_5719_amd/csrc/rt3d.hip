@@ -13,7 +13,7 @@
 //                   a layer lands in a distinct voxel: the deposits D_s go into an LDS window without
 //                   atomics, one segment index at a time, and each layer's window is written once to
 //                   a per-band partial plane P.  Deterministic; no float atomics.  The float64
-//                   exponential uses a 64-entry table of 2^(j/64) (per context, copied to LDS).
+//                   exponential uses a 128-entry table of 2^(j/128) (per context, copied to LDS).
 //   reduce_kernel_pair  per voxel (two neighbours of a row per thread), sums the partial planes of
 //                   all directions in a fixed order: J_fs = (1/chi) sum_d W_d |mu_d| sum_bands P, and
 //                   the OS right-hand side chi (J_fs - J).
@@ -569,7 +569,7 @@ int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream
     if (g->bottom_bc == 2) chk(dev_alloc(c, &c->bot_slope, size_t(g->nx) * g->ny));
     chk(dev_alloc(c, &c->xtab, kExpTab));
     if (!rc) {
-        // 2^(j/64) rounded to float64 from the 64-bit-mantissa long double exp2
+        // 2^(j/kExpTab) rounded to float64 from the 64-bit-mantissa long double exp2
         double tab[kExpTab];
         for (int j = 0; j < kExpTab; ++j) tab[j] = double(std::exp2(static_cast<long double>(j) / kExpTab));
         if (hipMemcpy(c->xtab, tab, sizeof(tab), hipMemcpyHostToDevice) != hipSuccess)
