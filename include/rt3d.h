@@ -82,10 +82,16 @@ typedef struct {
 
 typedef struct rt3d_ctx rt3d_ctx;
 
-/* Create a context: validates *g on the host, builds the angle set and the per-direction segment
- * tables, and allocates all device buffers on the current HIP device.  hip_stream is a hipStream_t
- * (NULL = the default stream); every kernel of this context is launched on it.
- * Errors: RT3D_ERR_ARG (bad descriptor or precision, out == NULL), RT3D_ERR_OOM, RT3D_ERR_HIP. */
+/* Create a context: validates *g on the host, builds the angle set, the per-direction segment
+ * tables and the sweep plan, and then allocates all device buffers on the current HIP device.
+ * hip_stream is a hipStream_t (NULL = the default stream); every kernel of this context is launched
+ * on it.  Size limit of the sweep: a workgroup holds whole x-rows of lines (nx <= 1024 with the
+ * default shape) and the float64 deposit windows of a band, 2 (rows + the angle set's row spread per
+ * layer) nx values, fit 48 KB of LDS; with the default shape nx may reach 1024 for 2 x 4 angles, 512
+ * for 8 x 8, 256 for 16 x 16 and 180 for 24 x 24 (ny and nz are limited by memory only).
+ * rt3d_validate checks the same without a device.
+ * Errors: RT3D_ERR_ARG (bad descriptor or precision, out == NULL, a grid beyond the sweep's limits),
+ * RT3D_ERR_OOM, RT3D_ERR_HIP; the reason is in rt3d_last_error(NULL). */
 int rt3d_create(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, void *hip_stream);
 
 /* Free every device buffer and the context.  NULL is ignored. */
@@ -193,7 +199,9 @@ int rt3d_get_stats(rt3d_ctx *ctx, char *json_buf, int buflen);
 /* Static text for a status code. */
 const char *rt3d_status_str(int status);
 
-/* Last error message of a context ("" if none); valid until the next call on the context. */
+/* Last error message of a context ("" if none); valid until the next call on the context.  With
+ * ctx == NULL: the message of the calling thread's last rt3d_create, rt3d_batch_create or
+ * rt3d_validate ("" if it succeeded), valid until that thread's next such call. */
 const char *rt3d_last_error(const rt3d_ctx *ctx);
 
 /* ---- adjoint: gradients through the converged solution ------------------------------------
@@ -268,7 +276,8 @@ enum {
  * and sweep_shape (rt3d_sweep_shapes) shared by all.  hip_stream: a hipStream_t other than the
  * legacy default stream (graphs are captured from it), or NULL for a stream the batch creates (default
  * priority) and destroys.  Errors: RT3D_ERR_ARG (any bad descriptor, n_members < 1, bad precision
- * or shape, a shape whose bands do not fit a grid), RT3D_ERR_OOM, RT3D_ERR_HIP. */
+ * or shape, a shape whose bands do not fit a grid), RT3D_ERR_OOM, RT3D_ERR_HIP; the reason, prefixed
+ * "member i:" when a member failed, is in rt3d_batch_last_error(NULL). */
 int rt3d_batch_create(rt3d_batch **out, int n_members, const rt3d_grid_desc *descs, int precision,
                       int sweep_shape, void *hip_stream);
 
@@ -278,7 +287,8 @@ void rt3d_batch_destroy(rt3d_batch *b);
 /* Number of members (0 for NULL). */
 int rt3d_batch_size(const rt3d_batch *b);
 
-/* Last error message of the batch ("" if none), prefixed "member i:" when a member failed. */
+/* Last error message of the batch ("" if none), prefixed "member i:" when a member failed.  With
+ * b == NULL: as rt3d_last_error(NULL), the calling thread's last failed creation. */
 const char *rt3d_batch_last_error(const rt3d_batch *b);
 
 /* Per member, exactly as rt3d_set_medium / rt3d_set_J / rt3d_get_J of a context; member in
@@ -337,8 +347,9 @@ int rt3d_quadrature(int n_theta, int n_phi, double *mu, double *ox, double *oy, 
 int rt3d_segment_table(const rt3d_grid_desc *g, int d, int k, int *di, int *dj, double *len,
                        int max_seg);
 
-/* Validate a descriptor and (optionally, any may be NULL) host medium arrays exactly as
- * rt3d_create / rt3d_set_medium do.  Returns RT3D_OK or RT3D_ERR_ARG. */
+/* Validate a descriptor (including the sweep's size limits for the shape rt3d_create would take)
+ * and (optionally, any may be NULL) host medium arrays exactly as rt3d_create / rt3d_set_medium do,
+ * on the host only.  Returns RT3D_OK or RT3D_ERR_ARG; the reason is in rt3d_last_error(NULL). */
 int rt3d_validate(const rt3d_grid_desc *g, const double *chi, const double *eps, const double *B);
 
 #ifdef __cplusplus

@@ -704,17 +704,22 @@ extern "C" {
 int rt3d_batch_create(rt3d_batch **out, int n_members, const rt3d_grid_desc *descs, int precision, int sweep_shape,
                       void *hip_stream)
 {
-    if (!out) return RT3D_ERR_ARG;
+    auto reject = [](int rc, const std::string &msg) {
+        set_thread_error(msg);
+        return rc;
+    };
+    if (!out) return reject(RT3D_ERR_ARG, "out is NULL");
     *out = nullptr;
-    if (n_members < 1 || !descs) return RT3D_ERR_ARG;
-    if (precision != RT3D_FP64 && precision != RT3D_FP32_SWEEP) return RT3D_ERR_ARG;
-    if (sweep_shape < 0 || sweep_shape >= n_sweep_shapes()) return RT3D_ERR_ARG;
+    if (n_members < 1 || !descs) return reject(RT3D_ERR_ARG, "n_members < 1 or descs is NULL");
+    if (precision != RT3D_FP64 && precision != RT3D_FP32_SWEEP) return reject(RT3D_ERR_ARG, "bad precision");
+    if (sweep_shape < 0 || sweep_shape >= n_sweep_shapes()) return reject(RT3D_ERR_ARG, "sweep shape out of range");
     for (int i = 0; i < n_members; ++i) {
         std::string msg;
-        if (validate_desc(&descs[i], msg) != RT3D_OK) return RT3D_ERR_ARG;
+        if (validate_desc(&descs[i], msg) != RT3D_OK)
+            return reject(RT3D_ERR_ARG, "member " + std::to_string(i) + ": " + msg);
     }
     rt3d_batch *b = new (std::nothrow) rt3d_batch();
-    if (!b) return RT3D_ERR_OOM;
+    if (!b) return reject(RT3D_ERR_OOM, "out of host memory");
     b->n = n_members;
     b->precision = precision;
     b->shape = sweep_shape;
@@ -722,22 +727,27 @@ int rt3d_batch_create(rt3d_batch **out, int n_members, const rt3d_grid_desc *des
     if (hip_stream) {
         b->stream = static_cast<hipStream_t>(hip_stream);
     } else {
-        if (hipStreamCreate(&b->stream) != hipSuccess) { delete b; return RT3D_ERR_HIP; }
+        if (hipStreamCreate(&b->stream) != hipSuccess) { delete b; return reject(RT3D_ERR_HIP, "hipStreamCreate failed"); }
         b->own_stream = true;
     }
     int rc = RT3D_OK;
+    std::string msg;
     b->m.assign(n_members, nullptr);
     for (int i = 0; i < n_members && !rc; ++i) {
-        std::string msg;
         rc = create_ctx(&b->m[i], &descs[i], precision, b->stream, sweep_shape, msg);
+        if (rc) msg = "member " + std::to_string(i) + ": " + msg;
     }
-    if (!rc) rc = build_tables(b);
+    if (!rc) {
+        rc = build_tables(b);
+        if (rc) msg = b->err;
+    }
     if (rc) {
         rt3d_batch_destroy(b);
-        return rc;
+        return reject(rc, msg);
     }
     b->h_state.assign(n_members, MemberState{});
     *out = b;
+    set_thread_error(std::string());
     return RT3D_OK;
 }
 
@@ -752,7 +762,7 @@ void rt3d_batch_destroy(rt3d_batch *b)
     delete b;
 }
 
-const char *rt3d_batch_last_error(const rt3d_batch *b) { return b ? b->err.c_str() : ""; }
+const char *rt3d_batch_last_error(const rt3d_batch *b) { return b ? b->err.c_str() : thread_error(); }
 
 int rt3d_batch_size(const rt3d_batch *b) { return b ? b->n : 0; }
 

@@ -118,8 +118,16 @@ int n_sweep_shapes();
 // New context with the given sweep shape (index into the shape table); stream may be null.
 int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream_t stream, int shape,
                std::string &msg);
-// (Re)build the sweep plan for a shape and upload its tables; Lambda* and the state are kept.
-int install_plan(rt3d_ctx *c, int shape);
+// The sweep plan of a grid and angle set for a shape, on the host (no device work); false with the
+// reason in msg when the grid does not fit the sweep kernel's line and LDS budgets.
+bool build_plan(const rt3d_grid_desc &g, const rt3d::AngleSet &A, int shape, rt3d::SweepPlan &plan,
+                std::string &msg);
+// (Re)build the sweep plan for a shape (or take the given one) and upload its tables; Lambda* and
+// the state are kept.
+int install_plan(rt3d_ctx *c, int shape, rt3d::SweepPlan *built = nullptr);
+// Message of the calling thread's last failed context or batch creation ("" after a success).
+void set_thread_error(const std::string &msg);
+const char *thread_error();
 // One formal solution from the current J (source, sweep, reduce; no residual), as the context's
 // precision sweeps it.
 int run_fs_plain(rt3d_ctx *c);

@@ -441,6 +441,21 @@ void free_all(rt3d_ctx *c)
 
 int n_sweep_shapes() { return int(sizeof(kSweepShapes) / sizeof(kSweepShapes[0])); }
 
+// Sweep shape of new contexts: RT3D_SWEEP_SHAPE indexes the shape table (default 0, 512 x 2).
+int env_sweep_shape()
+{
+    int shape = 0;
+    if (const char *e = std::getenv("RT3D_SWEEP_SHAPE")) {
+        const int v = std::atoi(e);
+        if (v >= 0 && v < n_sweep_shapes()) shape = v;
+    }
+    return shape;
+}
+
+thread_local std::string t_create_error;
+void set_thread_error(const std::string &msg) { t_create_error = msg; }
+const char *thread_error() { return t_create_error.c_str(); }
+
 int run_fs_plain(rt3d_ctx *c) { return run_fs(c, nullptr, false, c->precision == RT3D_FP32_SWEEP); }
 
 std::string device_key()
@@ -474,16 +489,26 @@ void free_plan(rt3d_ctx *c)
     c->plan_ok = false;
 }
 
-int install_plan(rt3d_ctx *c, int shape)
+bool build_plan(const rt3d_grid_desc &g, const rt3d::AngleSet &A, int shape, rt3d::SweepPlan &plan,
+                std::string &msg)
+{
+    if (shape < 0 || shape >= n_sweep_shapes()) { msg = "sweep shape out of range"; return false; }
+    const SweepShape sh = kSweepShapes[shape];
+    // one plan for both precisions: the LDS windows are budgeted for float64
+    return rt3d::build_sweep_plan(g.nx, g.ny, g.nz, A, sh.threads * sh.lines, 16 * sh.threads, kWindowBytes,
+                                  int(sizeof(double)), plan, msg);
+}
+
+int install_plan(rt3d_ctx *c, int shape, rt3d::SweepPlan *built)
 {
     if (shape < 0 || shape >= n_sweep_shapes()) return fail(c, RT3D_ERR_ARG, "sweep shape out of range");
-    const SweepShape sh = kSweepShapes[shape];
     rt3d::SweepPlan plan;
-    std::string msg;
-    // one plan for both precisions: the LDS windows are budgeted for float64
-    if (!rt3d::build_sweep_plan(c->g.nx, c->g.ny, c->g.nz, c->A, sh.threads * sh.lines, 16 * sh.threads,
-                                kWindowBytes, int(sizeof(double)), plan, msg))
-        return fail(c, RT3D_ERR_ARG, msg);
+    if (built) {
+        plan = std::move(*built);
+    } else {
+        std::string msg;
+        if (!build_plan(c->g, c->A, shape, plan, msg)) return fail(c, RT3D_ERR_ARG, msg);
+    }
     int rc = sync(c);
     if (rc) return rc;
     free_plan(c);
@@ -529,6 +554,9 @@ int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream
     c->real_size = (precision == RT3D_FP64) ? sizeof(double) : sizeof(float);
     c->V = long(g->nx) * g->ny * g->nz;
     if (!rt3d::make_angle_set(g->n_theta, g->n_phi, c->A)) { delete c; msg = "bad angle set"; return RT3D_ERR_ARG; }
+    // the sweep plan first: a grid that does not fit the sweep kernel fails before any allocation
+    rt3d::SweepPlan plan;
+    if (!build_plan(*g, c->A, shape, plan, msg)) { delete c; return RT3D_ERR_ARG; }
     if (const char *e = std::getenv("RT3D_JACOBI_XCD")) c->jacobi_xcd = std::max(0, std::min(4, std::atoi(e)));
     if (const char *e = std::getenv("RT3D_ANCHOR_RATIO")) c->anchor_ratio = std::max(0.0, std::atof(e));
     // Lambda* walk may stop at the first non-neighbour only if no line wraps back within two layers
@@ -575,7 +603,7 @@ int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream
         if (hipMemcpy(c->xtab, tab, sizeof(tab), hipMemcpyHostToDevice) != hipSuccess)
             rc = fail(c, RT3D_ERR_HIP, "upload of the exponential table");
     }
-    if (!rc) rc = install_plan(c, shape);
+    if (!rc) rc = install_plan(c, shape, &plan);
     if (rc) {
         msg = c->err;
         free_all(c);
@@ -610,7 +638,7 @@ const char *rt3d_status_str(int status)
     }
 }
 
-const char *rt3d_last_error(const rt3d_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+const char *rt3d_last_error(const rt3d_ctx *ctx) { return ctx ? ctx->err.c_str() : thread_error(); }
 
 int rt3d_quadrature(int n_theta, int n_phi, double *mu, double *ox, double *oy, double *w)
 {
@@ -646,22 +674,32 @@ int rt3d_validate(const rt3d_grid_desc *g, const double *chi, const double *eps,
 {
     std::string msg;
     int rc = validate_desc(g, msg);
-    if (rc) return rc;
-    return validate_medium_host(long(g->nx) * g->ny * g->nz, chi, eps, B, msg);
+    if (!rc) {
+        rt3d::AngleSet A;
+        rt3d::SweepPlan plan;
+        if (!rt3d::make_angle_set(g->n_theta, g->n_phi, A)) {
+            msg = "bad angle set";
+            rc = RT3D_ERR_ARG;
+        } else if (!build_plan(*g, A, env_sweep_shape(), plan, msg)) {
+            rc = RT3D_ERR_ARG;
+        }
+    }
+    if (!rc) rc = validate_medium_host(long(g->nx) * g->ny * g->nz, chi, eps, B, msg);
+    set_thread_error(rc ? msg : std::string());
+    return rc;
 }
 
 int rt3d_create(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, void *hip_stream)
 {
-    if (!out) return RT3D_ERR_ARG;
-    *out = nullptr;
-    // workgroup shape of the sweep: RT3D_SWEEP_SHAPE indexes the shape table (default 512 x 2)
-    int shape = 0;
-    if (const char *e = std::getenv("RT3D_SWEEP_SHAPE")) {
-        const int v = std::atoi(e);
-        if (v >= 0 && v < n_sweep_shapes()) shape = v;
+    if (!out) {
+        set_thread_error("out is NULL");
+        return RT3D_ERR_ARG;
     }
+    *out = nullptr;
     std::string msg;
-    return create_ctx(out, g, precision, static_cast<hipStream_t>(hip_stream), shape, msg);
+    const int rc = create_ctx(out, g, precision, static_cast<hipStream_t>(hip_stream), env_sweep_shape(), msg);
+    set_thread_error(rc ? msg : std::string());
+    return rc;
 }
 
 void rt3d_destroy(rt3d_ctx *ctx)

@@ -118,13 +118,16 @@ def library():
     return _lib
 
 
-def _raise(ctx, status: int, what: str, last_error=None):
+def _raise(ctx, status: int, what: str, last_error=None, creation=False):
     if status == RT3D_OK:
         return status
-    msg = ""
+    m = None
     if ctx:
         m = (last_error or _lib.rt3d_last_error)(ctx)
-        msg = m.decode() if m else ""
+    elif creation:
+        # with a NULL handle the library reports the calling thread's last failed creation
+        m = _lib.rt3d_last_error(None)
+    msg = m.decode() if m else ""
     if not msg:
         msg = _lib.rt3d_status_str(status).decode()
     raise Rt3dError(status, f"{what}: {msg}")
@@ -177,7 +180,7 @@ def rt3d_create(desc: GridDesc, precision: int = RT3D_FP64, stream=None):
             pass
     ctx = C.c_void_p()
     st = _lib.rt3d_create(C.byref(ctx), C.byref(desc), int(precision), C.c_void_p(stream))
-    _raise(None, st, "rt3d_create")
+    _raise(None, st, "rt3d_create", creation=True)
     return ctx
 
 
@@ -379,7 +382,7 @@ def rt3d_batch_create(descs, precision: int = RT3D_FP64, sweep_shape: int = 0, s
     b = C.c_void_p()
     st = _lib.rt3d_batch_create(C.byref(b), len(descs), C.cast(arr, _vp), int(precision), int(sweep_shape),
                                 C.c_void_p(stream or 0))
-    _raise(None, st, "rt3d_batch_create")
+    _raise(None, st, "rt3d_batch_create", creation=True)
     return b
 
 

@@ -114,6 +114,23 @@ def test_deposits_are_a_bijection_per_segment(R):
                 assert len(np.unique(vox)) == nx * ny
 
 
+def test_validation_reports_the_sweep_size_limits(R):
+    """A grid wider than the sweep kernel's budgets (whole x-rows per workgroup, float64 deposit
+    windows of rows + row spread in 48 KB of LDS) is rejected on the host, by rt3d_validate and by
+    rt3d_create before any device allocation, with the reason in rt3d_last_error(NULL)."""
+    for nt, nph, nmax in ((16, 16, 256), (8, 8, 512), (2, 4, 1024)):
+        assert R.rt3d_validate(R._desc(nmax, 4, 3, nt, nph)) == R.RT3D_OK
+        assert R.rt3d_last_error(None) == ""
+        assert R.rt3d_validate(R._desc(nmax + 1, 4, 3, nt, nph)) == R.RT3D_ERR_ARG
+        msg = R.rt3d_last_error(None)
+        assert ("LDS" in msg) or ("lines" in msg), msg
+        with pytest.raises(R.Rt3dError) as e:
+            R.rt3d_create(R._desc(nmax + 1, 4, 3, nt, nph), R.RT3D_FP64, 0)
+        assert e.value.status == R.RT3D_ERR_ARG and msg in str(e.value)
+    assert R.rt3d_validate(R._desc(2, 5, 5, 8, 8)) == R.RT3D_ERR_ARG
+    assert "nx, ny, nz" in R.rt3d_last_error(None)
+
+
 def test_validation_rejects_bad_input(R):
     good = R._desc(5, 5, 5, 8, 8)
     assert R.rt3d_validate(good) == R.RT3D_OK

@@ -169,8 +169,13 @@ def test_batch_stop_states_and_errors(R):
         assert np.array_equal(s.get_J(), J_b)
     with pytest.raises(R.Rt3dError):
         R.Batch([])
-    with pytest.raises(R.Rt3dError):
+    with pytest.raises(R.Rt3dError) as e:
         R.Batch([dict(grids[0], n_phi=6)])
+    assert "member 0" in str(e.value)
+    # a member wider than the sweep's LDS budget (nx > 256 at 16 x 16 angles) names itself
+    with pytest.raises(R.Rt3dError) as e:
+        R.Batch([grids[0], dict(nx=257, ny=4, nz=3, n_theta=16, n_phi=16)])
+    assert e.value.status == R.RT3D_ERR_ARG and "member 1" in str(e.value) and "LDS" in str(e.value)
 
 
 def test_set_sweep_shape_changes_only_rounding(R):
