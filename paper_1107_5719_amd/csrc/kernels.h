@@ -17,7 +17,7 @@ namespace {
 
 // Sweep workgroup shapes (threads, lines per thread and direction); the context picks one.
 struct SweepShape { int threads, lines; };
-// Measured on MI355X at 129^3 x 256: 512 x 2 is fastest (56 VGPRs, 8 waves/SIMD; the sweep is
+// Measured on MI355X at 129^3 x 256: 512 x 2 is fastest (64 VGPRs, 8 waves/SIMD; the sweep is
 // latency-bound, so occupancy beats lines per thread and prefetching).
 constexpr SweepShape kSweepShapes[] = {{512, 2}, {512, 4}, {256, 8}, {1024, 2}, {256, 4}, {256, 2}};
 // Calls f(NT, LPT) (as integral constants) for the sweep shape with the given index.
@@ -322,8 +322,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
     }
 }
 
+// Two lines per thread fit 64 VGPRs (float64: one value reloaded from scratch per layer), which lets
+// 8 waves share a SIMD (the windows take ~38 KB of LDS at 129 columns, so 4 workgroups of 512 fit a
+// CU); the segment loop waits on its gathers, and 8 waves hide that better than the 6 that 73 VGPRs
+// allow.  Shapes with more lines per thread keep the compiler's choice, and so does the batched
+// kernel (its member arguments would spill inside the segment loop).
+template <int LPT> constexpr int kSweepMinWaves = LPT <= 2 ? 8 : 1;
+
 template <typename real, int NT, int LPT>
-__global__ __launch_bounds__(NT) void sweep_kernel(SweepArgs a)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kSweepMinWaves<LPT>))) void sweep_kernel(SweepArgs a)
 {
     extern __shared__ unsigned char smem_raw[];
     sweep_body<real, NT, LPT>(a, a.items[blockIdx.x], smem_raw);
