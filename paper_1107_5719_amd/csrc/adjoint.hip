@@ -305,7 +305,7 @@ int adjoint_os_step(rt3d_ctx *c, int M, double *dmax, double *numax, int *bad)
     hipLaunchKernelGGL(reduce_kernel_pair<double>,
                        dim3(((c->g.nx + 1) / 2 * c->g.ny + kPlaneThreads - 1) / kPlaneThreads, c->g.nz),
                        dim3(kPlaneThreads), 0, c->stream, ra);
-    if ((rc = check_launch(c, "reduce_kernel (adjoint)"))) return rc;
+    if ((rc = check_launch(c, "reduce_kernel_pair (adjoint)"))) return rc;
     HIP_TRY(c, hipMemsetAsync(c->d_scal, 0, kScalarBytes, c->stream), "memset");
     const bool f32 = c->precision == RT3D_FP32_SWEEP;
     const double *in = nullptr;
