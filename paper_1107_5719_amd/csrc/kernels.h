@@ -325,8 +325,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
 // Two lines per thread fit 64 VGPRs (float64: one value reloaded from scratch per layer), which lets
 // 8 waves share a SIMD (the windows take ~38 KB of LDS at 129 columns, so 4 workgroups of 512 fit a
 // CU); the segment loop waits on its gathers, and 8 waves hide that better than the 6 that 73 VGPRs
-// allow.  Shapes with more lines per thread keep the compiler's choice, and so does the batched
-// kernel (its member arguments would spill inside the segment loop).
+// allow.  Shapes with more lines per thread keep the compiler's choice; the batched kernel has a
+// bound of its own.
 template <int LPT> constexpr int kSweepMinWaves = LPT <= 2 ? 8 : 1;
 
 template <typename real, int NT, int LPT>
