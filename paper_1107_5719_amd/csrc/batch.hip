@@ -484,8 +484,8 @@ int build_tables(rt3d_batch *b)
         NgArgs &g = ng[i];
         g.V = c->V; g.order = c->ng_order; g.hist = c->ng_hist; g.work = c->ng_work; g.J = c->J;
         sc[i] = MemberScalars{c->d_maxrel, c->d_maxdist, c->d_flag};
-        b->smem64 = std::max(b->smem64, 2 * size_t(c->plan.max_win_rows) * nx * sizeof(double));
-        b->smem32 = std::max(b->smem32, 2 * size_t(c->plan.max_win_rows) * nx * sizeof(float));
+        b->smem64 = std::max(b->smem64, sweep_smem_bytes(c->plan.max_win_rows, nx, false));
+        b->smem32 = std::max(b->smem32, sweep_smem_bytes(c->plan.max_win_rows, nx, true));
         // sweep work: a band costs about (segments over all layers) x (line slots per thread)
         for (const WorkItem &it : c->plan.items) {
             double segs = 0.0;

@@ -36,7 +36,14 @@ inline void with_sweep_shape(int shape, F &&f)
     default: f(ShapeTag<512, 2>{}); break;
     }
 }
-constexpr size_t kWindowBytes = 48 * 1024;   // LDS for the two deposit windows of a band
+constexpr size_t kWindowBytes = 48 * 1024;   // LDS for the two deposit windows of a band (float64)
+// Dynamic LDS of a sweep workgroup: the two deposit windows and, in float32, the staged chi,S cells of
+// the window rows (the float32 total equals the float64 windows, so one LDS budget serves both).
+inline size_t sweep_smem_bytes(int max_win_rows, int nx, bool f32)
+{
+    const size_t cells = size_t(max_win_rows) * size_t(nx);
+    return f32 ? cells * (2 * sizeof(float) + sizeof(float2)) : cells * 2 * sizeof(double);
+}
 constexpr int kPlaneThreads = 256;   // voxel-parallel kernels: one thread per voxel of a k-plane
 
 template <typename real> struct Vec2;
@@ -203,6 +210,28 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
     real *winA = reinterpret_cast<real *>(smem_raw);
     real *winB = winA + wsize;
     const real2 *cs = static_cast<const real2 *>(a.cs);
+    // float32: the chi,S cells of the band's window rows are staged in LDS once per layer.  Window row
+    // w holds grid row (j0 + rmin + w) mod ny, so a line's gather cell has the index of its deposit
+    // cell.  (A float64 stage, 16 bytes a cell, would not fit beside the windows without halving the
+    // resident waves; float64 gathers from global memory.)
+    constexpr bool kStaged = std::is_same<real, float>::value;
+    real2 *stage = reinterpret_cast<real2 *>(winB + wsize);
+    auto stage_layer = [&](int kk) {
+        const rt3d::PairLayer Lk = a.player[it.pair * nz + kk];
+        const real2 *csk = cs + long(kk) * plane;
+        const int base = it.j0 + Lk.rmin;
+        const int prs = NT / nx, pcs = NT - prs * nx;     // NT cells = prs rows + pcs columns
+        int w = int(threadIdx.x) / nx, col = int(threadIdx.x) - w * nx;
+        for (int e = threadIdx.x; e < wsize; e += NT) {
+            stage[e] = csk[((base + w) % ny) * nx + col];
+            w += prs;
+            col += pcs;
+            if (col >= nx) {
+                col -= nx;
+                ++w;
+            }
+        }
+    };
     real *P = static_cast<real *>(a.P) + pi.p_off + long(it.band) * nz * wsize;
 
     for (int e = threadIdx.x; e < 2 * wsize; e += NT) winA[e] = real(0);
@@ -222,6 +251,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
         IA[t] = real(a.I_top);
         IB[t] = real(a.I_top);
     }
+    if constexpr (kStaged) stage_layer(pi.down ? nz - 1 : 0);
     __syncthreads();
 
     for (int step = 0; step < nz; ++step) {
@@ -258,12 +288,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
             unsigned colA[LPT], colB[LPT];
 #pragma unroll
             for (int t = 0; t < LPT; ++t) {
-                const unsigned grow = wrap_once(grow0[t] + unsigned(g.smnx), plane);
                 colA[t] = wrap_once(unsigned(li[t] + g.saA), nx);
                 colB[t] = wrap_once(unsigned(li[t] + g.saB), nx);
-                if (li[t] >= 0) {
-                    cA[t] = csk[grow + colA[t]];
-                    cB[t] = csk[grow + colB[t]];
+                if constexpr (!kStaged) {
+                    const unsigned grow = wrap_once(grow0[t] + unsigned(g.smnx), plane);
+                    if (li[t] >= 0) {
+                        cA[t] = csk[grow + colA[t]];
+                        cB[t] = csk[grow + colB[t]];
+                    }
                 }
             }
             // At one segment index the lines of a direction deposit into distinct cells (and the two
@@ -276,6 +308,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
                 const unsigned wrow = lbase[t] + unsigned(g.sbnx);
                 wA[t] = wrow + colA[t];
                 wB[t] = wrow + colB[t];
+                if constexpr (kStaged) {
+                    if (li[t] >= 0) {
+                        cA[t] = stage[wA[t]];
+                        cB[t] = stage[wB[t]];
+                    }
+                }
                 oA[t] = li[t] >= 0 ? winA[wA[t]] : real(0);
                 oB[t] = li[t] >= 0 ? winB[wB[t]] : real(0);
             }
@@ -304,6 +342,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
             Pk[e] = winA[e] + winB[e];
             winA[e] = real(0);
             winB[e] = real(0);
+        }
+        if constexpr (kStaged) {
+            if (step + 1 < nz) stage_layer(pi.down ? k - 1 : k + 1);
         }
         __syncthreads();
     }

@@ -224,7 +224,7 @@ int launch_sweep(rt3d_ctx *c, bool fp32, bool diff)
     a.Iem = c->Iem;
     a.Iem_base = diff ? c->Iem_a : nullptr;
     a.xtab = c->xtab;
-    const size_t smem = 2 * size_t(c->plan.max_win_rows) * c->g.nx * (fp32 ? sizeof(float) : sizeof(double));
+    const size_t smem = sweep_smem_bytes(c->plan.max_win_rows, c->g.nx, fp32);
     const dim3 grid(c->plan.items.size());
     TimedLaunch t(c, K_SWEEP);
     if (fp32) c->fp32_sweeps += 1; else c->fp64_sweeps += 1;
