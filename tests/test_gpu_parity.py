@@ -62,6 +62,7 @@ FS_CASES = [
     ((6, 5, 7), 2, 4, 7, 0.2, 0),        # smallest angle set; every line runs through voxel edges
     ((5, 8, 6), 8, 4, 8, 0.0, 0),        # n_phi = 4 with steep and shallow directions
     ((6, 7, 5), 8, 8, 9, 0.1, 2),        # LTE-diffusion inner condition
+    ((3, 4, 256), 16, 16, 10, 0.0, 0),   # the widest grid for 16 x 16 angles: windows fill the LDS budget
 ]
 
 
