@@ -131,6 +131,20 @@ def test_validation_reports_the_sweep_size_limits(R):
     assert "nx, ny, nz" in R.rt3d_last_error(None)
 
 
+def test_failed_batch_creation_names_the_member(R):
+    """rt3d_batch_create validates every member descriptor on the host, before any device work; the
+    reason of the failure, naming the member, is in rt3d_batch_last_error(NULL)."""
+    good, bad = R._desc(5, 5, 5, 8, 8), R._desc(5, 5, 5, 8, 6)
+    with pytest.raises(R.Rt3dError) as e:
+        R.rt3d_batch_create([good, bad], R.RT3D_FP64, 0)
+    assert e.value.status == R.RT3D_ERR_ARG
+    assert "member 1" in str(e.value) and "n_phi" in str(e.value)
+    assert R.rt3d_batch_last_error(None).startswith("member 1")
+    with pytest.raises(R.Rt3dError) as e:
+        R.rt3d_batch_create([good], R.RT3D_FP64, 99)
+    assert "sweep shape" in str(e.value)
+
+
 def test_validation_rejects_bad_input(R):
     good = R._desc(5, 5, 5, 8, 8)
     assert R.rt3d_validate(good) == R.RT3D_OK
