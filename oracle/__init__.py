@@ -40,14 +40,32 @@ def build(force: bool = True) -> str:
 
 
 _lib = None
+_lib_path = None
+
+
+def build_native(directory: str) -> str:
+    """Compile oracle.c with the flags of the timed CPU baseline (gcc -O3 -march=native, OpenMP over
+    directions) into `directory` -- on the host that will run it, since the instruction set follows
+    that host -- and return the library's path.  The checker library (``build``) stays portable."""
+    path = os.path.join(directory, "liboracle_native.so")
+    cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", path, "-lm"]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return path
+
+
+def use_library(path=None):
+    """Load the oracle from another build of oracle.c (None: the in-tree checker library)."""
+    global _lib, _lib_path
+    _lib, _lib_path = None, path
+    return lib()
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _lib_path is None and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build()
-        L = C.CDLL(_LIB)
+        L = C.CDLL(_lib_path or _LIB)
         i, d = C.c_int, C.c_double
         L.orc_gauss_legendre.argtypes = [i, _dp, _dp]
         L.orc_quadrature.argtypes = [i, i, _dp, _dp, _dp, _dp]

@@ -559,10 +559,14 @@ static void os_inner(int nx, int ny, int nz, const double *eps, const double *Ls
     orc_gs_colour(nz, 0, 0, &ncz);
     const int n_pass = method == 1 ? ncx * ncy * ncz : 1;
     for (int m = 0; m < M; ++m) {
-        /* Jacobi reads the previous sweep (dJ) and writes dJn; Gauss-Seidel reads and writes dJ */
+        /* Jacobi reads the previous sweep (dJ) and writes dJn; Gauss-Seidel reads and writes dJ.
+         * Within a Jacobi sweep (and within one colour of a Gauss-Seidel pass) no voxel reads a value
+         * written in the same pass, so the layers may be updated by several threads at once; each
+         * voxel's sum keeps its order, so the result does not depend on the thread count. */
         const double *src = dJ;
         double *dst = method == 1 ? dJ : dJn;
         for (int pass = 0; pass < n_pass; ++pass)
+#pragma omp parallel for schedule(static)
             for (int k = 0; k < nz; ++k)
                 for (int j = 0; j < ny; ++j)
                     for (int i = 0; i < nx; ++i) {

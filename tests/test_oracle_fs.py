@@ -213,3 +213,41 @@ def test_lte_diffusion_boundary_pins(orc):
     J3 = orc.formal_solution(chi3, S3, 8, 8, I_top=0.2, I_bot=B3[0], I_slope=sl)
     J1 = orc.pp1d(chi_k, S_k, 8, I_top=0.2, I_bot=B_k[0], I_slope=(B_k[0] - B_k[1]) / (0.5 * (chi_k[0] + chi_k[1])))
     np.testing.assert_allclose(J3, np.broadcast_to(J1[:, None, None], J3.shape), rtol=1e-13)
+
+
+def test_lte_diffusion_slope_pinned_by_optical_depth(orc):
+    """The gradient of the LTE-diffusion condition, pinned by two facts that do not restate its formula.
+
+    * Definition: with B a linear function a + s tau of the optical depth tau measured inwards from
+      the top (tau of a voxel centre = the opacity of all voxels above it plus half its own), the
+      condition's dB/dtau is s in every column, for any opacities.
+    * Transfer: for S = B = a + s tau (eps = 1) in a semi-infinite medium the emergent intensity is
+      exactly a + s mu.  A finite slab closed by the diffusion condition emits that value up to the
+      discretisation (piecewise-constant S; the condition sits half a voxel below the bottom centre),
+      so its error falls in proportion to the layer thickness under refinement; closed by I = B_0 or
+      by the slope with the wrong sign, the error stays at the order of s mu e^{-tau/mu}."""
+    rng = np.random.default_rng(3)
+    nz, ny, nx = 5, 4, 6
+    chi = np.exp(rng.uniform(np.log(0.01), np.log(50.0), (nz, ny, nx)))
+    a, s = 1.3, 0.45
+    tau_c = np.cumsum(chi[::-1], axis=0)[::-1] - 0.5 * chi
+    B = a + s * tau_c
+    np.testing.assert_allclose(orc.diffusion_slope(chi, B), s, rtol=1e-10)
+    mu = orc.quadrature(8, 8)[0]
+    exact = a + s * mu[mu > 0]
+    tau_b = 2.0
+    errs = {"diffusion": [], "B": [], "negative": []}
+    for N in (16, 32, 64, 128):
+        chi_k = np.full(N, tau_b / N)
+        B_k = a + s * (np.cumsum(chi_k[::-1])[::-1] - 0.5 * chi_k)
+        chi3 = np.broadcast_to(chi_k[:, None, None], (N, 3, 3)).copy()
+        B3 = np.broadcast_to(B_k[:, None, None], (N, 3, 3)).copy()
+        sl = orc.diffusion_slope(chi3, B3)
+        for name, slope in (("diffusion", sl), ("B", None), ("negative", -sl)):
+            _, Iem = orc.formal_solution(chi3, B3, 8, 8, I_bot=B3[0], I_slope=slope, want_emergent=True)
+            errs[name].append(float(np.max(np.abs(Iem[:, 1, 1] - exact))))
+    e = errs["diffusion"]
+    for coarse, fine in zip(e, e[1:]):
+        assert 1.8 < coarse / fine < 2.2, e
+    assert e[-1] < 0.01 * errs["B"][-1]
+    assert min(errs["B"]) > 0.05 and min(errs["negative"]) > 0.1, errs
