@@ -24,50 +24,101 @@ sys.path.insert(0, ROOT)
 
 METRIC = "voxel·angle FS updates/s + time-to-converged J, 129³×256 angles, FP32 vs FP64"
 HBM_PEAK_GBS = 8000.0
-# MI355X vector peaks: 256 CUs x 2.4 GHz; FP64 78.6 TFLOP/s, FP32 157.3 TFLOP/s (FMA = 2 flops)
-ALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
-# Arithmetic per voxel-angle update of the sweep, counted per segment and multiplied by the mean
-# segments per voxel-angle of the 16 x 16 angle set (4.05): dtau = chi l (1); e^-dtau - 1 (float64 by
-# the 128-entry table: clamp, scale-and-round FMA, subtract, 1 reduction FMA, 4 Horner FMAs, r p,
-# scale by 2^k, s - 1, final FMA = 12; float32 with 8 Horner FMAs and no table = 17); (I - S) em1 (2);
-# I += dI (1); D = S dtau - dI (1); window += D (1): 18 (float64) / 23 (float32) per segment, i.e.
-# 73 / 93 vector operations per update, each priced as an FMA issue slot (2 flops).
-SWEEP_OPS_PER_UPDATE = {"fp64": 73, "fp32": 93}
+# MI355X vector issue: 256 CUs x 4 SIMDs x 2.4 GHz; float64 16 lanes per SIMD and cycle (78.6 TFLOP/s
+# counting an FMA as 2 flops, i.e. 39.3e12 lane-instructions/s), float32 32 lanes (78.6e12)
+VALU_ISSUE_PEAK = {"fp64": 39.3e12, "fp32": 78.6e12}
 SWEEP_KERNEL = {"fp64": "sweep_kernel<double,512,2>", "fp32": "sweep_kernel<float,512,2>"}
 JACOBI_KERNEL = {"fp64": "jacobi_kernel_column<double>", "fp32": "jacobi_kernel_column<float>"}
+# the (M, Ng order, Ng every) schedules over which time to converged J is summarised (median, worst)
+SCHEDULES = [(12, 3, 6), (20, 3, 6), (30, 3, 6), (40, 3, 6), (12, 3, 8), (20, 3, 8), (30, 3, 8), (40, 3, 8)]
 
 
-def sweep_bytes_per_update(precision: str) -> int:
-    """Algorithmic HBM bytes of the sweep kernel per voxel-angle update: chi and S of the voxel read
-    once per direction, and one partial-plane value per direction pair (x-mirrored directions share
-    it), i.e. half a value per direction."""
+def sweep_bytes_per_update(precision: str, G: int = 1) -> int:
+    """Algorithmic HBM bytes of the formal-solution sweep per voxel-angle update, (2 s_r + 16) / G: chi
+    and S of the voxel (s_r bytes each: 8 in float64, 4 in float32 sweeps) and a float64 read-modify-
+    write of the voxel's J partial, shared by the G directions that use one staged slab (G = 1 here:
+    every direction gathers its own chi, S)."""
     s_r = 8 if precision == "fp64" else 4
-    return 2 * s_r + s_r // 2
+    return (2 * s_r + 16) // G
 
 
-def jacobi_bytes_per_voxel(precision: str) -> int:
+def jacobi_bytes_per_voxel(coef: str) -> int:
     """Algorithmic HBM bytes of one intermediate Jacobi sweep per voxel: 13 stored coefficients (the
     other 13 are their mirrors), the right-hand side chi (J_fs - J), E = (1 - eps)/D, the previous
-    (1 - eps) dJ and the new one (float64 but for the coefficients of the FP32 form)."""
-    return 13 * (8 if precision == "fp64" else 4) + 4 * 8
+    (1 - eps) dJ and the new one (float64 but for float32-stored coefficients)."""
+    return 13 * (8 if coef == "fp64" else 4) + 4 * 8
+
+
+def _kernel_sha() -> str:
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_1107_5719_amd", "csrc", "kernels.h")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
 def measured_traffic(kernel: str):
     """HBM bytes per dispatch (FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration) from the
     committed rocprofv3 summary, or None if the kernel source changed since it was measured."""
-    import hashlib
-
-    src = os.path.join(ROOT, "paper_1107_5719_amd", "csrc", "kernels.h")
     prof = os.path.join(ROOT, "profiles", "strat129_hbm_bytes.txt")
     if not os.path.exists(prof):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = _kernel_sha()
     for line in open(prof):
         if line.startswith("TRAFFIC "):
             f = dict(kv.split("=", 1) for kv in line.split()[1:])
             if f["kernel"] == kernel and f["source_sha"] == sha:
                 return int(f["fetch_bytes"]) + int(f["write_bytes"])
     return None
+
+
+def measured_valu(kernel: str):
+    """SQ_INSTS_VALU (wave instructions per dispatch) of a kernel from the committed rocprofv3
+    counter summary, or None if the kernel source changed since it was measured."""
+    prof = os.path.join(ROOT, "profiles", "strat129_sq_counters.txt")
+    if not os.path.exists(prof):
+        return None
+    sha = None
+    for line in open(prof):
+        if line.startswith("# kernel source sha256[:16]:"):
+            sha = line.rsplit(":", 1)[1].strip()
+        elif line.startswith(kernel + " ") and sha == _kernel_sha():
+            f = dict(kv.split("=", 1) for kv in line.split() if "=" in kv)
+            return float(f["SQ_INSTS_VALU"])
+    return None
+
+
+def oracle_reference(w, med):
+    """The oracle's tightly converged J of a workload, as written by the committed CPU-only script
+    (python -m oracle.make_reference <name>) into oracle/reference/: (J, meta) when the stored file
+    belongs to these inputs, else (None, reason).  The input hash follows the script's definition:
+    SHA-256 of the grid, angle set, top light and the chi, eps, B arrays."""
+    import hashlib
+
+    import numpy as np
+
+    base = os.path.join(ROOT, "oracle", "reference", w.name)
+    if not (os.path.exists(base + ".npz") and os.path.exists(base + ".json")):
+        return None, f"no stored oracle solution (python -m oracle.make_reference {w.name})"
+    meta = json.load(open(base + ".json"))
+    h = hashlib.sha256(f"{w.nx}x{w.ny}x{w.nz}|{w.n_theta}x{w.n_phi}|I_top={w.I_top!r}".encode())
+    for k in ("chi", "eps", "B"):
+        h.update(np.ascontiguousarray(med[k], dtype=np.float64).tobytes())
+    if meta.get("input_sha256") != h.hexdigest():
+        return None, "stored oracle solution belongs to other inputs"
+    J = np.load(base + ".npz", allow_pickle=False)["J"]
+    if hashlib.sha256(np.ascontiguousarray(J).tobytes()).hexdigest() != meta.get("J_sha256"):
+        return None, "stored oracle solution does not match its recorded hash"
+    src = hashlib.sha256(open(os.path.join(ROOT, "oracle", "oracle.c"), "rb").read()).hexdigest()
+    meta = {k: meta[k] for k in ("tol", "iterations", "final_max_rel_dJ", "min_max_rel_dJ", "stop",
+                                 "inner_sweeps", "ng_order", "ng_every") if k in meta}
+    meta["oracle_source_unchanged"] = src == json.load(open(base + ".json")).get("oracle_sha256")
+    return J, meta
+
+
+def _rel_err(J, ref) -> float:
+    import torch
+
+    return float(torch.max(torch.abs(J / ref - 1)).item())
 
 
 def _cpu_model() -> str:
@@ -80,9 +131,12 @@ def _cpu_model() -> str:
     return f"unknown ({os.cpu_count()} logical CPUs visible)"
 
 
-def _timed_steps(rt3d, torch, w, d_med, prec, stream, steps, warmup, M):
-    """K timed OS steps after W warm-up steps; per-kernel HIP-event times from the library."""
+def _timed_steps(rt3d, torch, w, d_med, prec, stream, steps, warmup, M, coef=None):
+    """K timed OS steps after W warm-up steps; per-kernel HIP-event times from the library.  coef:
+    storage of the Jacobi coefficients (None: the form's default)."""
     s = rt3d.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi, I_top=w.I_top, precision=prec, stream=stream)
+    if coef is not None:
+        s.set_coef_storage(coef)
     s.set_medium(d_med["chi"], d_med["eps"], d_med["B"])
     t0 = time.perf_counter()
     s.build_lstar()
@@ -105,9 +159,12 @@ def _timed_steps(rt3d, torch, w, d_med, prec, stream, steps, warmup, M):
     return elapsed, per_launch, lstar_s, st
 
 
-def _converge(rt3d, torch, w, d_med, prec, stream, M, ng_order, ng_every, tol, max_iter, os_method=0):
+def _converge(rt3d, torch, w, d_med, prec, stream, M, ng_order, ng_every, tol, max_iter, os_method=0,
+              coef=None):
     """Time from resident inputs (Lambda* build included) to max rel dJ < tol."""
     s = rt3d.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi, I_top=w.I_top, precision=prec, stream=stream)
+    if coef is not None:
+        s.set_coef_storage(coef)
     s.set_medium(d_med["chi"], d_med["eps"], d_med["B"])
     s.set_os_method(os_method)
     if ng_order:
@@ -190,7 +247,7 @@ def _batched(rt3d, torch, n_wl, M, ng, tol, ref_tol, max_iter, cache):
 
     for name, prec in (("batched_fp64", rt3d.RT3D_FP64), ("batched_fp32", rt3d.RT3D_FP32_SWEEP)):
         Js, res = run_batch(prec, tol, 5)
-        res["max_rel_err_vs_reference"] = err(Js)
+        res["max_rel_err_vs_batched_fp64_reference"] = err(Js)
         out[name] = res
     # plain float64 path, one wavelength after another
     singles = []
@@ -213,7 +270,7 @@ def _batched(rt3d, torch, n_wl, M, ng, tol, ref_tol, max_iter, cache):
     for s in singles:
         s.close()
     out["sequential_fp64"] = {"seconds": round(secs, 4), "iters_max": max(its), "iters_sum": sum(its),
-                              "max_rel_err_vs_reference": err(Js)}
+                              "max_rel_err_vs_batched_fp64_reference": err(Js)}
     out["batched_fp64_speedup"] = round(secs / out["batched_fp64"]["seconds"], 3)
     out["batched_fp32_speedup"] = round(secs / out["batched_fp32"]["seconds"], 3)
     return out
@@ -297,6 +354,33 @@ def _adjoint(rt3d, torch, n_fd, M):
     return out
 
 
+def _config_line(rt3d, torch, w, stream, steps, warmup, M, ng, max_iter):
+    """One smaller workload: OS-step rate of both forms and their time to converged J (tol of the
+    workload, Lambda* included), with the error against the oracle's stored solution."""
+    from paper_1107_5719_amd.inputs import make_medium
+
+    med = make_medium(w)
+    d_med = {k: torch.from_numpy(v).cuda() for k, v in med.items()}
+    J_orc, meta = oracle_reference(w, med)
+    J_orc = None if J_orc is None else torch.from_numpy(J_orc).cuda()
+    row = {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} voxels x {w.n_dir} angles, eps={w.eps:g}, "
+                       f"tau_total={w.tau_total:g}, noise {w.noise} sigma={w.sigma}, seed {w.seed}",
+           "tol": w.tol, "inner_sweeps": M, "ng_order": ng[0], "ng_every": ng[1], "oracle_reference": meta}
+    for form, prec in (("fp64", rt3d.RT3D_FP64), ("fp32", rt3d.RT3D_FP32_SWEEP)):
+        elapsed, per_launch, lstar_s, st = _timed_steps(rt3d, torch, w, d_med, prec, stream, steps, warmup, M)
+        J, conv = _converge(rt3d, torch, w, d_med, prec, stream, M, ng[0], ng[1], w.tol, max_iter)
+        if J_orc is not None:
+            conv["max_rel_err_vs_oracle"] = _rel_err(J, J_orc)
+        row[form] = {"ms_per_step": round(1e3 * elapsed / steps, 4),
+                     "voxel_angle_updates_per_s": w.n_vox * w.n_dir * steps / elapsed,
+                     "kernel_ms_per_launch": {k: (round(v, 4) if v is not None else None)
+                                              for k, v in per_launch.items()},
+                     "time_to_converged": conv}
+    row["fp32_form_speedup"] = round(row["fp64"]["time_to_converged"]["seconds"] /
+                                     row["fp32"]["time_to_converged"]["seconds"], 3)
+    return row
+
+
 def _paper_grids(rt3d, torch, stream, steps, M, ng, max_iter):
     """The paper's slab on its two timing grids (65^3 and 129^2 x 193, 256 angles): OS-step rate and
     time to converged J (tol 1e-8, Lambda* included), both forms."""
@@ -344,6 +428,8 @@ def main() -> int:
     ap.add_argument("--adjoint-fd-voxels", type=int, default=50,
                     help="finite-difference checks of the adjoint at 65^3 x 64 (0 skips them; -1 skips "
                          "the adjoint measurement)")
+    ap.add_argument("--configs", type=int, default=1,
+                    help="also measure the 17^3 x 64 and 65^3 x 256 workloads (0 skips)")
     ap.add_argument("--paper-grids", type=int, default=1,
                     help="also measure the paper's slab on its 65^3 and 129^2 x 193 grids (0 skips)")
     ap.add_argument("--tune-cache", default=None,
@@ -411,67 +497,130 @@ def main() -> int:
                       "lstar_build_s": round(lstar_s, 4),
                       "sweeps": {"fp64": st["fp64_sweeps"], "fp32": st["fp32_sweeps"]}}
     main_form = args.precision
-    sweep_ms = step[main_form]["kernel_ms_per_launch"]["sweep"]
-    upd_per_s = V * n_dir / (sweep_ms * 1e-3)
-    tflops = 2 * SWEEP_OPS_PER_UPDATE[main_form] * upd_per_s / 1e12
-    b_unit = sweep_bytes_per_update(main_form)
-    hbm_gbs = b_unit * upd_per_s / 1e9
-    roofline = {"kernel": SWEEP_KERNEL[main_form], "bound": "alu", "achieved": round(tflops, 2),
-                "peak": ALU_PEAK_TFLOPS[main_form], "unit": "TFLOP/s",
-                "frac": round(tflops / ALU_PEAK_TFLOPS[main_form], 4),
-                "traffic": measured_traffic(SWEEP_KERNEL[main_form]),
-                "ops_per_update": 2 * SWEEP_OPS_PER_UPDATE[main_form], "ms_per_launch": sweep_ms,
-                "hbm_view": {"achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "bytes_per_update": b_unit}}
-    jac_ms = step[main_form]["kernel_ms_per_launch"]["jacobi"]
-    jac_gbs = jacobi_bytes_per_voxel(main_form) * V / (jac_ms * 1e-3) / 1e9
-    roofline_jacobi = {"kernel": JACOBI_KERNEL[main_form], "bound": "hbm", "achieved": round(jac_gbs, 1),
-                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(jac_gbs / HBM_PEAK_GBS, 4),
-                       "traffic": measured_traffic(JACOBI_KERNEL[main_form]),
-                       "bytes_per_voxel": jacobi_bytes_per_voxel(main_form), "ms_per_launch": jac_ms}
+    upd = V * n_dir
 
-    # ---- time to converged J, both forms, against a tight float64 reference -------------------------
+    def sweep_roofline(form):
+        """The sweep against HBM with the algorithmic bytes (2 s_r + 16)/G per voxel-angle update at
+        G = 1, from its average launch time in the timed steps (HIP events on the context stream)."""
+        sweep_ms = step[form]["kernel_ms_per_launch"]["sweep"]
+        upd_per_s = upd / (sweep_ms * 1e-3)
+        b_unit = sweep_bytes_per_update(form)
+        gbs = b_unit * upd_per_s / 1e9
+        traffic = measured_traffic(SWEEP_KERNEL[form])
+        valu = measured_valu(SWEEP_KERNEL[form])
+        r = {"kernel": SWEEP_KERNEL[form], "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+             "G": 1, "bytes_per_update": b_unit, "updates_per_launch": upd, "ms_per_launch": sweep_ms}
+        # beside it: the measured HBM traffic (rocprofv3 FETCH_SIZE + WRITE_SIZE per launch) over the same
+        # duration, and the vector issue (rocprofv3 SQ_INSTS_VALU x 64 lanes per update) against the
+        # chip's issue rate for the sweep's precision
+        r["counter_view"] = None if traffic is None else {
+            "achieved": round(traffic / (sweep_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(traffic / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "bytes_per_update": round(traffic / upd, 2)}
+        r["alu_view"] = None if valu is None else {
+            "achieved": round(64 * valu / (sweep_ms * 1e-3) / 1e12, 2), "peak": VALU_ISSUE_PEAK[form] / 1e12,
+            "unit": "T lane-instructions/s", "frac": round(64 * valu / (sweep_ms * 1e-3) / VALU_ISSUE_PEAK[form], 4),
+            "lane_instructions_per_update": round(64 * valu / upd, 1)}
+        return r
+
+    roofline = sweep_roofline(main_form)
+    roofline_other = sweep_roofline("fp32" if main_form == "fp64" else "fp64")
+    roofline_jacobi = {}
+    for form, coef in (("fp64", "fp64"), ("fp32", "fp32")):
+        jac_ms = step[form]["kernel_ms_per_launch"]["jacobi"]
+        jac_gbs = jacobi_bytes_per_voxel(coef) * V / (jac_ms * 1e-3) / 1e9
+        traffic = measured_traffic(JACOBI_KERNEL[form])
+        roofline_jacobi[form] = {
+            "kernel": JACOBI_KERNEL[form], "bound": "hbm", "achieved": round(jac_gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(jac_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_over_algorithmic": None if traffic is None else round(traffic / (jacobi_bytes_per_voxel(coef) * V), 3),
+            "bytes_per_voxel": jacobi_bytes_per_voxel(coef), "coef_storage": coef, "ms_per_launch": jac_ms,
+            "os_solve_ms": round(M * jac_ms, 3)}
+
+    # ---- time to converged J, both forms, against the oracle's tightly converged J ---------------------
+    J_orc, orc_meta = oracle_reference(w, med)
+    J_orc = None if J_orc is None else torch.from_numpy(J_orc).to(dev)
     conv = None
     if args.converge_max_iter > 0:
-        conv = {"tol": w.tol, "inner_sweeps": M, "ng_order": args.ng_order, "ng_every": args.ng_every}
-        J_ref, ref = _converge(rt3d, torch, w, d_med, rt3d.RT3D_FP64, stream, M, args.ng_order,
-                               args.ng_every, args.reference_tol, 20 * args.converge_max_iter)
-        conv["reference"] = {"tol": args.reference_tol, **ref}
+        conv = {"tol": w.tol, "inner_sweeps": M, "ng_order": args.ng_order, "ng_every": args.ng_every,
+                "oracle_reference": orc_meta}
+        # a float64 GPU solve to reference_tol: the reference when no oracle solution is stored
+        J_gref, ref = _converge(rt3d, torch, w, d_med, rt3d.RT3D_FP64, stream, M, args.ng_order,
+                                args.ng_every, args.reference_tol, 20 * args.converge_max_iter)
+        conv["gpu_fp64_reference"] = {"tol": args.reference_tol, **ref}
+        if J_orc is not None:
+            conv["gpu_fp64_reference"]["max_rel_err_vs_oracle"] = _rel_err(J_gref, J_orc)
+
+        def errs(J):
+            e = {"max_rel_err_vs_gpu_fp64_reference": _rel_err(J, J_gref)}
+            if J_orc is not None:
+                e["max_rel_err_vs_oracle"] = _rel_err(J, J_orc)
+            return e
+
         for name, prec in forms.items():
             J, res = _converge(rt3d, torch, w, d_med, prec, stream, M, args.ng_order, args.ng_every, w.tol,
                                args.converge_max_iter)
-            res["max_rel_err_vs_reference"] = float(torch.max(torch.abs(J / J_ref - 1)).item())
-            conv[name] = res
+            conv[name] = {**res, **errs(J)}
         conv["fp32_form_speedup"] = round(conv["fp64"]["seconds"] / conv["fp32"]["seconds"], 3)
-        # the same comparison under a second schedule that is less sensitive to M (Ng 3 every 8, M = 20),
-        # so that the forms' ratio does not rest on one sharp optimum of the step count
-        alt = {"inner_sweeps": 20, "ng_order": 3, "ng_every": 8}
+        # sweep precision x coefficient storage, each at the schedule above: the float32-sweep effect
+        # with equal coefficient storage
+        grid = {}
+        for sname, prec in forms.items():
+            for cname, coef in (("fp64", rt3d.RT3D_COEF_FP64), ("fp32", rt3d.RT3D_COEF_FP32)):
+                J, res = _converge(rt3d, torch, w, d_med, prec, stream, M, args.ng_order, args.ng_every, w.tol,
+                                   args.converge_max_iter, coef=coef)
+                grid[f"sweeps_{sname}_coef_{cname}"] = {**res, **errs(J)}
+        for cname in ("fp64", "fp32"):
+            grid[f"fp32_sweep_speedup_coef_{cname}"] = round(
+                grid[f"sweeps_fp64_coef_{cname}"]["seconds"] / grid[f"sweeps_fp32_coef_{cname}"]["seconds"], 3)
+        conv["precision_grid"] = grid
+        # a fixed set of schedules (M x Ng every), so that the forms' comparison does not rest on one
+        # sharp optimum of the outer step count
+        import statistics
+
+        sched = {"schedules": [list(x) for x in SCHEDULES]}
         for name, prec in forms.items():
-            J, res = _converge(rt3d, torch, w, d_med, prec, stream, 20, 3, 8, w.tol, args.converge_max_iter)
-            res["max_rel_err_vs_reference"] = float(torch.max(torch.abs(J / J_ref - 1)).item())
-            alt[name] = res
-        alt["fp32_form_speedup"] = round(alt["fp64"]["seconds"] / alt["fp32"]["seconds"], 3)
-        conv["second_schedule"] = alt
+            rows = []
+            for (m_, o_, e_) in SCHEDULES:
+                J, res = _converge(rt3d, torch, w, d_med, prec, stream, m_, o_, e_, w.tol, args.converge_max_iter)
+                rows.append({"inner_sweeps": m_, "ng_order": o_, "ng_every": e_, "seconds": res["seconds"],
+                             "outer_iterations": res["outer_iterations"], "converged": res["converged"],
+                             **errs(J)})
+            secs = [r["seconds"] for r in rows]
+            sched[name] = {"runs": rows, "median_s": statistics.median(secs), "worst_s": max(secs),
+                           "best_s": min(secs)}
+        sched["fp32_form_speedup_median"] = round(sched["fp64"]["median_s"] / sched["fp32"]["median_s"], 3)
+        sched["fp32_form_speedup_worst"] = round(sched["fp64"]["worst_s"] / sched["fp32"]["worst_s"], 3)
+        conv["schedules"] = sched
         # the Fortran code's other inner solve: multicolour Gauss-Seidel, float64, half the sweeps
         if args.gs_inner_sweeps > 0:
             J, res = _converge(rt3d, torch, w, d_med, rt3d.RT3D_FP64, stream, args.gs_inner_sweeps,
                                args.ng_order, args.ng_every, w.tol, args.converge_max_iter,
                                os_method=rt3d.RT3D_OS_GAUSS_SEIDEL)
-            res["max_rel_err_vs_reference"] = float(torch.max(torch.abs(J / J_ref - 1)).item())
-            conv["gauss_seidel_fp64"] = {"inner_sweeps": args.gs_inner_sweeps, **res}
-        # equal accuracy: the time each form needs to come within 1e-5 and within 1e-8 of the reference
-        # (stopping at c < target / 100; the error reached is reported beside the time)
+            conv["gauss_seidel_fp64"] = {"inner_sweeps": args.gs_inner_sweeps, **res, **errs(J)}
+        # equal accuracy: the time each form needs to come within 1e-5 and within 1e-8 of the oracle (of
+        # the GPU reference when no oracle solution is stored), stopping at c < target / 100
         conv["accuracy_targets"] = {}
         for target in (1e-5, 1e-8):
             row = {"stop_tol": target / 100}
             for name, prec in forms.items():
                 J, res = _converge(rt3d, torch, w, d_med, prec, stream, M, args.ng_order, args.ng_every,
                                    target / 100, 20 * args.converge_max_iter)
-                err = float(torch.max(torch.abs(J / J_ref - 1)).item())
-                row[name] = {"seconds": res["seconds"], "outer_iterations": res["outer_iterations"],
-                             "max_rel_err_vs_reference": err, "within_target": err <= target}
+                e = errs(J)
+                err = e.get("max_rel_err_vs_oracle", e["max_rel_err_vs_gpu_fp64_reference"])
+                row[name] = {"seconds": res["seconds"], "outer_iterations": res["outer_iterations"], **e,
+                             "within_target": err <= target}
             row["fp32_form_speedup"] = round(row["fp64"]["seconds"] / row["fp32"]["seconds"], 3)
             conv["accuracy_targets"][f"{target:g}"] = row
+
+    # ---- the smaller benchmark configurations: 17^3 x 64 (eps 1e-2) and 65^3 x 256 (GRF, eps 1e-4) ------
+    configs = None
+    if args.configs:
+        configs = {}
+        for cname in ("strat17", "grf65"):
+            configs[cname] = _config_line(rt3d, torch, WORKLOADS[cname], stream, args.steps, args.warmup, M,
+                                          (args.ng_order, args.ng_every), args.converge_max_iter)
 
     # ---- many wavelengths on uneven grids: batched forms against one-at-a-time ------------------------
     batched = None
@@ -496,8 +645,17 @@ def main() -> int:
     # ---- CPU oracle on a bounded sample of the same workload -------------------------------------
     cpu = None
     if not args.no_cpu_baseline:
+        import tempfile
+
         import oracle
 
+        # the oracle as it stands, compiled here with the baseline's flags (gcc -O3 -march=native)
+        try:
+            oracle.use_library(oracle.build_native(tempfile.mkdtemp(prefix="rt3d_oracle_")))
+            build_flags = "gcc -O3 -march=native -fopenmp"
+        except Exception as e:            # no compiler on this host: the in-tree build
+            oracle.use_library(None)
+            build_flags = f"gcc -O2 -fopenmp (in-tree build; native build failed: {e})"
         threads = min(os.cpu_count() or 1, 16)
         dirs = list(range(0, n_dir, args.cpu_sample_every))
         S = med["eps"] * med["B"] + (1 - med["eps"]) * med["B"]
@@ -520,6 +678,7 @@ def main() -> int:
                                 "sample": f"{len(dirs1)} directions (every {8 * args.cpu_sample_every}th), "
                                           f"{t1:.2f} s wall"}
         cpu["host_cpu"] = _cpu_model()
+        cpu["build"] = build_flags
 
     out = {
         "metric": METRIC,
@@ -543,9 +702,11 @@ def main() -> int:
                            "M Jacobi sweeps, J update + max rel dJ"},
         "forms": step,
         "roofline": roofline,
+        "roofline_other_form": roofline_other,
         "roofline_jacobi": roofline_jacobi,
         "cpu_baseline": cpu,
         "time_to_converged": conv,
+        "configs": configs,
         "batched": batched,
         "adjoint": adjoint,
         "paper_grids": paper_grids,

@@ -97,8 +97,10 @@ int rt3d_create(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, void *hi
 /* Free every device buffer and the context.  NULL is ignored. */
 void rt3d_destroy(rt3d_ctx *ctx);
 
-/* Set the medium: chi (opacity per unit voxel edge, finite and > 0), eps (thermalisation
- * parameter, 0 < eps <= 1) and B (Planck function, finite), each [nz][ny][nx].  Host data is
+/* Set the medium (section "Method": opacities go in, the solution stays on the device; section "Test
+ * case setup" for the coherent scattering source S = eps B + (1-eps) J): chi (opacity per unit voxel
+ * edge, finite and > 0), eps (thermalisation parameter, 0 < eps <= 1) and B (Planck function, finite),
+ * each [nz][ny][nx], caller-owned (host or device per ptr_kind; copied, not kept).  Host data is
  * validated on the host; device data is validated by a device check that reads back one flag.
  * Resets J to B and invalidates Lambda*.  Errors: RT3D_ERR_ARG, RT3D_ERR_HIP. */
 int rt3d_set_medium(rt3d_ctx *ctx, const double *chi, const double *eps, const double *B,
@@ -111,35 +113,53 @@ int rt3d_set_J(rt3d_ctx *ctx, const double *J, int ptr_kind);
 /* Copy the current iterate J out.  Errors: RT3D_ERR_STATE, RT3D_ERR_ARG, RT3D_ERR_HIP. */
 int rt3d_get_J(rt3d_ctx *ctx, double *J_out, int ptr_kind);
 
-/* One formal solution for all directions: J_fs = sum_d W_d Ibar(d) for the source S_or_null
- * ([nz][ny][nx]) or, when S_or_null is NULL, for S = eps B + (1-eps) J.  Boundary light as in the
- * descriptor.  Also records the top-plane intensities of the upward lines.
- * Errors: RT3D_ERR_STATE, RT3D_ERR_ARG, RT3D_ERR_HIP. */
+/* One formal solution for all directions (section "Implementation of the formal solution and
+ * Lambda* computation": characteristics started on the inner and outer x-y planes and tracked through
+ * the periodic grid, every direction independent; the per-voxel collection of the characteristics'
+ * contributions is that section's second pass): J_fs = sum_d W_d Ibar(d) for the source S_or_null
+ * ([nz][ny][nx], caller-owned, host or device per ptr_kind) or, when S_or_null is NULL, for
+ * S = eps B + (1-eps) J (section "Test case setup").  J_fs_out ([nz][ny][nx], caller-owned) receives
+ * J_fs.  Boundary light as in the descriptor.  Also records the top-plane intensities of the upward
+ * lines.  With host buffers the call synchronises before returning.
+ * Errors: RT3D_ERR_STATE (no medium), RT3D_ERR_ARG (null output, bad ptr_kind, non-finite host S),
+ * RT3D_ERR_HIP; on error J and the medium are unchanged. */
 int rt3d_formal_solution(rt3d_ctx *ctx, const double *S_or_null, double *J_fs_out, int ptr_kind);
 
-/* Build Lambda* (the 27-point band of Lambda) for the current chi; idempotent until the next
- * rt3d_set_medium.  Errors: RT3D_ERR_STATE, RT3D_ERR_HIP. */
+/* Build Lambda* for the current chi (section "Implementation of the formal solution and Lambda*
+ * computation": the nearest-neighbour Lambda* operator computed from the same characteristics as the
+ * formal solution; section "Method" for its role in the operator splitting): the exact 27-point band
+ * of Lambda, Lambda*_vu = dJ_v/dS_u for u in the 3x3x3 block of v, kept in float64 inside the context,
+ * and the Jacobi coefficients of the OS step derived from it (see rt3d_set_coef_storage).
+ * Idempotent until the next rt3d_set_medium.  Errors: RT3D_ERR_STATE (no medium), RT3D_ERR_HIP. */
 int rt3d_build_lstar(rt3d_ctx *ctx);
 
-/* Copy Lambda* out as [27][nz][ny][nx].  Errors: RT3D_ERR_STATE (not built), RT3D_ERR_ARG,
- * RT3D_ERR_HIP. */
+/* Copy Lambda* (section "Implementation of the formal solution and Lambda* computation") out as
+ * float64 [27][nz][ny][nx] in the neighbour order o above into the caller-owned buffer out (host or
+ * device per ptr_kind; 27 V doubles).  Synchronises before returning.
+ * Errors: RT3D_ERR_STATE (not built), RT3D_ERR_ARG (null output, bad ptr_kind), RT3D_ERR_HIP. */
 int rt3d_get_lstar(rt3d_ctx *ctx, double *out, int ptr_kind);
 
-/* One OS step (builds Lambda* first if needed): S from J, FS, r = J_fs - J, inner_sweeps >= 1
- * Jacobi sweeps from dJ = 0, J <- J + dJ, *max_rel_dJ_out = max_v |dJ_v| / |J_v| (may be NULL).
+/* One OS step (section "Implementation of the operator splitting step": the OS equations
+ * (1 - Lambda* (1-eps)) dJ = J_fs - J_old solved by Jacobi ("Jordan") iterations over the 3D grid;
+ * section "Method" for the outer iteration), building Lambda* first if needed: S from J, FS,
+ * r = J_fs - J, inner_sweeps >= 1 Jacobi sweeps from dJ = 0 (or Gauss-Seidel sweeps, see
+ * rt3d_set_os_method), J <- J + dJ, *max_rel_dJ_out = max_v |dJ_v| / |J_v| (may be NULL).
+ * Synchronises before returning (it reads the convergence measure back).
  * In the RT3D_FP32_SWEEP form the context keeps an anchor iterate Ja with its float64 formal
  * solution F_a; a step sweeps the source change (1-eps)(J - Ja) in float32 with no boundary light and
  * uses J_fs = F_a + that sweep, summed in float64, so the float32 error scales with |J - Ja| rather
  * than with J.  A float64 sweep re-anchors at the current J on the first step, after rt3d_set_J or
  * rt3d_set_medium, and whenever the last step's c fell below 1e-2 of max_v |J_v - Ja_v| / |J_v|.  The
- * Jacobi coefficients are stored in float32 in this form (they only precondition; the fixed point is
- * set by the residual); the Jacobi arithmetic is float64.
+ * Jacobi coefficients are stored in float32 in this form by default (rt3d_set_coef_storage); the
+ * Jacobi arithmetic is float64.
  * Errors: RT3D_ERR_STATE, RT3D_ERR_ARG, RT3D_ERR_NONFINITE (J is then not trustworthy),
  * RT3D_ERR_HIP. */
 int rt3d_os_step(rt3d_ctx *ctx, int inner_sweeps, double *max_rel_dJ_out);
 
-/* OS steps until max_rel_dJ < tol or max_iter steps.  *iters_out and *final_rel_dJ_out (may be
- * NULL) receive the step count and the last c.  The RT3D_FP32_SWEEP form accepts c < tol only from a
+/* The outer OS iteration (sections "Method" and "Implementation of the operator splitting step"):
+ * rt3d_os_step until max_rel_dJ < tol or max_iter steps, with Ng acceleration when set
+ * (rt3d_set_acceleration).  *iters_out and *final_rel_dJ_out (may be NULL) receive the step count and
+ * the last c.  The RT3D_FP32_SWEEP form accepts c < tol only from a
  * step whose formal solution was float64 (a re-anchoring step); a float32 step below tol triggers one.  Returns RT3D_ERR_NOT_CONVERGED when max_iter was
  * reached (J and c remain valid), RT3D_ERR_NONFINITE, RT3D_ERR_ARG, RT3D_ERR_STATE, RT3D_ERR_HIP. */
 int rt3d_solve_to_convergence(rt3d_ctx *ctx, double tol, int max_iter, int inner_sweeps,
@@ -168,6 +188,21 @@ int rt3d_set_acceleration(rt3d_ctx *ctx, int ng_order, int ng_every);
  * Errors: RT3D_ERR_ARG (unknown method). */
 enum { RT3D_OS_JACOBI = 0, RT3D_OS_GAUSS_SEIDEL = 1 };
 int rt3d_set_os_method(rt3d_ctx *ctx, int method);
+
+/* Storage precision of the Jacobi coefficients of the OS step (section "Implementation of the
+ * operator splitting step": the Jacobi sweeps read Lambda* in every iteration, which makes the OS step
+ * the second most time-consuming part).  The coefficients chi_v Lambda*_vu of the 13 upper neighbours
+ * of each voxel (the lower ones follow by reciprocity) are stored in float64 (RT3D_COEF_FP64, the
+ * default of the RT3D_FP64 form) or float32 (RT3D_COEF_FP32, the default of the RT3D_FP32_SWEEP form,
+ * half the bytes per sweep); the Jacobi arithmetic, the per-voxel diagonal terms and Lambda* itself
+ * stay float64.  The coefficients only precondition the OS step: float32 storage changes the iterates
+ * by about 1e-7 of dJ but not the fixed point, which the residual J_fs - J sets.  Allocates the new
+ * store (13 V values) on the device before freeing the old one, and re-derives the coefficients from
+ * Lambda* when it is built.  Applies to rt3d_os_step, rt3d_solve_to_convergence and the adjoint solve
+ * of this context.  Errors: RT3D_ERR_ARG (unknown storage), RT3D_ERR_OOM, RT3D_ERR_HIP (the context
+ * keeps its previous storage after RT3D_ERR_OOM). */
+enum { RT3D_COEF_FP64 = 0, RT3D_COEF_FP32 = 1 };
+int rt3d_set_coef_storage(rt3d_ctx *ctx, int storage);
 
 /* Top-plane intensities of the upward lines from the last formal solution, [n_theta/2 * n_phi][ny][nx]
  * in direction order (the upward directions are d = n_dir/2 .. n_dir-1); entry (j,i) belongs to the

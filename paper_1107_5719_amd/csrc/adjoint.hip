@@ -307,7 +307,6 @@ int adjoint_os_step(rt3d_ctx *c, int M, double *dmax, double *numax, int *bad)
                        dim3(kPlaneThreads), 0, c->stream, ra);
     if ((rc = check_launch(c, "reduce_kernel_pair (adjoint)"))) return rc;
     HIP_TRY(c, hipMemsetAsync(c->d_scal, 0, kScalarBytes, c->stream), "memset");
-    const bool f32 = c->precision == RT3D_FP32_SWEEP;
     const double *in = nullptr;
     double *bufs[2] = {c->dJa, c->dJb};
     for (int m = 0; m < M; ++m) {
@@ -315,14 +314,14 @@ int adjoint_os_step(rt3d_ctx *c, int M, double *dmax, double *numax, int *bad)
         JacobiArgs ja{};
         ja.nx = c->g.nx; ja.ny = c->g.ny; ja.nz = c->g.nz;
         ja.b = c->adj_r;
-        ja.Kc = f32 ? static_cast<const void *>(c->Kc32) : static_cast<const void *>(c->Kc);
+        ja.Kc = c->coef_fp32 ? static_cast<const void *>(c->Kc32) : static_cast<const void *>(c->Kc);
         ja.invD = c->invD; ja.E = c->Ecoef;
         ja.w_in = in;
         ja.w_out = last ? nullptr : bufs[m & 1];
         ja.J = last ? c->adj_nu : nullptr;
         ja.maxrel = c->d_maxrel; ja.maxdist = c->d_maxdist; ja.nonfinite = c->d_flag;
         ja.abs_measure = 1;
-        launch_jacobi_sweep(ja, c->jacobi_xcd, f32, c->stream);
+        launch_jacobi_sweep(ja, c->jacobi_xcd, c->coef_fp32 != 0, c->stream);
         if ((rc = check_launch(c, "jacobi_kernel (adjoint)"))) return rc;
         in = ja.w_out;
     }

@@ -52,6 +52,7 @@ struct MemberState {
 
 struct BatchParams {
     double tol;
+    double anchor_ratio;  // FP32 form: re-anchor when c < anchor_ratio * max|J - Ja|/|J| (as a context)
     int max_iter, fp32, ng_order, ng_every;
 };
 
@@ -85,7 +86,7 @@ __global__ void ctl_pre_kernel(int n, MemberState *st, const BatchParams *prm)
     MemberState &s = st[m];
     if (!s.active) { s.mode = 0; return; }
     if (!prm->fp32) { s.mode = 1; return; }
-    const bool refresh = !s.anchor_valid || s.force_refresh || s.c_last < kAnchorRatioDefault * s.da_last;
+    const bool refresh = !s.anchor_valid || s.force_refresh || s.c_last < prm->anchor_ratio * s.da_last;
     s.mode = refresh ? 1 : 2;
 }
 
@@ -565,7 +566,7 @@ int build_jacobi_args(rt3d_batch *b, int M)
             JacobiArgs &a = ja[size_t(s) * n + i];
             a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
             a.b = c->r; a.w_in = in; a.w_out = out;
-            a.Kc = f32 ? static_cast<const void *>(c->Kc32) : static_cast<const void *>(c->Kc);
+            a.Kc = c->coef_fp32 ? static_cast<const void *>(c->Kc32) : static_cast<const void *>(c->Kc);
             a.invD = c->invD; a.E = c->Ecoef;
             a.J = last ? c->J : nullptr;
             a.maxrel = c->d_maxrel; a.nonfinite = c->d_flag;
@@ -644,9 +645,11 @@ int enqueue_iteration(rt3d_batch *b, int M)
     }
     hipLaunchKernelGGL(clear_scalars_kernel, ctl, ctl_t, 0, b->stream, n, b->d_scalars);
     if ((rc = launch_check(b, "clear_scalars_kernel"))) return rc;
+    // members keep the coefficient storage of the batch's precision (float32 in the FP32 form)
+    const bool k32 = b->m[0]->coef_fp32 != 0;
     for (int s = 0; s < M; ++s) {
         const JacobiArgs *args = b->d_jac + size_t(s) * n;
-        if (f32)
+        if (k32)
             hipLaunchKernelGGL(jacobi_kernel_batch_column<float>, dim3(b->n_columns), dim3(kPlaneThreads), 0,
                                b->stream, args, b->d_columns, b->d_state);
         else
@@ -918,7 +921,12 @@ int rt3d_batch_solve(rt3d_batch *b, double tol, int max_iter, int inner_sweeps, 
     }
     int rc = ensure_tables(b);
     if (rc) return rc;
-    BatchParams prm{tol, max_iter, f32 ? 1 : 0, b->ng_order, b->ng_every};
+    // the FP32 form's re-anchoring ratio of the members' contexts (read when they were created, so the
+    // same for all of them), as a single solve of each member would use it
+    const double ratio = b->m[0]->anchor_ratio;
+    for (int i = 1; i < n; ++i)
+        if (b->m[i]->anchor_ratio != ratio) return bfail(b, RT3D_ERR_ARG, "members differ in their anchoring ratio");
+    BatchParams prm{tol, ratio, max_iter, f32 ? 1 : 0, b->ng_order, b->ng_every};
     BHIP_TRY(b, hipMemcpyAsync(b->d_state, h.data(), n * sizeof(MemberState), hipMemcpyHostToDevice, b->stream), "state");
     BHIP_TRY(b, hipMemcpyAsync(b->d_params, &prm, sizeof(prm), hipMemcpyHostToDevice, b->stream), "params");
     rc = capture_graph(b, inner_sweeps);

@@ -47,7 +47,8 @@ struct rt3d_ctx {
     float *seg_len32 = nullptr;
     // FP32 form: anchor iterate, its float64 formal solution and top-plane light, float coefficients
     double *Ja = nullptr, *Fa = nullptr, *Iem_a = nullptr;
-    float *Kc32 = nullptr;                                     // Jacobi coefficients (FP32 form)
+    float *Kc32 = nullptr;                                     // Jacobi coefficients stored in float32
+    int coef_fp32 = 0;          // Jacobi coefficients stored in float32 (Kc32) rather than float64 (Kc)
     unsigned long long *d_maxdist = nullptr;
     bool anchor_valid = false, force_refresh = false, last_step_anchored = false;
     double c_last = INFINITY, da_last = 0.0;

@@ -325,7 +325,7 @@ int finish_lstar(rt3d_ctx *c)
     int rc;
     {
         TimedLaunch t(c, K_COEF);
-        if (c->precision == RT3D_FP32_SWEEP)
+        if (c->coef_fp32)
             hipLaunchKernelGGL(coef_kernel<float>, plane_grid(c), dim3(kPlaneThreads), 0, c->stream, c->g.nx,
                                c->g.ny, c->g.nz, c->L, c->chi, c->eps, c->Kc32, c->invD, c->Ecoef);
         else
@@ -347,7 +347,7 @@ int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update, b
     const bool f32 = c->precision == RT3D_FP32_SWEEP;
     a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
     a.b = c->r; a.w_in = w_in; a.w_out = w_out;
-    a.Kc = f32 ? static_cast<const void *>(c->Kc32) : static_cast<const void *>(c->Kc);
+    a.Kc = c->coef_fp32 ? static_cast<const void *>(c->Kc32) : static_cast<const void *>(c->Kc);
     a.invD = c->invD; a.E = c->Ecoef;
     a.J = update ? c->J : nullptr;
     a.maxrel = c->d_maxrel; a.nonfinite = c->d_flag;
@@ -363,11 +363,12 @@ int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update, b
 int gauss_seidel_sweeps(rt3d_ctx *c, int M)
 {
     const bool f32 = c->precision == RT3D_FP32_SWEEP;
+    const bool k32 = c->coef_fp32 != 0;
     HIP_TRY(c, hipMemsetAsync(c->dJa, 0, size_t(c->V) * sizeof(double), c->stream), "memset");
     JacobiArgs a{};
     a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz;
     a.b = c->r; a.w_in = c->dJa; a.w_out = c->dJa;
-    a.Kc = f32 ? static_cast<const void *>(c->Kc32) : static_cast<const void *>(c->Kc);
+    a.Kc = k32 ? static_cast<const void *>(c->Kc32) : static_cast<const void *>(c->Kc);
     a.invD = c->invD; a.E = c->Ecoef;
     a.maxrel = c->d_maxrel; a.nonfinite = c->d_flag;
     a.maxdist = c->d_maxdist;
@@ -385,7 +386,7 @@ int gauss_seidel_sweeps(rt3d_ctx *c, int M)
                                                colour_count(cz, c->g.nz, false));
                     const long total = long(cnt.x) * cnt.y * cnt.z;
                     const dim3 grid(unsigned((total + kPlaneThreads - 1) / kPlaneThreads));
-                    if (f32)
+                    if (k32)
                         hipLaunchKernelGGL(jacobi_kernel_colour<float>, grid, dim3(kPlaneThreads), 0, c->stream, a, col, cnt);
                     else
                         hipLaunchKernelGGL(jacobi_kernel_colour<double>, grid, dim3(kPlaneThreads), 0, c->stream, a, col, cnt);
@@ -398,7 +399,7 @@ int gauss_seidel_sweeps(rt3d_ctx *c, int M)
 
 int launch_jacobi_args(rt3d_ctx *c, const JacobiArgs &a)
 {
-    launch_jacobi_sweep(a, c->jacobi_xcd, c->precision == RT3D_FP32_SWEEP, c->stream);
+    launch_jacobi_sweep(a, c->jacobi_xcd, c->coef_fp32 != 0, c->stream);
     return check_launch(c, "jacobi_kernel");
 }
 
@@ -577,7 +578,10 @@ int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream
     chk(dev_alloc(c, &c->dJa, V)); chk(dev_alloc(c, &c->dJb, V)); chk(dev_alloc(c, &c->Sbuf, V));
     chk(dev_alloc(c, &c->L, 27 * V));
     chk(dev_alloc(c, &c->invD, V)); chk(dev_alloc(c, &c->Ecoef, V));
-    if (precision == RT3D_FP64) chk(dev_alloc(c, &c->Kc, 13 * V));
+    // Jacobi coefficients: float64 in the FP64 form, float32 in the FP32 form (rt3d_set_coef_storage)
+    c->coef_fp32 = precision == RT3D_FP32_SWEEP ? 1 : 0;
+    if (c->coef_fp32) chk(dev_alloc(c, &c->Kc32, 13 * V));
+    else chk(dev_alloc(c, &c->Kc, 13 * V));
     chk(dev_alloc(c, &c->Iem, size_t(c->A.n_dir / 2) * g->nx * g->ny));
     {
         double2 *cs = nullptr;
@@ -587,7 +591,6 @@ int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream
     if (precision == RT3D_FP32_SWEEP) {
         chk(dev_alloc(c, &c->Ja, V)); chk(dev_alloc(c, &c->Fa, V));
         chk(dev_alloc(c, &c->Iem_a, size_t(c->A.n_dir / 2) * g->nx * g->ny));
-        chk(dev_alloc(c, &c->Kc32, 13 * V));
     }
     chk(dev_alloc(c, &c->d_scal, kScalarBytes / sizeof(unsigned long long)));
     if (!rc) {
@@ -985,6 +988,43 @@ int rt3d_set_os_method(rt3d_ctx *c, int method)
     return RT3D_OK;
 }
 
+int rt3d_set_coef_storage(rt3d_ctx *c, int storage)
+{
+    if (!c) return RT3D_ERR_ARG;
+    if (storage != RT3D_COEF_FP64 && storage != RT3D_COEF_FP32)
+        return fail(c, RT3D_ERR_ARG, "storage must be RT3D_COEF_FP64 or RT3D_COEF_FP32");
+    const int want = storage == RT3D_COEF_FP32 ? 1 : 0;
+    if (want == c->coef_fp32) return RT3D_OK;
+    int rc = sync(c);
+    if (rc) return rc;
+    // allocate the new store before freeing the old one, so that a failure leaves the context as it was
+    if (want) {
+        float *k = nullptr;
+        rc = dev_alloc(c, &k, 13 * size_t(c->V));
+        if (rc) return rc;
+        hipFree(c->Kc);
+        c->Kc = nullptr;
+        c->device_bytes -= 13 * size_t(c->V) * sizeof(double);
+        c->Kc32 = k;
+    } else {
+        double *k = nullptr;
+        rc = dev_alloc(c, &k, 13 * size_t(c->V));
+        if (rc) return rc;
+        hipFree(c->Kc32);
+        c->Kc32 = nullptr;
+        c->device_bytes -= 13 * size_t(c->V) * sizeof(float);
+        c->Kc = k;
+    }
+    c->coef_fp32 = want;
+    // the coefficients follow from Lambda* (kept in float64); re-derive them in the new precision
+    if (c->have_lstar) {
+        rc = finish_lstar(c);
+        if (rc) return rc;
+        return sync(c);
+    }
+    return RT3D_OK;
+}
+
 int rt3d_get_emergent_top(rt3d_ctx *c, double *out, int ptr_kind)
 {
     if (!c) return RT3D_ERR_ARG;
@@ -1032,12 +1072,13 @@ int rt3d_get_stats(rt3d_ctx *c, char *buf, int buflen)
                   "\"nx\":%d,\"ny\":%d,\"nz\":%d,\"n_dir\":%d,\"precision\":\"%s\",\"outer_iters\":%ld,"
                   "\"inner_sweeps\":%ld,\"fp64_sweeps\":%ld,\"fp32_sweeps\":%ld,\"device_bytes\":%zu,\"partial_plane_bytes\":%lld,"
                   "\"sweep_workgroups\":%zu,\"sweep_shape\":%d,\"sweep_threads\":%d,\"sweep_lines\":%d,\"mean_segments\":%.6f,"
-                  "\"os_method\":\"%s\",\"timing\":%d,\"kernels\":{",
+                  "\"os_method\":\"%s\",\"coef_storage\":\"%s\",\"timing\":%d,\"kernels\":{",
                   c->g.nx, c->g.ny, c->g.nz, c->A.n_dir, c->precision == RT3D_FP64 ? "fp64" : "fp32_sweep",
                   c->outer_iters, c->inner_sweeps, c->fp64_sweeps, c->fp32_sweeps, c->device_bytes,
                   (long long)(c->plan.p_elems * (long long)sizeof(double)), c->plan.items.size(),
                   c->sweep_shape, kSweepShapes[c->sweep_shape].threads, kSweepShapes[c->sweep_shape].lines, c->plan.mean_segments,
-                  c->os_method == RT3D_OS_GAUSS_SEIDEL ? "gauss_seidel" : "jacobi", c->timing);
+                  c->os_method == RT3D_OS_GAUSS_SEIDEL ? "gauss_seidel" : "jacobi", c->coef_fp32 ? "fp32" : "fp64",
+                  c->timing);
     s += tmp;
     for (int k = 0; k < K_COUNT; ++k) {
         std::snprintf(tmp, sizeof tmp, "%s\"%s\":{\"launches\":%ld,\"timed\":%ld,\"total_ms\":%.6f}", k ? "," : "",

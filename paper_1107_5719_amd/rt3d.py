@@ -36,11 +36,13 @@ RT3D_MEMBER_MAX_ITER = 2
 RT3D_MEMBER_NONFINITE = 3
 RT3D_OS_JACOBI = 0
 RT3D_OS_GAUSS_SEIDEL = 1
+RT3D_COEF_FP64 = 0
+RT3D_COEF_FP32 = 1
 
 EXPORTED = [
     "rt3d_create", "rt3d_destroy", "rt3d_set_medium", "rt3d_set_J", "rt3d_get_J",
     "rt3d_formal_solution", "rt3d_build_lstar", "rt3d_get_lstar", "rt3d_os_step",
-    "rt3d_solve_to_convergence", "rt3d_set_acceleration", "rt3d_set_os_method", "rt3d_get_emergent_top", "rt3d_set_timing", "rt3d_get_stats",
+    "rt3d_solve_to_convergence", "rt3d_set_acceleration", "rt3d_set_os_method", "rt3d_set_coef_storage", "rt3d_get_emergent_top", "rt3d_set_timing", "rt3d_get_stats",
     "rt3d_status_str", "rt3d_last_error", "rt3d_quadrature", "rt3d_segment_table", "rt3d_validate",
     "rt3d_adjoint_emergent", "rt3d_get_history", "rt3d_sweep_shapes", "rt3d_set_sweep_shape", "rt3d_autotune",
     "rt3d_batch_create", "rt3d_batch_destroy", "rt3d_batch_size", "rt3d_batch_last_error",
@@ -79,6 +81,7 @@ _sig = {
     "rt3d_solve_to_convergence": (_i, [_vp, _d, _i, _i, C.POINTER(_i), C.POINTER(_d)]),
     "rt3d_set_acceleration": (_i, [_vp, _i, _i]),
     "rt3d_set_os_method": (_i, [_vp, _i]),
+    "rt3d_set_coef_storage": (_i, [_vp, _i]),
     "rt3d_get_emergent_top": (_i, [_vp, _vp, _i]),
     "rt3d_set_timing": (_i, [_vp, _i]),
     "rt3d_get_stats": (_i, [_vp, C.c_char_p, _i]),
@@ -256,6 +259,10 @@ def rt3d_set_acceleration(ctx, ng_order: int, ng_every: int):
 
 def rt3d_set_os_method(ctx, method: int):
     return _raise(ctx, _lib.rt3d_set_os_method(ctx, int(method)), "rt3d_set_os_method")
+
+
+def rt3d_set_coef_storage(ctx, storage: int):
+    return _raise(ctx, _lib.rt3d_set_coef_storage(ctx, int(storage)), "rt3d_set_coef_storage")
 
 
 def rt3d_get_emergent_top(ctx, out):
@@ -542,6 +549,10 @@ class Solver:
     def set_os_method(self, method):
         """RT3D_OS_JACOBI or RT3D_OS_GAUSS_SEIDEL (multicolour) for the inner solve of the OS step."""
         rt3d_set_os_method(self.ctx, method)
+
+    def set_coef_storage(self, storage):
+        """RT3D_COEF_FP64 or RT3D_COEF_FP32: storage precision of the OS step's Jacobi coefficients."""
+        rt3d_set_coef_storage(self.ctx, storage)
 
     def emergent_top(self, out=None):
         out = np.zeros((self.n_dir // 2, self.shape[1], self.shape[2])) if out is None else out

@@ -49,29 +49,36 @@ def _single(R, g, precision, shape=0):
     return s
 
 
+# sweep shapes the batched tests run: the default one and 256 x 2, which the autotuner picks for the
+# benchmark's 64-wavelength batch (each shape is its own kernel instantiation)
+SHAPES = [0, 5]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"shape{x}" for x in SHAPES])
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32_sweep"])
-def test_batch_formal_solution_bitwise(R, precision):
+def test_batch_formal_solution_bitwise(R, precision, shape):
     mem = _members()
-    with R.Batch([m["grid"] for m in mem], precision=precision) as b:
+    with R.Batch([m["grid"] for m in mem], precision=precision, sweep_shape=shape) as b:
         for i, m in enumerate(mem):
             b.set_medium(i, m["chi"], m["eps"], m["B"])
             b.set_J(i, m["B"] * 0.5 + 0.25)
         b.formal_solution()
         got = [b.get_Jfs(i) for i in range(len(mem))]
     for i, m in enumerate(mem):
-        with _single(R, m["grid"], precision) as s:
+        with _single(R, m["grid"], precision, shape) as s:
             s.set_medium(m["chi"], m["eps"], m["B"])
             s.set_J(m["B"] * 0.5 + 0.25)
             ref = s.formal_solution()
         assert np.array_equal(got[i], ref), f"member {i}: max diff {np.max(np.abs(got[i] - ref))}"
 
 
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"shape{x}" for x in SHAPES])
 @pytest.mark.parametrize("precision,ng", [(0, (0, 0)), (0, (2, 4)), (1, (0, 0)), (1, (3, 6))],
                          ids=["fp64", "fp64-ng2", "fp32", "fp32-ng3"])
-def test_batch_solve_bitwise(R, precision, ng):
+def test_batch_solve_bitwise(R, precision, ng, shape):
     mem = _members(seed=7)
     tol, max_iter, M = 1e-9, 300, 6
-    with R.Batch([m["grid"] for m in mem], precision=precision) as b:
+    with R.Batch([m["grid"] for m in mem], precision=precision, sweep_shape=shape) as b:
         for i, m in enumerate(mem):
             b.set_medium(i, m["chi"], m["eps"], m["B"])
         if ng[0]:
@@ -81,7 +88,7 @@ def test_batch_solve_bitwise(R, precision, ng):
     assert st == R.RT3D_OK
     assert (states == R.RT3D_MEMBER_CONVERGED).all()
     for i, m in enumerate(mem):
-        with _single(R, m["grid"], precision) as s:
+        with _single(R, m["grid"], precision, shape) as s:
             s.set_medium(m["chi"], m["eps"], m["B"])
             if ng[0]:
                 s.set_acceleration(*ng)
@@ -128,6 +135,33 @@ def test_batch_member_matches_oracle(R, orc):
         assert it_o == iters[i], f"member {i}: {iters[i]} vs oracle {it_o} iterations"
         err = np.max(np.abs(Jb[i] - J_orc) / np.abs(J_orc))
         assert err <= RTOL, f"member {i}: rel err {err:.3e}"
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32_sweep"])
+def test_batch_real_size_members_match_oracle(R, orc, precision):
+    """Members of the benchmark's many-wavelength workload (its first three wavelengths, 64 angles: a
+    33^3, a 65^3 and a 97^3 grid with their drawn chi0 and eps), batched with the benchmark's settings (sweep shape 256 x 2, M = 8,
+    Ng order 3 every 6 steps) for a fixed number of iterations: the 33^3 member against the oracle's
+    iterate after the same steps (FP64 form 1e-10, FP32-sweep form 1e-5)."""
+    allm = wavelength_batch(3)          # the workload's first three wavelengths: 33^3, 97^3, 65^3
+    pick = sorted(allm, key=lambda m: m["grid"]["nx"])
+    assert [m["grid"]["nx"] for m in pick] == [33, 65, 97]
+    steps, M = 12, 8
+    with R.Batch([m["grid"] for m in pick], precision=precision, sweep_shape=5) as b:
+        for i, m in enumerate(pick):
+            b.set_medium(i, m["chi"], m["eps"], m["B"])
+        b.set_acceleration(3, 6)
+        st, iters, cs, states = b.solve(1e-300, steps, M, poll_every=4, check=False)
+        J33 = b.get_J(0)
+    assert (iters == steps).all() and (states == R.RT3D_MEMBER_MAX_ITER).all()
+    m, g = pick[0], pick[0]["grid"]
+    J_orc, it_o, c_o, ok = orc.solve_ng(m["chi"], m["eps"], m["B"], g["n_theta"], g["n_phi"], 1e-300, steps, M,
+                                        3, 6)
+    assert it_o == steps
+    err = np.max(np.abs(J33 - J_orc) / np.abs(J_orc))
+    bar = RTOL if precision == 0 else 1e-5
+    assert err <= bar, f"33^3 member after {steps} steps: rel err {err:.3e} (eps {m['eps'].flat[0]:.2e})"
+    print(f"33^3 member (eps {m['eps'].flat[0]:.3e}): max rel error {err:.3e} after {steps} steps")
 
 
 def test_batch_stop_states_and_errors(R):
@@ -178,17 +212,24 @@ def test_batch_stop_states_and_errors(R):
     assert e.value.status == R.RT3D_ERR_ARG and "member 1" in str(e.value) and "LDS" in str(e.value)
 
 
-def test_set_sweep_shape_changes_only_rounding(R):
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32_sweep"])
+def test_set_sweep_shape_changes_only_rounding(R, orc, precision):
+    """Every sweep shape gives J_fs within rounding of every other (float64: 1e-13; float32 sweeps:
+    1e-6, each shape's float32 window sums split differently across bands) and of the oracle."""
     m = random_medium(14, 11, 9, seed=5, chi_range=(1e-3, 1e1))
+    S = m["eps"] * m["B"] + (1 - m["eps"]) * m["B"]
+    J_orc = orc.formal_solution(m["chi"], S, 8, 8, I_bot=m["B"][0])
     J = {}
     for shape in range(len(R.rt3d_sweep_shapes())):
-        with R.Solver(14, 11, 9, 8, 8) as s:
+        with R.Solver(14, 11, 9, 8, 8, precision=precision) as s:
             s.set_medium(m["chi"], m["eps"], m["B"])
             s.set_sweep_shape(shape)
             assert s.stats()["sweep_shape"] == shape
             J[shape] = s.formal_solution()
+    rtol = 1e-13 if precision == 0 else 1e-6
     for shape, x in J.items():
-        np.testing.assert_allclose(x, J[0], rtol=1e-13, atol=0)
+        np.testing.assert_allclose(x, J[0], rtol=rtol, atol=0)
+        np.testing.assert_allclose(x, J_orc, rtol=1e-10 if precision == 0 else 1e-5, atol=0)
 
 
 def test_autotune_cache(R, tmp_path):

@@ -182,3 +182,51 @@ def test_step_history_and_jsonl_log(R, tmp_path):
     assert h["ng"].sum() >= 1 and (h["ms"] > 0).all()
     lines = [json.loads(x) for x in log.read_text().splitlines()]
     assert len(lines) == it and lines[-1]["max_rel_dJ"] == c and lines[0]["inner_sweeps"] == 6
+
+
+def test_coef_storage_setting(R, orc):
+    """Jacobi coefficients stored in float32 in the FP64 form and in float64 in the FP32 form: the
+    iterates move by the coefficients' rounding only (float32 storage in the FP64 form stays within
+    1e-6 of the oracle's iterates), switching back restores the default iterates bitwise, and the fixed
+    point does not depend on the storage (both forms, both storages: the dense solution)."""
+    nz, ny, nx = 6, 5, 7
+    m = random_medium(nx, ny, nz, seed=21, chi_range=(1e-2, 1e2), eps_range=(1e-3, 1.0))
+    L = orc.lstar(m["chi"], 8, 8)
+    J_o = m["B"].copy()
+    ref = []
+    for _ in range(4):
+        J_o, c_o = orc.os_step(m["chi"], m["eps"], m["B"], L, J_o, 8, 8, M=5, I_top=0.2)
+        ref.append(J_o.copy())
+    runs = {}
+    for storage in (R.RT3D_COEF_FP64, R.RT3D_COEF_FP32, R.RT3D_COEF_FP64):
+        with R.Solver(nx, ny, nz, 8, 8, I_top=0.2) as s:
+            s.set_medium(m["chi"], m["eps"], m["B"])
+            s.build_lstar()
+            s.set_coef_storage(R.RT3D_COEF_FP32)      # change after the build: coefficients re-derived
+            s.set_coef_storage(storage)
+            assert s.stats()["coef_storage"] == ("fp32" if storage else "fp64")
+            its = []
+            for _ in range(4):
+                s.os_step(5)
+                its.append(s.get_J())
+            runs.setdefault(storage, []).append(its)
+    for a, b in zip(runs[R.RT3D_COEF_FP64][0], runs[R.RT3D_COEF_FP64][1]):
+        assert np.array_equal(a, b)
+    for got, want in zip(runs[R.RT3D_COEF_FP64][0], ref):
+        assert _rel(got, want) < 1e-10
+    worst = max(_rel(got, want) for got, want in zip(runs[R.RT3D_COEF_FP32][0], ref))
+    assert 0.0 < worst < 1e-6, worst
+    Jd = orc.dense_os_solution(m["chi"], m["eps"], m["B"], 8, 8, I_top=0.2)
+    for precision in (0, 1):
+        for storage in (R.RT3D_COEF_FP64, R.RT3D_COEF_FP32):
+            with R.Solver(nx, ny, nz, 8, 8, I_top=0.2, precision=precision) as s:
+                s.set_medium(m["chi"], m["eps"], m["B"])
+                s.set_coef_storage(storage)
+                st, it, c = s.solve(1e-13, 2000, 8)
+                assert st == R.RT3D_OK
+                err = _rel(s.get_J(), Jd)
+                assert err < (1e-10 if precision == 0 else 1e-7), (precision, storage, err)
+    with R.Solver(4, 4, 4, 2, 4) as s:
+        with pytest.raises(R.Rt3dError) as e:
+            s.set_coef_storage(2)
+        assert e.value.status == R.RT3D_ERR_ARG
