@@ -369,6 +369,25 @@ int rt3d_batch_autotune(rt3d_batch *b, const char *cache_path, int repeats, int 
  * Errors: RT3D_ERR_ARG (buffer too small or NULL). */
 int rt3d_batch_get_stats(rt3d_batch *b, char *json_buf, int buflen);
 
+/* ---- allocation-free formal solution ------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the formal solution of rt3d_formal_solution without a context.
+ * chi, S ([nz][ny][nx]), I_bot ([ny][nx], the intensity entering the bottom plane, e.g. B of the
+ * bottom layer; NULL or bottom_bc 1 for none) and J_fs ([nz][ny][nx], the output) are caller-owned
+ * device buffers valid on hip_stream (a hipStream_t; NULL = the default stream).  The grid descriptor
+ * is taken as for rt3d_create (bottom_bc 0 or 1; the LTE-diffusion condition needs a context), with
+ * the default sweep shape (shape 0 of rt3d_sweep_shapes); J_fs is bitwise what rt3d_formal_solution
+ * of a context with that shape gives for the same S and boundary light.  The library allocates no
+ * device memory for it: the packed medium, the plan's tables and the partial planes live in a
+ * file-scope device array of 128 MiB per device (held from the library's load until the process
+ * ends); direction pairs are swept in ranges whose partial planes fit.  Host memory is used for the
+ * plan.  Calls that overlap on one device (other streams or threads) share that array and race; the
+ * call returns after its work on hip_stream has finished.  Errors: RT3D_ERR_ARG (bad descriptor, null
+ * pointer, bottom_bc 2, a grid beyond the sweep's limits, or one whose medium and tables or one pair's
+ * partial planes exceed the 128 MiB), RT3D_ERR_HIP; the reason is in rt3d_last_error(NULL). */
+int rt3d_formal_solution_noalloc(const rt3d_grid_desc *g, const double *chi, const double *S,
+                                 const double *I_bot, double *J_fs, void *hip_stream);
+
 /* ---- host-only helpers (no device needed) ------------------------------------------------- */
 
 /* The angle set: mu[d], ox[d], oy[d] (direction cosines) and weights w[d] for d = a*n_phi + b,

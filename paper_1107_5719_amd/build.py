@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librt3d.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("geometry.cpp", "tune_cache.cpp", "rt3d.hip", "batch.hip", "adjoint.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("geometry.cpp", "tune_cache.cpp", "rt3d.hip", "batch.hip", "adjoint.hip", "noalloc.hip")]
 HEADERS = [os.path.join(CSRC, h) for h in ("geometry.h", "context.h", "kernels.h", "tune_cache.h")]
 
 HIPCC_FLAGS = [

@@ -179,6 +179,8 @@ struct SweepArgs {
     const double *Islope;         // [ny][nx] LTE-diffusion gradient: upward lines add mu * Islope (or null)
     double I_top;
     void *P;                      // real
+    long p_shift;                 // subtracted from every pair's partial-plane offset (0, or the first
+                                  // pair's offset when P holds a range of pairs only)
     double *Iem;                  // [n_up][ny][nx] or null
     const double *Iem_base;       // added to Iem in difference mode (or null)
     const double *xtab;           // [kExpTab] 2^(j/kExpTab), the float64 exponential's table
@@ -232,7 +234,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
             }
         }
     };
-    real *P = static_cast<real *>(a.P) + pi.p_off + long(it.band) * nz * wsize;
+    real *P = static_cast<real *>(a.P) + (pi.p_off - a.p_shift) + long(it.band) * nz * wsize;
 
     for (int e = threadIdx.x; e < 2 * wsize; e += NT) winA[e] = real(0);
     __shared__ double xtab[kExpTab];
@@ -386,6 +388,7 @@ struct ReduceArgs {
     const rt3d::PairInfo *pairs;
     const int *row_min;
     const void *P;            // real
+    long p_shift;             // subtracted from every pair's partial-plane offset (see SweepArgs)
     const double *chi;
     const double *J;          // for r = J_fs - J (may be null)
     const double *base;       // difference mode: J_fs of the anchor, added (may be null)
@@ -417,7 +420,7 @@ __device__ inline void reduce_body(const ReduceArgs &a, int p, int k)
         const int off0 = jj - b * rows;
         const long plane = long(Hw) * nx;
         const long band_stride = long(nz) * plane;
-        const real *Pq = P + pi.p_off + long(k) * plane + i;
+        const real *Pq = P + (pi.p_off - a.p_shift) + long(k) * plane + i;
         // the band that starts the row's window offset, and the band before it (cyclically)
         const int b1 = (b == 0) ? nb - 1 : b - 1;
         const int off1 = off0 + ((b1 == nb - 1) ? pi.last_rows : rows);
@@ -446,8 +449,12 @@ __device__ inline void reduce_body(const ReduceArgs &a, int p, int k)
 // voxel pairs of plane k): the band lookup is shared and the partials of both are read together,
 // the per-voxel sums in the order of reduce_body (so the results are bitwise those of reduce_body).
 // Measured at 129^3 x 256: 0.69 against 0.74 ms (float64), 0.51 against 0.59 ms (float32).
+// Direction pairs [q0, q1) only: the running sum starts from 0 (first) or from the raw sum a range
+// before left in Jfs, and is finished (divided by chi, the residual formed) only when last, so ranges
+// taken in order give bitwise the sum of one pass over all pairs.
 template <typename real>
-__device__ inline void reduce_body_pair(const ReduceArgs &a, int p2, int k)
+__device__ inline void reduce_body_pair_range(const ReduceArgs &a, int p2, int k, int q0, int q1, bool first,
+                                              bool last)
 {
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int hx = (nx + 1) / 2;
@@ -456,9 +463,10 @@ __device__ inline void reduce_body_pair(const ReduceArgs &a, int p2, int k)
     const bool two = i0 + 1 < nx;
     const int d1 = two ? 1 : 0;          // the second voxel's offset (0: none, reads the first again)
     const real *P = static_cast<const real *>(a.P);
-    double acc0 = 0.0, acc1 = 0.0;
+    const long v0 = long(k) * nx * ny + long(j) * nx + i0;
+    double acc0 = first ? 0.0 : a.Jfs[v0], acc1 = (first || !two) ? 0.0 : a.Jfs[v0 + 1];
 #pragma unroll 4
-    for (int q = 0; q < a.n_pair; ++q) {
+    for (int q = q0; q < q1; ++q) {
         const rt3d::PairInfo pi = a.pairs[q];
         const int rows = pi.band_rows, nb = pi.n_bands, Hw = pi.win_rows;
         const int rmin = a.row_min[pi.dA * nz + k];
@@ -470,7 +478,7 @@ __device__ inline void reduce_body_pair(const ReduceArgs &a, int p2, int k)
         const int off0 = jj - b * rows;
         const long plane = long(Hw) * nx;
         const long band_stride = long(nz) * plane;
-        const real *Pq = P + pi.p_off + long(k) * plane + i0;
+        const real *Pq = P + (pi.p_off - a.p_shift) + long(k) * plane + i0;
         const int b1 = (b == 0) ? nb - 1 : b - 1;
         const int off1 = off0 + ((b1 == nb - 1) ? pi.last_rows : rows);
         const long o0 = long(b) * band_stride + long(off0) * nx;
@@ -493,8 +501,12 @@ __device__ inline void reduce_body_pair(const ReduceArgs &a, int p2, int k)
         acc1 += pi.wmu * s1;
     }
     for (int t = 0; t < (two ? 2 : 1); ++t) {
-        const long v = long(k) * nx * ny + long(j) * nx + i0 + t;
+        const long v = v0 + t;
         const double acc = t ? acc1 : acc0;
+        if (!last) {
+            a.Jfs[v] = acc;
+            continue;
+        }
         const double Jfs = a.base ? a.base[v] + acc / a.chi[v] : acc / a.chi[v];
         a.Jfs[v] = Jfs;
         if (a.rb) a.rb[v] = a.chi[v] * (Jfs - a.J[v]);
@@ -502,9 +514,24 @@ __device__ inline void reduce_body_pair(const ReduceArgs &a, int p2, int k)
 }
 
 template <typename real>
+__device__ inline void reduce_body_pair(const ReduceArgs &a, int p2, int k)
+{
+    reduce_body_pair_range<real>(a, p2, k, 0, a.n_pair, true, true);
+}
+
+template <typename real>
 __global__ __launch_bounds__(kPlaneThreads) void reduce_kernel_pair(ReduceArgs a)
 {
     reduce_body_pair<real>(a, blockIdx.x * kPlaneThreads + threadIdx.x, blockIdx.y);
+}
+
+// pairs [q0, q1) only (see reduce_body_pair_range)
+template <typename real>
+__global__ __launch_bounds__(kPlaneThreads) void reduce_kernel_pair_range(ReduceArgs a, int q0, int q1, int first,
+                                                                          int last)
+{
+    reduce_body_pair_range<real>(a, blockIdx.x * kPlaneThreads + threadIdx.x, blockIdx.y, q0, q1, first != 0,
+                                 last != 0);
 }
 
 

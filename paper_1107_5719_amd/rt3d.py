@@ -48,7 +48,7 @@ EXPORTED = [
     "rt3d_batch_create", "rt3d_batch_destroy", "rt3d_batch_size", "rt3d_batch_last_error",
     "rt3d_batch_set_medium", "rt3d_batch_set_J", "rt3d_batch_get_J", "rt3d_batch_get_Jfs",
     "rt3d_batch_set_acceleration", "rt3d_batch_set_sweep_shape", "rt3d_batch_formal_solution",
-    "rt3d_batch_solve", "rt3d_batch_autotune", "rt3d_batch_get_stats",
+    "rt3d_batch_solve", "rt3d_batch_autotune", "rt3d_batch_get_stats", "rt3d_formal_solution_noalloc",
 ]
 
 
@@ -109,6 +109,7 @@ _sig = {
     "rt3d_batch_solve": (_i, [_vp, _d, _i, _i, _i, _vp, _vp, _vp]),
     "rt3d_batch_autotune": (_i, [_vp, C.c_char_p, _i, C.POINTER(_i), _vp]),
     "rt3d_batch_get_stats": (_i, [_vp, C.c_char_p, _i]),
+    "rt3d_formal_solution_noalloc": (_i, [C.POINTER(GridDesc), _vp, _vp, _vp, _vp, _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -213,6 +214,22 @@ def rt3d_set_J(ctx, J):
 def rt3d_get_J(ctx, out):
     p, k, h = _arg(out, writable=True)
     return _raise(ctx, _lib.rt3d_get_J(ctx, p, k), "rt3d_get_J")
+
+
+def rt3d_formal_solution_noalloc(nx, ny, nz, n_theta, n_phi, chi, S, I_bot, J_fs, I_top=0.0, bottom_bc=0,
+                                 stream=None):
+    """The context-free, allocation-free formal solution: chi, S, J_fs (and I_bot, or None) are
+    contiguous float64 CUDA tensors; stream a raw hipStream_t handle (int) or None."""
+    d = _desc(nx, ny, nz, n_theta, n_phi, I_top, bottom_bc)
+    V = nx * ny * nz
+    pc, kc, _ = _arg(chi, V)
+    ps, ks, _ = _arg(S, V)
+    pj, kj, _ = _arg(J_fs, V, writable=True)
+    pb, kb, _ = _arg(I_bot, nx * ny)
+    if RT3D_HOST in (kc, ks, kj) or (I_bot is not None and kb != RT3D_DEVICE):
+        raise ValueError("rt3d_formal_solution_noalloc takes device tensors only")
+    rc = _lib.rt3d_formal_solution_noalloc(C.byref(d), pc, ps, pb, pj, _vp(stream) if stream else None)
+    return _raise(None, rc, "rt3d_formal_solution_noalloc", creation=True)
 
 
 def rt3d_formal_solution(ctx, S, out):
