@@ -15,8 +15,9 @@
  *
  * Environment variables read when a context is created (tuning experiments; the defaults are the
  * measured best): RT3D_SWEEP_SHAPE (index into rt3d_sweep_shapes), RT3D_JACOBI_XCD (Jacobi launch
- * layout 0..4; all give bitwise the same iterates), RT3D_ANCHOR_RATIO (re-anchoring ratio of the
- * RT3D_FP32_SWEEP form, default 1e-2).
+ * layout 0..4; all give bitwise the same iterates), RT3D_JACOBI_ALTERNATE (0: the column layout walks
+ * every sweep bottom first instead of alternating; same iterates), RT3D_ANCHOR_RATIO (re-anchoring
+ * ratio of the RT3D_FP32_SWEEP form, default 1e-2).
  *
  * Discretisation (the paper defers it to earlier papers of its series; these are the readings):
  *   voxels    unit cubes (i,j,k), i fastest; k = 0 is the bottom (inner boundary), k = nz-1 the top;
@@ -87,8 +88,9 @@ typedef struct rt3d_ctx rt3d_ctx;
  * hip_stream is a hipStream_t (NULL = the default stream); every kernel of this context is launched
  * on it.  Size limit of the sweep: a workgroup holds whole x-rows of lines (nx <= 1024 with the
  * default shape) and the float64 deposit windows of a band, 2 (rows + the angle set's row spread per
- * layer) nx values, fit 48 KB of LDS; with the default shape nx may reach 1024 for 2 x 4 angles, 512
- * for 8 x 8, 256 for 16 x 16 and 180 for 24 x 24 (ny and nz are limited by memory only).
+ * layer) nx values, fit the LDS: 48 KB when they can (several workgroups per CU), else up to 156 KB
+ * (one per CU); with the default shape nx may reach 1024 for 2 x 4 and 8 x 8 angles, 832 for 16 x 16
+ * and 587 for 24 x 24 (ny and nz are limited by memory only).
  * rt3d_validate checks the same without a device.
  * Errors: RT3D_ERR_ARG (bad descriptor or precision, out == NULL, a grid beyond the sweep's limits),
  * RT3D_ERR_OOM, RT3D_ERR_HIP; the reason is in rt3d_last_error(NULL). */

@@ -35,6 +35,8 @@ struct rt3d_ctx {
     double anchor_ratio = kAnchorRatioDefault;   // FP32 form: re-anchor when c < ratio * max|J - Ja|/|J|
     int jacobi_xcd = 4;        // Jacobi grid: 0 plain, 1 chunks padded to 8 per plane, 2 contiguous chunk
                                // ranges per XCD, 3 2D tiles, 4 columns (default) (RT3D_JACOBI_XCD)
+    bool jacobi_alternate = true;   // column layout: consecutive sweeps walk the layers in opposite
+                                    // orders (RT3D_JACOBI_ALTERNATE=0: always bottom first)
     // device buffers (owned)
     double *chi = nullptr, *eps = nullptr, *B = nullptr, *J = nullptr, *Jfs = nullptr, *r = nullptr;
     double *dJa = nullptr, *dJb = nullptr, *L = nullptr, *Iem = nullptr;

@@ -37,6 +37,10 @@ inline void with_sweep_shape(int shape, F &&f)
     }
 }
 constexpr size_t kWindowBytes = 48 * 1024;   // LDS for the two deposit windows of a band (float64)
+// Grids whose windows do not fit kWindowBytes (wide rows, shallow angle sets) take up to this much of
+// the 160 KB of LDS a gfx950 workgroup may use (the rest holds the kernel's static LDS): one workgroup
+// per CU then, but no width limit below the line budget of a workgroup.
+constexpr size_t kWindowBytesWide = 156 * 1024;
 // Dynamic LDS of a sweep workgroup: the two deposit windows and, in float32, the staged chi,S cells of
 // the window rows (the float32 total equals the float64 windows, so one LDS budget serves both).
 inline size_t sweep_smem_bytes(int max_win_rows, int nx, bool f32)
@@ -892,13 +896,17 @@ __device__ inline void jacobi_column_body(const JacobiArgs &a, int p, int kc)
     if (a.J) jacobi_block_max(a, q, dist, bad);
 }
 
+// reverse: the column layers in descending order (top first).  Consecutive sweeps alternate, so each
+// starts where the previous one ended and finds its most recent planes still in the caches; the order
+// of the blocks does not change any voxel's sum.
 template <typename coef>
-__global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel_column(JacobiArgs a, int group)
+__global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel_column(JacobiArgs a, int group, int reverse)
 {
     const int blk = blockIdx.x;
     const int xcd = blk & 7, slot = blk >> 3;
     const int kc = slot / group;
-    jacobi_column_body<coef>(a, (xcd * group + (slot - kc * group)) * kPlaneThreads + threadIdx.x, kc);
+    const int kcol = reverse ? int(gridDim.x) / (8 * group) - 1 - kc : kc;
+    jacobi_column_body<coef>(a, (xcd * group + (slot - kc * group)) * kPlaneThreads + threadIdx.x, kcol);
 }
 
 // Gauss-Seidel colour pass.  The voxels are coloured per axis so that no two 27-point neighbours share
@@ -934,15 +942,17 @@ inline int colour_count(int c, int n, bool periodic)
 
 // One Jacobi sweep in the given grid layout: 0 one block per chunk of a plane, 1 the same padded to
 // a multiple of 8 chunks per plane, 2 contiguous chunk ranges per XCD, 3 2D tiles, 4 columns.
-inline void launch_jacobi_sweep(const JacobiArgs &a, int layout, bool f32, hipStream_t stream)
+// reverse: the column layout walks its column layers top first (see jacobi_kernel_column).
+inline void launch_jacobi_sweep(const JacobiArgs &a, int layout, bool f32, hipStream_t stream, bool reverse = false)
 {
     const int chunks = (a.nx * a.ny + kPlaneThreads - 1) / kPlaneThreads;
     const int group = (chunks + 7) / 8;
     const dim3 blk(kPlaneThreads);
     if (layout == 4) {
         const dim3 grid(unsigned(8 * group) * unsigned((a.nz + kJacCol - 1) / kJacCol));
-        if (f32) hipLaunchKernelGGL(jacobi_kernel_column<float>, grid, blk, 0, stream, a, group);
-        else hipLaunchKernelGGL(jacobi_kernel_column<double>, grid, blk, 0, stream, a, group);
+        const int rev = reverse ? 1 : 0;
+        if (f32) hipLaunchKernelGGL(jacobi_kernel_column<float>, grid, blk, 0, stream, a, group, rev);
+        else hipLaunchKernelGGL(jacobi_kernel_column<double>, grid, blk, 0, stream, a, group, rev);
     } else if (layout == 3) {
         const int tiles_x = (a.nx + kTileX - 1) / kTileX, tiles_y = (a.ny + kTileY - 1) / kTileY;
         const int tgroup = (tiles_x * tiles_y + 7) / 8;

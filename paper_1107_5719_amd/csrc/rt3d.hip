@@ -338,10 +338,10 @@ int finish_lstar(rt3d_ctx *c)
     return RT3D_OK;
 }
 
-int launch_jacobi_args(rt3d_ctx *c, const JacobiArgs &a);
+int launch_jacobi_args(rt3d_ctx *c, const JacobiArgs &a, bool reverse = false);
 int gauss_seidel_sweeps(rt3d_ctx *c, int M);
 
-int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update, bool chosen)
+int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update, bool chosen, bool reverse)
 {
     JacobiArgs a{};
     const bool f32 = c->precision == RT3D_FP32_SWEEP;
@@ -354,7 +354,7 @@ int launch_jacobi(rt3d_ctx *c, const double *w_in, double *w_out, bool update, b
     a.Ja = (f32 && update) ? c->Ja : nullptr;
     a.maxdist = c->d_maxdist;
     TimedLaunch t(c, K_JACOBI, chosen);
-    return launch_jacobi_args(c, a);
+    return launch_jacobi_args(c, a, reverse);
 }
 
 // M multicolour Gauss-Seidel sweeps from dJ = 0, colour after colour in the order
@@ -397,9 +397,9 @@ int gauss_seidel_sweeps(rt3d_ctx *c, int M)
     return RT3D_OK;
 }
 
-int launch_jacobi_args(rt3d_ctx *c, const JacobiArgs &a)
+int launch_jacobi_args(rt3d_ctx *c, const JacobiArgs &a, bool reverse)
 {
-    launch_jacobi_sweep(a, c->jacobi_xcd, c->coef_fp32 != 0, c->stream);
+    launch_jacobi_sweep(a, c->jacobi_xcd, c->coef_fp32 != 0, c->stream, reverse && c->jacobi_alternate);
     return check_launch(c, "jacobi_kernel");
 }
 
@@ -496,9 +496,17 @@ bool build_plan(const rt3d_grid_desc &g, const rt3d::AngleSet &A, int shape, rt3
 {
     if (shape < 0 || shape >= n_sweep_shapes()) { msg = "sweep shape out of range"; return false; }
     const SweepShape sh = kSweepShapes[shape];
-    // one plan for both precisions: the LDS windows are budgeted for float64
-    return rt3d::build_sweep_plan(g.nx, g.ny, g.nz, A, sh.threads * sh.lines, 16 * sh.threads, kWindowBytes,
-                                  int(sizeof(double)), plan, msg);
+    // one plan for both precisions: the LDS windows are budgeted for float64; a grid whose windows do
+    // not fit the usual budget (which keeps several workgroups per CU) takes the wide one
+    if (rt3d::build_sweep_plan(g.nx, g.ny, g.nz, A, sh.threads * sh.lines, 16 * sh.threads, kWindowBytes,
+                               int(sizeof(double)), plan, msg))
+        return true;
+    std::string msg_wide;
+    if (rt3d::build_sweep_plan(g.nx, g.ny, g.nz, A, sh.threads * sh.lines, 16 * sh.threads, kWindowBytesWide,
+                               int(sizeof(double)), plan, msg_wide))
+        return true;
+    msg = msg_wide;
+    return false;
 }
 
 int install_plan(rt3d_ctx *c, int shape, rt3d::SweepPlan *built)
@@ -560,6 +568,7 @@ int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream
     rt3d::SweepPlan plan;
     if (!build_plan(*g, c->A, shape, plan, msg)) { delete c; return RT3D_ERR_ARG; }
     if (const char *e = std::getenv("RT3D_JACOBI_XCD")) c->jacobi_xcd = std::max(0, std::min(4, std::atoi(e)));
+    if (const char *e = std::getenv("RT3D_JACOBI_ALTERNATE")) c->jacobi_alternate = std::atoi(e) != 0;
     if (const char *e = std::getenv("RT3D_ANCHOR_RATIO")) c->anchor_ratio = std::max(0.0, std::atof(e));
     // Lambda* walk may stop at the first non-neighbour only if no line wraps back within two layers
     {
@@ -879,7 +888,9 @@ int rt3d_os_step(rt3d_ctx *c, int inner_sweeps, double *max_rel_dJ_out)
             // sampled timing: the intermediate sweeps 1 .. M-2 as one group (the first sweep, from
             // dJ = 0, and the last, which updates J, are cheaper and dearer); with M <= 2 the first
             if (m == 1 && inner_sweeps > 2) group.emplace(c, K_JACOBI, inner_sweeps - 2);
-            rc = launch_jacobi(c, in, out, last, inner_sweeps <= 2 && m == 0);
+            // even sweeps top first: the first reads the right-hand side the reduction wrote last at the
+            // top, and each later sweep starts where the one before ended
+            rc = launch_jacobi(c, in, out, last, inner_sweeps <= 2 && m == 0, (m & 1) == 0);
             if (m == inner_sweeps - 2 && group) group->end();
             if (rc) return rc;
             in = out;

@@ -65,9 +65,11 @@ def test_ng_argument_checks(R):
 
 
 # (nz, ny, nx), angles, seed: window rows wrapping several times round a short y period (ny = 3),
-# and the widest grid 16 x 16 angles allow (nx = 256: windows and staged chi,S fill the LDS budget)
+# the widest 16 x 16 grid whose windows and staged chi,S fit the 48 KB budget (nx = 256), and wider
+# grids in the wide budget (nx = 300, 520)
 FP32_CASES = [((5, 5, 5), 8, 8, 1), ((11, 7, 9), 16, 16, 2), ((4, 40, 33), 16, 16, 5),
-              ((5, 3, 3), 16, 16, 7), ((3, 4, 256), 16, 16, 8)]
+              ((5, 3, 3), 16, 16, 7), ((3, 4, 256), 16, 16, 8), ((3, 4, 300), 16, 16, 9),
+              ((4, 5, 520), 16, 16, 10)]
 
 
 @pytest.mark.parametrize("case", FP32_CASES, ids=[str(c[0]) for c in FP32_CASES])

@@ -62,7 +62,9 @@ FS_CASES = [
     ((6, 5, 7), 2, 4, 7, 0.2, 0),        # smallest angle set; every line runs through voxel edges
     ((5, 8, 6), 8, 4, 8, 0.0, 0),        # n_phi = 4 with steep and shallow directions
     ((6, 7, 5), 8, 8, 9, 0.1, 2),        # LTE-diffusion inner condition
-    ((3, 4, 256), 16, 16, 10, 0.0, 0),   # the widest grid for 16 x 16 angles: windows fill the LDS budget
+    ((3, 4, 256), 16, 16, 10, 0.0, 0),   # the widest grid whose 16 x 16 windows fit the 48 KB budget
+    ((3, 4, 300), 16, 16, 11, 0.0, 0),   # wider: windows in the wide LDS budget
+    ((4, 5, 520), 16, 16, 12, 0.2, 0),   # one row per band, ~100 KB of windows
 ]
 
 
@@ -321,19 +323,22 @@ def test_determinism_and_resume(R):
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32_sweep"])
 def test_jacobi_grid_layouts_agree_bitwise(R, precision, monkeypatch):
     """Every launch layout of the Jacobi sweep (one block per plane chunk, padded, XCD-grouped, 2D
-    tiles, columns marched in z) computes each voxel's sum in the same order, so OS steps agree
-    bitwise; the grid (nz = 10, not a multiple of the column height; 37 x 9 columns, a ragged last
+    tiles, columns marched in z, in either order of the column layers) computes each voxel's sum in
+    the same order, so OS steps agree bitwise; the grid (nz = 10, not a multiple of the column height; 37 x 9 columns, a ragged last
     chunk) also checks the column form's ends.  The layout is read from RT3D_JACOBI_XCD when a context
     is created."""
     m = random_medium(37, 9, 10, seed=77, chi_range=(1e-3, 3e1), eps_range=(1e-4, 0.3))
     out = {}
-    for layout in range(5):
-        monkeypatch.setenv("RT3D_JACOBI_XCD", str(layout))
+    # layouts 0..4; "4+" is the column layout walking every sweep bottom first (RT3D_JACOBI_ALTERNATE=0)
+    layouts = (0, 1, 2, 3, 4, "4+")
+    for layout in layouts:
+        monkeypatch.setenv("RT3D_JACOBI_XCD", str(layout)[0])
+        monkeypatch.setenv("RT3D_JACOBI_ALTERNATE", "0" if str(layout).endswith("+") else "1")
         with R.Solver(37, 9, 10, 4, 8, precision=precision) as s:
             s.set_medium(m["chi"], m["eps"], m["B"])
             cs = [s.os_step(7) for _ in range(3)]
             out[layout] = (s.get_J(), cs)
-    for layout in range(1, 5):
+    for layout in layouts[1:]:
         assert np.array_equal(out[layout][0], out[0][0]), f"layout {layout}"
         assert out[layout][1] == out[0][1]
 
