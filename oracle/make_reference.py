@@ -84,6 +84,7 @@ def make(name: str, tol: float, M: int, ng_order: int, ng_every: int, threads: i
 
     w = WORKLOADS[name]
     med = make_medium(w)
+    src_sha = oracle_sha256()          # the source the loaded library was built from
     t0 = time.perf_counter()
     L = oracle.lstar(med["chi"], w.n_theta, w.n_phi, n_threads=threads)
     print(f"{name}: Lambda* built in {time.perf_counter() - t0:.1f} s", flush=True)
@@ -117,7 +118,7 @@ def make(name: str, tol: float, M: int, ng_order: int, ng_every: int, threads: i
             "inner_sweeps": M, "ng_order": ng_order, "ng_every": ng_every, "iterations": n,
             "final_max_rel_dJ": c, "min_max_rel_dJ": min(c, c_min), "stop": reason,
             "seconds": round(secs, 1), "threads": threads,
-            "input_sha256": input_sha256(w, med), "oracle_sha256": oracle_sha256(),
+            "input_sha256": input_sha256(w, med), "oracle_sha256": src_sha,
             "J_sha256": array_sha256(J)}
     with open(os.path.join(REF_DIR, f"{name}.json"), "w") as f:
         json.dump(meta, f, indent=1)

@@ -183,8 +183,6 @@ struct SweepArgs {
     const double *Islope;         // [ny][nx] LTE-diffusion gradient: upward lines add mu * Islope (or null)
     double I_top;
     void *P;                      // real
-    long p_shift;                 // subtracted from every pair's partial-plane offset (0, or the first
-                                  // pair's offset when P holds a range of pairs only)
     double *Iem;                  // [n_up][ny][nx] or null
     const double *Iem_base;       // added to Iem in difference mode (or null)
     const double *xtab;           // [kExpTab] 2^(j/kExpTab), the float64 exponential's table
@@ -238,7 +236,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
             }
         }
     };
-    real *P = static_cast<real *>(a.P) + (pi.p_off - a.p_shift) + long(it.band) * nz * wsize;
+    real *P = static_cast<real *>(a.P) + pi.p_off + long(it.band) * nz * wsize;
 
     for (int e = threadIdx.x; e < 2 * wsize; e += NT) winA[e] = real(0);
     __shared__ double xtab[kExpTab];
@@ -392,7 +390,6 @@ struct ReduceArgs {
     const rt3d::PairInfo *pairs;
     const int *row_min;
     const void *P;            // real
-    long p_shift;             // subtracted from every pair's partial-plane offset (see SweepArgs)
     const double *chi;
     const double *J;          // for r = J_fs - J (may be null)
     const double *base;       // difference mode: J_fs of the anchor, added (may be null)
@@ -424,7 +421,7 @@ __device__ inline void reduce_body(const ReduceArgs &a, int p, int k)
         const int off0 = jj - b * rows;
         const long plane = long(Hw) * nx;
         const long band_stride = long(nz) * plane;
-        const real *Pq = P + (pi.p_off - a.p_shift) + long(k) * plane + i;
+        const real *Pq = P + pi.p_off + long(k) * plane + i;
         // the band that starts the row's window offset, and the band before it (cyclically)
         const int b1 = (b == 0) ? nb - 1 : b - 1;
         const int off1 = off0 + ((b1 == nb - 1) ? pi.last_rows : rows);
@@ -482,7 +479,7 @@ __device__ inline void reduce_body_pair_range(const ReduceArgs &a, int p2, int k
         const int off0 = jj - b * rows;
         const long plane = long(Hw) * nx;
         const long band_stride = long(nz) * plane;
-        const real *Pq = P + (pi.p_off - a.p_shift) + long(k) * plane + i0;
+        const real *Pq = P + pi.p_off + long(k) * plane + i0;
         const int b1 = (b == 0) ? nb - 1 : b - 1;
         const int off1 = off0 + ((b1 == nb - 1) ? pi.last_rows : rows);
         const long o0 = long(b) * band_stride + long(off0) * nx;

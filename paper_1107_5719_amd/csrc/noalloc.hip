@@ -104,13 +104,15 @@ int rt3d_formal_solution_noalloc(const rt3d_grid_desc *g, const double *chi, con
     const long V = long(nx) * ny * nz;
     const SweepShape shape = kSweepShapes[0];
 
-    // workspace layout: exponential table, {chi, S}, pair table, layer table, pair segments, row minima,
+    // workspace layout: exponential table, {chi, S}, pair tables, layer table, pair segments, row minima,
     // work items of every range, then the partial planes of one range of pairs
     std::vector<double> tab(kExpTab);
     for (int j = 0; j < kExpTab; ++j) tab[j] = double(std::exp2(static_cast<long double>(j) / kExpTab));
     // ranges of pairs whose partial planes fit what the tables leave of the workspace
+    // (one copy of the pair table per range, at most one range per pair, with the partial-plane
+    // offsets relative to the range's first pair)
     const size_t fixed = align256(tab.size() * sizeof(double)) + align256(size_t(V) * sizeof(double2)) +
-                         align256(plan.pairs.size() * sizeof(rt3d::PairInfo)) +
+                         align256(plan.pairs.size() * plan.pairs.size() * sizeof(rt3d::PairInfo)) +
                          align256(plan.player.size() * sizeof(rt3d::PairLayer)) +
                          align256(plan.pseg.size() * sizeof(rt3d::PairSeg)) +
                          align256(plan.row_min.size() * sizeof(int)) +
@@ -146,6 +148,15 @@ int rt3d_formal_solution_noalloc(const rt3d_grid_desc *g, const double *chi, con
             if (it.pair >= q_begin[r] && it.pair < q_begin[r + 1]) items.push_back(it);
     }
     item_begin.push_back(int(items.size()));
+    // per range, the pair table with the offsets of its partial planes taken from the range's first pair
+    std::vector<rt3d::PairInfo> range_pairs;
+    for (int r = 0; r < n_range; ++r) {
+        const int64_t shift = plan.pairs[q_begin[r]].p_off;
+        for (rt3d::PairInfo pi : plan.pairs) {
+            pi.p_off -= shift;          // negative for the pairs before the range, which it does not touch
+            range_pairs.push_back(pi);
+        }
+    }
 
     void *base = nullptr;
     int rc = scratch_address(&base);
@@ -153,7 +164,7 @@ int rt3d_formal_solution_noalloc(const rt3d_grid_desc *g, const double *chi, con
     unsigned char *p = static_cast<unsigned char *>(base);
     unsigned char *d_tab = p;        p += align256(tab.size() * sizeof(double));
     unsigned char *d_cs = p;         p += align256(size_t(V) * sizeof(double2));
-    unsigned char *d_pairs = p;      p += align256(plan.pairs.size() * sizeof(rt3d::PairInfo));
+    unsigned char *d_pairs = p;      p += align256(plan.pairs.size() * plan.pairs.size() * sizeof(rt3d::PairInfo));
     unsigned char *d_player = p;     p += align256(plan.player.size() * sizeof(rt3d::PairLayer));
     unsigned char *d_pseg = p;       p += align256(plan.pseg.size() * sizeof(rt3d::PairSeg));
     unsigned char *d_rowmin = p;     p += align256(plan.row_min.size() * sizeof(int));
@@ -164,7 +175,7 @@ int rt3d_formal_solution_noalloc(const rt3d_grid_desc *g, const double *chi, con
         hipStreamSynchronize(st);
         return noalloc_fail(code, m);
     };
-    if ((rc = upload(d_tab, tab, st)) || (rc = upload(d_pairs, plan.pairs, st)) ||
+    if ((rc = upload(d_tab, tab, st)) || (rc = upload(d_pairs, range_pairs, st)) ||
         (rc = upload(d_player, plan.player, st)) || (rc = upload(d_pseg, plan.pseg, st)) ||
         (rc = upload(d_rowmin, plan.row_min, st)) || (rc = upload(d_items, items, st)))
         return drain_fail(rc, thread_error());
@@ -178,7 +189,7 @@ int rt3d_formal_solution_noalloc(const rt3d_grid_desc *g, const double *chi, con
     sa.n_down = A.n_dir / 2;
     sa.pseg = reinterpret_cast<const rt3d::PairSeg *>(d_pseg);
     sa.player = reinterpret_cast<const rt3d::PairLayer *>(d_player);
-    sa.pairs = reinterpret_cast<const rt3d::PairInfo *>(d_pairs);
+    const rt3d::PairInfo *d_range_pairs = reinterpret_cast<const rt3d::PairInfo *>(d_pairs);
     sa.cs = d_cs;
     sa.Ibot = g->bottom_bc == 1 ? nullptr : I_bot;
     sa.Islope = nullptr;
@@ -189,7 +200,7 @@ int rt3d_formal_solution_noalloc(const rt3d_grid_desc *g, const double *chi, con
     sa.xtab = reinterpret_cast<const double *>(d_tab);
     ReduceArgs ra{};
     ra.nx = nx; ra.ny = ny; ra.nz = nz; ra.n_pair = plan.n_pair;
-    ra.pairs = sa.pairs;
+
     ra.row_min = reinterpret_cast<const int *>(d_rowmin);
     ra.P = d_P;
     ra.chi = chi;
@@ -199,8 +210,8 @@ int rt3d_formal_solution_noalloc(const rt3d_grid_desc *g, const double *chi, con
     for (int r = 0; r < n_range; ++r) {
         const int n_items = item_begin[r + 1] - item_begin[r];
         sa.items = reinterpret_cast<const rt3d::WorkItem *>(d_items) + item_begin[r];
-        sa.p_shift = long(plan.pairs[q_begin[r]].p_off);
-        ra.p_shift = sa.p_shift;
+        sa.pairs = d_range_pairs + size_t(r) * plan.pairs.size();
+        ra.pairs = sa.pairs;
         if (n_items > 0)
             hipLaunchKernelGGL((sweep_kernel<double, 512, 2>), dim3(unsigned(n_items)), dim3(shape.threads), smem, st, sa);
         e = hipGetLastError();
