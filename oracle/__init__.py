@@ -87,6 +87,9 @@ def lib():
         L.orc_solve_ng.argtypes = [i, i, i, i, i, _dp, _dp, _dp, d, i, C.c_void_p, _dp, d, i, i, i, i,
                                    C.POINTER(C.c_int), C.POINTER(C.c_double), i]
         L.orc_ng_extrapolate.argtypes = [C.c_long, i, _dp, i, _dp]
+        L.orc_anderson_mix.argtypes = [C.c_long, i, _dp, _dp, _dp]
+        L.orc_solve_anderson.argtypes = [i, i, i, i, i, _dp, _dp, _dp, d, i, C.c_void_p, _dp, d, i, i, i,
+                                         C.POINTER(C.c_int), C.POINTER(C.c_double), i]
         L.orc_pp1d.argtypes = [i, i, _dp, _dp, d, d, d, _dp]
         L.orc_fs_complex.argtypes = [i, i, i, i, i, _dp, C.c_void_p, _dp, C.c_void_p, d, C.c_void_p,
                                      C.c_void_p, C.c_void_p, _dp, _dp, C.c_void_p, C.c_void_p]
@@ -276,6 +279,32 @@ def solve_ng(chi, eps, B, n_theta, n_phi, tol, max_iter, M, ng_order, ng_every, 
                                    int(ng_order), int(ng_every), C.byref(it), C.byref(c), n_threads),
                 "solve_ng")
     return J, it.value, c.value, rc == 0
+
+
+def solve_anderson(chi, eps, B, n_theta, n_phi, tol, max_iter, M, depth, J0=None, Lstar=None, I_top=0.0,
+                   bottom_from_B=True, n_threads=0):
+    """Outer OS iteration with Anderson mixing of depth 1..8.  Returns (J, iters, c, converged)."""
+    chi, eps, B = _f64(chi), _f64(eps), _f64(B)
+    nz, ny, nx = chi.shape
+    J = (B if J0 is None else _f64(J0)).copy()
+    Ls = None if Lstar is None else _f64(Lstar)
+    it = C.c_int(0)
+    c = C.c_double(0.0)
+    rc = _check(lib().orc_solve_anderson(nx, ny, nz, n_theta, n_phi, chi, eps, B, float(I_top),
+                                         _bottom_mode(bottom_from_B), _ptr(Ls), J, float(tol), int(max_iter),
+                                         int(M), int(depth), C.byref(it), C.byref(c), n_threads),
+                "solve_anderson")
+    return J, it.value, c.value, rc == 0
+
+
+def anderson_mix(X, G):
+    """One Anderson mixing step from the window of inputs X[0..k] and outputs G[0..k] (oldest first).
+    Returns (next input, ok)."""
+    xs = _f64(np.stack([np.ravel(x) for x in X]))
+    gs = _f64(np.stack([np.ravel(g) for g in G]))
+    out = np.zeros(xs.shape[1])
+    rc = _check(lib().orc_anderson_mix(xs.shape[1], xs.shape[0] - 1, xs, gs, out), "anderson_mix")
+    return out.reshape(np.shape(X[0])), rc == 0
 
 
 def ng_extrapolate(hist, order):

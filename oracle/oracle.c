@@ -781,6 +781,126 @@ int orc_solve_ng(int nx, int ny, int nz, int n_theta, int n_phi, const double *c
     return (c < tol) ? ORC_OK : 1;
 }
 
+/* Anderson mixing (type II) of the outer iteration -- an alternative to Ng's extrapolation, not from
+ * the paper: every OS step x -> g = G(x) joins a sliding window of the newest k + 1 pairs (x_i, g_i),
+ * i = 0 (oldest) .. k (newest), with residuals f_i = g_i - x_i.  With df_j = f_k - f_{k-j} and
+ * dg_j = g_k - g_{k-j} (j = 1..k), gamma minimises sum_v w_v (f_k - sum_j gamma_j df_j)_v^2 with the
+ * weights w = 1 / g_k^2 of Ng's extrapolation, and the next input is g_k - sum_j gamma_j dg_j.  For an
+ * affine G the residual of that input is the weighted least-squares residual over the window.
+ * Returns 0, or 1 if the normal equations are singular or their solution is not finite (out is then
+ * g_k). */
+static int anderson_mix(long V, int k, double *const *X, double *const *G, double *out)
+{
+    double A[8][8] = {{0}}, b[8] = {0}, gam[8] = {0};
+    if (k < 1 || k > 8) return 1;
+    const double *gk = G[k], *xk = X[k];
+    for (long v = 0; v < V; ++v) {
+        const double w = 1.0 / (gk[v] * gk[v]);
+        const double fk = gk[v] - xk[v];
+        double df[8];
+        for (int j = 1; j <= k; ++j) df[j - 1] = fk - (G[k - j][v] - X[k - j][v]);
+        for (int i = 0; i < k; ++i) {
+            b[i] += w * df[i] * fk;
+            for (int j = 0; j < k; ++j) A[i][j] += w * df[i] * df[j];
+        }
+    }
+    int bad = 0;
+    for (int c = 0; c < k && !bad; ++c) {          /* Gaussian elimination, partial pivoting */
+        int p = c;
+        for (int r = c + 1; r < k; ++r) if (fabs(A[r][c]) > fabs(A[p][c])) p = r;
+        if (!(fabs(A[p][c]) > 0.0)) { bad = 1; break; }
+        if (p != c) {
+            for (int q = 0; q < k; ++q) { double t = A[c][q]; A[c][q] = A[p][q]; A[p][q] = t; }
+            double t = b[c]; b[c] = b[p]; b[p] = t;
+        }
+        for (int r = c + 1; r < k; ++r) {
+            double f = A[r][c] / A[c][c];
+            for (int q = c; q < k; ++q) A[r][q] -= f * A[c][q];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int c = k - 1; c >= 0 && !bad; --c) {
+        double t = b[c];
+        for (int q = c + 1; q < k; ++q) t -= A[c][q] * gam[q];
+        gam[c] = t / A[c][c];
+        if (!isfinite(gam[c])) bad = 1;
+    }
+    for (long v = 0; v < V; ++v) {
+        double x = gk[v];
+        if (!bad)
+            for (int j = 1; j <= k; ++j) x -= gam[j - 1] * (gk[v] - G[k - j][v]);
+        out[v] = x;
+    }
+    return bad;
+}
+
+/* Exported for the pins: X_flat, G_flat are [k+1][V] (oldest first). */
+int orc_anderson_mix(long V, int k, const double *X_flat, const double *G_flat, double *out)
+{
+    double *xs[9], *gs[9];
+    if (k < 1 || k > 8) return ORC_EARG;
+    for (int q = 0; q <= k; ++q) {
+        xs[q] = (double *)(X_flat + (size_t)q * V);
+        gs[q] = (double *)(G_flat + (size_t)q * V);
+    }
+    return anderson_mix(V, k, xs, gs, out);
+}
+
+/* Outer OS iteration with Anderson mixing of depth m (1..8): the input of every step after the first
+ * is the mixing of the newest min(steps, m + 1) pairs; c is that of the OS step just taken, and on
+ * c < tol J receives its output g. */
+int orc_solve_anderson(int nx, int ny, int nz, int n_theta, int n_phi, const double *chi,
+                       const double *eps, const double *B, double I_top, int bottom_from_B,
+                       const double *Lstar, double *J, double tol, int max_iter, int M, int depth,
+                       int *iters, double *c_out, int n_threads)
+{
+    if (depth < 1 || depth > 8) return ORC_EARG;
+    const long V = (long)nx * ny * nz;
+    double *Lown = NULL;
+    if (!Lstar) {
+        Lown = (double *)malloc(sizeof(double) * 27 * V);
+        if (!Lown) return ORC_ENOMEM;
+        int rc = orc_lstar(nx, ny, nz, n_theta, n_phi, chi, Lown, n_threads);
+        if (rc) { free(Lown); return rc; }
+        Lstar = Lown;
+    }
+    const int cap = depth + 1;
+    double *buf = (double *)malloc(sizeof(double) * (size_t)(2 * cap + 1) * V);
+    if (!buf) { free(Lown); return ORC_ENOMEM; }
+    double *X[9], *G[9];
+    for (int q = 0; q < cap; ++q) { X[q] = buf + (size_t)q * V; G[q] = buf + (size_t)(cap + q) * V; }
+    double *x = buf + (size_t)2 * cap * V;          /* input of the next step */
+    memcpy(x, J, sizeof(double) * V);
+    int count = 0, n = 0, rc = ORC_OK;
+    double c = INFINITY;
+    while (n < max_iter) {
+        /* the window, oldest first: shift out the oldest pair when full */
+        if (count == cap) {
+            double *tx = X[0], *tg = G[0];
+            for (int q = 0; q + 1 < cap; ++q) { X[q] = X[q + 1]; G[q] = G[q + 1]; }
+            X[cap - 1] = tx; G[cap - 1] = tg;
+            --count;
+        }
+        memcpy(X[count], x, sizeof(double) * V);
+        memcpy(G[count], x, sizeof(double) * V);
+        rc = orc_os_step(nx, ny, nz, n_theta, n_phi, chi, eps, B, I_top, bottom_from_B, Lstar, G[count], M,
+                         &c, NULL, n_threads);
+        ++n;
+        ++count;
+        if (rc != ORC_OK) break;
+        if (c < tol) break;
+        if (count >= 2) anderson_mix(V, count - 1, X, G, x);
+        else memcpy(x, G[0], sizeof(double) * V);
+    }
+    if (count > 0) memcpy(J, G[count - 1], sizeof(double) * V);
+    free(buf);
+    free(Lown);
+    if (iters) *iters = n;
+    if (c_out) *c_out = c;
+    if (rc != ORC_OK) return rc;
+    return (c < tol) ? ORC_OK : 1;
+}
+
 /* Outer OS iteration until c < tol (or max_iter steps).  J holds the initial guess on entry (the
  * usual start is J = B) and the last iterate on exit.  Lstar may be NULL: it is then built here.
  * Returns the number of steps in *iters and the last c in *c_out; the return code is 1 when

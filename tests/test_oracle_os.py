@@ -242,3 +242,54 @@ def test_gs_single_colour_pass_is_jacobi_on_that_colour(orc):
     off = (A - np.diag(np.diag(A))) @ np.where(last, 0.0, g1).ravel()
     ref = ((r.ravel() - off) / D.ravel()).reshape(shape)
     assert np.max(np.abs(g1[last] - ref[last])) < 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("p,depth", [(3, 3), (4, 6), (6, 8)])
+def test_anderson_terminates_on_affine_maps(orc, p, depth):
+    """Anderson mixing of a window of depth >= p on an affine map x -> A x + b whose A has p distinct
+    eigenvalues reaches the fixed point (I - A)^-1 b after p + 2 applications of the map (the residuals
+    then span A's Krylov space, so the least-squares residual vanishes whatever the weights); a window
+    shorter than p does not."""
+    rng = np.random.default_rng(p)
+    n = 40
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = rng.uniform(0.2, 0.95, p)
+    A = (Q * lam[rng.integers(0, p, n)]) @ Q.T
+    b = rng.uniform(1.0, 2.0, n)
+    xs = np.linalg.solve(np.eye(n) - A, b)
+
+    def run(win, steps):
+        x, X, G = np.full(n, 1.5), [], []
+        for _ in range(steps):
+            g = A @ x + b
+            X.append(x.copy())
+            G.append(g)
+            if len(X) > win + 1:
+                X.pop(0)
+                G.pop(0)
+            x = orc.anderson_mix(X, G)[0] if len(X) >= 2 else g
+        return np.max(np.abs(x - xs) / np.abs(xs))
+
+    assert run(depth, p + 2) < 1e-10
+    if p > 3:
+        assert run(p - 2, p + 2) > 1e-6
+
+
+def test_anderson_reaches_the_dense_solution_faster(orc):
+    """The OS iteration with Anderson mixing converges to the fixed point of the plain iteration (the
+    dense solution of the OS system on a tiny grid) and, on a stratified scattering column, in fewer
+    steps than the plain iteration."""
+    m = random_medium(5, 4, 5, seed=23, chi_range=(1e-2, 1e1), eps_range=(1e-2, 1.0))
+    Jd = orc.dense_os_solution(m["chi"], m["eps"], m["B"], 4, 8, I_top=0.1)
+    J, it, c, ok = orc.solve_anderson(m["chi"], m["eps"], m["B"], 4, 8, 1e-13, 500, 6, 5, I_top=0.1)
+    assert ok
+    assert np.max(np.abs(J / Jd - 1)) < 1e-10
+    nz, ny, nx = 33, 5, 6
+    chi = np.broadcast_to(stratified_profile(nz, 300.0)[:, None, None], (nz, ny, nx)).copy()
+    chi *= np.exp(0.1 * np.random.default_rng(17).standard_normal(chi.shape))
+    eps = np.full(chi.shape, 1e-3)
+    B = np.ones(chi.shape)
+    J_p, it_p, _, ok_p = orc.solve(chi, eps, B, 8, 8, 1e-10, 3000, 10)
+    J_a, it_a, _, ok_a = orc.solve_anderson(chi, eps, B, 8, 8, 1e-10, 3000, 10, 5)
+    assert ok_p and ok_a and it_a < it_p / 2
+    assert np.max(np.abs(J_a / J_p - 1)) < 1e-7
