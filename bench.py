@@ -31,6 +31,8 @@ SWEEP_KERNEL = {"fp64": "sweep_kernel<double,512,2>", "fp32": "sweep_kernel<floa
 JACOBI_KERNEL = {"fp64": "jacobi_kernel_column<double>", "fp32": "jacobi_kernel_column<float>"}
 # the (M, Ng order, Ng every) schedules over which time to converged J is summarised (median, worst)
 SCHEDULES = [(12, 3, 6), (20, 3, 6), (30, 3, 6), (40, 3, 6), (12, 3, 8), (20, 3, 8), (30, 3, 8), (40, 3, 8)]
+# the (M, depth) schedules of Anderson mixing
+AA_SCHEDULES = [(12, 5), (20, 5), (30, 5), (12, 8), (20, 8), (30, 8)]
 
 
 def sweep_bytes_per_update(precision: str, G: int = 1) -> int:
@@ -160,14 +162,17 @@ def _timed_steps(rt3d, torch, w, d_med, prec, stream, steps, warmup, M, coef=Non
 
 
 def _converge(rt3d, torch, w, d_med, prec, stream, M, ng_order, ng_every, tol, max_iter, os_method=0,
-              coef=None):
-    """Time from resident inputs (Lambda* build included) to max rel dJ < tol."""
+              coef=None, anderson=0):
+    """Time from resident inputs (Lambda* build included) to max rel dJ < tol (Ng or, with anderson > 0,
+    Anderson mixing of that depth)."""
     s = rt3d.Solver(w.nx, w.ny, w.nz, w.n_theta, w.n_phi, I_top=w.I_top, precision=prec, stream=stream)
     if coef is not None:
         s.set_coef_storage(coef)
     s.set_medium(d_med["chi"], d_med["eps"], d_med["B"])
     s.set_os_method(os_method)
-    if ng_order:
+    if anderson:
+        s.set_anderson(anderson)
+    elif ng_order:
         s.set_acceleration(ng_order, ng_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -593,6 +598,32 @@ def main() -> int:
         sched["fp32_form_speedup_median"] = round(sched["fp64"]["median_s"] / sched["fp32"]["median_s"], 3)
         sched["fp32_form_speedup_worst"] = round(sched["fp64"]["worst_s"] / sched["fp32"]["worst_s"], 3)
         conv["schedules"] = sched
+        # Anderson mixing of the outer iteration instead of Ng (window depth x inner sweeps M)
+        aa = {"schedules": [list(x) for x in AA_SCHEDULES]}
+        for name, prec in forms.items():
+            rows = []
+            for (m_, dep) in AA_SCHEDULES:
+                J, res = _converge(rt3d, torch, w, d_med, prec, stream, m_, 0, 0, w.tol, args.converge_max_iter,
+                                   anderson=dep)
+                rows.append({"inner_sweeps": m_, "depth": dep, "seconds": res["seconds"],
+                             "outer_iterations": res["outer_iterations"], "converged": res["converged"],
+                             **errs(J)})
+            secs = [r["seconds"] for r in rows]
+            aa[name] = {"runs": rows, "median_s": statistics.median(secs), "worst_s": max(secs),
+                        "best_s": min(secs)}
+        aa["fp32_form_speedup_median"] = round(aa["fp64"]["median_s"] / aa["fp32"]["median_s"], 3)
+        for name in forms:
+            aa[f"{name}_speedup_over_ng_median"] = round(sched[name]["median_s"] / aa[name]["median_s"], 3)
+            aa[f"{name}_speedup_over_ng_worst"] = round(sched[name]["worst_s"] / aa[name]["worst_s"], 3)
+        conv["anderson"] = aa
+        # headline: the median over each acceleration's fixed schedule set (no single tuned schedule)
+        conv["headline"] = {
+            "method": "median time to converged J over the fixed schedule sets (Anderson mixing: depth 5 and 8 x "
+                      "M = 12, 20, 30; Ng order 3 every 6 or 8 steps x M = 12, 20, 30, 40), Lambda* build included",
+            "anderson_fp64_s": aa["fp64"]["median_s"], "anderson_fp32_s": aa["fp32"]["median_s"],
+            "ng_fp64_s": sched["fp64"]["median_s"], "ng_fp32_s": sched["fp32"]["median_s"],
+            "fp32_form_speedup_anderson": aa["fp32_form_speedup_median"],
+            "fp32_form_speedup_ng": sched["fp32_form_speedup_median"]}
         # the Fortran code's other inner solve: multicolour Gauss-Seidel, float64, half the sweeps
         if args.gs_inner_sweeps > 0:
             J, res = _converge(rt3d, torch, w, d_med, rt3d.RT3D_FP64, stream, args.gs_inner_sweeps,

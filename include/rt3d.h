@@ -178,6 +178,18 @@ int rt3d_solve_to_convergence(rt3d_ctx *ctx, double tol, int max_iter, int inner
  * Errors: RT3D_ERR_ARG, RT3D_ERR_OOM, RT3D_ERR_HIP. */
 int rt3d_set_acceleration(rt3d_ctx *ctx, int ng_order, int ng_every);
 
+/* Anderson mixing of rt3d_solve_to_convergence, an alternative to Ng's extrapolation (not from the
+ * paper; the outer iteration is an affine map of J, and mixing over a sliding window accelerates it
+ * like a restarted Krylov method): every OS step x -> g joins a window of the newest depth + 1 pairs
+ * (x_i, g_i), and from the second step on the next input is g_k - sum_j gamma_j (g_k - g_{k-j}), where
+ * gamma minimises sum_v (f_k - sum_j gamma_j (f_k - f_{k-j}))_v^2 / g_k,v^2, f = g - x (the weights of
+ * Ng's method); a singular or non-finite solve keeps g_k.  The window slides (no restart).  depth 0
+ * switches it off (the default); 1 <= depth <= 8.  Setting a depth switches Ng acceleration off and
+ * rt3d_set_acceleration with ng_order > 0 switches Anderson mixing off.  Dot products are reduced in a
+ * fixed order (bitwise reproducible).  Allocates 2 (depth + 1) V float64 on the device.  The batched
+ * form and the adjoint solve use Ng only.  Errors: RT3D_ERR_ARG, RT3D_ERR_OOM, RT3D_ERR_HIP. */
+int rt3d_set_anderson(rt3d_ctx *ctx, int depth);
+
 /* Inner solve of the OS step (section "Implementation of the operator splitting step": the Fortran
  * code solves the OS equations by Jordan (Jacobi) or Gauss-Seidel iterations; its GPU version uses
  * Jacobi).  RT3D_OS_JACOBI (the default): inner_sweeps Jacobi sweeps from dJ = 0.
@@ -224,7 +236,7 @@ int rt3d_set_timing(rt3d_ctx *ctx, int enable);
 /* The per-step record since the last rt3d_set_medium, rt3d_set_J or start of
  * rt3d_solve_to_convergence (at most 100000 steps): max |dJ|/|J| (c_out), host wall milliseconds of the
  * step (ms_out) and flags (flags_out: 1 = the step's formal solution was float64, 2 = Ng extrapolated
- * after it).  Fills the first min(n, max_n) entries of the arrays (any may be NULL) and returns n, the
+ * after it, 4 = Anderson mixing after it).  Fills the first min(n, max_n) entries of the arrays (any may be NULL) and returns n, the
  * number of records.  Errors: RT3D_ERR_ARG. */
 int rt3d_get_history(rt3d_ctx *ctx, double *c_out, double *ms_out, int *flags_out, int max_n);
 

@@ -72,6 +72,10 @@ struct rt3d_ctx {
     double *adj_nu = nullptr, *adj_fs = nullptr, *adj_r = nullptr, *adj_f = nullptr, *adj_pull = nullptr;
     double *adj_g = nullptr;            // [n_up][ny][nx]: dL/dI_em
     double *adj_qs = nullptr;           // [n_up][ny][nx]: adjoint at the start of upward lines (bottom_bc 2)
+    // Anderson mixing (alternative to Ng): rings of the window's OS-step inputs and outputs
+    int aa_depth = 0;
+    double *aa_x = nullptr, *aa_g = nullptr;   // [aa_depth + 1][V] each
+    double *aa_work = nullptr;                 // [kAaWork]
     // Ng acceleration
     int ng_order = 0, ng_every = 0;
     double *ng_hist = nullptr;          // [ng_order + 2][V] ring of iterates

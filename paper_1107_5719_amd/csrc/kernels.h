@@ -1111,6 +1111,136 @@ __global__ __launch_bounds__(256) void ng_combine_kernel(NgArgs a, int m)
     if (v < a.V) ng_combine_body(a, m, v);
 }
 
+// ------------------------------------------------------------------------------------------------
+// Anderson mixing of the outer iteration: windows of (input, output) pairs of the OS step in two rings
+// of V-vectors; slot[0..k] are the ring entries of the window, oldest first.  The weighted dot products
+// use the fixed two-level partition of the Ng kernels (bitwise reproducible).
+// ------------------------------------------------------------------------------------------------
+
+constexpr int kAaMaxDepth = 8;
+constexpr int kAaSums = kAaMaxDepth * (kAaMaxDepth + 1) / 2 + kAaMaxDepth;   // A (upper) and b
+constexpr int kAaBlocks = 512;
+constexpr int kAaThreads = 256;
+constexpr int kAaSumOff = kAaBlocks * kAaSums;
+constexpr int kAaCoefOff = kAaSumOff + kAaSums;     // gamma_1..gamma_8 and a valid flag
+constexpr int kAaWork = kAaCoefOff + kAaMaxDepth + 1;
+
+struct AaArgs {
+    long V;
+    int k;                          // differences in the window (1..kAaMaxDepth)
+    int slot[kAaMaxDepth + 1];      // ring entries of the window, oldest first
+    const double *X, *G;            // rings [depth + 1][V] of inputs and outputs
+    double *work;                   // [kAaWork]
+    double *J;                      // receives the mixed input of the next step
+};
+
+// Index of the sum A_ij (i <= j < k) and of b_i in a block's partial sums.
+__host__ __device__ constexpr int aa_a_index(int i, int j) { return j * (j + 1) / 2 + i; }
+__host__ __device__ constexpr int aa_b_index(int i) { return kAaMaxDepth * (kAaMaxDepth + 1) / 2 + i; }
+
+// One block's share of A_ij = sum_v w df_i df_j and b_i = sum_v w df_i f_k, w = 1/g_k^2, f = g - x,
+// df_j = f_k - f_{k-j}; the sums of a thread, then of a wavefront (xor tree), then of the block's
+// wavefronts in order.  Whole block.
+__global__ __launch_bounds__(kAaThreads) void aa_dots_kernel(AaArgs a)
+{
+    const int k = a.k;
+    double acc[kAaSums];
+#pragma unroll
+    for (int q = 0; q < kAaSums; ++q) acc[q] = 0.0;
+    const double *gk = a.G + long(a.slot[k]) * a.V, *xk = a.X + long(a.slot[k]) * a.V;
+    for (long v = long(blockIdx.x) * kAaThreads + threadIdx.x; v < a.V; v += long(kAaBlocks) * kAaThreads) {
+        const double g = gk[v];
+        const double w = 1.0 / (g * g);
+        const double fk = g - xk[v];
+        double df[kAaMaxDepth];
+#pragma unroll
+        for (int j = 1; j <= kAaMaxDepth; ++j) {
+            if (j > k) break;
+            const long o = long(a.slot[k - j]) * a.V + v;
+            df[j - 1] = fk - (a.G[o] - a.X[o]);
+        }
+#pragma unroll
+        for (int j = 0; j < kAaMaxDepth; ++j) {
+            if (j >= k) break;
+#pragma unroll
+            for (int i = 0; i <= j; ++i) acc[aa_a_index(i, j)] += w * df[i] * df[j];
+            acc[aa_b_index(j)] += w * df[j] * fk;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kAaSums; ++q)
+        for (int offs = 32; offs > 0; offs >>= 1) acc[q] += __shfl_xor(acc[q], offs);
+    __shared__ double part[kAaThreads / 64][kAaSums];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int q = 0; q < kAaSums; ++q) part[wid][q] = acc[q];
+    __syncthreads();
+    if (threadIdx.x < kAaSums) {
+        double s = part[0][threadIdx.x];
+        for (int w2 = 1; w2 < kAaThreads / 64; ++w2) s += part[w2][threadIdx.x];
+        a.work[blockIdx.x * kAaSums + threadIdx.x] = s;
+    }
+}
+
+// Sums the block partials in a fixed order, then thread 0 solves the k x k normal equations A gamma = b
+// by Gaussian elimination with partial pivoting; a singular system or a non-finite solution clears the
+// valid flag (the output g_k is then kept as the next input).
+__global__ __launch_bounds__(kAaThreads) void aa_solve_kernel(AaArgs a)
+{
+    __shared__ double tot[kAaSums];
+    if (threadIdx.x < kAaSums) {
+        double s = 0.0;
+        for (int b = 0; b < kAaBlocks; ++b) s += a.work[b * kAaSums + threadIdx.x];
+        tot[threadIdx.x] = s;
+        a.work[kAaSumOff + threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int n = a.k;
+    double A[kAaMaxDepth][kAaMaxDepth], b[kAaMaxDepth], g[kAaMaxDepth];
+    for (int i = 0; i < n; ++i) {
+        b[i] = tot[aa_b_index(i)];
+        g[i] = 0.0;
+        for (int j = 0; j < n; ++j) A[i][j] = i <= j ? tot[aa_a_index(i, j)] : tot[aa_a_index(j, i)];
+    }
+    bool ok = true;
+    for (int c = 0; c < n && ok; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r) if (fabs(A[r][c]) > fabs(A[p][c])) p = r;
+        if (!(fabs(A[p][c]) > 0.0)) { ok = false; break; }
+        if (p != c) {
+            for (int q = 0; q < n; ++q) { const double t = A[c][q]; A[c][q] = A[p][q]; A[p][q] = t; }
+            const double t = b[c]; b[c] = b[p]; b[p] = t;
+        }
+        for (int r = c + 1; r < n; ++r) {
+            const double f = A[r][c] / A[c][c];
+            for (int q = c; q < n; ++q) A[r][q] -= f * A[c][q];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = n - 1; r >= 0 && ok; --r) {
+        double t = b[r];
+        for (int q = r + 1; q < n; ++q) t -= A[r][q] * g[q];
+        g[r] = t / A[r][r];
+        if (!isfinite(g[r])) ok = false;
+    }
+    for (int i = 0; i < kAaMaxDepth; ++i) a.work[kAaCoefOff + i] = i < n ? g[i] : 0.0;
+    a.work[kAaCoefOff + kAaMaxDepth] = ok ? 1.0 : 0.0;
+}
+
+// J = g_k - sum_j gamma_j (g_k - g_{k-j}) when the solve succeeded, else g_k.
+__global__ __launch_bounds__(256) void aa_combine_kernel(AaArgs a)
+{
+    const long v = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= a.V) return;
+    const double *cf = a.work + kAaCoefOff;
+    const double gk = a.G[long(a.slot[a.k]) * a.V + v];
+    double x = gk;
+    if (cf[kAaMaxDepth] != 0.0)
+        for (int j = 1; j <= a.k; ++j) x -= cf[j - 1] * (gk - a.G[long(a.slot[a.k - j]) * a.V + v]);
+    a.J[v] = x;
+}
+
 // finiteness / range check of a device medium
 __global__ void check_medium_kernel(long V, const double *chi, const double *eps, const double *B,
                                     int *flag)

@@ -423,6 +423,28 @@ int ng_step(rt3d_ctx *c, int m)
     return check_launch(c, "ng_combine_kernel");
 }
 
+// The next input of the outer iteration by Anderson mixing of the window slots[0..k] (oldest first):
+// dot products, the small solve and the combination on the device, no host round trip.
+int anderson_step(rt3d_ctx *c, int k, const int *slots)
+{
+    AaArgs a{};
+    a.V = c->V;
+    a.k = k;
+    for (int q = 0; q <= k; ++q) a.slot[q] = slots[q];
+    a.X = c->aa_x;
+    a.G = c->aa_g;
+    a.work = c->aa_work;
+    a.J = c->J;
+    hipLaunchKernelGGL(aa_dots_kernel, dim3(kAaBlocks), dim3(kAaThreads), 0, c->stream, a);
+    int rc = check_launch(c, "aa_dots_kernel");
+    if (rc) return rc;
+    hipLaunchKernelGGL(aa_solve_kernel, dim3(1), dim3(kAaThreads), 0, c->stream, a);
+    rc = check_launch(c, "aa_solve_kernel");
+    if (rc) return rc;
+    hipLaunchKernelGGL(aa_combine_kernel, dim3(unsigned((c->V + 255) / 256)), dim3(256), 0, c->stream, a);
+    return check_launch(c, "aa_combine_kernel");
+}
+
 void free_plan(rt3d_ctx *c);
 
 void free_all(rt3d_ctx *c)
@@ -430,7 +452,7 @@ void free_all(rt3d_ctx *c)
     free_plan(c);
     void *ptrs[] = {c->chi, c->eps, c->B, c->J, c->Jfs, c->r, c->dJa, c->dJb, c->L, c->Kc, c->invD, c->Ecoef, c->Iem,
                     c->Sbuf, c->bot_slope, c->xtab, c->cs, c->Ja, c->Fa, c->Iem_a, c->Kc32, c->d_scal,
-                    c->ng_hist, c->ng_work, c->adj_Ient, c->adj_Qx, c->adj_nu, c->adj_fs, c->adj_r,
+                    c->ng_hist, c->ng_work, c->aa_x, c->aa_g, c->aa_work, c->adj_Ient, c->adj_Qx, c->adj_nu, c->adj_fs, c->adj_r,
                     c->adj_f, c->adj_pull, c->adj_g, c->adj_qs};
     for (void *p : ptrs)
         if (p) hipFree(p);
@@ -442,6 +464,21 @@ void free_all(rt3d_ctx *c)
 }
 
 int n_sweep_shapes() { return int(sizeof(kSweepShapes) / sizeof(kSweepShapes[0])); }
+
+// Ng's history and Anderson's window (whichever is set) with their device buffers
+void free_acceleration(rt3d_ctx *c)
+{
+    size_t bytes = 0;
+    if (c->ng_hist) bytes += size_t(c->ng_order + 2) * c->V * sizeof(double) + kNgWork * sizeof(double);
+    if (c->aa_x) bytes += 2 * size_t(c->aa_depth + 1) * c->V * sizeof(double) + kAaWork * sizeof(double);
+    c->device_bytes -= std::min(bytes, c->device_bytes);
+    for (double **p : {&c->ng_hist, &c->ng_work, &c->aa_x, &c->aa_g, &c->aa_work}) {
+        if (*p) hipFree(*p);
+        *p = nullptr;
+    }
+    c->ng_order = c->ng_every = 0;
+    c->aa_depth = 0;
+}
 
 // Sweep shape of new contexts: RT3D_SWEEP_SHAPE indexes the shape table (default 0, 512 x 2).
 int env_sweep_shape()
@@ -939,15 +976,39 @@ int rt3d_solve_to_convergence(rt3d_ctx *c, double tol, int max_iter, int inner_s
         HIP_TRY(c, hipMemcpyAsync(c->ng_hist, c->J, vbytes, hipMemcpyDeviceToDevice, c->stream), "ng hist");
         nh = 1;
     }
+    // Anderson window: ring entries of the newest pairs (input, output of the OS step), oldest first
+    const int cap = c->aa_depth + 1;
+    int aa_count = 0, aa_next = 0;
+    int aa_slots[kAaMaxDepth + 1];
     while (n < max_iter) {
+        if (c->aa_depth > 0) {
+            if (aa_count == cap) {            // drop the oldest pair
+                for (int q = 0; q + 1 < cap; ++q) aa_slots[q] = aa_slots[q + 1];
+                --aa_count;
+            }
+            aa_slots[aa_count] = aa_next;
+            aa_next = (aa_next + 1) % cap;
+            HIP_TRY(c, hipMemcpyAsync(c->aa_x + long(aa_slots[aa_count]) * c->V, c->J, vbytes,
+                                      hipMemcpyDeviceToDevice, c->stream), "anderson input");
+        }
         rc = rt3d_os_step(c, inner_sweeps, &cval);
         ++n;
         if (rc != RT3D_OK) break;
+        if (c->aa_depth > 0) {
+            HIP_TRY(c, hipMemcpyAsync(c->aa_g + long(aa_slots[aa_count]) * c->V, c->J, vbytes,
+                                      hipMemcpyDeviceToDevice, c->stream), "anderson output");
+            ++aa_count;
+        }
         if (cval < tol) {
             // the FP32 form accepts convergence only from a step whose residual is float64
             if (c->precision != RT3D_FP32_SWEEP || c->last_step_anchored) break;
             c->force_refresh = true;
             continue;
+        }
+        if (c->aa_depth > 0 && aa_count >= 2) {
+            rc = anderson_step(c, aa_count - 1, aa_slots);
+            if (rc) break;
+            if (!c->history.empty()) c->history.back().flags |= 4;
         }
         if (c->ng_order > 0) {
             HIP_TRY(c, hipMemcpyAsync(c->ng_hist + long(nh % R) * c->V, c->J, vbytes,
@@ -977,16 +1038,32 @@ int rt3d_set_acceleration(rt3d_ctx *c, int ng_order, int ng_every)
         return fail(c, RT3D_ERR_ARG, "ng_order must be 0..3 and ng_every >= ng_order + 1");
     int rc = sync(c);
     if (rc) return rc;
-    if (c->ng_hist) { hipFree(c->ng_hist); c->ng_hist = nullptr; }
-    if (c->ng_work) { hipFree(c->ng_work); c->ng_work = nullptr; }
-    c->ng_order = 0;
-    c->ng_every = 0;
+    free_acceleration(c);
     if (ng_order == 0) return RT3D_OK;
     rc = dev_alloc(c, &c->ng_hist, size_t(ng_order + 2) * c->V);
     if (!rc) rc = dev_alloc(c, &c->ng_work, size_t(kNgWork));
     if (rc) return rc;
     c->ng_order = ng_order;
     c->ng_every = ng_every;
+    return RT3D_OK;
+}
+
+int rt3d_set_anderson(rt3d_ctx *c, int depth)
+{
+    if (!c) return RT3D_ERR_ARG;
+    if (depth < 0 || depth > kAaMaxDepth) return fail(c, RT3D_ERR_ARG, "Anderson depth must be 0..8");
+    int rc = sync(c);
+    if (rc) return rc;
+    free_acceleration(c);
+    if (depth == 0) return RT3D_OK;
+    rc = dev_alloc(c, &c->aa_x, size_t(depth + 1) * c->V);
+    if (!rc) rc = dev_alloc(c, &c->aa_g, size_t(depth + 1) * c->V);
+    if (!rc) rc = dev_alloc(c, &c->aa_work, size_t(kAaWork));
+    if (rc) {
+        free_acceleration(c);
+        return rc;
+    }
+    c->aa_depth = depth;
     return RT3D_OK;
 }
 

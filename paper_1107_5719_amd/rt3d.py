@@ -42,7 +42,7 @@ RT3D_COEF_FP32 = 1
 EXPORTED = [
     "rt3d_create", "rt3d_destroy", "rt3d_set_medium", "rt3d_set_J", "rt3d_get_J",
     "rt3d_formal_solution", "rt3d_build_lstar", "rt3d_get_lstar", "rt3d_os_step",
-    "rt3d_solve_to_convergence", "rt3d_set_acceleration", "rt3d_set_os_method", "rt3d_set_coef_storage", "rt3d_get_emergent_top", "rt3d_set_timing", "rt3d_get_stats",
+    "rt3d_solve_to_convergence", "rt3d_set_acceleration", "rt3d_set_anderson", "rt3d_set_os_method", "rt3d_set_coef_storage", "rt3d_get_emergent_top", "rt3d_set_timing", "rt3d_get_stats",
     "rt3d_status_str", "rt3d_last_error", "rt3d_quadrature", "rt3d_segment_table", "rt3d_validate",
     "rt3d_adjoint_emergent", "rt3d_get_history", "rt3d_sweep_shapes", "rt3d_set_sweep_shape", "rt3d_autotune",
     "rt3d_batch_create", "rt3d_batch_destroy", "rt3d_batch_size", "rt3d_batch_last_error",
@@ -80,6 +80,7 @@ _sig = {
     "rt3d_os_step": (_i, [_vp, _i, C.POINTER(_d)]),
     "rt3d_solve_to_convergence": (_i, [_vp, _d, _i, _i, C.POINTER(_i), C.POINTER(_d)]),
     "rt3d_set_acceleration": (_i, [_vp, _i, _i]),
+    "rt3d_set_anderson": (_i, [_vp, _i]),
     "rt3d_set_os_method": (_i, [_vp, _i]),
     "rt3d_set_coef_storage": (_i, [_vp, _i]),
     "rt3d_get_emergent_top": (_i, [_vp, _vp, _i]),
@@ -274,6 +275,10 @@ def rt3d_set_acceleration(ctx, ng_order: int, ng_every: int):
                   "rt3d_set_acceleration")
 
 
+def rt3d_set_anderson(ctx, depth: int):
+    return _raise(ctx, _lib.rt3d_set_anderson(ctx, int(depth)), "rt3d_set_anderson")
+
+
 def rt3d_set_os_method(ctx, method: int):
     return _raise(ctx, _lib.rt3d_set_os_method(ctx, int(method)), "rt3d_set_os_method")
 
@@ -300,22 +305,25 @@ def rt3d_get_stats(ctx) -> dict:
 
 
 def rt3d_get_history(ctx) -> dict:
-    """The per-step record (see include/rt3d.h): arrays max_rel_dJ, ms, float64_fs, ng."""
+    """The per-step record (see include/rt3d.h): arrays max_rel_dJ, ms, float64_fs, ng, anderson."""
     n = _lib.rt3d_get_history(ctx, None, None, None, 0)
     _raise(ctx, min(n, 0), "rt3d_get_history")
     c = np.zeros(n)
     ms = np.zeros(n)
     fl = np.zeros(n, dtype=np.int32)
     _lib.rt3d_get_history(ctx, c.ctypes.data_as(_vp), ms.ctypes.data_as(_vp), fl.ctypes.data_as(_vp), n)
-    return {"max_rel_dJ": c, "ms": ms, "float64_fs": (fl & 1) != 0, "ng": (fl & 2) != 0}
+    return {"max_rel_dJ": c, "ms": ms, "float64_fs": (fl & 1) != 0, "ng": (fl & 2) != 0,
+            "anderson": (fl & 4) != 0}
 
 
 def write_history_jsonl(path, history: dict, **extra):
-    """One JSON object per step ({"step", "max_rel_dJ", "ms", "float64_fs", "ng", **extra}), appended."""
+    """One JSON object per step ({"step", "max_rel_dJ", "ms", "float64_fs", "ng", "anderson", **extra}),
+    appended."""
     with open(path, "a") as f:
         for q in range(len(history["max_rel_dJ"])):
             rec = {"step": q + 1, "max_rel_dJ": float(history["max_rel_dJ"][q]), "ms": float(history["ms"][q]),
-                   "float64_fs": bool(history["float64_fs"][q]), "ng": bool(history["ng"][q])}
+                   "float64_fs": bool(history["float64_fs"][q]), "ng": bool(history["ng"][q]),
+                   "anderson": bool(history["anderson"][q])}
             rec.update(extra)
             f.write(json.dumps(rec) + "\n")
 
@@ -562,6 +570,10 @@ class Solver:
 
     def set_acceleration(self, ng_order, ng_every):
         rt3d_set_acceleration(self.ctx, ng_order, ng_every)
+
+    def set_anderson(self, depth):
+        """Anderson mixing of the outer iteration with a window of depth (1..8) differences; 0 off."""
+        rt3d_set_anderson(self.ctx, depth)
 
     def set_os_method(self, method):
         """RT3D_OS_JACOBI or RT3D_OS_GAUSS_SEIDEL (multicolour) for the inner solve of the OS step."""

@@ -232,3 +232,63 @@ def test_coef_storage_setting(R, orc):
         with pytest.raises(R.Rt3dError) as e:
             s.set_coef_storage(2)
         assert e.value.status == R.RT3D_ERR_ARG
+
+
+@pytest.mark.parametrize("depth", [3, 5, 8])
+def test_anderson_solve_parity(R, orc, depth):
+    """Anderson mixing on the GPU follows the oracle's mixing (independent code) step for step: the same
+    number of outer iterations and the same J to 1e-10, on a stratified scattering column."""
+    nz, ny, nx = 33, 5, 6
+    chi = np.broadcast_to(stratified_profile(nz, 300.0)[:, None, None], (nz, ny, nx)).copy()
+    chi *= np.exp(0.1 * np.random.default_rng(17).standard_normal(chi.shape))
+    eps = np.full(chi.shape, 1e-3)
+    B = np.ones(chi.shape)
+    M = 10
+    J_o, it_o, c_o, ok = orc.solve_anderson(chi, eps, B, 8, 8, 1e-10, 2000, M, depth)
+    assert ok
+    with R.Solver(nx, ny, nz, 8, 8) as s:
+        s.set_medium(chi, eps, B)
+        s.set_anderson(depth)
+        st, it, c = s.solve(1e-10, 2000, M)
+        assert st == R.RT3D_OK
+        h = s.history()
+        J = s.get_J()
+    assert it == it_o, f"{it} vs oracle {it_o} steps"
+    assert _rel(J, J_o) < 1e-10
+    # mixing from the second step on (the window needs two pairs), none after the converged step
+    assert h["anderson"][1:-1].all() and not h["anderson"][0] and not h["anderson"][-1] and not h["ng"].any()
+
+
+def test_anderson_fixed_point_and_settings(R, orc):
+    """Both forms with Anderson mixing reach the dense fixed point; depth 0 and Ng switch it off."""
+    nz, ny, nx = 5, 4, 6
+    m = random_medium(nx, ny, nz, seed=29, chi_range=(1e-2, 1e1), eps_range=(1e-3, 1.0))
+    Jd = orc.dense_os_solution(m["chi"], m["eps"], m["B"], 4, 8, I_top=0.1)
+    for precision in (0, 1):
+        with R.Solver(nx, ny, nz, 4, 8, I_top=0.1, precision=precision) as s:
+            s.set_medium(m["chi"], m["eps"], m["B"])
+            s.set_anderson(6)
+            st, it, c = s.solve(1e-13, 2000, 8)
+            assert st == R.RT3D_OK
+            assert _rel(s.get_J(), Jd) < (1e-10 if precision == 0 else 1e-7)
+    with R.Solver(nx, ny, nz, 4, 8) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        for bad in (-1, 9):
+            with pytest.raises(R.Rt3dError) as e:
+                s.set_anderson(bad)
+            assert e.value.status == R.RT3D_ERR_ARG
+        s.set_anderson(4)
+        s.set_acceleration(3, 6)             # Ng switches Anderson off
+        s.solve(1e-9, 500, 6)
+        h = s.history()
+        assert h["ng"].any() and not h["anderson"].any()
+        s.set_anderson(4)                    # and Anderson switches Ng off
+        s.set_J(m["B"])
+        s.solve(1e-9, 500, 6)
+        h = s.history()
+        assert h["anderson"].any() and not h["ng"].any()
+        s.set_anderson(0)
+        s.set_J(m["B"])
+        s.solve(1e-9, 500, 6)
+        h = s.history()
+        assert not h["anderson"].any() and not h["ng"].any()
