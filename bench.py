@@ -112,7 +112,7 @@ def oracle_reference(w, med):
         return None, "stored oracle solution does not match its recorded hash"
     src = hashlib.sha256(open(os.path.join(ROOT, "oracle", "oracle.c"), "rb").read()).hexdigest()
     meta = {k: meta[k] for k in ("tol", "iterations", "final_max_rel_dJ", "min_max_rel_dJ", "stop",
-                                 "inner_sweeps", "ng_order", "ng_every") if k in meta}
+                                 "inner_sweeps", "ng_order", "ng_every", "anderson_depth") if k in meta}
     meta["oracle_source_unchanged"] = src == json.load(open(base + ".json")).get("oracle_sha256")
     return J, meta
 
