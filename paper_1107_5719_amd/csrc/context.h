@@ -37,6 +37,8 @@ struct rt3d_ctx {
                                // ranges per XCD, 3 2D tiles, 4 columns (default) (RT3D_JACOBI_XCD)
     bool jacobi_alternate = true;   // column layout: consecutive sweeps walk the layers in opposite
                                     // orders (RT3D_JACOBI_ALTERNATE=0: always bottom first)
+    int jacobi_height = 0;     // column layout: voxels per column, 1, 2 or 4 (0: by grid size;
+                               // RT3D_JACOBI_COLUMN)
     // device buffers (owned)
     double *chi = nullptr, *eps = nullptr, *B = nullptr, *J = nullptr, *Jfs = nullptr, *r = nullptr;
     double *dJa = nullptr, *dJb = nullptr, *L = nullptr, *Iem = nullptr;

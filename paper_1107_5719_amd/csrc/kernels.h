@@ -828,15 +828,16 @@ __global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel_tiled(JacobiArgs 
     jacobi_core<coef>(a, valid ? i : 0, valid ? j : 0, k, valid);
 }
 
-// Column form: a thread takes kJacCol voxels (i, j, k0 .. k0 + kJacCol - 1) and marches up them,
-// keeping the previous iterates of three planes in registers, so each voxel loads one new plane of
-// nine iterates instead of 26 neighbours (the coefficient streams and the per-voxel sums are those of
-// jacobi_core, in the same order).  Blocks are dealt to the XCDs in contiguous ranges of chunks per
-// column layer, as in jacobi_kernel_grouped.
+// Column form: a thread takes H voxels (i, j, k0 .. k0 + H - 1) and marches up them, keeping the
+// previous iterates of three planes in registers, so each voxel loads one new plane of nine iterates
+// instead of 26 neighbours (the coefficient streams and the per-voxel sums are those of jacobi_core,
+// in the same order).  Blocks are dealt to the XCDs in contiguous ranges of chunks per column layer,
+// as in jacobi_kernel_grouped.  H = 4 on grids that fill the chip; smaller grids take shorter columns
+// (more threads), see jacobi_column_height.
 constexpr int kJacCol = 4;
 // Column layer kc of the columns p (p = j nx + i; p >= nx ny: no voxels).  The whole block must call
 // this (it ends with a block reduction when J is updated).
-template <typename coef>
+template <typename coef, int H = kJacCol>
 __device__ inline void jacobi_column_body(const JacobiArgs &a, int p, int kc)
 {
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -845,7 +846,7 @@ __device__ inline void jacobi_column_body(const JacobiArgs &a, int p, int kc)
     double q = 0.0, dist = 0.0;
     bool bad = false;
     if (valid) {
-        const int j = p / nx, i = p - j * nx, k0 = kc * kJacCol;
+        const int j = p / nx, i = p - j * nx, k0 = kc * H;
         const long plane = long(nx) * ny, V = plane * nz;
         const int im = (i == 0) ? nx - 1 : i - 1, ip = (i == nx - 1) ? 0 : i + 1;
         const int jm = (j == 0) ? ny - 1 : j - 1, jp = (j == ny - 1) ? 0 : j + 1;
@@ -863,7 +864,7 @@ __device__ inline void jacobi_column_body(const JacobiArgs &a, int p, int kc)
             }
         }
 #pragma unroll
-        for (int t = 0; t < kJacCol; ++t) {
+        for (int t = 0; t < H; ++t) {
             const int k = k0 + t;
             if (k >= nz) break;
             const long kp = k < nz - 1 ? k + 1 : k;
@@ -896,14 +897,24 @@ __device__ inline void jacobi_column_body(const JacobiArgs &a, int p, int kc)
 // reverse: the column layers in descending order (top first).  Consecutive sweeps alternate, so each
 // starts where the previous one ended and finds its most recent planes still in the caches; the order
 // of the blocks does not change any voxel's sum.
-template <typename coef>
+template <typename coef, int H = kJacCol>
 __global__ __launch_bounds__(kPlaneThreads) void jacobi_kernel_column(JacobiArgs a, int group, int reverse)
 {
     const int blk = blockIdx.x;
     const int xcd = blk & 7, slot = blk >> 3;
     const int kc = slot / group;
     const int kcol = reverse ? int(gridDim.x) / (8 * group) - 1 - kc : kc;
-    jacobi_column_body<coef>(a, (xcd * group + (slot - kc * group)) * kPlaneThreads + threadIdx.x, kcol);
+    jacobi_column_body<coef, H>(a, (xcd * group + (slot - kc * group)) * kPlaneThreads + threadIdx.x, kcol);
+}
+
+// Column height of the column form, from the number of workgroups that columns of 4 give: 4 for
+// grids that fill the chip with them, 2 for mid-size grids, 1 for small ones.  Measured per float64
+// sweep (H = 4 / 2 / 1): 129^3 (2178 workgroups of 4) 67.8 / 67.3 / 70.5 us, 65^3 (289) 13.8 / 13.3 /
+// 14.1 us, 17^3 (10) 8.0 / 5.2 / 3.9 us.  Every height gives the same per-voxel sums.
+inline int jacobi_column_height(int nx, int ny, int nz)
+{
+    const long blocks4 = (long(nx) * ny + kPlaneThreads - 1) / kPlaneThreads * ((nz + 3) / 4);
+    return blocks4 >= 1024 ? 4 : (blocks4 >= 128 ? 2 : 1);
 }
 
 // Gauss-Seidel colour pass.  The voxels are coloured per axis so that no two 27-point neighbours share
@@ -940,16 +951,27 @@ inline int colour_count(int c, int n, bool periodic)
 // One Jacobi sweep in the given grid layout: 0 one block per chunk of a plane, 1 the same padded to
 // a multiple of 8 chunks per plane, 2 contiguous chunk ranges per XCD, 3 2D tiles, 4 columns.
 // reverse: the column layout walks its column layers top first (see jacobi_kernel_column).
-inline void launch_jacobi_sweep(const JacobiArgs &a, int layout, bool f32, hipStream_t stream, bool reverse = false)
+// height: column height of layout 4 (1, 2 or 4; 0: jacobi_column_height).
+inline void launch_jacobi_sweep(const JacobiArgs &a, int layout, bool f32, hipStream_t stream, bool reverse = false,
+                                int height = 0)
 {
     const int chunks = (a.nx * a.ny + kPlaneThreads - 1) / kPlaneThreads;
     const int group = (chunks + 7) / 8;
     const dim3 blk(kPlaneThreads);
     if (layout == 4) {
-        const dim3 grid(unsigned(8 * group) * unsigned((a.nz + kJacCol - 1) / kJacCol));
+        const int H = height > 0 ? height : jacobi_column_height(a.nx, a.ny, a.nz);
+        const dim3 grid(unsigned(8 * group) * unsigned((a.nz + H - 1) / H));
         const int rev = reverse ? 1 : 0;
-        if (f32) hipLaunchKernelGGL(jacobi_kernel_column<float>, grid, blk, 0, stream, a, group, rev);
-        else hipLaunchKernelGGL(jacobi_kernel_column<double>, grid, blk, 0, stream, a, group, rev);
+        if (H == 1) {
+            if (f32) hipLaunchKernelGGL((jacobi_kernel_column<float, 1>), grid, blk, 0, stream, a, group, rev);
+            else hipLaunchKernelGGL((jacobi_kernel_column<double, 1>), grid, blk, 0, stream, a, group, rev);
+        } else if (H == 2) {
+            if (f32) hipLaunchKernelGGL((jacobi_kernel_column<float, 2>), grid, blk, 0, stream, a, group, rev);
+            else hipLaunchKernelGGL((jacobi_kernel_column<double, 2>), grid, blk, 0, stream, a, group, rev);
+        } else {
+            if (f32) hipLaunchKernelGGL((jacobi_kernel_column<float, 4>), grid, blk, 0, stream, a, group, rev);
+            else hipLaunchKernelGGL((jacobi_kernel_column<double, 4>), grid, blk, 0, stream, a, group, rev);
+        }
     } else if (layout == 3) {
         const int tiles_x = (a.nx + kTileX - 1) / kTileX, tiles_y = (a.ny + kTileY - 1) / kTileY;
         const int tgroup = (tiles_x * tiles_y + 7) / 8;
