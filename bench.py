@@ -188,13 +188,14 @@ def _converge(rt3d, torch, w, d_med, prec, stream, M, ng_order, ng_every, tol, m
                "fp32_sweeps": st["fp32_sweeps"]}
 
 
-def _batched(rt3d, torch, n_wl, M, ng, tol, ref_tol, max_iter, cache):
+def _batched(rt3d, torch, n_wl, M, ng, tol, ref_tol, max_iter, cache, aa_depth=0, aa_sweeps=None):
     """The many-wavelength form: n_wl wavelengths, grids drawn from {33, 65, 97}^3, 64 angles each.
 
     Time to converged J of all of them (inputs resident, Lambda* builds included) for three forms:
     the plain float64 path one wavelength at a time (one context each, shape autotuned per grid),
     the batch in float64 and the batch with float32 sweeps; each against a float64 batch solved to
-    ref_tol.  Also the batched formal-solution rate."""
+    ref_tol.  Also the batched formal-solution rate, and (aa_depth > 0) the three forms again with
+    Anderson mixing of that depth instead of Ng, at aa_sweeps inner sweeps (default M)."""
     from paper_1107_5719_amd.inputs import wavelength_batch
 
     mem = wavelength_batch(n_wl)
@@ -212,7 +213,7 @@ def _batched(rt3d, torch, n_wl, M, ng, tol, ref_tol, max_iter, cache):
         getter(i, J)
         return J
 
-    def run_batch(prec, tol_, fs_reps):
+    def run_batch(prec, tol_, fs_reps, aa=0, M=M):
         b = rt3d.Batch(grids, precision=prec)
         for i, d in enumerate(dm):
             b.set_medium(i, d["chi"], d["eps"], d["B"])
@@ -226,7 +227,9 @@ def _batched(rt3d, torch, n_wl, M, ng, tol, ref_tol, max_iter, cache):
                 b.formal_solution()
             dt = (time.perf_counter() - t0) / fs_reps
             fs = {"ms": round(1e3 * dt, 3), "voxel_angle_updates_per_s": vox_ang / dt}
-        if ng[0]:
+        if aa:
+            b.set_anderson(aa)
+        elif ng[0]:
             b.set_acceleration(*ng)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -255,29 +258,51 @@ def _batched(rt3d, torch, n_wl, M, ng, tol, ref_tol, max_iter, cache):
         res["max_rel_err_vs_batched_fp64_reference"] = err(Js)
         out[name] = res
     # plain float64 path, one wavelength after another
-    singles = []
-    for i, g in enumerate(grids):
-        s = rt3d.Solver(g["nx"], g["ny"], g["nz"], g["n_theta"], g["n_phi"])
-        s.set_medium(dm[i]["chi"], dm[i]["eps"], dm[i]["B"])
-        s.autotune(cache, repeats=3)
-        if ng[0]:
-            s.set_acceleration(*ng)
-        singles.append(s)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    its = []
-    for s in singles:
-        st, it, c = s.solve(tol, max_iter, M)
-        its.append(it)
-    torch.cuda.synchronize()
-    secs = time.perf_counter() - t0
-    Js = [fetch(lambda i_, J_: singles[i_].get_J(J_), i) for i in range(len(grids))]
-    for s in singles:
-        s.close()
-    out["sequential_fp64"] = {"seconds": round(secs, 4), "iters_max": max(its), "iters_sum": sum(its),
-                              "max_rel_err_vs_batched_fp64_reference": err(Js)}
+    def run_sequential(aa=0, M=M):
+        singles = []
+        for i, g in enumerate(grids):
+            s = rt3d.Solver(g["nx"], g["ny"], g["nz"], g["n_theta"], g["n_phi"])
+            s.set_medium(dm[i]["chi"], dm[i]["eps"], dm[i]["B"])
+            s.autotune(cache, repeats=3)
+            if aa:
+                s.set_anderson(aa)
+            elif ng[0]:
+                s.set_acceleration(*ng)
+            singles.append(s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = []
+        for s in singles:
+            st, it, c = s.solve(tol, max_iter, M)
+            its.append(it)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        Js = [fetch(lambda i_, J_: singles[i_].get_J(J_), i) for i in range(len(grids))]
+        for s in singles:
+            s.close()
+        return {"seconds": round(secs, 4), "iters_max": max(its), "iters_sum": sum(its),
+                "max_rel_err_vs_batched_fp64_reference": err(Js)}
+
+    out["sequential_fp64"] = run_sequential()
+    secs = out["sequential_fp64"]["seconds"]
     out["batched_fp64_speedup"] = round(secs / out["batched_fp64"]["seconds"], 3)
     out["batched_fp32_speedup"] = round(secs / out["batched_fp32"]["seconds"], 3)
+    if aa_depth > 0:
+        M_aa = aa_sweeps or M
+        aa = {"depth": aa_depth, "inner_sweeps": M_aa}
+        for name, prec in (("batched_fp64", rt3d.RT3D_FP64), ("batched_fp32", rt3d.RT3D_FP32_SWEEP)):
+            Js, res = run_batch(prec, tol, 0, aa=aa_depth, M=M_aa)
+            res["max_rel_err_vs_batched_fp64_reference"] = err(Js)
+            res.pop("formal_solution", None)
+            aa[name] = res
+        aa["sequential_fp64"] = run_sequential(aa=aa_depth, M=M_aa)
+        secs_aa = aa["sequential_fp64"]["seconds"]
+        aa["batched_fp64_speedup"] = round(secs_aa / aa["batched_fp64"]["seconds"], 3)
+        aa["batched_fp32_speedup"] = round(secs_aa / aa["batched_fp32"]["seconds"], 3)
+        # against the plain float64 path with Ng (the form above)
+        aa["batched_fp64_speedup_over_sequential_ng"] = round(secs / aa["batched_fp64"]["seconds"], 3)
+        aa["batched_fp32_speedup_over_sequential_ng"] = round(secs / aa["batched_fp32"]["seconds"], 3)
+        out["anderson"] = aa
     return out
 
 
@@ -430,6 +455,10 @@ def main() -> int:
     ap.add_argument("--batch-wavelengths", type=int, default=64,
                     help="wavelengths of the batched-form measurement (0 skips it)")
     ap.add_argument("--batch-inner-sweeps", type=int, default=8)
+    ap.add_argument("--batch-anderson-depth", type=int, default=8,
+                    help="also time the batched and one-at-a-time forms with Anderson mixing of this depth (0 skips)")
+    ap.add_argument("--batch-anderson-sweeps", type=int, default=4,
+                    help="inner sweeps of the Anderson-mixing runs of the batched measurement")
     ap.add_argument("--adjoint-fd-voxels", type=int, default=50,
                     help="finite-difference checks of the adjoint at 65^3 x 64 (0 skips them; -1 skips "
                          "the adjoint measurement)")
@@ -660,7 +689,8 @@ def main() -> int:
 
         cache = args.tune_cache or os.path.join(tempfile.gettempdir(), "rt3d_tune.json")
         batched = _batched(rt3d, torch, args.batch_wavelengths, args.batch_inner_sweeps,
-                           (args.ng_order, args.ng_every), w.tol, args.reference_tol, 3000, cache)
+                           (args.ng_order, args.ng_every), w.tol, args.reference_tol, 3000, cache,
+                           aa_depth=args.batch_anderson_depth, aa_sweeps=args.batch_anderson_sweeps)
 
     # ---- the paper's slab on the paper's grids ------------------------------------------------------
     paper_grids = None

@@ -353,6 +353,12 @@ int rt3d_batch_get_Jfs(rt3d_batch *b, int member, double *Jfs_out, int ptr_kind)
 /* Ng acceleration for every member, as rt3d_set_acceleration.  Errors as there. */
 int rt3d_batch_set_acceleration(rt3d_batch *b, int ng_order, int ng_every);
 
+/* Anderson mixing for every member, as rt3d_set_anderson (depth 0..8; switches Ng off, and
+ * rt3d_batch_set_acceleration with an order > 0 switches it off): each member keeps its own window in
+ * the member state on the device, so its iterates are bitwise those of solving it alone with the
+ * same depth.  Errors as there. */
+int rt3d_batch_set_anderson(rt3d_batch *b, int depth);
+
 /* Rebuild every member's plan for a shape, as rt3d_set_sweep_shape.  After RT3D_ERR_ARG from a
  * member the batch cannot sweep (RT3D_ERR_STATE) until a shape change succeeds. */
 int rt3d_batch_set_sweep_shape(rt3d_batch *b, int shape);

@@ -46,7 +46,11 @@ struct MemberState {
     int nh;              // iterates in the Ng history since the last extrapolation
     int ng_store;        // ring slot that receives J in this iteration, or -1
     int ng_newest;       // ring index of the newest iterate when extrapolating in this iteration, or -1
-    int pad0, pad1;
+    int aa_count;        // Anderson window: (input, output) pairs held, their ring slots oldest first,
+    int aa_next;         // the slot the next input takes, and whether this iteration mixes
+    int aa_mix;
+    int aa_slot[kAaMaxDepth + 1];
+    int pad0;
     double c_last, da_last;
 };
 
@@ -54,6 +58,8 @@ struct BatchParams {
     double tol;
     double anchor_ratio;  // FP32 form: re-anchor when c < anchor_ratio * max|J - Ja|/|J| (as a context)
     int max_iter, fp32, ng_order, ng_every;
+    int aa_depth;         // Anderson mixing window (0: off)
+    int pad;
 };
 
 struct MemberScalars {
@@ -85,6 +91,16 @@ __global__ void ctl_pre_kernel(int n, MemberState *st, const BatchParams *prm)
     if (m >= n) return;
     MemberState &s = st[m];
     if (!s.active) { s.mode = 0; return; }
+    if (prm->aa_depth > 0) {
+        // the step's input joins the Anderson window (the oldest pair leaves a full window)
+        const int cap = prm->aa_depth + 1;
+        if (s.aa_count == cap) {
+            for (int q = 0; q + 1 < cap; ++q) s.aa_slot[q] = s.aa_slot[q + 1];
+            --s.aa_count;
+        }
+        s.aa_slot[s.aa_count] = s.aa_next;
+        s.aa_next = (s.aa_next + 1) % cap;
+    }
     if (!prm->fp32) { s.mode = 1; return; }
     const bool refresh = !s.anchor_valid || s.force_refresh || s.c_last < prm->anchor_ratio * s.da_last;
     s.mode = refresh ? 1 : 2;
@@ -182,7 +198,9 @@ __global__ void ctl_post_kernel(int n, MemberState *st, const BatchParams *prm, 
     MemberState &s = st[m];
     s.ng_store = -1;
     s.ng_newest = -1;
+    s.aa_mix = 0;
     if (s.mode == 0) return;
+    if (prm->aa_depth > 0) s.aa_count += 1;      // the step's output joins the window (aa_output_kernel)
     const double c = __longlong_as_double(static_cast<long long>(*sc[m].maxrel));
     const double d = __longlong_as_double(static_cast<long long>(*sc[m].maxdist));
     const bool anchored = s.mode == 1;
@@ -214,6 +232,8 @@ __global__ void ctl_post_kernel(int n, MemberState *st, const BatchParams *prm, 
             s.ng_newest = (s.nh - 1) % R;
             s.nh = 1;
         }
+    } else if (prm->aa_depth > 0 && s.aa_count >= 2) {
+        s.aa_mix = 1;
     }
     if (s.iters >= prm->max_iter) {
         s.status = RT3D_MEMBER_MAX_ITER;
@@ -259,6 +279,51 @@ __global__ void ng_combine_kernel_batch(const NgArgs *args, const MemberState *s
         ng_combine_body(a, newest, v);
 }
 
+// Anderson window: J enters the input ring before the step (mode != 0) and the output ring after it
+__global__ void aa_store_kernel(const AaArgs *args, const MemberState *st, int output)
+{
+    const int m = blockIdx.y;
+    const MemberState &s = st[m];
+    if (s.mode == 0) return;
+    const AaArgs a = args[m];
+    const int slot = output ? s.aa_slot[s.aa_count - 1] : s.aa_slot[s.aa_count];
+    double *dst = (output ? const_cast<double *>(a.G) : const_cast<double *>(a.X)) + long(slot) * a.V;
+    for (long v = long(blockIdx.x) * blockDim.x + threadIdx.x; v < a.V; v += long(gridDim.x) * blockDim.x)
+        dst[v] = a.J[v];
+}
+
+// the window of member m as the single-problem mixing takes it
+__device__ inline AaArgs aa_member_args(const AaArgs *args, const MemberState &s, int m)
+{
+    AaArgs a = args[m];
+    a.k = s.aa_count - 1;
+    for (int q = 0; q <= kAaMaxDepth; ++q) a.slot[q] = q < s.aa_count ? s.aa_slot[q] : 0;
+    return a;
+}
+
+__global__ __launch_bounds__(kAaThreads) void aa_dots_kernel_batch(const AaArgs *args, const MemberState *st)
+{
+    const int m = blockIdx.y;
+    if (!st[m].aa_mix) return;
+    aa_dots_body(aa_member_args(args, st[m], m), blockIdx.x);
+}
+
+__global__ __launch_bounds__(kAaThreads) void aa_solve_kernel_batch(const AaArgs *args, const MemberState *st)
+{
+    const int m = blockIdx.y;
+    if (!st[m].aa_mix) return;
+    aa_solve_body(aa_member_args(args, st[m], m));
+}
+
+__global__ void aa_combine_kernel_batch(const AaArgs *args, const MemberState *st)
+{
+    const int m = blockIdx.y;
+    if (!st[m].aa_mix) return;
+    const AaArgs a = aa_member_args(args, st[m], m);
+    for (long v = long(blockIdx.x) * blockDim.x + threadIdx.x; v < a.V; v += long(gridDim.x) * blockDim.x)
+        aa_combine_body(a, v);
+}
+
 // after an extrapolation the ring restarts from the new iterate
 __global__ void ng_restart_kernel(const CopyArgs *args, const MemberState *st)
 {
@@ -280,6 +345,7 @@ struct rt3d_batch {
     bool own_stream = false;
     std::vector<rt3d_ctx *> m;
     int ng_order = 0, ng_every = 0;
+    int aa_depth = 0;                  // Anderson mixing instead of Ng (0: off)
     // device tables (owned)
     MemberState *d_state = nullptr;
     BatchParams *d_params = nullptr;
@@ -289,6 +355,7 @@ struct rt3d_batch {
     ReduceArgs *d_red = nullptr;       // [3][n]: with residual; difference (FP32 form); no residual
     CopyArgs *d_copy = nullptr;        // [n]
     NgArgs *d_ng = nullptr;            // [n]
+    AaArgs *d_aa = nullptr;            // [n] (window slots come from the member state)
     JacobiArgs *d_jac = nullptr;       // [M][n]
     int jac_M = 0;
     BatchItem *d_items = nullptr;
@@ -351,7 +418,7 @@ void free_tables(rt3d_batch *b)
 {
     drop_graph(b);
     bfree(b->d_state); bfree(b->d_params); bfree(b->d_scalars);
-    bfree(b->d_src); bfree(b->d_sw); bfree(b->d_red); bfree(b->d_copy); bfree(b->d_ng); bfree(b->d_jac);
+    bfree(b->d_src); bfree(b->d_sw); bfree(b->d_red); bfree(b->d_copy); bfree(b->d_ng); bfree(b->d_aa); bfree(b->d_jac);
     bfree(b->d_items); bfree(b->d_planes); bfree(b->d_columns);
     b->jac_M = 0;
     b->tables_ok = false;
@@ -437,6 +504,7 @@ int build_tables(rt3d_batch *b)
     std::vector<ReduceArgs> red(3 * n);
     std::vector<CopyArgs> cp(n);
     std::vector<NgArgs> ng(n);
+    std::vector<AaArgs> aa(n);
     std::vector<MemberScalars> sc(n);
     std::vector<std::pair<double, BatchItem>> work;
     std::vector<PlaneBlock> planes, columns;
@@ -484,6 +552,8 @@ int build_tables(rt3d_batch *b)
         k.hist = c->ng_hist;
         NgArgs &g = ng[i];
         g.V = c->V; g.order = c->ng_order; g.hist = c->ng_hist; g.work = c->ng_work; g.J = c->J;
+        AaArgs &w = aa[i];
+        w.V = c->V; w.k = 0; w.X = c->aa_x; w.G = c->aa_g; w.work = c->aa_work; w.J = c->J;
         sc[i] = MemberScalars{c->d_maxrel, c->d_maxdist, c->d_flag};
         b->smem64 = std::max(b->smem64, sweep_smem_bytes(c->plan.max_win_rows, nx, false));
         b->smem32 = std::max(b->smem32, sweep_smem_bytes(c->plan.max_win_rows, nx, true));
@@ -519,7 +589,8 @@ int build_tables(rt3d_batch *b)
     int rc = RT3D_OK;
     auto chk = [&](int r) { if (!rc) rc = r; };
     chk(bupload(b, b->d_src, src)); chk(bupload(b, b->d_sw, sw)); chk(bupload(b, b->d_red, red));
-    chk(bupload(b, b->d_copy, cp)); chk(bupload(b, b->d_ng, ng)); chk(bupload(b, b->d_scalars, sc));
+    chk(bupload(b, b->d_copy, cp)); chk(bupload(b, b->d_ng, ng)); chk(bupload(b, b->d_aa, aa));
+    chk(bupload(b, b->d_scalars, sc));
     chk(bupload(b, b->d_items, items)); chk(bupload(b, b->d_planes, planes));
     chk(bupload(b, b->d_columns, columns));
     if (rc) return rc;
@@ -624,6 +695,10 @@ int enqueue_iteration(rt3d_batch *b, int M)
     int rc;
     hipLaunchKernelGGL(ctl_pre_kernel, ctl, ctl_t, 0, b->stream, n, b->d_state, b->d_params);
     if ((rc = launch_check(b, "ctl_pre_kernel"))) return rc;
+    if (b->aa_depth > 0) {
+        hipLaunchKernelGGL(aa_store_kernel, aux, dim3(256), 0, b->stream, b->d_aa, b->d_state, 0);
+        if ((rc = launch_check(b, "aa_store_kernel"))) return rc;
+    }
     // formal solution: float64 (mode 1), and in the FP32 form the float32 difference (mode 2)
     hipLaunchKernelGGL(source_kernel_batch<double>, dim3(b->n_planes), dim3(kPlaneThreads), 0, b->stream,
                        b->d_src, b->d_planes, b->d_state, 1);
@@ -667,6 +742,14 @@ int enqueue_iteration(rt3d_batch *b, int M)
         hipLaunchKernelGGL(ng_combine_kernel_batch, aux, dim3(256), 0, b->stream, b->d_ng, b->d_state);
         hipLaunchKernelGGL(ng_restart_kernel, aux, dim3(256), 0, b->stream, b->d_copy, b->d_state);
         if ((rc = launch_check(b, "ng kernels"))) return rc;
+    }
+    if (b->aa_depth > 0) {
+        hipLaunchKernelGGL(aa_store_kernel, aux, dim3(256), 0, b->stream, b->d_aa, b->d_state, 1);
+        hipLaunchKernelGGL(aa_dots_kernel_batch, dim3(kAaBlocks, n), dim3(kAaThreads), 0, b->stream, b->d_aa,
+                           b->d_state);
+        hipLaunchKernelGGL(aa_solve_kernel_batch, dim3(1, n), dim3(kAaThreads), 0, b->stream, b->d_aa, b->d_state);
+        hipLaunchKernelGGL(aa_combine_kernel_batch, aux, dim3(256), 0, b->stream, b->d_aa, b->d_state);
+        if ((rc = launch_check(b, "anderson kernels"))) return rc;
     }
     return RT3D_OK;
 }
@@ -828,6 +911,21 @@ int rt3d_batch_set_acceleration(rt3d_batch *b, int ng_order, int ng_every)
     }
     b->ng_order = ng_order;
     b->ng_every = ng_every;
+    if (ng_order > 0) b->aa_depth = 0;
+    invalidate_tables(b);
+    return RT3D_OK;
+}
+
+int rt3d_batch_set_anderson(rt3d_batch *b, int depth)
+{
+    if (!b) return RT3D_ERR_ARG;
+    if (depth < 0 || depth > kAaMaxDepth) return bfail(b, RT3D_ERR_ARG, "depth must be 0..8");
+    for (int i = 0; i < b->n; ++i) {
+        const int rc = rt3d_set_anderson(b->m[i], depth);
+        if (rc) return member_fail(b, i, rc);
+    }
+    b->aa_depth = depth;
+    if (depth > 0) b->ng_order = b->ng_every = 0;
     invalidate_tables(b);
     return RT3D_OK;
 }
@@ -926,7 +1024,7 @@ int rt3d_batch_solve(rt3d_batch *b, double tol, int max_iter, int inner_sweeps, 
     const double ratio = b->m[0]->anchor_ratio;
     for (int i = 1; i < n; ++i)
         if (b->m[i]->anchor_ratio != ratio) return bfail(b, RT3D_ERR_ARG, "members differ in their anchoring ratio");
-    BatchParams prm{tol, ratio, max_iter, f32 ? 1 : 0, b->ng_order, b->ng_every};
+    BatchParams prm{tol, ratio, max_iter, f32 ? 1 : 0, b->ng_order, b->ng_every, b->aa_depth, 0};
     BHIP_TRY(b, hipMemcpyAsync(b->d_state, h.data(), n * sizeof(MemberState), hipMemcpyHostToDevice, b->stream), "state");
     BHIP_TRY(b, hipMemcpyAsync(b->d_params, &prm, sizeof(prm), hipMemcpyHostToDevice, b->stream), "params");
     rc = capture_graph(b, inner_sweeps);

@@ -1162,15 +1162,15 @@ __host__ __device__ constexpr int aa_b_index(int i) { return kAaMaxDepth * (kAaM
 
 // One block's share of A_ij = sum_v w df_i df_j and b_i = sum_v w df_i f_k, w = 1/g_k^2, f = g - x,
 // df_j = f_k - f_{k-j}; the sums of a thread, then of a wavefront (xor tree), then of the block's
-// wavefronts in order.  Whole block.
-__global__ __launch_bounds__(kAaThreads) void aa_dots_kernel(AaArgs a)
+// wavefronts in order.  Whole block; blk is the block's index among the kAaBlocks of the pass.
+__device__ inline void aa_dots_body(const AaArgs &a, int blk)
 {
     const int k = a.k;
     double acc[kAaSums];
 #pragma unroll
     for (int q = 0; q < kAaSums; ++q) acc[q] = 0.0;
     const double *gk = a.G + long(a.slot[k]) * a.V, *xk = a.X + long(a.slot[k]) * a.V;
-    for (long v = long(blockIdx.x) * kAaThreads + threadIdx.x; v < a.V; v += long(kAaBlocks) * kAaThreads) {
+    for (long v = long(blk) * kAaThreads + threadIdx.x; v < a.V; v += long(kAaBlocks) * kAaThreads) {
         const double g = gk[v];
         const double w = 1.0 / (g * g);
         const double fk = g - xk[v];
@@ -1200,14 +1200,16 @@ __global__ __launch_bounds__(kAaThreads) void aa_dots_kernel(AaArgs a)
     if (threadIdx.x < kAaSums) {
         double s = part[0][threadIdx.x];
         for (int w2 = 1; w2 < kAaThreads / 64; ++w2) s += part[w2][threadIdx.x];
-        a.work[blockIdx.x * kAaSums + threadIdx.x] = s;
+        a.work[blk * kAaSums + threadIdx.x] = s;
     }
 }
 
+__global__ __launch_bounds__(kAaThreads) void aa_dots_kernel(AaArgs a) { aa_dots_body(a, blockIdx.x); }
+
 // Sums the block partials in a fixed order, then thread 0 solves the k x k normal equations A gamma = b
 // by Gaussian elimination with partial pivoting; a singular system or a non-finite solution clears the
-// valid flag (the output g_k is then kept as the next input).
-__global__ __launch_bounds__(kAaThreads) void aa_solve_kernel(AaArgs a)
+// valid flag (the output g_k is then kept as the next input).  Whole block.
+__device__ inline void aa_solve_body(const AaArgs &a)
 {
     __shared__ double tot[kAaSums];
     if (threadIdx.x < kAaSums) {
@@ -1250,17 +1252,23 @@ __global__ __launch_bounds__(kAaThreads) void aa_solve_kernel(AaArgs a)
     a.work[kAaCoefOff + kAaMaxDepth] = ok ? 1.0 : 0.0;
 }
 
-// J = g_k - sum_j gamma_j (g_k - g_{k-j}) when the solve succeeded, else g_k.
-__global__ __launch_bounds__(256) void aa_combine_kernel(AaArgs a)
+__global__ __launch_bounds__(kAaThreads) void aa_solve_kernel(AaArgs a) { aa_solve_body(a); }
+
+// J = g_k - sum_j gamma_j (g_k - g_{k-j}) when the solve succeeded, else g_k (voxel v).
+__device__ inline void aa_combine_body(const AaArgs &a, long v)
 {
-    const long v = long(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (v >= a.V) return;
     const double *cf = a.work + kAaCoefOff;
     const double gk = a.G[long(a.slot[a.k]) * a.V + v];
     double x = gk;
     if (cf[kAaMaxDepth] != 0.0)
         for (int j = 1; j <= a.k; ++j) x -= cf[j - 1] * (gk - a.G[long(a.slot[a.k - j]) * a.V + v]);
     a.J[v] = x;
+}
+
+__global__ __launch_bounds__(256) void aa_combine_kernel(AaArgs a)
+{
+    const long v = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v < a.V) aa_combine_body(a, v);
 }
 
 // finiteness / range check of a device medium

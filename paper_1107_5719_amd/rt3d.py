@@ -47,7 +47,8 @@ EXPORTED = [
     "rt3d_adjoint_emergent", "rt3d_get_history", "rt3d_sweep_shapes", "rt3d_set_sweep_shape", "rt3d_autotune",
     "rt3d_batch_create", "rt3d_batch_destroy", "rt3d_batch_size", "rt3d_batch_last_error",
     "rt3d_batch_set_medium", "rt3d_batch_set_J", "rt3d_batch_get_J", "rt3d_batch_get_Jfs",
-    "rt3d_batch_set_acceleration", "rt3d_batch_set_sweep_shape", "rt3d_batch_formal_solution",
+    "rt3d_batch_set_acceleration", "rt3d_batch_set_anderson", "rt3d_batch_set_sweep_shape",
+    "rt3d_batch_formal_solution",
     "rt3d_batch_solve", "rt3d_batch_autotune", "rt3d_batch_get_stats", "rt3d_formal_solution_noalloc",
 ]
 
@@ -105,6 +106,7 @@ _sig = {
     "rt3d_batch_get_J": (_i, [_vp, _i, _vp, _i]),
     "rt3d_batch_get_Jfs": (_i, [_vp, _i, _vp, _i]),
     "rt3d_batch_set_acceleration": (_i, [_vp, _i, _i]),
+    "rt3d_batch_set_anderson": (_i, [_vp, _i]),
     "rt3d_batch_set_sweep_shape": (_i, [_vp, _i]),
     "rt3d_batch_formal_solution": (_i, [_vp]),
     "rt3d_batch_solve": (_i, [_vp, _d, _i, _i, _i, _vp, _vp, _vp]),
@@ -467,6 +469,10 @@ def rt3d_batch_set_acceleration(b, ng_order: int, ng_every: int):
                    "rt3d_batch_set_acceleration")
 
 
+def rt3d_batch_set_anderson(b, depth: int):
+    return _braise(b, _lib.rt3d_batch_set_anderson(b, int(depth)), "rt3d_batch_set_anderson")
+
+
 def rt3d_batch_set_sweep_shape(b, shape: int):
     return _braise(b, _lib.rt3d_batch_set_sweep_shape(b, int(shape)), "rt3d_batch_set_sweep_shape")
 
@@ -659,6 +665,10 @@ class Batch:
 
     def set_acceleration(self, ng_order, ng_every):
         rt3d_batch_set_acceleration(self.b, ng_order, ng_every)
+
+    def set_anderson(self, depth):
+        """Anderson mixing of depth 0..8 for every member (0: off); switches Ng off."""
+        rt3d_batch_set_anderson(self.b, depth)
 
     def set_sweep_shape(self, shape):
         rt3d_batch_set_sweep_shape(self.b, shape)

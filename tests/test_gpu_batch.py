@@ -73,16 +73,25 @@ def test_batch_formal_solution_bitwise(R, precision, shape):
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=[f"shape{x}" for x in SHAPES])
-@pytest.mark.parametrize("precision,ng", [(0, (0, 0)), (0, (2, 4)), (1, (0, 0)), (1, (3, 6))],
-                         ids=["fp64", "fp64-ng2", "fp32", "fp32-ng3"])
+@pytest.mark.parametrize("precision,ng", [(0, (0, 0)), (0, (2, 4)), (1, (0, 0)), (1, (3, 6)), (0, "aa5"),
+                                          (1, "aa3")],
+                         ids=["fp64", "fp64-ng2", "fp32", "fp32-ng3", "fp64-aa5", "fp32-aa3"])
 def test_batch_solve_bitwise(R, precision, ng, shape):
+    """Every member of the batched solve takes bitwise the steps of solving it alone (Ng, or Anderson
+    mixing with the window kept per member on the device)."""
     mem = _members(seed=7)
     tol, max_iter, M = 1e-9, 300, 6
+
+    def accelerate(x):
+        if isinstance(ng, str):
+            x.set_anderson(int(ng[2:]))
+        elif ng[0]:
+            x.set_acceleration(*ng)
+
     with R.Batch([m["grid"] for m in mem], precision=precision, sweep_shape=shape) as b:
         for i, m in enumerate(mem):
             b.set_medium(i, m["chi"], m["eps"], m["B"])
-        if ng[0]:
-            b.set_acceleration(*ng)
+        accelerate(b)
         st, iters, cs, states = b.solve(tol, max_iter, M, poll_every=3)
         Jb = [b.get_J(i) for i in range(len(mem))]
     assert st == R.RT3D_OK
@@ -90,8 +99,7 @@ def test_batch_solve_bitwise(R, precision, ng, shape):
     for i, m in enumerate(mem):
         with _single(R, m["grid"], precision, shape) as s:
             s.set_medium(m["chi"], m["eps"], m["B"])
-            if ng[0]:
-                s.set_acceleration(*ng)
+            accelerate(s)
             st1, it1, c1 = s.solve(tol, max_iter, M)
             J1 = s.get_J()
         assert st1 == R.RT3D_OK
