@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # counting an FMA as 2 flops, i.e. 39.3e12 lane-instructions/s), float32 32 lanes (78.6e12)
 VALU_ISSUE_PEAK = {"fp64": 39.3e12, "fp32": 78.6e12}
 SWEEP_KERNEL = {"fp64": "sweep_kernel<double,512,2>", "fp32": "sweep_kernel<float,512,2>"}
-JACOBI_KERNEL = {"fp64": "jacobi_kernel_column<double>", "fp32": "jacobi_kernel_column<float>"}
+JACOBI_KERNEL = {"fp64": "jacobi_kernel_column<double,4>", "fp32": "jacobi_kernel_column<float,4>"}
 # the (M, Ng order, Ng every) schedules over which time to converged J is summarised (median, worst)
 SCHEDULES = [(12, 3, 6), (20, 3, 6), (30, 3, 6), (40, 3, 6), (12, 3, 8), (20, 3, 8), (30, 3, 8), (40, 3, 8)]
 # the (M, depth) schedules of Anderson mixing
