@@ -350,13 +350,16 @@ int rt3d_batch_set_J(rt3d_batch *b, int member, const double *J, int ptr_kind);
 int rt3d_batch_get_J(rt3d_batch *b, int member, double *J_out, int ptr_kind);
 int rt3d_batch_get_Jfs(rt3d_batch *b, int member, double *Jfs_out, int ptr_kind);
 
-/* Ng acceleration for every member, as rt3d_set_acceleration.  Errors as there. */
+/* Ng acceleration for every member, as rt3d_set_acceleration (order 0 switches all acceleration off,
+ * Anderson mixing included).  Errors as there; after an error the batch runs without acceleration
+ * until a setter succeeds. */
 int rt3d_batch_set_acceleration(rt3d_batch *b, int ng_order, int ng_every);
 
-/* Anderson mixing for every member, as rt3d_set_anderson (depth 0..8; switches Ng off, and
- * rt3d_batch_set_acceleration with an order > 0 switches it off): each member keeps its own window in
- * the member state on the device, so its iterates are bitwise those of solving it alone with the
- * same depth.  Errors as there. */
+/* Anderson mixing for every member, as rt3d_set_anderson (depth 0..8; 0 switches all acceleration
+ * off).  Like the context calls, this and rt3d_batch_set_acceleration replace each other's setting.
+ * Each member keeps its own window in the member state on the device, so its iterates are bitwise
+ * those of solving it alone with the same depth.  Errors as there; after an error the batch runs
+ * without acceleration until a setter succeeds. */
 int rt3d_batch_set_anderson(rt3d_batch *b, int depth);
 
 /* Rebuild every member's plan for a shape, as rt3d_set_sweep_shape.  After RT3D_ERR_ARG from a

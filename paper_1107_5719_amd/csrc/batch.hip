@@ -902,17 +902,21 @@ int rt3d_batch_get_Jfs(rt3d_batch *b, int member, double *Jfs_out, int ptr_kind)
     return RT3D_OK;
 }
 
+// Either setter replaces the members' acceleration (as on a context, where each frees the other's
+// buffers).  The batch runs without acceleration until every member has taken the new setting, so
+// that a member failing half-way never leaves the batch pointing at buffers that were freed.
 int rt3d_batch_set_acceleration(rt3d_batch *b, int ng_order, int ng_every)
 {
     if (!b) return RT3D_ERR_ARG;
+    b->ng_order = b->ng_every = 0;
+    b->aa_depth = 0;
+    invalidate_tables(b);
     for (int i = 0; i < b->n; ++i) {
         const int rc = rt3d_set_acceleration(b->m[i], ng_order, ng_every);
         if (rc) return member_fail(b, i, rc);
     }
     b->ng_order = ng_order;
     b->ng_every = ng_every;
-    if (ng_order > 0) b->aa_depth = 0;
-    invalidate_tables(b);
     return RT3D_OK;
 }
 
@@ -920,13 +924,14 @@ int rt3d_batch_set_anderson(rt3d_batch *b, int depth)
 {
     if (!b) return RT3D_ERR_ARG;
     if (depth < 0 || depth > kAaMaxDepth) return bfail(b, RT3D_ERR_ARG, "depth must be 0..8");
+    b->ng_order = b->ng_every = 0;
+    b->aa_depth = 0;
+    invalidate_tables(b);
     for (int i = 0; i < b->n; ++i) {
         const int rc = rt3d_set_anderson(b->m[i], depth);
         if (rc) return member_fail(b, i, rc);
     }
     b->aa_depth = depth;
-    if (depth > 0) b->ng_order = b->ng_every = 0;
-    invalidate_tables(b);
     return RT3D_OK;
 }
 

@@ -108,6 +108,38 @@ def test_batch_solve_bitwise(R, precision, ng, shape):
         assert np.array_equal(Jb[i], J1), f"member {i}: max diff {np.max(np.abs(Jb[i] - J1))}"
 
 
+def test_batch_acceleration_setters_replace_each_other(R):
+    """Ng and Anderson settings replace each other on the batch as on a context (each frees the
+    other's member buffers): switching back and forth, or off, solves like a batch that was set so
+    from the start."""
+    mem = _members(seed=11)
+    grids = [m["grid"] for m in mem]
+
+    def solve(setup):
+        with R.Batch(grids) as b:
+            for i, m in enumerate(mem):
+                b.set_medium(i, m["chi"], m["eps"], m["B"])
+            setup(b)
+            st, iters, cs, states = b.solve(1e-9, 400, 5, poll_every=4)
+            assert st == R.RT3D_OK
+            return iters.copy(), [b.get_J(i) for i in range(len(mem))]
+
+    plain = solve(lambda b: None)
+    ng = solve(lambda b: b.set_acceleration(3, 6))
+    aa = solve(lambda b: b.set_anderson(4))
+    for want, setup in ((plain, lambda b: (b.set_anderson(4), b.set_acceleration(0, 0))),
+                        (plain, lambda b: (b.set_acceleration(3, 6), b.set_anderson(0))),
+                        (ng, lambda b: (b.set_anderson(4), b.set_acceleration(3, 6))),
+                        (aa, lambda b: (b.set_acceleration(3, 6), b.set_anderson(4)))):
+        got = solve(setup)
+        assert np.array_equal(got[0], want[0])
+        for a, c in zip(got[1], want[1]):
+            assert np.array_equal(a, c)
+    with R.Batch(grids) as b:
+        with pytest.raises(R.Rt3dError):
+            b.set_anderson(9)
+
+
 def test_batch_poll_interval_does_not_change_iterates(R):
     mem = _members(seed=3)
     res = []
