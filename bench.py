@@ -413,7 +413,8 @@ def _config_line(rt3d, torch, w, stream, steps, warmup, M, ng, max_iter):
 
 def _paper_grids(rt3d, torch, stream, steps, M, ng, max_iter):
     """The paper's slab on its two timing grids (65^3 and 129^2 x 193, 256 angles): OS-step rate and
-    time to converged J (tol 1e-8, Lambda* included), both forms."""
+    time to converged J (tol 1e-8, Lambda* included), both forms, with the error against the oracle's
+    tightly converged J when one is stored."""
     from paper_1107_5719_amd.inputs import WORKLOADS, make_medium
 
     out = {}
@@ -422,11 +423,16 @@ def _paper_grids(rt3d, torch, stream, steps, M, ng, max_iter):
         med = make_medium(w)
         d_med = {k: torch.from_numpy(v).cuda() for k, v in med.items()}
         row = {"grid": f"{w.nx}x{w.ny}x{w.nz} x {w.n_dir} angles"}
+        J_orc, orc_meta = oracle_reference(w, med)
+        row["oracle_reference"] = orc_meta
+        J_orc = None if J_orc is None else torch.from_numpy(J_orc).cuda()
         for form, prec in (("fp64", rt3d.RT3D_FP64), ("fp32", rt3d.RT3D_FP32_SWEEP)):
             elapsed, per_launch, lstar_s, st = _timed_steps(rt3d, torch, w, d_med, prec, stream, steps, 1, M)
             conv = None
             if max_iter > 0:
                 J, conv = _converge(rt3d, torch, w, d_med, prec, stream, M, ng[0], ng[1], w.tol, max_iter)
+                if J_orc is not None:
+                    conv["max_rel_err_vs_oracle"] = _rel_err(J, J_orc)
             row[form] = {"ms_per_step": round(1e3 * elapsed / steps, 3),
                          "voxel_angle_updates_per_s": w.n_vox * w.n_dir * steps / elapsed,
                          "sweep_ms": per_launch["sweep"], "time_to_converged": conv}
