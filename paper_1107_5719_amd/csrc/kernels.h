@@ -57,28 +57,33 @@ template <> struct Vec2<float> { using type = float2; };
 // e^x - 1 for x <= 0 (the argument is always -dtau).  No range branches: x is clamped where e^x
 // vanishes.
 //
-// float64, Tang's table method: x = (128 k + j) ln2/128 + r with 0 <= j < 128 and |r| <= ln2/256, so
-// e^x - 1 = 2^k T_j (1 + r p(r)) - 1 with T_j = 2^(j/128) read from a table and p the Taylor
-// polynomial of (e^r - 1)/r through r^4 (truncation below 3e-17 relative).  The multiple n = 128 k + j
-// is the nearest integer to x 128/ln2, taken from the rounding of x 128/ln2 + 1.5 * 2^52 (the spacing
-// of doubles there is 1, so the low word of the sum is n in two's complement).  2^k T_j - 1 is exact
-// when 2^k T_j >= 1/2 and is far from zero otherwise; the rounding of T_j bounds the relative error
-// by about 4e-15 where the result is small (|x| a few times ln2/256), and below ln2/256 the result is
-// r p(r) itself.  The sweep reduces with one fma on the rounded ln2/128: its error in r, |n| times
-// half an ulp of ln2/128, moves e^x by at most 1e-16 |x| e^x relative (below 3e-17 absolute).
-// exp_pair_tab splits ln2/128 into a high part whose product with n is exact and a low part, so that
-// e^x itself stays accurate to a few ulps for thick segments.
-constexpr int kExpTabLog2 = 7;
+// float64, Tang's table method with N = 16: x = (16 k + j) ln2/16 + r with 0 <= j < 16 and
+// |r| <= ln2/32, so e^x - 1 = 2^k T_j (1 + r p(r)) - 1 with T_j = 2^(j/16) read from a table and p the
+// Taylor polynomial of (e^r - 1)/r through r^6 (truncation below 1e-16 relative).  The multiple
+// n = 16 k + j is the nearest integer to x 16/ln2, taken from the rounding of x 16/ln2 + 1.5 * 2^52
+// (the spacing of doubles there is 1, so the low word of the sum is n in two's complement).
+// 2^k T_j - 1 is exact when 2^k T_j >= 1/2 and is far from zero otherwise; the rounding of T_j bounds
+// the relative error by a few 1e-15 where the result is small (|x| a few times ln2/32), and below
+// ln2/32 the result is r p(r) itself.  The sweep reduces with one fma on the rounded ln2/16: its error
+// in r, |n| times half an ulp of ln2/16, moves e^x by at most 1e-16 |x| e^x relative (below 3e-17
+// absolute).  exp_pair_tab splits ln2/16 into a high part whose product with n is exact and a low
+// part, so that e^x itself stays accurate to a few ulps for thick segments.  The table (128 bytes,
+// in LDS) is small enough that the lanes' lookups never meet in an LDS bank: a 128-entry table with
+// the polynomial through r^4 took 2-3% longer per sweep (host emulation against long-double expm1 over
+// 3e7 samples of x in [-2000, -1e-14]: at most 2.7e-15 relative here, 3.9e-15 with 128 entries).
+constexpr int kExpTabLog2 = 4;
 constexpr int kExpTab = 1 << kExpTabLog2;
-constexpr double kExpInvStep = 184.66496523378731;                // 128 / ln2
-constexpr double kExpStep = 0.0054152123481245725;                 // ln2 / 128
-constexpr double kExpStepHi = 6.93147180369123816490e-01 / 128;   // 21 trailing zero bits
-constexpr double kExpStepLo = 1.90821492927058770002e-10 / 128;
+constexpr double kExpInvStep = 184.66496523378731 / 8;            // 16 / ln2 (128 / ln2, exactly scaled)
+constexpr double kExpStep = 0.0054152123481245725 * 8;             // ln2 / 16
+constexpr double kExpStepHi = 6.93147180369123816490e-01 / 16;    // 21 trailing zero bits
+constexpr double kExpStepLo = 1.90821492927058770002e-10 / 16;
 constexpr double kExpRound = 6755399441055744.0;                   // 1.5 * 2^52
 
 __device__ inline double expm1_poly(double r)
 {
-    double p = 1.0 / 120.0;
+    double p = 1.0 / 5040.0;
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
     p = fma(p, r, 1.0 / 24.0);
     p = fma(p, r, 1.0 / 6.0);
     p = fma(p, r, 0.5);
