@@ -9,7 +9,7 @@ time-to-converged J.  Inputs (chi, eps, B) are resident in HBM before timing sta
 
 value = voxel-angle FS updates per second of whole steps = V * n_dir * steps / elapsed.
 
-Prints one JSON line.  Multi-GPU runs are not part of this build: --gpus > 1 exits with a message.
+Prints one JSON line.  The library runs on one GPU: --gpus > 1 exits with a message.
 """
 from __future__ import annotations
 
@@ -494,9 +494,9 @@ def main() -> int:
         return 0
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the path "
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); the path "
               "would shard over directions with one all-reduce of J_fs per iteration, which is not "
-              "part of this build.", file=sys.stderr)
+              "implemented.", file=sys.stderr)
         return 2
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: launched with WORLD_SIZE > 1; one GPU only", file=sys.stderr)
