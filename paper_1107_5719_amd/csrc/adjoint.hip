@@ -290,7 +290,7 @@ int adjoint_os_step(rt3d_ctx *c, int M, double *dmax, double *numax, int *bad)
     w.Iem = nullptr;
     w.Iem_base = nullptr;
     w.xtab = c->xtab;
-    const size_t smem = sweep_smem_bytes(c->plan.max_win_rows, c->g.nx, false);
+    const size_t smem = sweep_smem_bytes(c->plan, false);
     const dim3 grid(c->plan.items.size());
     with_sweep_shape(c->sweep_shape, [&](auto tag) {
         using Tag = decltype(tag);

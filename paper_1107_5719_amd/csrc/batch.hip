@@ -555,8 +555,8 @@ int build_tables(rt3d_batch *b)
         AaArgs &w = aa[i];
         w.V = c->V; w.k = 0; w.X = c->aa_x; w.G = c->aa_g; w.work = c->aa_work; w.J = c->J;
         sc[i] = MemberScalars{c->d_maxrel, c->d_maxdist, c->d_flag};
-        b->smem64 = std::max(b->smem64, sweep_smem_bytes(c->plan.max_win_rows, nx, false));
-        b->smem32 = std::max(b->smem32, sweep_smem_bytes(c->plan.max_win_rows, nx, true));
+        b->smem64 = std::max(b->smem64, sweep_smem_bytes(c->plan, false));
+        b->smem32 = std::max(b->smem32, sweep_smem_bytes(c->plan, true));
         // sweep work: a band costs about (segments over all layers) x (line slots per thread)
         for (const WorkItem &it : c->plan.items) {
             double segs = 0.0;

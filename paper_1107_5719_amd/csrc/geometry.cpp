@@ -193,7 +193,7 @@ static int pos_mod(int a, int n)
 }
 
 bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int lines_per_wg, int target_seg_per_wg,
-                      size_t window_bytes_max, int elem_bytes, SweepPlan &P, std::string &err)
+                      size_t lds_bytes_max, SweepPlan &P, std::string &err)
 {
     P = SweepPlan();
     P.nx = nx;
@@ -277,10 +277,14 @@ bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int lines_per_w
             int rows = int(std::lround(target_seg_per_wg / (2.0 * nx * seg_per_layer[dA])));
             rows = std::max(rows, std::max(1, span[dA]));
             rows = std::min(rows, max_rows);
-            while (rows > 1 && size_t(2) * (rows + span[dA]) * nx * elem_bytes > window_bytes_max) --rows;
+            auto lds = [&](int r) {
+                return std::max(sweep_lds_bytes(r + span[dA], r, nx, false),
+                                sweep_lds_bytes(r + span[dA], r, nx, true));
+            };
+            while (rows > 1 && lds(rows) > lds_bytes_max) --rows;
             rows = std::min(rows, ny);
-            if (size_t(2) * (rows + span[dA]) * nx * elem_bytes > window_bytes_max) {
-                err = "the deposit windows of one band exceed the LDS budget";
+            if (lds(rows) > lds_bytes_max) {
+                err = "the deposit window of one band exceeds the LDS budget";
                 return false;
             }
             pi.band_rows = rows;
@@ -289,16 +293,18 @@ bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int lines_per_w
             pi.last_rows = ny - (pi.n_bands - 1) * rows;
             pi.inv_rows = 1.0f / float(rows);
             P.max_win_rows = std::max(P.max_win_rows, pi.win_rows);
+            P.max_band_rows = std::max(P.max_band_rows, pi.band_rows);
             P.pairs.push_back(pi);
+            const size_t pl0 = P.player.size();
             for (int k = 0; k < nz; ++k) {
-                const size_t ka = size_t(dA) * nz + k, kb = size_t(dB) * nz + k;
+                const size_t ka = size_t(dA) * nz + k;
                 PairLayer pl{int(P.pseg.size()), P.seg_n[ka], P.row_min[ka], 0};
                 P.player.push_back(pl);
                 for (int s = 0; s < P.seg_n[ka]; ++s) {
-                    const int ia = P.seg_off[ka] + s, ib = P.seg_off[kb] + s;
+                    const int ia = P.seg_off[ka] + s;
                     PairSeg ps{};
                     ps.saA = P.seg_a[ia];
-                    ps.saB = P.seg_a[ib];
+                    ps.shB = 0;
                     ps.smnx = P.seg_bm[ia] * nx;
                     ps.sbnx = P.seg_bb[ia] * nx;
                     ps.len = P.seg_len[ia];
@@ -306,6 +312,22 @@ bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int lines_per_w
                     P.pseg.push_back(ps);
                 }
             }
+            // moves of the B lines: a slot holds the B line whose top column is its A line's plus
+            // 2 dA, so when dA changes by delta to the next segment in sweep order (layers top down
+            // for downward pairs) the B line moves by -2 delta columns
+            std::vector<int> order;            // the pair's segments in sweep order, unreduced dA
+            std::vector<size_t> at;
+            for (int st = 0; st < nz; ++st) {
+                const int k = pi.down ? nz - 1 - st : st;
+                const size_t ka = size_t(dA) * nz + k;
+                const size_t base = size_t(P.player[pl0 + k].off);
+                for (int s = 0; s < P.seg_n[ka]; ++s) {
+                    order.push_back(P.seg_ai[P.seg_off[ka] + s]);
+                    at.push_back(base + size_t(s));
+                }
+            }
+            for (size_t i = 0; i + 1 < order.size(); ++i)
+                P.pseg[at[i]].shB = pos_mod(-2 * (order[i + 1] - order[i]), nx);
         }
     }
     P.n_pair = int(P.pairs.size());

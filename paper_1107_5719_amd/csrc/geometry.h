@@ -60,11 +60,13 @@ struct PairInfo {
     double mu;         // direction cosine with the z axis (the same for both)
 };
 
-// Segment s of a pair in one layer, packed for one scalar load: column offsets of both directions
-// (modulo nx), the row offset modulo ny times nx (global row step), the row offset within the band
+// Segment s of a pair in one layer, packed for one scalar load: the column offset of direction A
+// (modulo nx; B's is its negative), the move of the B lines between the slots of their row after
+// this segment (-2 times the change of A's column offset to the next segment in sweep order, modulo
+// nx; 0: none), the row offset modulo ny times nx (global row step), the row offset within the band
 // window times nx (LDS row step), and the length in both precisions.
 struct PairSeg {
-    int saA, saB, smnx, sbnx;
+    int saA, shB, smnx, sbnx;
     double len;
     float len32;
     int pad;
@@ -98,13 +100,24 @@ struct SweepPlan {
     std::vector<WorkItem> items;          // in dispatch order (most expensive first)
     int64_t p_elems = 0;                  // size of the partial-plane buffer P in elements
     int max_win_rows = 0;
+    int max_band_rows = 0;
     int max_seg_per_layer = 0;
     double mean_segments = 0.0;           // per voxel and angle
 };
 
+// LDS of one sweep workgroup for a band of band_rows line rows and a deposit window of win_rows rows:
+// the window and two exchange buffers of one value per line, and in float32 the staged chi,S pairs of
+// the window cells.
+inline size_t sweep_lds_bytes(int win_rows, int band_rows, int nx, bool f32)
+{
+    const size_t cells = size_t(win_rows) * size_t(nx), lines = size_t(band_rows) * size_t(nx);
+    return f32 ? cells * (sizeof(float) + 2 * sizeof(float)) + 2 * lines * sizeof(float)
+               : (cells + 2 * lines) * sizeof(double);
+}
+
 // Build segment tables and the band plan.  lines_per_wg bounds the lines of one direction in one
-// band; window_bytes_max bounds the two LDS deposit windows of a band (element size elem_bytes).
+// band; lds_bytes_max bounds a band's LDS in either precision (sweep_lds_bytes).
 bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int lines_per_wg, int target_seg_per_wg,
-                      size_t window_bytes_max, int elem_bytes, SweepPlan &plan, std::string &err);
+                      size_t lds_bytes_max, SweepPlan &plan, std::string &err);
 
 }  // namespace rt3d

@@ -36,17 +36,16 @@ inline void with_sweep_shape(int shape, F &&f)
     default: f(ShapeTag<512, 2>{}); break;
     }
 }
-constexpr size_t kWindowBytes = 48 * 1024;   // LDS for the two deposit windows of a band (float64)
+constexpr size_t kWindowBytes = 48 * 1024;   // LDS budget of a band (deposit window, exchange, stage)
 // Grids whose windows do not fit kWindowBytes (wide rows, shallow angle sets) take up to this much of
 // the 160 KB of LDS a gfx950 workgroup may use (the rest holds the kernel's static LDS): one workgroup
 // per CU then, but no width limit below the line budget of a workgroup.
 constexpr size_t kWindowBytesWide = 156 * 1024;
-// Dynamic LDS of a sweep workgroup: the two deposit windows and, in float32, the staged chi,S cells of
-// the window rows (the float32 total equals the float64 windows, so one LDS budget serves both).
-inline size_t sweep_smem_bytes(int max_win_rows, int nx, bool f32)
+// Dynamic LDS of a sweep workgroup: the largest deposit window and band of the plan (each band lays
+// out its own window, exchange buffers and float32 stage within this).
+inline size_t sweep_smem_bytes(const rt3d::SweepPlan &plan, bool f32)
 {
-    const size_t cells = size_t(max_win_rows) * size_t(nx);
-    return f32 ? cells * (2 * sizeof(float) + sizeof(float2)) : cells * 2 * sizeof(double);
+    return rt3d::sweep_lds_bytes(plan.max_win_rows, plan.max_band_rows, plan.nx, f32);
 }
 constexpr int kPlaneThreads = 256;   // voxel-parallel kernels: one thread per voxel of a k-plane
 
@@ -196,10 +195,16 @@ struct SweepArgs {
 __device__ inline double expm1_sweep(double x, const double *tab) { return expm1_nonpos_tab(x, tab); }
 __device__ inline float expm1_sweep(float x, const double *) { return expm1_nonpos(x); }
 
-// One workgroup sweeps the lines of one band for both directions of an x-mirrored pair.  Thread t
-// owns lines q = t + i*NT (i < LPT) of the band, for both directions.  Per layer and segment index s
-// the lines of one direction deposit into pairwise distinct cells of that direction's LDS window, so
-// each window is updated with a plain read-add-write and a barrier separates segment indices.
+// One workgroup sweeps the lines of one band for both directions A and B of an x-mirrored pair.  The
+// two directions' segments have equal lengths and row offsets and negated column offsets, so at every
+// segment index a line of A and a line of B cross the same voxel: slot q = (row, column c) of the band
+// holds the A line whose top column is c and the B line whose top column is c + 2 dA (mod nx), dA
+// being A's column offset at that segment; both are in voxel column c + dA.  The pair then shares the
+// voxel's chi,S, the exponential of its optical depth and the deposit cell.  Where dA changes between
+// consecutive segments the B lines move between the slots of their row, through a double-buffered
+// LDS array (the barrier that ends every segment index orders the write before the read).  Thread t
+// owns slots q = t + i*NT (i < LPT).  Per segment index the slots deposit into pairwise distinct cells
+// of the band's LDS window, so the window is updated with a plain read-add-write.
 template <typename real> __device__ inline real seg_length(const rt3d::PairSeg &g);
 template <> __device__ inline double seg_length<double>(const rt3d::PairSeg &g) { return g.len; }
 template <> __device__ inline float seg_length<float>(const rt3d::PairSeg &g) { return g.len32; }
@@ -216,15 +221,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
     const unsigned plane = unsigned(nx) * unsigned(ny);
     const int nlines = it.rows * nx;
     const int wsize = pi.win_rows * nx;
-    real *winA = reinterpret_cast<real *>(smem_raw);
-    real *winB = winA + wsize;
     const real2 *cs = static_cast<const real2 *>(a.cs);
     // float32: the chi,S cells of the band's window rows are staged in LDS once per layer.  Window row
-    // w holds grid row (j0 + rmin + w) mod ny, so a line's gather cell has the index of its deposit
-    // cell.  (A float64 stage, 16 bytes a cell, would not fit beside the windows without halving the
-    // resident waves; float64 gathers from global memory.)
+    // w holds grid row (j0 + rmin + w) mod ny, so a slot's gather cell has the index of its deposit
+    // cell.  (A float64 stage, 16 bytes a cell, would not fit beside the window without halving the
+    // resident waves; float64 gathers from global memory.)  LDS: [stage (float32)] window, exchange.
     constexpr bool kStaged = std::is_same<real, float>::value;
-    real2 *stage = reinterpret_cast<real2 *>(winB + wsize);
+    real2 *stage = reinterpret_cast<real2 *>(smem_raw);
+    real *win = kStaged ? reinterpret_cast<real *>(stage + wsize) : reinterpret_cast<real *>(smem_raw);
+    real *xch = win + wsize;                                   // [2][nlines]
     auto stage_layer = [&](int kk) {
         const rt3d::PairLayer Lk = a.player[it.pair * nz + kk];
         const real2 *csk = cs + long(kk) * plane;
@@ -243,7 +248,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
     };
     real *P = static_cast<real *>(a.P) + pi.p_off + long(it.band) * nz * wsize;
 
-    for (int e = threadIdx.x; e < 2 * wsize; e += NT) winA[e] = real(0);
+    for (int e = threadIdx.x; e < wsize; e += NT) win[e] = real(0);
     __shared__ double xtab[kExpTab];
     if (std::is_same<real, double>::value && threadIdx.x < kExpTab) xtab[threadIdx.x] = a.xtab[threadIdx.x];
 
@@ -263,6 +268,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
     if constexpr (kStaged) stage_layer(pi.down ? nz - 1 : 0);
     __syncthreads();
 
+    int xpar = 0;              // exchange buffer of the last move of the B lines
+    bool moved = false;        // the B lines were written to it before the last barrier
+    unsigned sa_last = 0;      // A's column offset at the last segment (the B lines' top columns)
     for (int step = 0; step < nz; ++step) {
         const int k = pi.down ? nz - 1 - step : step;
         const rt3d::PairLayer L = a.player[it.pair * nz + k];
@@ -275,82 +283,79 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
             grow0[t] = r * unsigned(nx);
         }
         if (!pi.down && step == 0) {
-            // upward lines enter through the bottom plane: boundary light of the entry voxel
+            // upward lines enter through the bottom plane: boundary light of the entry voxel, the
+            // same voxel for the slot's A and B lines
             const rt3d::PairSeg g = a.pseg[L.off];
 #pragma unroll
             for (int t = 0; t < LPT; ++t) {
                 if (li[t] < 0) continue;
                 const unsigned row = wrap_once(grow0[t] + unsigned(g.smnx), plane);
-                const unsigned cA = wrap_once(unsigned(li[t] + g.saA), nx);
-                const unsigned cB = wrap_once(unsigned(li[t] + g.saB), nx);
-                const double sA = a.Islope ? pi.mu * a.Islope[row + cA] : 0.0;
-                const double sB = a.Islope ? pi.mu * a.Islope[row + cB] : 0.0;
-                IA[t] = a.Ibot ? real(a.Ibot[row + cA] + sA) : real(0);
-                IB[t] = a.Ibot ? real(a.Ibot[row + cB] + sB) : real(0);
+                const unsigned col = wrap_once(unsigned(li[t] + g.saA), nx);
+                const double sl = a.Islope ? pi.mu * a.Islope[row + col] : 0.0;
+                IA[t] = a.Ibot ? real(a.Ibot[row + col] + sl) : real(0);
+                IB[t] = IA[t];
             }
         }
         for (int s = 0; s < L.ns; ++s) {
             const rt3d::PairSeg g = a.pseg[L.off + s];
             const real len = seg_length<real>(g);
-            // gathers of segment s: the voxel of each line in the chi,S plane
-            real2 cA[LPT], cB[LPT];
-            unsigned colA[LPT], colB[LPT];
+            // gather of segment s: the voxel of each slot in the chi,S plane
+            real2 cv[LPT];
+            unsigned wc[LPT];
 #pragma unroll
             for (int t = 0; t < LPT; ++t) {
-                colA[t] = wrap_once(unsigned(li[t] + g.saA), nx);
-                colB[t] = wrap_once(unsigned(li[t] + g.saB), nx);
+                const unsigned col = wrap_once(unsigned(li[t] + g.saA), nx);
+                wc[t] = lbase[t] + unsigned(g.sbnx) + col;
                 if constexpr (!kStaged) {
                     const unsigned grow = wrap_once(grow0[t] + unsigned(g.smnx), plane);
-                    if (li[t] >= 0) {
-                        cA[t] = csk[grow + colA[t]];
-                        cB[t] = csk[grow + colB[t]];
-                    }
+                    if (li[t] >= 0) cv[t] = csk[grow + col];
                 }
             }
-            // At one segment index the lines of a direction deposit into distinct cells (and the two
-            // directions into separate windows), so the window cells are read first, ahead of the
-            // exponentials, and written after: one LDS wait per segment index, not one per deposit.
-            real oA[LPT], oB[LPT];
-            unsigned wA[LPT], wB[LPT];
+            // the B lines that moved at the end of the previous segment
+            if (moved) {
+#pragma unroll
+                for (int t = 0; t < LPT; ++t)
+                    if (li[t] >= 0) IB[t] = xch[xpar * nlines + int(lbase[t]) + li[t]];
+            }
+            // At one segment index the slots deposit into distinct cells, so the window cells are
+            // read first, ahead of the exponentials, and written after: one LDS wait per segment
+            // index, not one per deposit.
+            real o[LPT];
 #pragma unroll
             for (int t = 0; t < LPT; ++t) {
-                const unsigned wrow = lbase[t] + unsigned(g.sbnx);
-                wA[t] = wrow + colA[t];
-                wB[t] = wrow + colB[t];
                 if constexpr (kStaged) {
-                    if (li[t] >= 0) {
-                        cA[t] = stage[wA[t]];
-                        cB[t] = stage[wB[t]];
-                    }
+                    if (li[t] >= 0) cv[t] = stage[wc[t]];
                 }
-                oA[t] = li[t] >= 0 ? winA[wA[t]] : real(0);
-                oB[t] = li[t] >= 0 ? winB[wB[t]] : real(0);
+                o[t] = li[t] >= 0 ? win[wc[t]] : real(0);
             }
 #pragma unroll
             for (int t = 0; t < LPT; ++t) {
                 if (li[t] < 0) continue;
-                {
-                    const real dtau = cA[t].x * len;
-                    const real em1 = expm1_sweep(-dtau, xtab);     // e^{-dtau} - 1
-                    const real dI = (IA[t] - cA[t].y) * em1;
-                    IA[t] += dI;
-                    winA[wA[t]] = oA[t] + (cA[t].y * dtau - dI);    // chi * integral of I
-                }
-                {
-                    const real dtau = cB[t].x * len;
-                    const real em1 = expm1_sweep(-dtau, xtab);
-                    const real dI = (IB[t] - cB[t].y) * em1;
-                    IB[t] += dI;
-                    winB[wB[t]] = oB[t] + (cB[t].y * dtau - dI);
-                }
+                const real dtau = cv[t].x * len;
+                const real em1 = expm1_sweep(-dtau, xtab);     // e^{-dtau} - 1
+                const real dA = (IA[t] - cv[t].y) * em1;
+                const real dB = (IB[t] - cv[t].y) * em1;
+                IA[t] += dA;
+                IB[t] += dB;
+                const real sd = cv[t].y * dtau;
+                win[wc[t]] = o[t] + ((sd - dA) + (sd - dB));   // chi * integral of I, both lines
             }
+            // B lines move by -2 (change of dA) columns in their row before the next segment
+            moved = g.shB != 0;
+            if (moved) {
+                xpar ^= 1;
+#pragma unroll
+                for (int t = 0; t < LPT; ++t)
+                    if (li[t] >= 0)
+                        xch[xpar * nlines + int(lbase[t] + wrap_once(unsigned(li[t] + g.shB), nx))] = IB[t];
+            }
+            sa_last = unsigned(g.saA);
             __syncthreads();
         }
         real *Pk = P + long(k) * wsize;
         for (int e = threadIdx.x; e < wsize; e += NT) {
-            Pk[e] = winA[e] + winB[e];
-            winA[e] = real(0);
-            winB[e] = real(0);
+            Pk[e] = win[e];
+            win[e] = real(0);
         }
         if constexpr (kStaged) {
             if (step + 1 < nz) stage_layer(pi.down ? k - 1 : k + 1);
@@ -362,8 +367,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
 #pragma unroll
         for (int t = 0; t < LPT; ++t) {
             if (li[t] < 0) continue;
+            // the B line in this slot entered the top at column li + 2 dA (mod nx)
+            const unsigned colB = wrap_once(wrap_once(unsigned(li[t]) + sa_last, nx) + sa_last, nx);
             const long ea = ea0 + (it.j0 + lj[t]) * nx + li[t];
-            const long eb = eb0 + (it.j0 + lj[t]) * nx + li[t];
+            const long eb = eb0 + (it.j0 + lj[t]) * nx + colB;
             const double baseA = a.Iem_base ? a.Iem_base[ea] : 0.0;
             const double baseB = a.Iem_base ? a.Iem_base[eb] : 0.0;
             a.Iem[ea] = baseA + double(IA[t]);

@@ -205,7 +205,7 @@ int rt3d_formal_solution_noalloc(const rt3d_grid_desc *g, const double *chi, con
     ra.P = d_P;
     ra.chi = chi;
     ra.Jfs = J_fs;
-    const size_t smem = sweep_smem_bytes(plan.max_win_rows, nx, false);
+    const size_t smem = sweep_smem_bytes(plan, false);
     const dim3 red_grid(unsigned(((nx + 1) / 2 * ny + kPlaneThreads - 1) / kPlaneThreads), unsigned(nz));
     for (int r = 0; r < n_range; ++r) {
         const int n_items = item_begin[r + 1] - item_begin[r];

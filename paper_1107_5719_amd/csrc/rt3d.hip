@@ -225,7 +225,7 @@ int launch_sweep(rt3d_ctx *c, bool fp32, bool diff)
     a.Iem = c->Iem;
     a.Iem_base = diff ? c->Iem_a : nullptr;
     a.xtab = c->xtab;
-    const size_t smem = sweep_smem_bytes(c->plan.max_win_rows, c->g.nx, fp32);
+    const size_t smem = sweep_smem_bytes(c->plan, fp32);
     const dim3 grid(c->plan.items.size());
     TimedLaunch t(c, K_SWEEP);
     if (fp32) c->fp32_sweeps += 1; else c->fp64_sweeps += 1;
@@ -534,14 +534,14 @@ bool build_plan(const rt3d_grid_desc &g, const rt3d::AngleSet &A, int shape, rt3
 {
     if (shape < 0 || shape >= n_sweep_shapes()) { msg = "sweep shape out of range"; return false; }
     const SweepShape sh = kSweepShapes[shape];
-    // one plan for both precisions: the LDS windows are budgeted for float64; a grid whose windows do
-    // not fit the usual budget (which keeps several workgroups per CU) takes the wide one
+    // one plan for both precisions: a band's LDS is budgeted for the larger of the two; a grid whose
+    // bands do not fit the usual budget (which keeps several workgroups per CU) takes the wide one
     if (rt3d::build_sweep_plan(g.nx, g.ny, g.nz, A, sh.threads * sh.lines, 16 * sh.threads, kWindowBytes,
-                               int(sizeof(double)), plan, msg))
+                               plan, msg))
         return true;
     std::string msg_wide;
     if (rt3d::build_sweep_plan(g.nx, g.ny, g.nz, A, sh.threads * sh.lines, 16 * sh.threads, kWindowBytesWide,
-                               int(sizeof(double)), plan, msg_wide))
+                               plan, msg_wide))
         return true;
     msg = msg_wide;
     return false;

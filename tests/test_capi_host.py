@@ -115,13 +115,14 @@ def test_deposits_are_a_bijection_per_segment(R):
 
 
 def test_validation_reports_the_sweep_size_limits(R):
-    """A grid wider than the sweep kernel's budgets (whole x-rows per workgroup, float64 deposit
-    windows of rows + row spread in 156 KB of LDS) is rejected on the host, by rt3d_validate and by
-    rt3d_create before any device allocation, with the reason in rt3d_last_error(NULL).  Below that
-    the widths of wide grids (300 and 520 at 16 x 16 angles) are accepted."""
+    """A grid wider than the sweep kernel's budgets (whole x-rows per workgroup; a deposit window of
+    rows + row spread and two exchange rows per line row in 156 KB of LDS) is rejected on the host, by
+    rt3d_validate and by rt3d_create before any device allocation, with the reason in
+    rt3d_last_error(NULL).  Below that the widths of wide grids (300 and 520 at 16 x 16 angles) are
+    accepted."""
     for nx in (257, 300, 520):
         assert R.rt3d_validate(R._desc(nx, 5, 4, 16, 16)) == R.RT3D_OK
-    for nt, nph, nmax in ((16, 16, 832), (24, 24, 587), (8, 8, 1024), (2, 4, 1024)):
+    for nt, nph, nmax in ((16, 16, 1024), (24, 24, 753), (8, 8, 1024), (2, 4, 1024)):
         assert R.rt3d_validate(R._desc(nmax, 4, 3, nt, nph)) == R.RT3D_OK
         assert R.rt3d_last_error(None) == ""
         assert R.rt3d_validate(R._desc(nmax + 1, 4, 3, nt, nph)) == R.RT3D_ERR_ARG
