@@ -78,13 +78,22 @@ constexpr double kExpStepHi = 6.93147180369123816490e-01 / 16;    // 21 trailing
 constexpr double kExpStepLo = 1.90821492927058770002e-10 / 16;
 constexpr double kExpRound = 6755399441055744.0;                   // 1.5 * 2^52
 
+// a * b + c as one VOP3 v_fma_f64 with c in an SGPR pair.  For a constant addend the compiler would
+// otherwise keep c in VGPRs and copy it into the destination of a two-address v_fmac_f64 at every
+// use (a v_mov_b64 per polynomial step of every exponential in the sweep's segment loop).
+__device__ inline double fma3(double a, double b, double c)
+{
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+    return d;
+}
+
 __device__ inline double expm1_poly(double r)
 {
-    double p = 1.0 / 5040.0;
-    p = fma(p, r, 1.0 / 720.0);
-    p = fma(p, r, 1.0 / 120.0);
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
+    double p = fma3(r, 1.0 / 5040.0, 1.0 / 720.0);
+    p = fma3(p, r, 1.0 / 120.0);
+    p = fma3(p, r, 1.0 / 24.0);
+    p = fma3(p, r, 1.0 / 6.0);
     p = fma(p, r, 0.5);
     p = fma(p, r, 1.0);
     return p * r;
