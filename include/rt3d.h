@@ -88,10 +88,11 @@ typedef struct rt3d_ctx rt3d_ctx;
  * tables and the sweep plan, and then allocates all device buffers on the current HIP device.
  * hip_stream is a hipStream_t (NULL = the default stream); every kernel of this context is launched
  * on it.  Size limit of the sweep: a workgroup holds whole x-rows of lines (nx <= 1024 with the
- * default shape) and the float64 deposit windows of a band, 2 (rows + the angle set's row spread per
- * layer) nx values, fit the LDS: 48 KB when they can (several workgroups per CU), else up to 156 KB
- * (one per CU); with the default shape nx may reach 1024 for 2 x 4 and 8 x 8 angles, 832 for 16 x 16
- * and 587 for 24 x 24 (ny and nz are limited by memory only).
+ * default shape), and a band's LDS -- the deposit window of (rows + the angle set's row spread per
+ * layer) nx values, two exchange buffers of rows nx values and in float32 the staged chi,S cells of
+ * the window -- fits 48 KB when it can (several workgroups per CU), else up to 156 KB (one per CU);
+ * with the default shape nx may reach 1024 for 2 x 4, 8 x 8 and 16 x 16 angles and 753 for 24 x 24
+ * (ny and nz are limited by memory only).
  * rt3d_validate checks the same without a device.
  * Errors: RT3D_ERR_ARG (bad descriptor or precision, out == NULL, a grid beyond the sweep's limits),
  * RT3D_ERR_OOM, RT3D_ERR_HIP; the reason is in rt3d_last_error(NULL). */
