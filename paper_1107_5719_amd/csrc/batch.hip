@@ -117,9 +117,9 @@ __global__ __launch_bounds__(kPlaneThreads) void source_kernel_batch(const Sourc
     source_body<real>(a, b.chunk * kPlaneThreads + threadIdx.x, b.k);
 }
 
-// With two lines per thread the float64 batched sweep is held to 80 VGPRs (6 waves per SIMD instead
-// of 5 at its 88; no spills; the 64 VGPRs of the single-problem sweep would spill its member
-// arguments inside the segment loop): 14.4 -> 14.0 ms per batched formal solution of 64 wavelengths.
+// With two slots per thread the float64 batched sweep is held to 80 VGPRs (6 waves per SIMD; it takes
+// 76): 14.4 -> 14.0 ms per batched formal solution of 64 wavelengths when it needed 88.  Held to 64
+// (8 waves) it spills per layer and runs 13.7 against 12.4 ms.
 template <int LPT> constexpr int kBatchSweepMinWaves = LPT <= 2 ? 6 : 1;
 
 template <typename real, int NT, int LPT>

@@ -305,8 +305,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
                 IB[t] = IA[t];
             }
         }
+        rt3d::PairSeg g = a.pseg[L.off];
         for (int s = 0; s < L.ns; ++s) {
-            const rt3d::PairSeg g = a.pseg[L.off + s];
+            // the next segment's descriptor is loaded one segment ahead, so its load latency is not
+            // part of the chain of latencies of a segment index
+            const rt3d::PairSeg gn = a.pseg[L.off + min(s + 1, L.ns - 1)];
             const real len = seg_length<real>(g);
             // gather of segment s: the voxel of each slot in the chi,S plane
             real2 cv[LPT];
@@ -359,6 +362,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
                         xch[xpar * nlines + int(lbase[t] + wrap_once(unsigned(li[t] + g.shB), nx))] = IB[t];
             }
             sa_last = unsigned(g.saA);
+            g = gn;
             __syncthreads();
         }
         real *Pk = P + long(k) * wsize;
@@ -388,11 +392,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
     }
 }
 
-// Two lines per thread fit 64 VGPRs (float64: one value reloaded from scratch per layer), which lets
-// 8 waves share a SIMD (the windows take ~38 KB of LDS at 129 columns, so 4 workgroups of 512 fit a
-// CU); the segment loop waits on its gathers, and 8 waves hide that better than the 6 that 73 VGPRs
-// allow.  Shapes with more lines per thread keep the compiler's choice; the batched kernel has a
-// bound of its own.
+// Two slots per thread fit 64 VGPRs (59 in float64), which lets 8 waves share a SIMD (a band's LDS
+// takes ~33 KB at 129 columns in float64 and ~35 KB in float32, so 4 workgroups of 512 fit a CU); the
+// segment loop waits on its gathers, and 8 waves hide that better than 6.  Shapes with more slots per
+// thread keep the compiler's choice; the batched kernel has a bound of its own.
 template <int LPT> constexpr int kSweepMinWaves = LPT <= 2 ? 8 : 1;
 
 template <typename real, int NT, int LPT>
