@@ -8,8 +8,10 @@
 //   source_kernel   S = eps B + (1-eps) J packed with chi as {chi, S} per voxel (one 16-byte gather
 //                   per segment in the sweep).
 //   sweep_kernel    one workgroup per (x-mirrored direction pair, band of line rows): every thread
-//                   owns a few lines and carries their intensity down (or up) through all layers.
-//                   All lines of a direction share one segment table, so segment s of every line in
+//                   owns a few slots, each carrying a line of both directions through the same voxel
+//                   (the B lines move between slots at x-face crossings), down (or up) through all
+//                   layers; the two lines share the voxel's chi,S gather, exponential and deposit.
+//                   All lines of a direction share one segment table, so segment s of every slot in
 //                   a layer lands in a distinct voxel: the deposits D_s go into an LDS window without
 //                   atomics, one segment index at a time, and each layer's window is written once to
 //                   a per-band partial plane P.  Deterministic; no float atomics.  The float64
