@@ -89,10 +89,10 @@ typedef struct rt3d_ctx rt3d_ctx;
  * hip_stream is a hipStream_t (NULL = the default stream); every kernel of this context is launched
  * on it.  Size limit of the sweep: a workgroup holds whole x-rows of lines (nx <= 1024 with the
  * default shape), and a band's LDS -- the deposit window of (rows + the angle set's row spread per
- * layer) nx values, two exchange buffers of rows nx values and in float32 the staged chi,S cells of
- * the window -- fits 48 KB when it can (several workgroups per CU), else up to 156 KB (one per CU);
- * with the default shape nx may reach 1024 for 2 x 4, 8 x 8 and 16 x 16 angles and 753 for 24 x 24
- * (ny and nz are limited by memory only).
+ * layer) nx values and two exchange buffers of rows nx values, in float64 -- fits 48 KB when it can
+ * (several workgroups per CU), else up to 156 KB (one per CU); with the default shape nx may reach
+ * 1024 for up to 24 x 24 angles, 832 for 32 x 32 and 587 for 48 x 48 (ny and nz are limited by
+ * memory only).
  * rt3d_validate checks the same without a device.
  * Errors: RT3D_ERR_ARG (bad descriptor or precision, out == NULL, a grid beyond the sweep's limits),
  * RT3D_ERR_OOM, RT3D_ERR_HIP; the reason is in rt3d_last_error(NULL). */

@@ -106,13 +106,11 @@ struct SweepPlan {
 };
 
 // LDS of one sweep workgroup for a band of band_rows line rows and a deposit window of win_rows rows:
-// the window and two exchange buffers of one value per line, and in float32 the staged chi,S pairs of
-// the window cells.
+// the window and two exchange buffers of one value per line, in the sweep's precision.
 inline size_t sweep_lds_bytes(int win_rows, int band_rows, int nx, bool f32)
 {
     const size_t cells = size_t(win_rows) * size_t(nx), lines = size_t(band_rows) * size_t(nx);
-    return f32 ? cells * (sizeof(float) + 2 * sizeof(float)) + 2 * lines * sizeof(float)
-               : (cells + 2 * lines) * sizeof(double);
+    return (cells + 2 * lines) * (f32 ? sizeof(float) : sizeof(double));
 }
 
 // Build segment tables and the band plan.  lines_per_wg bounds the lines of one direction in one

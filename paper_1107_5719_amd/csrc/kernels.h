@@ -36,13 +36,13 @@ inline void with_sweep_shape(int shape, F &&f)
     default: f(ShapeTag<512, 2>{}); break;
     }
 }
-constexpr size_t kWindowBytes = 48 * 1024;   // LDS budget of a band (deposit window, exchange, stage)
+constexpr size_t kWindowBytes = 48 * 1024;   // LDS budget of a band (deposit window and exchange)
 // Grids whose windows do not fit kWindowBytes (wide rows, shallow angle sets) take up to this much of
 // the 160 KB of LDS a gfx950 workgroup may use (the rest holds the kernel's static LDS): one workgroup
 // per CU then, but no width limit below the line budget of a workgroup.
 constexpr size_t kWindowBytesWide = 156 * 1024;
 // Dynamic LDS of a sweep workgroup: the largest deposit window and band of the plan (each band lays
-// out its own window, exchange buffers and float32 stage within this).
+// out its own window and exchange buffers within this).
 inline size_t sweep_smem_bytes(const rt3d::SweepPlan &plan, bool f32)
 {
     return rt3d::sweep_lds_bytes(plan.max_win_rows, plan.max_band_rows, plan.nx, f32);
@@ -231,30 +231,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
     const int nlines = it.rows * nx;
     const int wsize = pi.win_rows * nx;
     const real2 *cs = static_cast<const real2 *>(a.cs);
-    // float32: the chi,S cells of the band's window rows are staged in LDS once per layer.  Window row
-    // w holds grid row (j0 + rmin + w) mod ny, so a slot's gather cell has the index of its deposit
-    // cell.  (A float64 stage, 16 bytes a cell, would not fit beside the window without halving the
-    // resident waves; float64 gathers from global memory.)  LDS: [stage (float32)] window, exchange.
-    constexpr bool kStaged = std::is_same<real, float>::value;
-    real2 *stage = reinterpret_cast<real2 *>(smem_raw);
-    real *win = kStaged ? reinterpret_cast<real *>(stage + wsize) : reinterpret_cast<real *>(smem_raw);
+    // LDS: the band's deposit window, then the two exchange buffers of the B lines
+    real *win = reinterpret_cast<real *>(smem_raw);
     real *xch = win + wsize;                                   // [2][nlines]
-    auto stage_layer = [&](int kk) {
-        const rt3d::PairLayer Lk = a.player[it.pair * nz + kk];
-        const real2 *csk = cs + long(kk) * plane;
-        const int base = it.j0 + Lk.rmin;
-        const int prs = NT / nx, pcs = NT - prs * nx;     // NT cells = prs rows + pcs columns
-        int w = int(threadIdx.x) / nx, col = int(threadIdx.x) - w * nx;
-        for (int e = threadIdx.x; e < wsize; e += NT) {
-            stage[e] = csk[((base + w) % ny) * nx + col];
-            w += prs;
-            col += pcs;
-            if (col >= nx) {
-                col -= nx;
-                ++w;
-            }
-        }
-    };
     real *P = static_cast<real *>(a.P) + pi.p_off + long(it.band) * nz * wsize;
 
     for (int e = threadIdx.x; e < wsize; e += NT) win[e] = real(0);
@@ -274,7 +253,6 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
         IA[t] = real(a.I_top);
         IB[t] = real(a.I_top);
     }
-    if constexpr (kStaged) stage_layer(pi.down ? nz - 1 : 0);
     __syncthreads();
 
     int xpar = 0;              // exchange buffer of the last move of the B lines
@@ -318,10 +296,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
             for (int t = 0; t < LPT; ++t) {
                 const unsigned col = wrap_once(unsigned(li[t] + g.saA), nx);
                 wc[t] = lbase[t] + unsigned(g.sbnx) + col;
-                if constexpr (!kStaged) {
-                    const unsigned grow = wrap_once(grow0[t] + unsigned(g.smnx), plane);
-                    if (li[t] >= 0) cv[t] = csk[grow + col];
-                }
+                const unsigned grow = wrap_once(grow0[t] + unsigned(g.smnx), plane);
+                if (li[t] >= 0) cv[t] = csk[grow + col];
             }
             // the B lines that moved at the end of the previous segment
             if (moved) {
@@ -334,12 +310,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
             // index, not one per deposit.
             real o[LPT];
 #pragma unroll
-            for (int t = 0; t < LPT; ++t) {
-                if constexpr (kStaged) {
-                    if (li[t] >= 0) cv[t] = stage[wc[t]];
-                }
-                o[t] = li[t] >= 0 ? win[wc[t]] : real(0);
-            }
+            for (int t = 0; t < LPT; ++t) o[t] = li[t] >= 0 ? win[wc[t]] : real(0);
 #pragma unroll
             for (int t = 0; t < LPT; ++t) {
                 if (li[t] < 0) continue;
@@ -370,9 +341,6 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
             Pk[e] = win[e];
             win[e] = real(0);
         }
-        if constexpr (kStaged) {
-            if (step + 1 < nz) stage_layer(pi.down ? k - 1 : k + 1);
-        }
         __syncthreads();
     }
     if (!pi.down && a.Iem) {
@@ -393,7 +361,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &i
 }
 
 // Two slots per thread fit 64 VGPRs (59 in float64), which lets 8 waves share a SIMD (a band's LDS
-// takes ~33 KB at 129 columns in float64 and ~35 KB in float32, so 4 workgroups of 512 fit a CU); the
+// takes ~33 KB at 129 columns in float64, half that in float32, so 4 workgroups of 512 fit a CU); the
 // segment loop waits on its gathers, and 8 waves hide that better than 6.  Shapes with more slots per
 // thread keep the compiler's choice; the batched kernel has a bound of its own.
 template <int LPT> constexpr int kSweepMinWaves = LPT <= 2 ? 8 : 1;

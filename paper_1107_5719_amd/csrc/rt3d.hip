@@ -15,8 +15,7 @@
 //                   a layer lands in a distinct voxel: the deposits D_s go into an LDS window without
 //                   atomics, one segment index at a time, and each layer's window is written once to
 //                   a per-band partial plane P.  Deterministic; no float atomics.  The float64
-//                   exponential uses a 16-entry table of 2^(j/16) (per context, copied to LDS);
-//                   float32 sweeps gather chi,S from the window rows staged in LDS per layer.
+//                   exponential uses a 16-entry table of 2^(j/16) (per context, copied to LDS).
 //   reduce_kernel_pair  per voxel (two neighbours of a row per thread), sums the partial planes of
 //                   all directions in a fixed order: J_fs = (1/chi) sum_d W_d |mu_d| sum_bands P, and
 //                   the OS right-hand side chi (J_fs - J).

@@ -122,7 +122,7 @@ def test_validation_reports_the_sweep_size_limits(R):
     accepted."""
     for nx in (257, 300, 520):
         assert R.rt3d_validate(R._desc(nx, 5, 4, 16, 16)) == R.RT3D_OK
-    for nt, nph, nmax in ((16, 16, 1024), (24, 24, 753), (8, 8, 1024), (2, 4, 1024)):
+    for nt, nph, nmax in ((16, 16, 1024), (24, 24, 1024), (32, 32, 832), (48, 48, 587), (8, 8, 1024), (2, 4, 1024)):
         assert R.rt3d_validate(R._desc(nmax, 4, 3, nt, nph)) == R.RT3D_OK
         assert R.rt3d_last_error(None) == ""
         assert R.rt3d_validate(R._desc(nmax + 1, 4, 3, nt, nph)) == R.RT3D_ERR_ARG

@@ -246,9 +246,9 @@ def test_batch_stop_states_and_errors(R):
     with pytest.raises(R.Rt3dError) as e:
         R.Batch([dict(grids[0], n_phi=6)])
     assert "member 0" in str(e.value)
-    # a member wider than the sweep's LDS allows (nx > 753 at 24 x 24 angles) names itself
+    # a member wider than the sweep's LDS allows (nx > 832 at 32 x 32 angles) names itself
     with pytest.raises(R.Rt3dError) as e:
-        R.Batch([grids[0], dict(nx=754, ny=4, nz=3, n_theta=24, n_phi=24)])
+        R.Batch([grids[0], dict(nx=833, ny=4, nz=3, n_theta=32, n_phi=32)])
     assert e.value.status == R.RT3D_ERR_ARG and "member 1" in str(e.value) and "LDS" in str(e.value)
 
 
