@@ -293,7 +293,6 @@ bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int lines_per_w
             pi.last_rows = ny - (pi.n_bands - 1) * rows;
             pi.inv_rows = 1.0f / float(rows);
             P.max_win_rows = std::max(P.max_win_rows, pi.win_rows);
-            P.max_band_rows = std::max(P.max_band_rows, pi.band_rows);
             P.pairs.push_back(pi);
             const size_t pl0 = P.player.size();
             for (int k = 0; k < nz; ++k) {

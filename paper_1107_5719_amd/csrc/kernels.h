@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "geometry.h"
@@ -41,11 +42,14 @@ constexpr size_t kWindowBytes = 48 * 1024;   // LDS budget of a band (deposit wi
 // the 160 KB of LDS a gfx950 workgroup may use (the rest holds the kernel's static LDS): one workgroup
 // per CU then, but no width limit below the line budget of a workgroup.
 constexpr size_t kWindowBytesWide = 156 * 1024;
-// Dynamic LDS of a sweep workgroup: the largest deposit window and band of the plan (each band lays
-// out its own window and exchange buffers within this).
+// Dynamic LDS of a sweep workgroup: the largest window and exchange buffers of any direction pair's
+// bands (each band lays out its own within this).
 inline size_t sweep_smem_bytes(const rt3d::SweepPlan &plan, bool f32)
 {
-    return rt3d::sweep_lds_bytes(plan.max_win_rows, plan.max_band_rows, plan.nx, f32);
+    size_t bytes = 0;
+    for (const rt3d::PairInfo &pi : plan.pairs)
+        bytes = std::max(bytes, rt3d::sweep_lds_bytes(pi.win_rows, pi.band_rows, plan.nx, f32));
+    return bytes;
 }
 constexpr int kPlaneThreads = 256;   // voxel-parallel kernels: one thread per voxel of a k-plane
 

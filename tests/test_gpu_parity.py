@@ -62,9 +62,12 @@ FS_CASES = [
     ((6, 5, 7), 2, 4, 7, 0.2, 0),        # smallest angle set; every line runs through voxel edges
     ((5, 8, 6), 8, 4, 8, 0.0, 0),        # n_phi = 4 with steep and shallow directions
     ((6, 7, 5), 8, 8, 9, 0.1, 2),        # LTE-diffusion inner condition
-    ((3, 4, 256), 16, 16, 10, 0.0, 0),   # the widest grid whose 16 x 16 windows fit the 48 KB budget
-    ((3, 4, 300), 16, 16, 11, 0.0, 0),   # wider: windows in the wide LDS budget
-    ((4, 5, 520), 16, 16, 12, 0.2, 0),   # one row per band, ~100 KB of windows
+    ((3, 4, 256), 16, 16, 10, 0.0, 0),   # wide rows, 16 x 16 angles in the 48 KB LDS budget
+    ((3, 4, 300), 16, 16, 11, 0.0, 0),   # about the widest in the 48 KB budget
+    ((4, 5, 520), 16, 16, 12, 0.2, 0),   # one row per band in the wide LDS budget
+    ((3, 4, 1024), 16, 16, 13, 0.1, 0),  # the widest grid: a whole workgroup per row
+    ((3, 5, 600), 32, 32, 14, 0.0, 0),   # 32 x 32 angles: the largest row spread, wide LDS budget
+    ((5, 6, 4), 8, 8, 15, 0.2, 0),       # nx = 4: a move of the B lines by two columns is half a row
 ]
 
 
