@@ -7,6 +7,7 @@ J.  The oracle never sees anything the GPU produced: both sides get the same see
 import numpy as np
 import pytest
 
+from lstar_bar import close_lstar
 from paper_1107_5719_amd.inputs import WORKLOADS, diffusion_medium, make_medium, random_medium
 
 pytestmark = pytest.mark.gpu
@@ -30,17 +31,6 @@ def _close(a, b, rtol=RTOL, floor=1e-300):
     lim = rtol * np.abs(b) + floor
     bad = err > lim
     assert not bad.any(), f"{bad.sum()} of {bad.size} off; worst rel {np.max(err / (np.abs(b) + floor)):.3e}"
-
-
-def _close_rows(L, L_ref, rtol=RTOL):
-    """Lambda* parity scaled per voxel row: |dL[o, v]| <= rtol * max_o' |L_ref[o', v]|.  Entries that
-    are exponentially small next to their row (thick voxels) carry the ~1e-14 rounding of the two
-    sides' independent segment lengths times chi, which is ~1e-10 of a 1e-70 entry; the row scale is
-    what enters the operator-splitting sum."""
-    scale = np.max(np.abs(L_ref), axis=0, keepdims=True)
-    err = np.abs(L - L_ref)
-    bad = err > rtol * scale + 1e-300
-    assert not bad.any(), f"{bad.sum()} of {bad.size} off; worst {np.max(err / (scale + 1e-300)):.3e}"
 
 
 def _medium_case(name):
@@ -121,7 +111,7 @@ def test_lstar_parity(R, orc, case):
         s.set_medium(m["chi"], m["eps"], m["B"])
         s.build_lstar()
         L = s.get_lstar()
-    _close_rows(L, L_orc)
+    close_lstar(L, L_orc, m["chi"], nt)
 
 
 def test_lstar_and_fs_parity_strat17(R, orc):
@@ -136,7 +126,7 @@ def test_lstar_and_fs_parity_strat17(R, orc):
         s.build_lstar()
         L = s.get_lstar()
     _close(J, J_orc)
-    _close_rows(L, L_orc)
+    close_lstar(L, L_orc, m["chi"], nt)
 
 
 @pytest.mark.parametrize("M", [1, 2, 7])
@@ -196,7 +186,7 @@ def test_fs_and_os_step_parity_grf65(R, orc):
         s.set_medium(m["chi"], m["eps"], m["B"])
         _close(s.formal_solution(None), J_fs_orc)
         s.build_lstar()
-        _close_rows(s.get_lstar(), L_orc)
+        close_lstar(s.get_lstar(), L_orc, m["chi"], w.n_theta)
         c = s.os_step(M)
         _close(s.get_J(), J1_orc)
         assert abs(c - c_orc) <= 1e-8 * c_orc
@@ -229,7 +219,7 @@ def test_paper_slab_grids_parity(R, orc):
         s.set_medium(m["chi"], m["eps"], m["B"])
         _close(s.formal_solution(S), J_fs_orc)
         s.build_lstar()
-        _close_rows(s.get_lstar(), L_orc)
+        close_lstar(s.get_lstar(), L_orc, m["chi"], w.n_theta)
         c = s.os_step(4)
         _close(s.get_J(), J1_orc)
         assert abs(c - c_orc) <= 1e-8 * c_orc
