@@ -447,9 +447,9 @@ int build_lstar_batched(rt3d_batch *b)
         if (c->have_lstar) continue;
         if (!c->plan_ok) return bfail(b, RT3D_ERR_STATE, "member " + std::to_string(i) + " has no sweep plan");
         LstarArgs a{};
-        a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.n_dir = c->A.n_dir;
+        a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.n_pair = c->plan.n_pair;
         a.early_exit = c->lstar_early_exit;
-        a.dirs = c->dirs; a.seg_off = c->seg_off; a.seg_n = c->seg_n; a.seg_ai = c->seg_ai;
+        a.pairs = c->pairs; a.seg_off = c->seg_off; a.seg_n = c->seg_n; a.seg_ai = c->seg_ai;
         a.seg_bi = c->seg_bi; a.seg_len = c->seg_len64; a.chi = c->chi; a.L = c->L;
         a.xtab = c->xtab;
         args.push_back(a);
@@ -459,8 +459,8 @@ int build_lstar_batched(rt3d_batch *b)
     std::vector<int> order(who.size());
     for (size_t q = 0; q < order.size(); ++q) order[q] = int(q);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        return long(args[x].nx) * args[x].ny * args[x].nz * args[x].n_dir >
-               long(args[y].nx) * args[y].ny * args[y].nz * args[y].n_dir;
+        return long(args[x].nx) * args[x].ny * args[x].nz * args[x].n_pair >
+               long(args[y].nx) * args[y].ny * args[y].nz * args[y].n_pair;
     });
     for (int q : order) {
         const int chunks = (args[q].nx * args[q].ny + kLstarThreads - 1) / kLstarThreads;

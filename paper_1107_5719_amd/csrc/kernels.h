@@ -537,9 +537,9 @@ __global__ __launch_bounds__(kPlaneThreads) void reduce_kernel_pair_range(Reduce
 // ------------------------------------------------------------------------------------------------
 
 struct LstarArgs {
-    int nx, ny, nz, n_dir;
+    int nx, ny, nz, n_pair;
     int early_exit;                 // 1: no line can wrap back onto a neighbour within two layers
-    const DirInfo *dirs;
+    const rt3d::PairInfo *pairs;    // x-mirrored direction pairs (the tables of direction dA are read)
     const int *seg_off, *seg_n, *seg_ai, *seg_bi;
     const double *seg_len;
     const double *chi;
@@ -576,7 +576,9 @@ __device__ inline int wrap_small(int a, int n)
 //   c_{s'->s} = (1 - e_{s'}) prod_{s' < s'' < s} e_{s''},  e = exp(-dtau).
 // The lines through v are the reference line shifted so that its segment s lies in v; walking that
 // line backwards through the current and the previous layer reaches every earlier segment that can
-// lie in the 3x3x3 block (lines are monotone in z).
+// lie in the 3x3x3 block (lines are monotone in z).  The two directions of an x-mirrored pair have
+// equal segment lengths and row offsets and negated column offsets, so one walk over direction A's
+// table serves both (B's voxels at the mirrored columns), and their self terms are equal.
 // One wavefront per workgroup: the 27 accumulators per thread live in LDS (13.8 KB per workgroup),
 // and small workgroups let many of them share a CU to hide the latency of the gathers along the
 // lines (measured at 129^3 x 256: 31.7 ms with 256 threads, 29.2 ms with 128, 26.4 ms with 64).
@@ -596,12 +598,15 @@ __device__ inline void lstar_body(const LstarArgs &a, int p, int k)
     for (int o = 0; o < 27; ++o) acc[o][threadIdx.x] = 0.0;
     __syncthreads();
     const double chiv = a.chi[v];
-    for (int d = 0; d < a.n_dir; ++d) {
-        const DirInfo di = a.dirs[d];
-        const double fac = di.wmu / chiv;
+    // 3x3x3 block index of a column offset m (mod n) from v: 0 for -1, 1 for 0, 2 for +1, -1 outside
+    auto block_col = [](int m, int n) { return (m == 0) ? 1 : (m == 1) ? 2 : (m == n - 1) ? 0 : -1; };
+    for (int q = 0; q < a.n_pair; ++q) {
+        const rt3d::PairInfo pi = a.pairs[q];
+        const double fac = pi.wmu / chiv;
+        const int d = pi.dA;
         const int dk = d * nz + k;
         const int off = a.seg_off[dk], n = a.seg_n[dk];
-        const int ku = di.down ? k + 1 : k - 1;
+        const int ku = pi.down ? k + 1 : k - 1;
         const bool has_up = ku >= 0 && ku < nz;
         const int offu = has_up ? a.seg_off[d * nz + ku] : 0;
         const int nu = has_up ? a.seg_n[d * nz + ku] : 0;
@@ -609,9 +614,9 @@ __device__ inline void lstar_body(const LstarArgs &a, int p, int k)
             const int as = a.seg_ai[off + s], bs = a.seg_bi[off + s];
             const double dtau = chiv * a.seg_len[off + s];
             const double em1 = expm1_nonpos_tab(-dtau, xtab);
-            acc[13][threadIdx.x] += fac * self_term(dtau, em1);
+            acc[13][threadIdx.x] += 2.0 * (fac * self_term(dtau, em1));
             const double g = -fac * em1;
-            double prod = 1.0;
+            double prodA = 1.0, prodB = 1.0;
             // walk back: current layer s-1 .. 0, then the previous layer from its last segment
             const int total = s + nu;
             for (int w = 0; w < total; ++w) {
@@ -623,19 +628,23 @@ __device__ inline void lstar_body(const LstarArgs &a, int p, int k)
                 // with early exit the offsets are -1, 0 or 1 here
                 const int mA = a.early_exit ? dA + (dA < 0 ? nx : 0) : wrap_small(dA, nx);
                 const int mB = a.early_exit ? dB + (dB < 0 ? ny : 0) : wrap_small(dB, ny);
-                int col = i + mA;
-                col -= (col >= nx) ? nx : 0;
+                const int mAm = (mA == 0) ? 0 : nx - mA;      // direction B's column offset, -dA mod nx
+                int colA = i + mA, colB = i + mAm;
+                colA -= (colA >= nx) ? nx : 0;
+                colB -= (colB >= nx) ? nx : 0;
                 int row = j + mB;
                 row -= (row >= ny) ? ny : 0;
-                const long u = long(k + dkk) * plane + long(row) * nx + col;
-                const double tau_u = a.chi[u] * a.seg_len[idx];
-                double e_u, em1_u;
-                exp_pair_tab(-tau_u, xtab, e_u, em1_u);
-                const double c = -em1_u * prod;
-                const int oi = (mA == 0) ? 1 : (mA == 1) ? 2 : (mA == nx - 1) ? 0 : -1;
-                const int oj = (mB == 0) ? 1 : (mB == 1) ? 2 : (mB == ny - 1) ? 0 : -1;
-                if (oi >= 0 && oj >= 0) acc[9 * (dkk + 1) + 3 * oj + oi][threadIdx.x] += g * c;
-                prod *= e_u;
+                const long ub = long(k + dkk) * plane + long(row) * nx;
+                const double len = a.seg_len[idx];
+                double eA, em1A, eB, em1B;
+                exp_pair_tab(-a.chi[ub + colA] * len, xtab, eA, em1A);
+                exp_pair_tab(-a.chi[ub + colB] * len, xtab, eB, em1B);
+                const int oj = block_col(mB, ny);
+                const int oiA = block_col(mA, nx), oiB = block_col(mAm, nx);
+                if (oiA >= 0 && oj >= 0) acc[9 * (dkk + 1) + 3 * oj + oiA][threadIdx.x] += g * (-em1A * prodA);
+                if (oiB >= 0 && oj >= 0) acc[9 * (dkk + 1) + 3 * oj + oiB][threadIdx.x] += g * (-em1B * prodB);
+                prodA *= eA;
+                prodB *= eB;
             }
         }
     }

@@ -305,9 +305,9 @@ int ensure_lstar(rt3d_ctx *c)
     if (c->have_lstar) return RT3D_OK;
     if (!c->plan_ok) return fail(c, RT3D_ERR_STATE, "no sweep plan (a shape change failed)");
     LstarArgs a{};
-    a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.n_dir = c->A.n_dir;
+    a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.n_pair = c->plan.n_pair;
     a.early_exit = c->lstar_early_exit;
-    a.dirs = c->dirs; a.seg_off = c->seg_off; a.seg_n = c->seg_n; a.seg_ai = c->seg_ai;
+    a.pairs = c->pairs; a.seg_off = c->seg_off; a.seg_n = c->seg_n; a.seg_ai = c->seg_ai;
     a.seg_bi = c->seg_bi; a.seg_len = c->seg_len64; a.chi = c->chi; a.L = c->L;
     a.xtab = c->xtab;
     {
