@@ -208,6 +208,13 @@ struct SweepArgs {
 __device__ inline double expm1_sweep(double x, const double *tab) { return expm1_nonpos_tab(x, tab); }
 __device__ inline float expm1_sweep(float x, const double *) { return expm1_nonpos(x); }
 
+template <typename real> __device__ inline real seg_length(const rt3d::PairSeg &g);
+template <> __device__ inline double seg_length<double>(const rt3d::PairSeg &g) { return g.len; }
+template <> __device__ inline float seg_length<float>(const rt3d::PairSeg &g) { return g.len32; }
+
+// x mod n for 0 <= x < 2n, as min(x, x - n) on unsigned integers (x - n wraps when x < n)
+__device__ inline unsigned wrap_once(unsigned x, unsigned n) { return min(x, x - n); }
+
 // One workgroup sweeps the lines of one band for both directions A and B of an x-mirrored pair.  The
 // two directions' segments have equal lengths and row offsets and negated column offsets, so at every
 // segment index a line of A and a line of B cross the same voxel: slot q = (row, column c) of the band
@@ -218,13 +225,6 @@ __device__ inline float expm1_sweep(float x, const double *) { return expm1_nonp
 // LDS array (the barrier that ends every segment index orders the write before the read).  Thread t
 // owns slots q = t + i*NT (i < LPT).  Per segment index the slots deposit into pairwise distinct cells
 // of the band's LDS window, so the window is updated with a plain read-add-write.
-template <typename real> __device__ inline real seg_length(const rt3d::PairSeg &g);
-template <> __device__ inline double seg_length<double>(const rt3d::PairSeg &g) { return g.len; }
-template <> __device__ inline float seg_length<float>(const rt3d::PairSeg &g) { return g.len32; }
-
-// x mod n for 0 <= x < 2n, as min(x, x - n) on unsigned integers (x - n wraps when x < n)
-__device__ inline unsigned wrap_once(unsigned x, unsigned n) { return min(x, x - n); }
-
 template <typename real, int NT, int LPT>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a, const WorkItem &it, unsigned char *smem_raw)
 {
