@@ -243,7 +243,9 @@ int rt3d_set_timing(rt3d_ctx *ctx, int enable);
 int rt3d_get_history(rt3d_ctx *ctx, double *c_out, double *ms_out, int *flags_out, int max_n);
 
 /* Statistics as a NUL-terminated JSON object: grid, angles, precision, outer iterations, inner
- * sweeps, device bytes, and per-kernel {launches, total_ms} when timing is enabled.
+ * sweeps, device bytes, the sweep plan (workgroups, shape, mean segments per voxel and angle, largest
+ * deposit window in rows, LDS bytes of a sweep workgroup), and per-kernel {launches, total_ms} when
+ * timing is enabled.
  * Errors: RT3D_ERR_ARG (buffer too small or NULL). */
 int rt3d_get_stats(rt3d_ctx *ctx, char *json_buf, int buflen);
 

@@ -234,7 +234,6 @@ bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int lines_per_w
                 P.seg_bi.push_back(L.dj[s]);
                 P.seg_len.push_back(L.len[s]);
             }
-            P.max_seg_per_layer = std::max(P.max_seg_per_layer, n);
             nseg += n;
         }
         total_segments += nseg;

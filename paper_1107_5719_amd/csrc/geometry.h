@@ -100,7 +100,6 @@ struct SweepPlan {
     std::vector<WorkItem> items;          // in dispatch order (most expensive first)
     int64_t p_elems = 0;                  // size of the partial-plane buffer P in elements
     int max_win_rows = 0;
-    int max_seg_per_layer = 0;
     double mean_segments = 0.0;           // per voxel and angle
 };
 

@@ -1161,17 +1161,19 @@ int rt3d_get_stats(rt3d_ctx *c, char *buf, int buflen)
     int rc = sync(c);
     if (rc) return rc;
     std::string s = "{";
-    char tmp[512];
+    char tmp[1024];
     std::snprintf(tmp, sizeof tmp,
                   "\"nx\":%d,\"ny\":%d,\"nz\":%d,\"n_dir\":%d,\"precision\":\"%s\",\"outer_iters\":%ld,"
                   "\"inner_sweeps\":%ld,\"fp64_sweeps\":%ld,\"fp32_sweeps\":%ld,\"device_bytes\":%zu,\"partial_plane_bytes\":%lld,"
                   "\"sweep_workgroups\":%zu,\"sweep_shape\":%d,\"sweep_threads\":%d,\"sweep_lines\":%d,\"mean_segments\":%.6f,"
+                  "\"max_window_rows\":%d,\"sweep_lds_bytes\":%zu,"
                   "\"os_method\":\"%s\",\"coef_storage\":\"%s\",\"jacobi_layout\":%d,\"jacobi_column\":%d,"
                   "\"timing\":%d,\"kernels\":{",
                   c->g.nx, c->g.ny, c->g.nz, c->A.n_dir, c->precision == RT3D_FP64 ? "fp64" : "fp32_sweep",
                   c->outer_iters, c->inner_sweeps, c->fp64_sweeps, c->fp32_sweeps, c->device_bytes,
                   (long long)(c->plan.p_elems * (long long)sizeof(double)), c->plan.items.size(),
                   c->sweep_shape, kSweepShapes[c->sweep_shape].threads, kSweepShapes[c->sweep_shape].lines, c->plan.mean_segments,
+                  c->plan.max_win_rows, sweep_smem_bytes(c->plan, c->precision != RT3D_FP64),
                   c->os_method == RT3D_OS_GAUSS_SEIDEL ? "gauss_seidel" : "jacobi", c->coef_fp32 ? "fp32" : "fp64",
                   c->jacobi_xcd, c->jacobi_height > 0 ? c->jacobi_height : jacobi_column_height(c->g.nx, c->g.ny, c->g.nz),
                   c->timing);

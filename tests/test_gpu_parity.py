@@ -382,3 +382,16 @@ def test_sampled_timing_counts(R):
         else:
             assert k["sweep"]["timed"] == 0 and k["jacobi"]["total_ms"] == 0
     assert np.array_equal(J[0], J[1]) and np.array_equal(J[0], J[2])
+
+
+def test_stats_report_the_sweep_plan(R):
+    """rt3d_get_stats names the sweep plan's largest window and a sweep workgroup's LDS: within the
+    48 KB budget for a grid whose bands fit it, in the wide budget (one workgroup per CU) for one
+    that needs it; float32 sweeps take half the bytes."""
+    with R.Solver(300, 4, 3, 16, 16) as s:
+        st = s.stats()
+        assert 0 < st["sweep_lds_bytes"] <= 48 * 1024 and st["max_window_rows"] > 0
+    with R.Solver(520, 5, 4, 16, 16) as s:
+        assert 48 * 1024 < s.stats()["sweep_lds_bytes"] <= 156 * 1024
+    with R.Solver(520, 5, 4, 16, 16, precision=R.RT3D_FP32_SWEEP) as s:
+        assert s.stats()["sweep_lds_bytes"] <= 78 * 1024
