@@ -397,41 +397,130 @@ struct ReduceArgs {
 // voxel row j at layer k is found from the row's offset to the layer's window origin; the previous
 // bands (cyclically) still cover the row while the offset stays inside their windows.
 template <typename real>
+struct PairBands {
+    const real *Pq;   // the pair's partial plane of layer k, at the voxel's column
+    long o0, o1;      // elements of the band that starts the row's window offset and of the band before it
+    int b1, off1;     // that earlier band (cyclically) and the row's offset in its window
+};
+
+template <typename real>
+__device__ inline PairBands<real> pair_bands(const ReduceArgs &a, const rt3d::PairInfo &pi, int i, int j, int k)
+{
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int rows = pi.band_rows, nb = pi.n_bands, Hw = pi.win_rows;
+    const int rmin = a.row_min[pi.dA * nz + k];
+    int jj = j - rmin;
+    jj += (jj < 0) ? ny : 0;
+    int b = min(int((float(jj) + 0.5f) * pi.inv_rows), nb - 1);
+    b -= (b * rows > jj) ? 1 : 0;
+    b += (b < nb - 1 && (b + 1) * rows <= jj) ? 1 : 0;
+    const int off0 = jj - b * rows;
+    const long plane = long(Hw) * nx;
+    const long band_stride = long(nz) * plane;
+    PairBands<real> r;
+    r.Pq = static_cast<const real *>(a.P) + pi.p_off + long(k) * plane + i;
+    r.b1 = (b == 0) ? nb - 1 : b - 1;
+    r.off1 = off0 + ((r.b1 == nb - 1) ? pi.last_rows : rows);
+    r.o0 = long(b) * band_stride + long(off0) * nx;
+    r.o1 = long(r.b1) * band_stride + long(r.off1) * nx;
+    return r;
+}
+
+// Row offset of the band before b1 (cyclically): it covers the row too when below the window height.
+__device__ inline int pair_bands_next_off(const rt3d::PairInfo &pi, int bb, int off)
+{
+    bb = (bb == 0) ? pi.n_bands - 1 : bb - 1;
+    return off + ((bb == pi.n_bands - 1) ? pi.last_rows : pi.band_rows);
+}
+
+// The angle sum of the direction pairs [q0, q1) for voxels (i, j, k) and (i + d1, j, k) (d1 = 0: one
+// voxel, read twice), added to acc0 / acc1 pair by pair in order, each pair's bands summed in the
+// order band b, b1, then earlier bands.  The partials of the first two bands of kPairGroup pairs are
+// loaded before any is summed (a pair whose row only one band covers loads the first band's element
+// again and does not add it), so a wave keeps that many loads in flight instead of waiting on each
+// pair; the rare third and later bands are read where they are added.  Measured per launch at
+// 129^3 x 256 (bitwise the same sums): 0.665 against 0.682 ms in float64, 0.475 against 0.516 ms in
+// float32; at 65^3 x 256 0.109 against 0.127 and 0.082 against 0.117 ms; groups of 8 pairs 0.657 /
+// 0.493 ms at 129^3.
+constexpr int kPairGroup = 4;
+template <typename real>
+__device__ inline void reduce_pairs(const ReduceArgs &a, int i, int d1, int j, int k, int q0, int q1, double &acc0,
+                                    double &acc1)
+{
+    constexpr int U = kPairGroup;
+    for (int qb = q0; qb < q1; qb += U) {
+        double x0[U], x1[U], y0[U], y1[U];
+        bool m1[U], more[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = min(qb + u, q1 - 1);
+            const rt3d::PairInfo pi = a.pairs[q];
+            const PairBands<real> pb = pair_bands<real>(a, pi, i, j, k);
+            m1[u] = pb.off1 < pi.win_rows;
+            more[u] = m1[u] && pair_bands_next_off(pi, pb.b1, pb.off1) < pi.win_rows;
+            const long o1 = m1[u] ? pb.o1 : pb.o0;
+            x0[u] = double(pb.Pq[pb.o0]);
+            x1[u] = double(pb.Pq[pb.o0 + d1]);
+            y0[u] = double(pb.Pq[o1]);
+            y1[u] = double(pb.Pq[o1 + d1]);
+        }
+        // keep the sums below the group's loads (the scheduler would otherwise interleave them and
+        // wait on each pair's loads before issuing the next pair's)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (qb + u >= q1) break;
+            const rt3d::PairInfo pi = a.pairs[qb + u];
+            double s0 = x0[u], s1 = x1[u];
+            if (m1[u]) {
+                s0 += y0[u];
+                s1 += y1[u];
+            }
+            if (more[u]) {
+                // bands thinner than the window halo: still earlier bands cover the row
+                const PairBands<real> pb = pair_bands<real>(a, pi, i, j, k);
+                const long band_stride = long(a.nz) * pi.win_rows * a.nx;
+                int bb = pb.b1, off = pb.off1;
+                while (true) {
+                    off = pair_bands_next_off(pi, bb, off);
+                    bb = (bb == 0) ? pi.n_bands - 1 : bb - 1;
+                    if (off >= pi.win_rows) break;
+                    const long o = long(bb) * band_stride + long(off) * a.nx;
+                    s0 += double(pb.Pq[o]);
+                    s1 += double(pb.Pq[o + d1]);
+                }
+            }
+            acc0 += pi.wmu * s0;
+            acc1 += pi.wmu * s1;
+        }
+    }
+}
+
+// One voxel per thread (the batched form; grouping its loads as reduce_pairs does measured slower
+// there, 12.7 against 12.5 ms per batched formal solution of 64 wavelengths), pair by pair.
+template <typename real>
 __device__ inline void reduce_body(const ReduceArgs &a, int p, int k)
 {
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     if (p >= nx * ny) return;
     const int j = p / nx, i = p - j * nx;
-    const real *P = static_cast<const real *>(a.P);
     double acc = 0.0;
 #pragma unroll 4
     for (int q = 0; q < a.n_pair; ++q) {
         const rt3d::PairInfo pi = a.pairs[q];
-        const int rows = pi.band_rows, nb = pi.n_bands, Hw = pi.win_rows;
-        const int rmin = a.row_min[pi.dA * nz + k];
-        int jj = j - rmin;
-        jj += (jj < 0) ? ny : 0;
-        int b = min(int((float(jj) + 0.5f) * pi.inv_rows), nb - 1);
-        b -= (b * rows > jj) ? 1 : 0;
-        b += (b < nb - 1 && (b + 1) * rows <= jj) ? 1 : 0;
-        const int off0 = jj - b * rows;
-        const long plane = long(Hw) * nx;
-        const long band_stride = long(nz) * plane;
-        const real *Pq = P + pi.p_off + long(k) * plane + i;
-        // the band that starts the row's window offset, and the band before it (cyclically)
-        const int b1 = (b == 0) ? nb - 1 : b - 1;
-        const int off1 = off0 + ((b1 == nb - 1) ? pi.last_rows : rows);
-        const double v0 = double(Pq[long(b) * band_stride + long(off0) * nx]);
-        const double v1 = (off1 < Hw) ? double(Pq[long(b1) * band_stride + long(off1) * nx]) : 0.0;
+        const PairBands<real> pb = pair_bands<real>(a, pi, i, j, k);
+        const double v0 = double(pb.Pq[pb.o0]);
+        const double v1 = (pb.off1 < pi.win_rows) ? double(pb.Pq[pb.o1]) : 0.0;
         double sd = v0 + v1;
-        if (off1 < Hw) {
+        if (pb.off1 < pi.win_rows) {
             // bands thinner than the window halo: still earlier bands may cover the row
-            int bb = b1, off = off1;
+            const long band_stride = long(nz) * pi.win_rows * nx;
+            int bb = pb.b1, off = pb.off1;
             while (true) {
-                bb = (bb == 0) ? nb - 1 : bb - 1;
-                off += (bb == nb - 1) ? pi.last_rows : rows;
-                if (off >= Hw) break;
-                sd += double(Pq[long(bb) * band_stride + long(off) * nx]);
+                off = pair_bands_next_off(pi, bb, off);
+                bb = (bb == 0) ? pi.n_bands - 1 : bb - 1;
+                if (off >= pi.win_rows) break;
+                sd += double(pb.Pq[long(bb) * band_stride + long(off) * nx]);
             }
         }
         acc += pi.wmu * sd;
@@ -445,7 +534,8 @@ __device__ inline void reduce_body(const ReduceArgs &a, int p, int k)
 // The same sum for two neighbouring voxels of one row per thread (p2 indexes the (ny, (nx + 1) / 2)
 // voxel pairs of plane k): the band lookup is shared and the partials of both are read together,
 // the per-voxel sums in the order of reduce_body (so the results are bitwise those of reduce_body).
-// Measured at 129^3 x 256: 0.69 against 0.74 ms (float64), 0.51 against 0.59 ms (float32).
+// Measured at 129^3 x 256 (before the loads were grouped): 0.69 against 0.74 ms (float64), 0.51
+// against 0.59 ms (float32).
 // Direction pairs [q0, q1) only: the running sum starts from 0 (first) or from the raw sum a range
 // before left in Jfs, and is finished (divided by chi, the residual formed) only when last, so ranges
 // taken in order give bitwise the sum of one pass over all pairs.
@@ -453,50 +543,15 @@ template <typename real>
 __device__ inline void reduce_body_pair_range(const ReduceArgs &a, int p2, int k, int q0, int q1, bool first,
                                               bool last)
 {
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nx = a.nx, ny = a.ny;
     const int hx = (nx + 1) / 2;
     if (p2 >= hx * ny) return;
     const int j = p2 / hx, i0 = 2 * (p2 - j * hx);
     const bool two = i0 + 1 < nx;
     const int d1 = two ? 1 : 0;          // the second voxel's offset (0: none, reads the first again)
-    const real *P = static_cast<const real *>(a.P);
     const long v0 = long(k) * nx * ny + long(j) * nx + i0;
     double acc0 = first ? 0.0 : a.Jfs[v0], acc1 = (first || !two) ? 0.0 : a.Jfs[v0 + 1];
-#pragma unroll 4
-    for (int q = q0; q < q1; ++q) {
-        const rt3d::PairInfo pi = a.pairs[q];
-        const int rows = pi.band_rows, nb = pi.n_bands, Hw = pi.win_rows;
-        const int rmin = a.row_min[pi.dA * nz + k];
-        int jj = j - rmin;
-        jj += (jj < 0) ? ny : 0;
-        int b = min(int((float(jj) + 0.5f) * pi.inv_rows), nb - 1);
-        b -= (b * rows > jj) ? 1 : 0;
-        b += (b < nb - 1 && (b + 1) * rows <= jj) ? 1 : 0;
-        const int off0 = jj - b * rows;
-        const long plane = long(Hw) * nx;
-        const long band_stride = long(nz) * plane;
-        const real *Pq = P + pi.p_off + long(k) * plane + i0;
-        const int b1 = (b == 0) ? nb - 1 : b - 1;
-        const int off1 = off0 + ((b1 == nb - 1) ? pi.last_rows : rows);
-        const long o0 = long(b) * band_stride + long(off0) * nx;
-        const long o1 = long(b1) * band_stride + long(off1) * nx;
-        double s0 = double(Pq[o0]), s1 = double(Pq[o0 + d1]);
-        if (off1 < Hw) {
-            s0 += double(Pq[o1]);
-            s1 += double(Pq[o1 + d1]);
-            int bb = b1, off = off1;
-            while (true) {
-                bb = (bb == 0) ? nb - 1 : bb - 1;
-                off += (bb == nb - 1) ? pi.last_rows : rows;
-                if (off >= Hw) break;
-                const long o = long(bb) * band_stride + long(off) * nx;
-                s0 += double(Pq[o]);
-                s1 += double(Pq[o + d1]);
-            }
-        }
-        acc0 += pi.wmu * s0;
-        acc1 += pi.wmu * s1;
-    }
+    reduce_pairs<real>(a, i0, d1, j, k, q0, q1, acc0, acc1);
     for (int t = 0; t < (two ? 2 : 1); ++t) {
         const long v = v0 + t;
         const double acc = t ? acc1 : acc0;
