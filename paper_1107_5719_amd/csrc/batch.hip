@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kPlaneThreads) void reduce_kernel_batch(const Reduc
     const PlaneBlock b = blocks[blockIdx.x];
     if (st && st[b.member].mode != want) return;
     const ReduceArgs a = args[b.member];
-    reduce_body<real>(a, b.chunk * kPlaneThreads + threadIdx.x, b.k);
+    reduce_body_pair<real>(a, b.chunk * kPlaneThreads + threadIdx.x, b.k);
 }
 
 __global__ void anchor_copy_kernel(const CopyArgs *args, const MemberState *st)
@@ -360,7 +360,8 @@ struct rt3d_batch {
     int jac_M = 0;
     BatchItem *d_items = nullptr;
     PlaneBlock *d_planes = nullptr, *d_columns = nullptr;
-    int n_items = 0, n_planes = 0, n_columns = 0;
+    PlaneBlock *d_pplanes = nullptr;   // the reduction's blocks: chunks of voxel pairs of a row
+    int n_items = 0, n_planes = 0, n_columns = 0, n_pplanes = 0;
     size_t smem64 = 0, smem32 = 0;
     long max_V = 0;
     bool tables_ok = false;            // argument arrays and block tables match the members
@@ -419,7 +420,7 @@ void free_tables(rt3d_batch *b)
     drop_graph(b);
     bfree(b->d_state); bfree(b->d_params); bfree(b->d_scalars);
     bfree(b->d_src); bfree(b->d_sw); bfree(b->d_red); bfree(b->d_copy); bfree(b->d_ng); bfree(b->d_aa); bfree(b->d_jac);
-    bfree(b->d_items); bfree(b->d_planes); bfree(b->d_columns);
+    bfree(b->d_items); bfree(b->d_planes); bfree(b->d_columns); bfree(b->d_pplanes);
     b->jac_M = 0;
     b->tables_ok = false;
 }
@@ -507,7 +508,7 @@ int build_tables(rt3d_batch *b)
     std::vector<AaArgs> aa(n);
     std::vector<MemberScalars> sc(n);
     std::vector<std::pair<double, BatchItem>> work;
-    std::vector<PlaneBlock> planes, columns;
+    std::vector<PlaneBlock> planes, columns, pplanes;
     const SweepShape sh = kSweepShapes[b->shape];
     b->smem64 = b->smem32 = 0;
     b->max_V = 0;
@@ -567,6 +568,10 @@ int build_tables(rt3d_batch *b)
         const int chunks = (nx * ny + kPlaneThreads - 1) / kPlaneThreads;
         for (int z = 0; z < nz; ++z)
             for (int ch = 0; ch < chunks; ++ch) planes.push_back(PlaneBlock{i, ch, z, 0});
+        // the reduction takes two neighbouring voxels of a row per thread, as for a single problem
+        const int pchunks = ((nx + 1) / 2 * ny + kPlaneThreads - 1) / kPlaneThreads;
+        for (int z = 0; z < nz; ++z)
+            for (int ch = 0; ch < pchunks; ++ch) pplanes.push_back(PlaneBlock{i, ch, z, 0});
         // the Jacobi sweep's column layers, XCD-aware as in the single-problem grid: each member starts
         // on a multiple of 8 blocks; block b of the member runs on XCD b % 8, which takes the contiguous
         // chunk range [xcd * G, (xcd + 1) * G) of every column layer (G = chunks padded to 8, / 8);
@@ -592,13 +597,14 @@ int build_tables(rt3d_batch *b)
     chk(bupload(b, b->d_copy, cp)); chk(bupload(b, b->d_ng, ng)); chk(bupload(b, b->d_aa, aa));
     chk(bupload(b, b->d_scalars, sc));
     chk(bupload(b, b->d_items, items)); chk(bupload(b, b->d_planes, planes));
-    chk(bupload(b, b->d_columns, columns));
+    chk(bupload(b, b->d_columns, columns)); chk(bupload(b, b->d_pplanes, pplanes));
     if (rc) return rc;
     if (!b->d_state) BHIP_TRY(b, hipMalloc(reinterpret_cast<void **>(&b->d_state), n * sizeof(MemberState)), "hipMalloc");
     if (!b->d_params) BHIP_TRY(b, hipMalloc(reinterpret_cast<void **>(&b->d_params), sizeof(BatchParams)), "hipMalloc");
     b->n_items = int(items.size());
     b->n_planes = int(planes.size());
     b->n_columns = int(columns.size());
+    b->n_pplanes = int(pplanes.size());
     bfree(b->d_jac);
     b->jac_M = 0;
     b->tables_ok = true;
@@ -708,11 +714,11 @@ int enqueue_iteration(rt3d_batch *b, int M)
     if ((rc = launch_check(b, "source_kernel_batch"))) return rc;
     if ((rc = launch_sweep_batch(b, false, b->d_sw, b->d_state, 1))) return rc;
     if (f32 && (rc = launch_sweep_batch(b, true, b->d_sw + n, b->d_state, 2))) return rc;
-    hipLaunchKernelGGL(reduce_kernel_batch<double>, dim3(b->n_planes), dim3(kPlaneThreads), 0, b->stream,
-                       b->d_red, b->d_planes, b->d_state, 1);
+    hipLaunchKernelGGL(reduce_kernel_batch<double>, dim3(b->n_pplanes), dim3(kPlaneThreads), 0, b->stream,
+                       b->d_red, b->d_pplanes, b->d_state, 1);
     if (f32)
-        hipLaunchKernelGGL(reduce_kernel_batch<float>, dim3(b->n_planes), dim3(kPlaneThreads), 0, b->stream,
-                           b->d_red + n, b->d_planes, b->d_state, 2);
+        hipLaunchKernelGGL(reduce_kernel_batch<float>, dim3(b->n_pplanes), dim3(kPlaneThreads), 0, b->stream,
+                           b->d_red + n, b->d_pplanes, b->d_state, 2);
     if ((rc = launch_check(b, "reduce_kernel_batch"))) return rc;
     if (f32) {
         hipLaunchKernelGGL(anchor_copy_kernel, aux, dim3(256), 0, b->stream, b->d_copy, b->d_state);
@@ -974,11 +980,11 @@ int rt3d_batch_formal_solution(rt3d_batch *b)
     if ((rc = launch_check(b, "source_kernel_batch"))) return rc;
     if ((rc = launch_sweep_batch(b, f32, b->d_sw, nullptr, 0))) return rc;
     if (f32)
-        hipLaunchKernelGGL(reduce_kernel_batch<float>, dim3(b->n_planes), dim3(kPlaneThreads), 0, b->stream,
-                           b->d_red + 2 * b->n, b->d_planes, nullptr, 0);
+        hipLaunchKernelGGL(reduce_kernel_batch<float>, dim3(b->n_pplanes), dim3(kPlaneThreads), 0, b->stream,
+                           b->d_red + 2 * b->n, b->d_pplanes, nullptr, 0);
     else
-        hipLaunchKernelGGL(reduce_kernel_batch<double>, dim3(b->n_planes), dim3(kPlaneThreads), 0, b->stream,
-                           b->d_red + 2 * b->n, b->d_planes, nullptr, 0);
+        hipLaunchKernelGGL(reduce_kernel_batch<double>, dim3(b->n_pplanes), dim3(kPlaneThreads), 0, b->stream,
+                           b->d_red + 2 * b->n, b->d_pplanes, nullptr, 0);
     if ((rc = launch_check(b, "reduce_kernel_batch"))) return rc;
     BHIP_TRY(b, hipStreamSynchronize(b->stream), "sync");
     for (rt3d_ctx *c : b->m) {

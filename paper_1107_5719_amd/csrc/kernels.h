@@ -496,46 +496,10 @@ __device__ inline void reduce_pairs(const ReduceArgs &a, int i, int d1, int j, i
     }
 }
 
-// One voxel per thread (the batched form; grouping its loads as reduce_pairs does measured slower
-// there, 12.7 against 12.5 ms per batched formal solution of 64 wavelengths), pair by pair.
-template <typename real>
-__device__ inline void reduce_body(const ReduceArgs &a, int p, int k)
-{
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    if (p >= nx * ny) return;
-    const int j = p / nx, i = p - j * nx;
-    double acc = 0.0;
-#pragma unroll 4
-    for (int q = 0; q < a.n_pair; ++q) {
-        const rt3d::PairInfo pi = a.pairs[q];
-        const PairBands<real> pb = pair_bands<real>(a, pi, i, j, k);
-        const double v0 = double(pb.Pq[pb.o0]);
-        const double v1 = (pb.off1 < pi.win_rows) ? double(pb.Pq[pb.o1]) : 0.0;
-        double sd = v0 + v1;
-        if (pb.off1 < pi.win_rows) {
-            // bands thinner than the window halo: still earlier bands may cover the row
-            const long band_stride = long(nz) * pi.win_rows * nx;
-            int bb = pb.b1, off = pb.off1;
-            while (true) {
-                off = pair_bands_next_off(pi, bb, off);
-                bb = (bb == 0) ? pi.n_bands - 1 : bb - 1;
-                if (off >= pi.win_rows) break;
-                sd += double(pb.Pq[long(bb) * band_stride + long(off) * nx]);
-            }
-        }
-        acc += pi.wmu * sd;
-    }
-    const long v = long(k) * nx * ny + p;
-    const double Jfs = a.base ? a.base[v] + acc / a.chi[v] : acc / a.chi[v];
-    a.Jfs[v] = Jfs;
-    if (a.rb) a.rb[v] = a.chi[v] * (Jfs - a.J[v]);
-}
-
-// The same sum for two neighbouring voxels of one row per thread (p2 indexes the (ny, (nx + 1) / 2)
-// voxel pairs of plane k): the band lookup is shared and the partials of both are read together,
-// the per-voxel sums in the order of reduce_body (so the results are bitwise those of reduce_body).
-// Measured at 129^3 x 256 (before the loads were grouped): 0.69 against 0.74 ms (float64), 0.51
-// against 0.59 ms (float32).
+// Two neighbouring voxels of one row per thread (p2 indexes the (ny, (nx + 1) / 2) voxel pairs of
+// plane k; the batched form takes the same blocks per member): the band lookup is shared and the
+// partials of both are read together.  Measured at 129^3 x 256 against one voxel per thread (before
+// the loads were grouped): 0.69 against 0.74 ms (float64), 0.51 against 0.59 ms (float32).
 // Direction pairs [q0, q1) only: the running sum starts from 0 (first) or from the raw sum a range
 // before left in Jfs, and is finished (divided by chi, the residual formed) only when last, so ranges
 // taken in order give bitwise the sum of one pass over all pairs.
