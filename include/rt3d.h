@@ -17,8 +17,9 @@
  * measured best): RT3D_SWEEP_SHAPE (index into rt3d_sweep_shapes), RT3D_JACOBI_XCD (Jacobi launch
  * layout 0..4; all give bitwise the same iterates), RT3D_JACOBI_ALTERNATE (0: the column layout walks
  * every sweep bottom first instead of alternating; same iterates), RT3D_JACOBI_COLUMN (voxels per
- * thread of the column layout, 1, 2 or 4; default by grid size; same iterates), RT3D_ANCHOR_RATIO
- * (re-anchoring ratio of the RT3D_FP32_SWEEP form, default 1e-2).
+ * thread of the column layout, 1, 2 or 4; default by grid size; same iterates), RT3D_JACOBI_WALK
+ * (1: odd column layers walk top down, 0: never, -1 (default): for float coefficients in columns of 4;
+ * same iterates), RT3D_ANCHOR_RATIO (re-anchoring ratio of the RT3D_FP32_SWEEP form, default 1e-2).
  *
  * Discretisation (the paper defers it to earlier papers of its series; these are the readings):
  *   voxels    unit cubes (i,j,k), i fastest; k = 0 is the bottom (inner boundary), k = nz-1 the top;

@@ -322,7 +322,7 @@ int adjoint_os_step(rt3d_ctx *c, int M, double *dmax, double *numax, int *bad)
         ja.maxrel = c->d_maxrel; ja.maxdist = c->d_maxdist; ja.nonfinite = c->d_flag;
         ja.abs_measure = 1;
         launch_jacobi_sweep(ja, c->jacobi_xcd, c->coef_fp32 != 0, c->stream, c->jacobi_alternate && (m & 1) == 0,
-                            c->jacobi_height);
+                            c->jacobi_height, c->jacobi_walk);
         if ((rc = check_launch(c, "jacobi_kernel (adjoint)"))) return rc;
         in = ja.w_out;
     }

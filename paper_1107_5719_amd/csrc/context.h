@@ -39,6 +39,8 @@ struct rt3d_ctx {
                                     // orders (RT3D_JACOBI_ALTERNATE=0: always bottom first)
     int jacobi_height = 0;     // column layout: voxels per column, 1, 2 or 4 (0: by grid size;
                                // RT3D_JACOBI_COLUMN)
+    int jacobi_walk = -1;      // column layout: odd column layers walk top down (1), never (0), or for
+                               // float coefficients in columns of 4 (-1) (RT3D_JACOBI_WALK)
     // device buffers (owned)
     double *chi = nullptr, *eps = nullptr, *B = nullptr, *J = nullptr, *Jfs = nullptr, *r = nullptr;
     double *dJa = nullptr, *dJb = nullptr, *L = nullptr, *Iem = nullptr;

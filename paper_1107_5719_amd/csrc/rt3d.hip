@@ -401,7 +401,7 @@ int gauss_seidel_sweeps(rt3d_ctx *c, int M)
 int launch_jacobi_args(rt3d_ctx *c, const JacobiArgs &a, bool reverse)
 {
     launch_jacobi_sweep(a, c->jacobi_xcd, c->coef_fp32 != 0, c->stream, reverse && c->jacobi_alternate,
-                        c->jacobi_height);
+                        c->jacobi_height, c->jacobi_walk);
     return check_launch(c, "jacobi_kernel");
 }
 
@@ -612,6 +612,7 @@ int create_ctx(rt3d_ctx **out, const rt3d_grid_desc *g, int precision, hipStream
         const int h = std::atoi(e);
         c->jacobi_height = (h == 1 || h == 2 || h == 4) ? h : 0;
     }
+    if (const char *e = std::getenv("RT3D_JACOBI_WALK")) c->jacobi_walk = std::max(-1, std::min(1, std::atoi(e)));
     if (const char *e = std::getenv("RT3D_ANCHOR_RATIO")) c->anchor_ratio = std::max(0.0, std::atof(e));
     // Lambda* walk may stop at the first non-neighbour only if no line wraps back within two layers
     {
@@ -1162,12 +1163,13 @@ int rt3d_get_stats(rt3d_ctx *c, char *buf, int buflen)
     if (rc) return rc;
     std::string s = "{";
     char tmp[1024];
+    const int jcol = c->jacobi_height > 0 ? c->jacobi_height : jacobi_column_height(c->g.nx, c->g.ny, c->g.nz);
     std::snprintf(tmp, sizeof tmp,
                   "\"nx\":%d,\"ny\":%d,\"nz\":%d,\"n_dir\":%d,\"precision\":\"%s\",\"outer_iters\":%ld,"
                   "\"inner_sweeps\":%ld,\"fp64_sweeps\":%ld,\"fp32_sweeps\":%ld,\"device_bytes\":%zu,\"partial_plane_bytes\":%lld,"
                   "\"sweep_workgroups\":%zu,\"sweep_shape\":%d,\"sweep_threads\":%d,\"sweep_lines\":%d,\"mean_segments\":%.6f,"
                   "\"max_window_rows\":%d,\"sweep_lds_bytes\":%zu,"
-                  "\"os_method\":\"%s\",\"coef_storage\":\"%s\",\"jacobi_layout\":%d,\"jacobi_column\":%d,"
+                  "\"os_method\":\"%s\",\"coef_storage\":\"%s\",\"jacobi_layout\":%d,\"jacobi_column\":%d,\"jacobi_alt_walk\":%d,"
                   "\"timing\":%d,\"kernels\":{",
                   c->g.nx, c->g.ny, c->g.nz, c->A.n_dir, c->precision == RT3D_FP64 ? "fp64" : "fp32_sweep",
                   c->outer_iters, c->inner_sweeps, c->fp64_sweeps, c->fp32_sweeps, c->device_bytes,
@@ -1175,8 +1177,8 @@ int rt3d_get_stats(rt3d_ctx *c, char *buf, int buflen)
                   c->sweep_shape, kSweepShapes[c->sweep_shape].threads, kSweepShapes[c->sweep_shape].lines, c->plan.mean_segments,
                   c->plan.max_win_rows, sweep_smem_bytes(c->plan, c->precision != RT3D_FP64),
                   c->os_method == RT3D_OS_GAUSS_SEIDEL ? "gauss_seidel" : "jacobi", c->coef_fp32 ? "fp32" : "fp64",
-                  c->jacobi_xcd, c->jacobi_height > 0 ? c->jacobi_height : jacobi_column_height(c->g.nx, c->g.ny, c->g.nz),
-                  c->timing);
+                  c->jacobi_xcd, jcol,
+                  (c->jacobi_xcd == 4 && jacobi_alt_walk(c->jacobi_walk, c->coef_fp32 != 0, jcol)) ? 1 : 0, c->timing);
     s += tmp;
     for (int k = 0; k < K_COUNT; ++k) {
         std::snprintf(tmp, sizeof tmp, "%s\"%s\":{\"launches\":%ld,\"timed\":%ld,\"total_ms\":%.6f}", k ? "," : "",

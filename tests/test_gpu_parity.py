@@ -316,24 +316,31 @@ def test_determinism_and_resume(R):
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32_sweep"])
 def test_jacobi_grid_layouts_agree_bitwise(R, precision, monkeypatch):
     """Every launch layout of the Jacobi sweep (one block per plane chunk, padded, XCD-grouped, 2D
-    tiles, columns of 1, 2 or 4 voxels marched in z, in either order of the column layers) computes
-    each voxel's sum in the same order, so OS steps agree bitwise; the grid (nz = 10, not a multiple
-    of the column height 4; 37 x 9 columns, a ragged last chunk) also checks the column form's ends.
-    The layout is read from RT3D_JACOBI_XCD, RT3D_JACOBI_ALTERNATE and RT3D_JACOBI_COLUMN when a
-    context is created."""
+    tiles, columns of 1, 2 or 4 voxels marched in z, in either order of the column layers, odd layers
+    walked bottom up or top down) computes each voxel's sum in the same order, so OS steps agree
+    bitwise; the grid (nz = 10, not a multiple of the column height 4; 37 x 9 columns, a ragged last
+    chunk) also checks the column form's ends.  The layout is read from RT3D_JACOBI_XCD,
+    RT3D_JACOBI_ALTERNATE, RT3D_JACOBI_COLUMN and RT3D_JACOBI_WALK when a context is created."""
     m = random_medium(37, 9, 10, seed=77, chi_range=(1e-3, 3e1), eps_range=(1e-4, 0.3))
     out = {}
-    # (layout, alternate, column height): layouts 0..3 ignore the rest; column height 0 is the size
-    # rule (1 on this grid)
-    layouts = ((0, 1, 0), (1, 1, 0), (2, 1, 0), (3, 1, 0), (4, 1, 0), (4, 0, 0), (4, 1, 2), (4, 1, 4),
-               (4, 0, 4))
+    # (layout, alternate, column height, walk): layouts 0..3 ignore the rest; column height 0 is the
+    # size rule (1 on this grid); walk -1 is the default rule (top-down odd layers for float
+    # coefficients in columns of 4, which the FP32-sweep form stores)
+    layouts = ((0, 1, 0, -1), (1, 1, 0, -1), (2, 1, 0, -1), (3, 1, 0, -1), (4, 1, 0, -1), (4, 0, 0, -1),
+               (4, 1, 2, -1), (4, 1, 4, -1), (4, 0, 4, -1), (4, 1, 4, 1), (4, 0, 4, 1), (4, 1, 4, 0),
+               (4, 1, 2, 1))
     for layout in layouts:
         monkeypatch.setenv("RT3D_JACOBI_XCD", str(layout[0]))
         monkeypatch.setenv("RT3D_JACOBI_ALTERNATE", str(layout[1]))
         monkeypatch.setenv("RT3D_JACOBI_COLUMN", str(layout[2]))
+        monkeypatch.setenv("RT3D_JACOBI_WALK", str(layout[3]))
         with R.Solver(37, 9, 10, 4, 8, precision=precision) as s:
             s.set_medium(m["chi"], m["eps"], m["B"])
             cs = [s.os_step(7) for _ in range(3)]
+            st = s.stats()
+            if layout[0] == 4 and layout[2] == 4:
+                want = layout[3] == 1 or (layout[3] == -1 and st["coef_storage"] == "fp32")
+                assert st["jacobi_alt_walk"] == int(want), layout
             out[layout] = (s.get_J(), cs)
     for layout in layouts[1:]:
         assert np.array_equal(out[layout][0], out[layouts[0]][0]), f"layout {layout}"
