@@ -4,7 +4,8 @@ It must give what rt3d_formal_solution of a context gives for the same S and bou
 same plan, kernels and summation order: bitwise, and so within the parity bar of 1e-10 of the
 oracle-checked path), on two calls in a row that share the device's workspace, the second with a
 smaller grid: the first (65^3 x 256 angles) is larger than the workspace holds at once, so its
-direction pairs are swept in several ranges; the second (17^3 x 64 angles) fits in one.
+direction pairs are swept in several ranges (46, 37 and 45 of its 128 pairs, so the reduction's
+groups of four pairs end inside a range); the second (17^3 x 64 angles) fits in one.
 """
 import numpy as np
 import pytest
