@@ -329,6 +329,12 @@ bool build_sweep_plan(int nx, int ny, int nz, const AngleSet &A, int lines_per_w
         }
     }
     P.n_pair = int(P.pairs.size());
+    // the Lambda* kernel takes the pairs as two runs, all of one vertical direction, then the other
+    for (int p = 1, changes = 0; p < P.n_pair; ++p)
+        if (P.pairs[p].down != P.pairs[p - 1].down && ++changes > 1) {
+            err = "direction pairs are not ordered by their vertical direction";
+            return false;
+        }
     int64_t off = 0;
     std::vector<std::pair<double, WorkItem>> work;
     for (int p = 0; p < P.n_pair; ++p) {

@@ -598,14 +598,18 @@ __device__ inline int wrap_small(int a, int n)
 // lie in the 3x3x3 block (lines are monotone in z).  The two directions of an x-mirrored pair have
 // equal segment lengths and row offsets and negated column offsets, so one walk over direction A's
 // table serves both (B's voxels at the mirrored columns), and their self terms are equal.
-// One wavefront per workgroup: the 27 accumulators per thread live in LDS (13.8 KB per workgroup),
-// and small workgroups let many of them share a CU to hide the latency of the gathers along the
-// lines (measured at 129^3 x 256: 31.7 ms with 256 threads, 29.2 ms with 128, 26.4 ms with 64).
+// One wavefront per workgroup, small workgroups letting many of them share a CU to hide the latency of
+// the gathers along the lines (measured at 129^3 x 256: 31.7 ms with 256 threads, 29.2 ms with 128,
+// 26.4 ms with 64).  The accumulators live in LDS.  A walk reaches the voxel's own layer and the one it
+// came from: layer k + 1 for the downward pairs, k - 1 for the upward ones, and the pairs come in two
+// runs (all of one vertical direction, then all of the other; the plan checks this).  So a thread
+// keeps 18 accumulators, its own layer's 9 and those of the run's other layer, which are stored and
+// cleared between the runs: every entry sums the same terms in the same order as with 27.
 constexpr int kLstarThreads = 64;
 // Columns p (p = j nx + i; p >= nx ny: none) of plane k; the whole block calls this.
 __device__ inline void lstar_body(const LstarArgs &a, int p, int k)
 {
-    __shared__ double acc[27][kLstarThreads];
+    __shared__ double acc[18][kLstarThreads];   // [0, 9): layer k; [9, 18): the current run's other layer
     __shared__ double xtab[kExpTab];
     for (int q = threadIdx.x; q < kExpTab; q += kLstarThreads) xtab[q] = a.xtab[q];
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -614,13 +618,28 @@ __device__ inline void lstar_body(const LstarArgs &a, int p, int k)
     const long plane = long(nx) * ny;
     const long V = plane * nz;
     const long v = k * plane + long(j) * nx + i;
-    for (int o = 0; o < 27; ++o) acc[o][threadIdx.x] = 0.0;
+    for (int o = 0; o < 18; ++o) acc[o][threadIdx.x] = 0.0;
     __syncthreads();
     const double chiv = a.chi[v];
     // 3x3x3 block index of a column offset m (mod n) from v: 0 for -1, 1 for 0, 2 for +1, -1 outside
     auto block_col = [](int m, int n) { return (m == 0) ? 1 : (m == 1) ? 2 : (m == n - 1) ? 0 : -1; };
+    // the other layer's 9 entries of the 27-point row (entries 0..8 for k - 1, 18..26 for k + 1)
+    auto store_other = [&](int down) {
+        const int o0 = down ? 18 : 0;
+        if (valid)
+            for (int o = 0; o < 9; ++o) a.L[(o0 + o) * V + v] = acc[9 + o][threadIdx.x];
+        for (int o = 0; o < 9; ++o) acc[9 + o][threadIdx.x] = 0.0;
+    };
+    int run_down = a.n_pair > 0 ? a.pairs[0].down : 0;
+    bool stored_up = false, stored_down = false;    // the layers k - 1 and k + 1 have been written
     for (int q = 0; q < a.n_pair; ++q) {
         const rt3d::PairInfo pi = a.pairs[q];
+        if (pi.down != run_down) {
+            store_other(run_down);
+            stored_down = stored_down || run_down;
+            stored_up = stored_up || !run_down;
+            run_down = pi.down;
+        }
         const double fac = pi.wmu / chiv;
         const int d = pi.dA;
         const int dk = d * nz + k;
@@ -633,15 +652,15 @@ __device__ inline void lstar_body(const LstarArgs &a, int p, int k)
             const int as = a.seg_ai[off + s], bs = a.seg_bi[off + s];
             const double dtau = chiv * a.seg_len[off + s];
             const double em1 = expm1_nonpos_tab(-dtau, xtab);
-            acc[13][threadIdx.x] += 2.0 * (fac * self_term(dtau, em1));
+            acc[4][threadIdx.x] += 2.0 * (fac * self_term(dtau, em1));
             const double g = -fac * em1;
             double prodA = 1.0, prodB = 1.0;
             // walk back: current layer s-1 .. 0, then the previous layer from its last segment
             const int total = s + nu;
             for (int w = 0; w < total; ++w) {
-                int idx, dkk;
-                if (w < s) { idx = off + s - 1 - w; dkk = 0; }
-                else { idx = offu + nu - 1 - (w - s); dkk = ku - k; }
+                int idx, base;
+                if (w < s) { idx = off + s - 1 - w; base = 0; }
+                else { idx = offu + nu - 1 - (w - s); base = 9; }
                 const int dA = a.seg_ai[idx] - as, dB = a.seg_bi[idx] - bs;
                 if (a.early_exit && (dA > 1 || dA < -1 || dB > 1 || dB < -1)) break;
                 // with early exit the offsets are -1, 0 or 1 here
@@ -653,22 +672,30 @@ __device__ inline void lstar_body(const LstarArgs &a, int p, int k)
                 colB -= (colB >= nx) ? nx : 0;
                 int row = j + mB;
                 row -= (row >= ny) ? ny : 0;
-                const long ub = long(k + dkk) * plane + long(row) * nx;
+                const long ub = long(base ? ku : k) * plane + long(row) * nx;
                 const double len = a.seg_len[idx];
                 double eA, em1A, eB, em1B;
                 exp_pair_tab(-a.chi[ub + colA] * len, xtab, eA, em1A);
                 exp_pair_tab(-a.chi[ub + colB] * len, xtab, eB, em1B);
                 const int oj = block_col(mB, ny);
                 const int oiA = block_col(mA, nx), oiB = block_col(mAm, nx);
-                if (oiA >= 0 && oj >= 0) acc[9 * (dkk + 1) + 3 * oj + oiA][threadIdx.x] += g * (-em1A * prodA);
-                if (oiB >= 0 && oj >= 0) acc[9 * (dkk + 1) + 3 * oj + oiB][threadIdx.x] += g * (-em1B * prodB);
+                if (oiA >= 0 && oj >= 0) acc[base + 3 * oj + oiA][threadIdx.x] += g * (-em1A * prodA);
+                if (oiB >= 0 && oj >= 0) acc[base + 3 * oj + oiB][threadIdx.x] += g * (-em1B * prodB);
                 prodA *= eA;
                 prodB *= eB;
             }
         }
     }
+    store_other(run_down);
+    stored_down = stored_down || run_down;
+    stored_up = stored_up || !run_down;
+    // a layer no run reached (all pairs of one vertical direction) has no entries
+    if (valid && !stored_up)
+        for (int o = 0; o < 9; ++o) a.L[o * V + v] = 0.0;
+    if (valid && !stored_down)
+        for (int o = 0; o < 9; ++o) a.L[(18 + o) * V + v] = 0.0;
     if (valid)
-        for (int o = 0; o < 27; ++o) a.L[o * V + v] = acc[o][threadIdx.x];
+        for (int o = 0; o < 9; ++o) a.L[(9 + o) * V + v] = acc[o][threadIdx.x];
 }
 
 __global__ __launch_bounds__(kLstarThreads) void lstar_kernel(LstarArgs a)
