@@ -117,9 +117,10 @@ __global__ __launch_bounds__(kPlaneThreads) void source_kernel_batch(const Sourc
     source_body<real>(a, b.chunk * kPlaneThreads + threadIdx.x, b.k);
 }
 
-// With two slots per thread the float64 batched sweep is held to 80 VGPRs (6 waves per SIMD; it takes
-// 76): 14.4 -> 14.0 ms per batched formal solution of 64 wavelengths when it needed 88.  Held to 64
-// (8 waves) it spills per layer and runs 13.7 against 12.4 ms.
+// With two slots per thread the float64 batched sweep is held to 80 VGPRs (6 waves per SIMD): 14.4 ->
+// 14.0 ms per batched formal solution of 64 wavelengths when it needed 88.  Held to 64 (8 waves) it
+// spills per layer and runs 13.7 against 12.4 ms.  With the paired lines it would take 82 and spills
+// 20 bytes at 80, yet 5 waves without the spill run slower: 12.1 against 11.7 ms (shape 256 x 2).
 template <int LPT> constexpr int kBatchSweepMinWaves = LPT <= 2 ? 6 : 1;
 
 template <typename real, int NT, int LPT>
