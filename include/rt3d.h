@@ -186,11 +186,13 @@ int rt3d_set_acceleration(rt3d_ctx *ctx, int ng_order, int ng_every);
  * like a restarted Krylov method): every OS step x -> g joins a window of the newest depth + 1 pairs
  * (x_i, g_i), and from the second step on the next input is g_k - sum_j gamma_j (g_k - g_{k-j}), where
  * gamma minimises sum_v (f_k - sum_j gamma_j (f_k - f_{k-j}))_v^2 / g_k,v^2, f = g - x (the weights of
- * Ng's method); a singular or non-finite solve keeps g_k.  The window slides (no restart).  depth 0
- * switches it off (the default); 1 <= depth <= 8.  Setting a depth switches Ng acceleration off and
- * rt3d_set_acceleration with ng_order > 0 switches Anderson mixing off.  Dot products are reduced in a
- * fixed order (bitwise reproducible).  Allocates 2 (depth + 1) V float64 on the device.  The batched
- * form and the adjoint solve use Ng only.  Errors: RT3D_ERR_ARG, RT3D_ERR_OOM, RT3D_ERR_HIP. */
+ * Ng's method); a singular or non-finite solve keeps g_k.  The window slides; in the RT3D_FP32_SWEEP
+ * form a step anchored in float64 restarts it from that step's pair.  depth 0 switches it off (the
+ * default); 1 <= depth <= 8.  Setting a depth switches Ng acceleration off and rt3d_set_acceleration
+ * with ng_order > 0 switches Anderson mixing off.  Dot products are reduced in a fixed order (bitwise
+ * reproducible).  Allocates 2 (depth + 1) V float64 on the device.  rt3d_batch_set_anderson is the
+ * batched form's counterpart; the adjoint solve does not mix.  Errors: RT3D_ERR_ARG, RT3D_ERR_OOM,
+ * RT3D_ERR_HIP. */
 int rt3d_set_anderson(rt3d_ctx *ctx, int depth);
 
 /* Inner solve of the OS step (section "Implementation of the operator splitting step": the Fortran

@@ -205,6 +205,11 @@ __global__ void ctl_post_kernel(int n, MemberState *st, const BatchParams *prm, 
     const double c = __longlong_as_double(static_cast<long long>(*sc[m].maxrel));
     const double d = __longlong_as_double(static_cast<long long>(*sc[m].maxdist));
     const bool anchored = s.mode == 1;
+    // FP32 form: an anchored step starts the Anderson window afresh, as in the single solve
+    if (prm->aa_depth > 0 && prm->fp32 && anchored && s.aa_count > 1) {
+        s.aa_slot[0] = s.aa_slot[s.aa_count - 1];
+        s.aa_count = 1;
+    }
     s.iters += 1;
     s.c_last = c;
     s.da_last = d;

@@ -1005,6 +1005,12 @@ int rt3d_solve_to_convergence(rt3d_ctx *c, double tol, int max_iter, int inner_s
             HIP_TRY(c, hipMemcpyAsync(c->aa_g + long(aa_slots[aa_count]) * c->V, c->J, vbytes,
                                       hipMemcpyDeviceToDevice, c->stream), "anderson output");
             ++aa_count;
+            // FP32 form: an anchored step starts the window afresh from its own pair; the earlier
+            // pairs' outputs carry float32 rounding relative to the previous anchor
+            if (c->precision == RT3D_FP32_SWEEP && c->last_step_anchored && aa_count > 1) {
+                aa_slots[0] = aa_slots[aa_count - 1];
+                aa_count = 1;
+            }
         }
         if (cval < tol) {
             // the FP32 form accepts convergence only from a step whose residual is float64
