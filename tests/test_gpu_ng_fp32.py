@@ -259,6 +259,26 @@ def test_anderson_solve_parity(R, orc, depth):
     assert h["anderson"][1:-1].all() and not h["anderson"][0] and not h["anderson"][-1] and not h["ng"].any()
 
 
+def test_fp32_form_anderson_restarts_at_anchored_steps(R):
+    """In the FP32 form a step anchored in float64 restarts the Anderson window from its own pair: no
+    mixing follows an anchored step (the window holds one pair), while every other step that has not
+    converged mixes (the window holds at least two)."""
+    m = random_medium(9, 8, 7, seed=41, chi_range=(1e-1, 3e1), eps_range=(1e-3, 1e-2))
+    tol = 1e-10
+    with R.Solver(9, 8, 7, 4, 8, precision=1) as s:
+        s.set_medium(m["chi"], m["eps"], m["B"])
+        s.set_anderson(5)
+        st, it, c = s.solve(tol, 1000, 8)
+        assert st == R.RT3D_OK
+        h = s.history()
+    f64, mixed, cv = h["float64_fs"], h["anderson"], h["max_rel_dJ"]
+    assert f64[0] and f64.sum() >= 3, "the solve should re-anchor at least twice"
+    assert not (f64 & mixed).any()
+    for q in range(1, len(f64)):
+        if not f64[q] and cv[q] >= tol:
+            assert mixed[q], f"step {q} did not mix"
+
+
 def test_anderson_fixed_point_and_settings(R, orc):
     """Both forms with Anderson mixing reach the dense fixed point; depth 0 and Ng switch it off."""
     nz, ny, nx = 5, 4, 6
